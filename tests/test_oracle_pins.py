@@ -1,0 +1,451 @@
+"""Pins of the CPU oracle against what the paper's model fixes (no GPU).
+
+Each test checks the oracle against something other than itself: a closed
+form of backward Euler with Coulomb contact (Sec. III-A/B), a library routine
+(numpy / scipy), brute-force finite differences, or an invariant.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+G = 9.81
+
+
+def quat_R(q):
+    x, y, z, w = np.asarray(q, dtype=float) / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def mass_matrix(batch, w, q):
+    off = batch.body_off
+    nb = off[w + 1] - off[w]
+    M = np.zeros((6 * nb, 6 * nb))
+    for i in range(nb):
+        gi = off[w] + i
+        M[6 * i:6 * i + 3, 6 * i:6 * i + 3] = batch.body_mass[gi] * np.eye(3)
+        R = quat_R(q[gi, 3:7])
+        M[6 * i + 3:6 * i + 6, 6 * i + 3:6 * i + 6] = R @ np.diag(batch.body_inertia[gi]) @ R.T
+    return M
+
+
+def run(batch, params, steps, ctrl=None, lam=None):
+    q, u = batch.q0.copy(), batch.u0.copy()
+    lam = np.zeros(batch.n_lam) if lam is None else lam
+    outs = []
+    for k in range(steps):
+        c = None if ctrl is None else ctrl(k)
+        o = oracle.step_forward(batch, params, q, u, lam, c)
+        q, u, lam = o["q"], o["u"], o["lam"]
+        outs.append(o)
+    return outs
+
+
+def contact_lams(batch, w, lam_slots):
+    """(lambda_n, lambda_t1, lambda_t2) per slot of world w."""
+    wd = batch.worlds[w]
+    base = batch.lam_off[w] + 5 * len(wd.joints) + wd.n_servo
+    return lam_slots[base:base + 3 * len(wd.slots)].reshape(-1, 3)
+
+
+# ----------------------------------------------------------------- closed forms
+
+def test_free_flight_closed_form():
+    """Backward Euler in free flight: v_n = v0 + n h g, x_n = x0 + n h v0 + h^2 g n(n+1)/2;
+    torque-free spin about a principal axis keeps omega and turns by 2 atan(h w / 2) per step."""
+    wd = scenes.World(contact_cap=0)
+    wd.add_body(2.0, (0.1, 0.2, 0.3), (0, 0, 5.0, 0, 0, 0, 1), (0.3, -0.2, 1.0, 0.0, 0.0, 1.7))
+    b = scenes.pack([wd])
+    P = scenes.solver_params(tol=1e-12)
+    n, h = 7, P["h"]
+    outs = run(b, P, n)
+    q, u = outs[-1]["q"][0], outs[-1]["u"][0]
+    g = np.array(P["gravity"])
+    v0 = np.array([0.3, -0.2, 1.0])
+    np.testing.assert_allclose(u[:3], v0 + n * h * g, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(q[:3], np.array([0, 0, 5.0]) + n * h * v0 + h * h * g * n * (n + 1) / 2,
+                               rtol=0, atol=1e-12)
+    np.testing.assert_allclose(u[3:], [0, 0, 1.7], atol=1e-12)
+    ang = n * 2 * math.atan(h * 1.7 / 2)
+    np.testing.assert_allclose(q[3:], [0, 0, math.sin(ang / 2), math.cos(ang / 2)], atol=1e-12)
+    assert all(o["status"][0] & 1 for o in outs)
+
+
+def test_sliding_box_worked_example():
+    """Each backward-Euler step removes mu g h of speed until the box sticks."""
+    gold = json.load(open(os.path.join(HERE, "golden", "sliding_box.json")))
+    mu, h, v0, T = gold["mu"], gold["h"], gold["v0"], gold["T"]
+    b = scenes.pack([scenes.box_world(None, v=(v0, 0, 0), mu=mu)])
+    P = scenes.solver_params(h=h, k_max=64)
+    outs = run(b, P, T)
+    speeds = [np.linalg.norm(o["u"][0, :3]) for o in outs]
+    np.testing.assert_allclose(speeds, gold["speeds"], atol=1e-9)
+    assert abs(outs[-1]["q"][0, 0] - gold["displacement"]) < 1e-9
+    for o in outs:
+        np.testing.assert_allclose(o["u"][0, 3:], 0, atol=1e-9)
+    # sliding friction force = mu m g (Sec. III-B, timestep consistency)
+    lam = contact_lams(b, 0, outs[0]["lam"])
+    assert abs(np.linalg.norm(lam[:, 1:].sum(0)) - mu * G) < 1e-8
+    assert abs(lam[:, 0].sum() - G) < 1e-8
+
+
+def test_sliding_box_gradient_closed_form():
+    """dx_T/dv0 = h sum_k [vv^T + |v_k|/|v0| (I - vv^T)] over the sliding steps."""
+    gold = json.load(open(os.path.join(HERE, "golden", "sliding_box.json")))
+    b = scenes.pack([scenes.box_world(None, v=(gold["v0"], 0, 0), mu=gold["mu"])])
+    P = scenes.solver_params(h=gold["h"], k_max=64, tol=1e-12)
+    T = gold["T"]
+    base = oracle.rollout(b, P, b.q0, b.u0, None, T, grad=False)
+    xT = base["qT"][0, :2]
+    for axis, want in ((0, gold["grad_along"]), (1, gold["grad_across"])):
+        b.target[0] = xT - 0.5 * np.eye(2)[axis]      # dL/dv0 = e_axis^T dx_T/dv0
+        r = oracle.rollout(b, P, b.q0, b.u0, None, T)
+        g = r["g_u0"][0]
+        assert abs(g[axis] - want) < 1e-7, (axis, g)
+        assert abs(g[1 - axis]) < 1e-7
+
+
+@pytest.mark.parametrize("h", [0.01, 0.05, 0.1])
+def test_timestep_consistent_friction(h):
+    """Converged sliding force mu m g and resting normal force m g for every h (Sec. III-B)."""
+    mu = 0.8
+    b = scenes.pack([scenes.box_world(None, v=(3.0, 0, 0), mu=mu), scenes.box_world(None, mu=mu)])
+    P = scenes.solver_params(h=h, k_max=64)
+    o = run(b, P, 1)[0]
+    assert np.all(o["status"] & 1)
+    slide, rest = contact_lams(b, 0, o["lam"]), contact_lams(b, 1, o["lam"])
+    tol = 10 * P["tol"] / h     # a residual of tol in r_dyn is tol / h in force
+    assert abs(np.linalg.norm(slide[:, 1:].sum(0)) - mu * G) < tol
+    assert abs(slide[:, 0].sum() - G) < tol
+    assert abs(rest[:, 0].sum() - G) < tol
+    np.testing.assert_allclose(o["u"][1], 0, atol=tol)
+
+
+def test_static_friction_on_incline():
+    """Gravity tilted by theta: tan(theta) < mu rests with friction -m g_t; tan(theta) > mu
+    slides with dv = h g (sin theta - mu cos theta) per step."""
+    mu = 0.8
+    for theta, rests in ((0.5, True), (0.8, False)):
+        g = (G * math.sin(theta), 0.0, -G * math.cos(theta))
+        b = scenes.pack([scenes.box_world(None, mu=mu)])
+        P = scenes.solver_params(gravity=g, k_max=64)
+        outs = run(b, P, 3)
+        for k, o in enumerate(outs):
+            assert o["status"][0] & 1
+            if rests:
+                np.testing.assert_allclose(o["u"][0], 0, atol=1e-10)
+                lam = contact_lams(b, 0, o["lam"])
+                # t1 = e_y, t2 = -e_x for the ground normal
+                assert abs(-lam[:, 2].sum() + G * math.sin(theta)) < 1e-8
+            else:
+                want = (k + 1) * P["h"] * G * (math.sin(theta) - mu * math.cos(theta))
+                assert abs(o["u"][0, 0] - want) < 1e-9
+
+
+def test_drop_and_inelastic_impact():
+    """A flat box falling onto the plane: v_z+ = max(v_z- - g h, -gap/h); no bounce (e = 0)."""
+    b = scenes.pack([scenes.box_world(None, z=0.1 + 0.03, v=(0, 0, -0.5))])
+    P = scenes.solver_params(k_max=64)
+    outs = run(b, P, 3)
+    h = P["h"]
+    vz1 = max(-0.5 - G * h, -0.03 / h)
+    assert abs(outs[0]["u"][0, 2] - vz1) < 1e-9
+    lam = contact_lams(b, 0, outs[0]["lam"])
+    assert abs(lam[:, 0].sum() - 1.0 * (vz1 + 0.5 + G * h) / h) < 1e-7
+    for o in outs[1:]:
+        assert abs(o["u"][0, 2]) < 1e-9
+        assert abs(o["q"][0, 2] - 0.1) < 1e-9
+
+
+def test_servo_two_body_closed_form():
+    """Velocity servo (Eq. (8), alpha = 1/k_p): lambda = k_p (u_bar - w_rel-) / (1 + h k_p / I_eff)."""
+    wd = scenes.World(contact_cap=0)
+    Ia, Ib = (0.3, 0.4, 0.5), (0.002, 0.0025, 0.002)
+    a = wd.add_body(10.0, Ia, (0, 0, 3, 0, 0, 0, 1), (0, 0, 0, 0, 0.2, 0))
+    c = wd.add_body(0.5, Ib, (0, 0, 3, 0, 0, 0, 1), (0, 0, 0, 0, 3.0, 0))
+    kp, ubar = 0.7, 10.0
+    wd.add_revolute(a, c, anchor_a=(0, 0, 0), anchor_b=(0, 0, 0), act=scenes.ACT_SERVO_VEL, kp=kp)
+    b = scenes.pack([wd])
+    P = scenes.solver_params(gravity=(0, 0, 0), k_max=64, tol=1e-13)
+    h = P["h"]
+    o = run(b, P, 1, ctrl=lambda k: np.array([ubar]))[0]
+    Ieff = 1.0 / (1.0 / Ia[1] + 1.0 / Ib[1])
+    lam_c = kp * (ubar - (3.0 - 0.2)) / (1 + h * kp / Ieff)
+    assert abs(o["u"][1, 4] - (3.0 + h * lam_c / Ib[1])) < 1e-10
+    assert abs(o["u"][0, 4] - (0.2 - h * lam_c / Ia[1])) < 1e-10
+
+
+def test_linear_momentum_conserved_in_flight():
+    """With g = 0 and no contact, joint and actuator forces are internal."""
+    wd = scenes.robot_world(None, with_obstacle=False)
+    for i in range(len(wd.q0)):
+        x = list(wd.q0[i])
+        x[2] += 3.0
+        wd.q0[i] = tuple(x)
+    rng = np.random.default_rng(3)
+    wd.u0 = [tuple(rng.normal(0, 0.3, 6)) for _ in wd.u0]
+    b = scenes.pack([wd])
+    P = scenes.solver_params(gravity=(0, 0, 0), k_max=64)
+    p0 = (b.body_mass[:, None] * b.u0[:, :3]).sum(0)
+    outs = run(b, P, 5, ctrl=lambda k: np.array([1.0, -0.5, 0.3, 2.0]))
+    for o in outs:
+        p = (b.body_mass[:, None] * o["u"][:, :3]).sum(0)
+        np.testing.assert_allclose(p, p0, atol=1e-9)
+
+
+# ------------------------------------------------------------ complementarity
+
+def _corner_state(batch, w, q, u, slot):
+    s = batch.slot_off[w] + slot
+    a = batch.body_off[w] + batch.slot_int[s, 1]
+    loc = batch.slot_real[s, :3]
+    R = quat_R(q[a, 3:7])
+    arm = R @ loc
+    p = q[a, :3] + arm
+    v = u[a, :3] + np.cross(u[a, 3:], arm)
+    return p, v, batch.slot_real[s, 4]
+
+
+def test_complementarity_and_cone_at_convergence():
+    """lambda_n >= 0, gap >= 0, lambda_n gap <= 1e-10; |lambda_f| <= mu lambda_n; sliding
+    friction opposes slip; sticking contacts do not slip (Eqs. (4)-(6))."""
+    b = scenes.box_batch(24, seed=5)
+    P = scenes.solver_params(k_max=64)
+    checked = 0
+    q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    for step in range(4):
+        o = oracle.step_forward(b, P, q, u, lam, None)
+        for w in range(b.n_worlds):
+            if not o["status"][w] & 1:
+                continue
+            L = contact_lams(b, w, o["lam"])
+            for c in o["act_slot"][b.slot_off[w]:b.slot_off[w] + o["n_act"][w]]:
+                p, v, mu = _corner_state(b, w, o["q"], o["u"], c)
+                ln, lt = L[c, 0], L[c, 1:]
+                gap = p[2]
+                assert ln >= -1e-9 and gap >= -1e-9
+                assert ln * gap <= 1e-10
+                lf = lt[0] * np.array([0, 1, 0]) + lt[1] * np.array([-1, 0, 0])
+                assert np.linalg.norm(lf) <= mu * ln * (1 + 1e-12) + 1e-12
+                vt = v - v[2] * np.array([0, 0, 1.0])
+                if np.linalg.norm(vt) > 1e-6 and ln > 1e-6:
+                    cosang = lf @ vt / (np.linalg.norm(lf) * np.linalg.norm(vt))
+                    assert cosang < -1 + 1e-9
+                    assert abs(np.linalg.norm(lf) - mu * ln) < 1e-8 * max(1, ln)
+                elif ln > 1e-6 and np.linalg.norm(lf) < mu * ln * (1 - 1e-6):
+                    assert np.linalg.norm(vt) < 1e-8
+                checked += 1
+        q, u, lam = o["q"], o["u"], o["lam"]
+    assert checked > 100
+
+
+def test_joint_constraints_hold_at_convergence():
+    b = scenes.robot_batch(4, seed=2)
+    K = scenes.ROBOT_KNOTS
+    knots = scenes.knots_array(b, K)
+    B = oracle.spline_basis(10, K, 0.1)
+    P = scenes.solver_params(k_max=64)
+    outs = run(b, P, 10, ctrl=lambda k: knots @ B[k])
+    for o in outs:
+        q = o["q"]
+        for w in range(b.n_worlds):
+            if not o["status"][w] & 1:
+                continue
+            j0 = b.joint_off[w]
+            for j in range(j0, b.joint_off[w + 1]):
+                a = b.body_off[w] + b.joint_body[j, 0]
+                c = b.body_off[w] + b.joint_body[j, 1]
+                fr = b.joint_frame[j]
+                pa = q[a, :3] + quat_R(q[a, 3:7]) @ fr[0:3]
+                pc = q[c, :3] + quat_R(q[c, 3:7]) @ fr[3:6]
+                assert np.linalg.norm(pa - pc) < 1e-9
+                axb = quat_R(q[c, 3:7]) @ fr[6:9]
+                assert abs(axb @ (quat_R(q[a, 3:7]) @ fr[9:12])) < 1e-9
+                assert abs(axb @ (quat_R(q[a, 3:7]) @ fr[12:15])) < 1e-9
+
+
+# --------------------------------------------------------- linear algebra pins
+
+def _iterate(batch, P, w, q, u, ctrl):
+    """A mid-iteration point: the converged state perturbed."""
+    info = oracle.inspect(batch, P, w, q, u, ctrl)
+    rng = np.random.default_rng(11)
+    uu = u[batch.body_off[w]:batch.body_off[w + 1]].reshape(-1) + rng.normal(0, 0.05, 6 * (
+        batch.body_off[w + 1] - batch.body_off[w]))
+    lam = np.abs(rng.normal(1.0, 0.3, info["m"]))
+    return info, uu, lam
+
+
+def test_textbook_jacobian_at_rest():
+    """At omega = 0 the position-level contact row is (n, a x n) and the friction rows (t, a x t)."""
+    b = scenes.pack([scenes.box_world(None, yaw=0.4)])
+    P = scenes.solver_params()
+    q, u = b.q0, b.u0
+    r = oracle.inspect(b, P, 0, q, u, None, np.zeros(6), np.ones(12))
+    R = quat_R(q[0, 3:7])
+    n = np.array([0, 0, 1.0])
+    t1, t2 = np.array([0, 1.0, 0]), np.array([-1.0, 0, 0])
+    for c, s in enumerate(r["act_slot"]):
+        arm = R @ b.slot_real[s, :3]
+        for k, d in enumerate((n, t1, t2)):
+            np.testing.assert_allclose(r["J"][3 * c + k], np.concatenate([d, np.cross(arm, d)]), atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["box", "robot"])
+def test_exact_jacobian_matches_finite_differences(kind):
+    if kind == "box":
+        b = scenes.pack([scenes.box_world(None, v=(0.7, -0.4, 0), w=(0.1, -0.2, 0.9), yaw=0.3)])
+        ctrl = None
+    else:
+        b = scenes.robot_batch(1, seed=4)
+        ctrl = np.array([0.5, -1.0, 1.5, 0.2])
+    P = scenes.solver_params()
+    q, u = b.q0, b.u0
+    info, uu, lam = _iterate(b, P, 0, q, u, ctrl)
+    m, nu = info["m"], info["nu"]
+    r = oracle.inspect(b, P, 0, q, u, ctrl, uu, lam)
+    D = r["D"]
+    Mi = np.linalg.inv(mass_matrix(b, 0, q))
+    Abar = r["J"] @ Mi @ r["J"].T
+    H = r["H"].copy()
+    H[nu:, nu:] -= P["h"] * P["delta_reg"] * np.diag(np.diag(Abar))
+    x0 = np.concatenate([uu, lam])
+    Hfd = np.zeros_like(H)
+    for j in range(nu + m):
+        e = np.zeros(nu + m)
+        d = 1e-6 * max(1.0, abs(x0[j]))
+        e[j] = d
+        Fp = oracle.inspect(b, P, 0, q, u, ctrl, (x0 + e)[:nu], (x0 + e)[nu:])["F"]
+        Fm = oracle.inspect(b, P, 0, q, u, ctrl, (x0 - e)[:nu], (x0 - e)[nu:])["F"]
+        Hfd[:, j] = D * (Fp - Fm) / (2 * d)
+    scale = np.maximum(1.0, np.abs(H))
+    assert np.max(np.abs(H - Hfd) / scale) < 2e-5
+
+
+def test_schur_elimination_matches_full_newton_system():
+    """Eqs. (12)-(13): the Schur route equals the direct solve of the full Newton system."""
+    b = scenes.robot_batch(1, seed=6)
+    ctrl = np.array([1.0, 0.5, -0.3, 0.8])
+    P = scenes.solver_params()
+    q, u = b.q0, b.u0
+    info, uu, lam = _iterate(b, P, 0, q, u, ctrl)
+    m, nu = info["m"], info["nu"]
+    r = oracle.inspect(b, P, 0, q, u, ctrl, uu, lam)
+    h = P["h"]
+    M = mass_matrix(b, 0, q)
+    J, Gu, Gl, D, F = r["J"], r["Gu"], r["Gl"], r["D"], r["F"]
+    Abar = J @ np.linalg.inv(M) @ J.T
+    K = np.block([[M, -h * J.T], [Gu, Gl + h * P["delta_reg"] * np.diag(np.diag(Abar))]])
+    dx = np.linalg.solve(K, -np.concatenate([F[:nu], D[nu:] * F[nu:]]))
+    dl = np.linalg.solve(r["A"], r["rhs"])
+    du = np.linalg.solve(M, h * J.T @ dl - F[:nu])
+    np.testing.assert_allclose(dl, dx[nu:], rtol=1e-8, atol=1e-9 * np.abs(dx[nu:]).max())
+    np.testing.assert_allclose(du, dx[:nu], rtol=1e-8, atol=1e-9 * np.abs(dx[:nu]).max())
+
+
+def test_spline_basis_matches_scipy():
+    from scipy.interpolate import CubicSpline
+    T, K, h = 100, 8, 0.1
+    B = oracle.spline_basis(T, K, h)
+    tk = np.arange(K) * T * h / (K - 1)
+    ts = np.arange(T) * h
+    for j in range(K):
+        y = np.zeros(K)
+        y[j] = 1
+        np.testing.assert_allclose(B[:, j], CubicSpline(tk, y, bc_type="natural")(ts), atol=1e-12)
+
+
+# ------------------------------------------------------------ gradients vs FD
+
+def _fd_check(b, P, T, which, knots=None, steps=None):
+    """Central differences of the rollout loss; ``steps`` selects the checked inputs."""
+    base = oracle.rollout(b, P, b.q0, b.u0, knots, T)
+    assert np.all(base["status"] & 1), base["status"]
+    if which == "u0":
+        x0, g = b.u0.copy(), base["g_u0"]
+    else:
+        x0, g = knots.copy(), base["g_knots"]
+    fd = np.zeros_like(x0)
+    flat = x0.reshape(-1)
+    idx = range(flat.size) if steps is None else steps
+    for i in idx:
+        d = 1e-6 * max(1.0, abs(flat[i]))
+        xp, xm = flat.copy(), flat.copy()
+        xp[i] += d
+        xm[i] -= d
+        if which == "u0":
+            lp = oracle.rollout(b, P, b.q0, xp.reshape(x0.shape), knots, T, grad=False)["loss"].sum()
+            lm = oracle.rollout(b, P, b.q0, xm.reshape(x0.shape), knots, T, grad=False)["loss"].sum()
+        else:
+            lp = oracle.rollout(b, P, b.q0, b.u0, xp.reshape(x0.shape), T, grad=False)["loss"].sum()
+            lm = oracle.rollout(b, P, b.q0, b.u0, xm.reshape(x0.shape), T, grad=False)["loss"].sum()
+        fd.reshape(-1)[i] = (lp - lm) / (2 * d)
+    g = g.reshape(-1)[list(idx)]
+    fdv = fd.reshape(-1)[list(idx)]
+    assert np.linalg.norm(fdv - g) <= 1e-5 * np.linalg.norm(g), (fdv, g)
+
+
+def tripod_world(v, w, yaw, target):
+    """A 0.5 x 0.3 x 0.2 m, 1 kg box on three bottom points (a determinate contact set)."""
+    sx, sy, sz = scenes.BOX_SIZE
+    wd = scenes.World(contact_cap=3)
+    wd.add_body(1.0, scenes.box_inertia(1.0, sx, sy, sz), (0, 0, sz / 2) + scenes.yaw_quat(yaw), tuple(v) + tuple(w))
+    for p in ((sx / 2, sy / 2, -sz / 2), (sx / 2, -sy / 2, -sz / 2), (-sx / 2, 0, -sz / 2)):
+        wd.add_slot(scenes.SLOT_PLANE, 0, local=p, mu=0.8)
+    wd.target = target
+    return wd
+
+
+def test_box_gradient_matches_finite_differences():
+    """Exact IFT adjoint (Eqs. (14)-(17)) against central differences on a sliding, spinning
+    body whose contact forces are determinate (three points).  Every velocity input is checked."""
+    b = scenes.pack([tripod_world((0.9, 0.4, 0), (0.05, -0.05, 1.2), 0.2, (0.3, -0.2))])
+    P = scenes.solver_params(k_max=64, tol=1e-12)
+    _fd_check(b, P, 3, "u0")
+
+
+def test_four_corner_box_in_plane_gradient():
+    """Four coplanar corners leave the normal-force split statically indeterminate: the
+    converged state depends on the regularised Newton path at the 1e-4 level, so the
+    in-plane gradient agrees with central differences to 1e-4 (roll and pitch sit on a
+    complementarity kink and are not differentiable)."""
+    b = scenes.pack([scenes.box_world(None, v=(0.9, 0.4, 0), w=(0, 0, 1.2), yaw=0.2, target=(0.3, -0.2))])
+    P = scenes.solver_params(k_max=64, tol=1e-12)
+    base = oracle.rollout(b, P, b.q0, b.u0, None, 3)
+    g = base["g_u0"][0, [0, 1, 5]]
+    fd = []
+    for i in (0, 1, 5):
+        up, um = b.u0.copy(), b.u0.copy()
+        up[0, i] += 1e-6
+        um[0, i] -= 1e-6
+        fd.append((oracle.rollout(b, P, b.q0, up, None, 3, grad=False)["loss"][0]
+                   - oracle.rollout(b, P, b.q0, um, None, 3, grad=False)["loss"][0]) / 2e-6)
+    assert np.linalg.norm(np.array(fd) - g) <= 1e-4 * np.linalg.norm(g)
+
+
+def test_robot_gradient_matches_finite_differences():
+    b = scenes.robot_batch(1, seed=1)
+    P = scenes.solver_params(k_max=64, tol=1e-12)
+    knots = scenes.knots_array(b, scenes.ROBOT_KNOTS)
+    _fd_check(b, P, 3, "knots", knots=knots, steps=[0, 1, 9, 17, 26, 31])
+
+
+# ------------------------------------------------------------- solver reading
+
+def test_frozen_weight_newton_stalls_where_generalized_newton_converges():
+    """The literal frozen-W iteration loses the normal/friction coupling and stalls on a
+    multi-contact sliding box; the generalized Jacobian converges (reading of Sec. III-C)."""
+    b = scenes.pack([scenes.box_world(None, v=(1.0, 0.5, 0), w=(0.5, 0, 0), yaw=0.3)])
+    lagged = oracle.step_forward(b, scenes.solver_params(k_max=40, newton_mode=1, ls_max=0),
+                                 b.q0, b.u0, np.zeros(b.n_lam), None)
+    exact = oracle.step_forward(b, scenes.solver_params(k_max=40), b.q0, b.u0, np.zeros(b.n_lam), None)
+    assert exact["status"][0] & 1
+    assert not lagged["status"][0] & 1
