@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark: forward + adjoint world-steps/s of the batched backward-Euler
+contact step (Ostrich) on one MI355X.
+
+Workload (one benchmark "step"): 8,192 wheeled-robot worlds (5 bodies, 4
+revolute wheel joints with spline-driven torques, ground plane and a
+1.2 x 0.8 x 0.15 m box obstacle), a T = 100 rollout at h = 0.1 s with the
+final-position loss, then its implicit adjoint with checkpoints every 10 steps
+(segments recomputed).  That is 819,200 forward world-steps and as many adjoint
+world-steps per benchmark step.  Inputs are seeded and synthetic and are
+resident in HBM before the timed region.
+
+Prints ONE JSON line (rank 0).  Extra fields: a roofline entry for the
+dominant kernel (the fused forward step), measured with HIP events on the
+launch stream, and the CPU oracle timed on a bounded sample of the same
+workload.
+"""
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_flops(m, iters, ls_evals=1.0):
+    """FP64 flops of one world-step of the fused forward kernel:
+    per Newton iteration the Schur assembly (24 m^2), the LU factor (2 m^3 / 3),
+    two triangular solves (2 m^2) and the residual evaluations (~400 m per
+    evaluation, 1 + ls_evals per iteration); plus the tape factor at the end."""
+    m = np.asarray(m, dtype=np.float64)
+    it = np.asarray(iters, dtype=np.float64)
+    per_it = 24 * m * m + 2.0 * m ** 3 / 3 + 2 * m * m + 400 * m * (1 + ls_evals)
+    tape = 24 * m * m + 2.0 * m ** 3 / 3
+    return float(np.sum(it * per_it + tape + 400 * m))
+
+
+def _oracle_worker(args):
+    seed, n, T = args
+    import oracle
+    import scenes
+    b = scenes.robot_batch(n, seed=seed)
+    P = scenes.solver_params()
+    knots = scenes.knots_array(b, scenes.ROBOT_KNOTS)
+    t0 = time.perf_counter()
+    oracle.rollout(b, P, b.q0, b.u0, knots, T, grad=True)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(T=20, worlds_per_core=4):
+    cores = max(1, min(16, os.cpu_count() or 1))
+    jobs = [(1000 + i, worlds_per_core, T) for i in range(cores)]
+    t0 = time.perf_counter()
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    ws = cores * worlds_per_core * T
+    return {"value": ws / wall, "unit": "fwd+adj world-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores * worlds_per_core} robot worlds x T={T} (forward + exact adjoint), "
+                      f"one process per core, {wall:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--worlds", type=int, default=8192)
+    ap.add_argument("--T", type=int, default=100)
+    ap.add_argument("--ckpt", type=int, default=10)
+    ap.add_argument("--team", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU kernel "
+              "(worlds are independent; multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import scenes
+    from paper_2609_08800_amd import Simulator, spline_basis
+
+    dev = torch.device("cuda:0")
+    P = scenes.solver_params()
+    W, T = args.worlds, args.T
+    batch = scenes.robot_batch(W, seed=0)
+    K = scenes.ROBOT_KNOTS
+    knots = torch.as_tensor(scenes.knots_array(batch, K), device=dev)
+    basis = torch.as_tensor(spline_basis(T, K, P["h"]), device=dev)
+    sim = Simulator(batch, P, device=dev, team=args.team)
+    q0 = torch.as_tensor(batch.q0, device=dev)
+    u0 = torch.as_tensor(batch.u0, device=dev)
+    lb = batch.loss_body
+    tg = torch.as_tensor(batch.target, device=dev)
+    ws = sim.new_workspace(T, args.ckpt)
+    torch.cuda.synchronize()
+
+    def one_step():
+        return sim.rollout(q0, u0, knots, basis, T, ckpt_every=args.ckpt, loss_body=lb, target=tg,
+                           phase=3, workspace=ws)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats(dev)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = one_step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt / args.steps * 1e3
+    world_steps = W * T * args.steps
+    value = world_steps / dt
+    status = out["status"].cpu().numpy()
+    peak_gb = (torch.cuda.max_memory_allocated(dev)) / 1e9
+
+    # Dominant kernel: the fused forward step.  Per-launch durations with HIP
+    # events on the launch stream over a forward pass of the same rollout.
+    stream = torch.cuda.current_stream(dev)
+    q, u = q0.clone(), u0.clone()
+    lam = torch.zeros(max(sim.NL, 1), dtype=torch.float64, device=dev)
+    ctrl_all = basis @ knots.t()
+    fwd_ms, flops, iters_all, m_all = [], 0.0, [], []
+    base_rows = np.array([5 * (batch.joint_off[w + 1] - batch.joint_off[w]) + batch.worlds[w].n_servo
+                          for w in range(W)])
+    for k in range(T):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        o = sim.step_forward(q, u, lam, ctrl_all[k])
+        e1.record(stream)
+        e1.synchronize()
+        fwd_ms.append(e0.elapsed_time(e1))
+        it = o["iters"].cpu().numpy()
+        m = base_rows + 3 * o["n_act"].cpu().numpy()
+        flops += algorithmic_flops(m, it)
+        iters_all.append(it)
+        m_all.append(m)
+        q, u, lam = o["q"], o["u"], o["lam"]
+    avg_ms = float(np.mean(fwd_ms))
+    achieved = flops / T / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
+                "kernel": "k_forward", "avg_launch_ms": round(avg_ms, 4),
+                "flop_per_launch": flops / T}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline()
+    iters_all = np.array(iters_all)
+    line = {
+        "metric": "fwd+adjoint world-steps/s at 8192 worlds (FP64)",
+        "value": round(value, 2),
+        "unit": "world-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "robot_over_box_obstacle", "worlds": W, "T": T, "h": P["h"],
+                   "ckpt_every": args.ckpt, "newton_k_max": P["k_max"], "tol": P["tol"],
+                   "parallelism": "one workgroup per world"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": {"peak_hbm_gb": round(peak_gb, 3),
+                  "forward_only_world_steps_per_s": round(W / (avg_ms * 1e-3), 1),
+                  "mean_newton_iters": round(float(iters_all.mean()), 3),
+                  "frac_converged": round(float(np.mean(status & 1)), 4),
+                  "mean_rows": round(float(np.mean(m_all)), 2)},
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

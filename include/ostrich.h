@@ -1,0 +1,167 @@
+/*
+ * ostrich.h -- C ABI of the MI355X (gfx950) implementation of the batched
+ * backward-Euler contact step with implicit differentiation (Ostrich:
+ * Kucera & Zimmermann, "Taking Large Strides Through Stiff Contact in
+ * Differentiable Dynamics").
+ *
+ * The method (Sec. III of the paper):
+ *   - Eqs. (1)-(2): backward Euler in maximal coordinates, q+ = q- + h G(q-) u+,
+ *     M~ (u+ - u-) = h (f_ext + J(q+)^T lambda+), J implicit at q+, G at q-;
+ *   - Eqs. (3)-(8): joints, Fischer-Burmeister normal contact, compliance-form
+ *     Coulomb friction with the weight W >= 0 and the cone clamp, implicit
+ *     servo rows;
+ *   - Eqs. (9)-(13): the stacked residual solved by non-smooth Newton on the
+ *     Schur system, with best-iterate selection over a fixed budget (Sec. III-C);
+ *   - Eqs. (14)-(19): the implicit-function adjoint that reuses the forward
+ *     Schur factor (Sec. III-D).
+ *
+ * Conventions.  All arrays are world-major and packed as the scene generators
+ * describe them: per body q = (x, y, z, qx, qy, qz, qw) (unit quaternion, x y z
+ * w order) and u = (v, w) (centre-of-mass velocity and angular velocity, both
+ * in the world frame); lambda is stored per world as [5 per revolute joint]
+ * [1 per servo row][3 per contact slot (normal, t1, t2)], slot-ordered, so a
+ * warm start matches contacts by slot.  All numbers are FP64, indices int32.
+ *
+ * Ownership.  Every array pointer passed to ostrich_step_* and
+ * ostrich_rollout is a DEVICE pointer owned by the caller; the library never
+ * allocates on these paths.  ostrich_ctx_create copies the batch descriptor
+ * (pointers only, the arrays stay the caller's and must outlive the context)
+ * and reads a few offsets to the host once to size its launches.  Every call
+ * is asynchronous on the given HIP stream.
+ *
+ * Errors.  Calls return 0 on success or a negative OSTRICH_E_* code; the
+ * calling thread's last message is available from ostrich_last_error().
+ * Per-world solver outcomes are status bits (OSTRICH_ST_*), not errors: a step
+ * that does not reach the tolerance returns its best iterate and sets
+ * OSTRICH_ST_BUDGET (Sec. III-C).
+ */
+#ifndef OSTRICH_H
+#define OSTRICH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OSTRICH_E_ARG (-1)         /* malformed argument (checked on the host) */
+#define OSTRICH_E_HIP (-2)         /* a HIP runtime call failed */
+#define OSTRICH_E_WORKSPACE (-3)   /* workspace smaller than required */
+#define OSTRICH_E_UNSUPPORTED (-4) /* world too large for the on-chip solver */
+
+#define OSTRICH_ST_CONVERGED 1     /* residual norm <= tol */
+#define OSTRICH_ST_BUDGET 2        /* budget exhausted: best iterate returned */
+#define OSTRICH_ST_NONFINITE 4     /* non-finite residual or factor */
+#define OSTRICH_ST_REGULARIZED 8   /* Schur regularisation had to be raised */
+#define OSTRICH_ST_OVERFLOW 16     /* more active contacts than contact_cap */
+
+/* Packed batch of worlds (device pointers).  Offsets have n_worlds+1 entries. */
+typedef struct {
+  int32_t n_worlds;
+  const int32_t* body_off;     /* bodies of world w: [body_off[w], body_off[w+1]) */
+  const double* body_mass;     /* [NB] */
+  const double* body_inertia;  /* [NB*3] principal moments in the body frame */
+  const int32_t* joint_off;
+  const int32_t* joint_body;   /* [NJ*2] world-local body indices (parent a, child b) */
+  const double* joint_frame;   /* [NJ*18] anchor_a, anchor_b, axis_b, perp1_a, perp2_a, axis_a (body frames) */
+  const int32_t* joint_act;    /* [NJ] 0 none, 1 torque, 2 velocity servo, 3 torque + zero-speed servo */
+  const double* joint_kp;      /* [NJ] servo gain k_p (compliance 1/k_p, Eq. (8)) */
+  const int32_t* ctrl_off;     /* controls: one per actuated joint, in joint order */
+  const int32_t* slot_off;     /* contact candidate slots */
+  const int32_t* slot_int;     /* [NS*4] kind (0 plane, 1 static box, 2 face of body b), body a, body b, obstacle */
+  const double* slot_real;     /* [NS*6] proxy offset in body a (3), proxy radius, mu, face half-height */
+  const int32_t* obs_off;
+  const double* obs_box;       /* [NO*6] centre (3), half extents (3): axis-aligned static boxes */
+  const int32_t* lam_off;      /* multiplier layout described above */
+  const int32_t* contact_cap;  /* [W] maximum active contacts of the world */
+  const int32_t* world_hmap;   /* [W] heightmap index or -1 */
+  int32_t hmap_n;
+  double hmap_spacing;
+  const double* hmap_origin;
+  const double* hmap_heights;
+} ostrich_batch;
+
+/* Solver parameters (host struct, copied at context creation). */
+typedef struct {
+  double h;            /* time step (s) */
+  double gravity[3];
+  double tol;          /* Newton tolerance on the residual norm */
+  int32_t k_max;       /* Newton budget */
+  int32_t k_min;       /* best-iterate floor (Sec. III-C) */
+  double eps;          /* smoothing of the FB function and of norms */
+  double delta_g;      /* guard of denominators */
+  double delta_reg;    /* relative Schur diagonal regularisation */
+  double delta0;       /* contact activation margin (m) */
+  int32_t ls_max;      /* step-length halvings of the residual-decrease test */
+  int32_t refine;      /* adjoint refinement sweeps toward the exact Jacobian (0: factor only) */
+  int32_t team;        /* threads per world (64, 128 or 256; 0 = default) */
+} ostrich_params;
+
+typedef struct ostrich_ctx ostrich_ctx;
+
+/* Last error message of the calling thread (never NULL). */
+const char* ostrich_last_error(void);
+
+/* Create a context for a packed batch.  Reads body/joint/slot offsets,
+ * joint_act and contact_cap to the host once to size the launches.  Fails
+ * with OSTRICH_E_UNSUPPORTED if one world needs more on-chip memory than a
+ * workgroup has. */
+int ostrich_ctx_create(const ostrich_batch* batch, const ostrich_params* params, ostrich_ctx** out);
+int ostrich_ctx_destroy(ostrich_ctx* ctx);
+
+/* Sizes the caller allocates: the per-step tape of all worlds (bytes), and
+ * the rollout workspace for horizon T and checkpoint interval k (0: keep every
+ * state and tape; k >= 1: keep every k-th state and recompute segments). */
+size_t ostrich_tape_bytes(const ostrich_ctx* ctx);
+size_t ostrich_rollout_workspace_bytes(const ostrich_ctx* ctx, int32_t T, int32_t ckpt_every);
+
+/* Capacities used for the launches: bodies, joints, slots, contacts, rows
+ * per world, and the LDS bytes of one world.  out[6]. */
+int ostrich_ctx_caps(const ostrich_ctx* ctx, int64_t* out);
+
+/* One backward-Euler step of every world (Sec. III-A..C, A1-A8 of the hot
+ * path): contact refresh at q-, fused Newton loop, best iterate, q+.
+ *   q_prev [NB*7], u_prev [NB*6], lam_prev [NL]: state s-;  ctrl [NCTRL]
+ *   q_next, u_next, lam_next: state s+ (written)
+ *   act_slot [NS]: per world the active slot ids in ascending order, -1 padded
+ *   n_act, status, iters [W] int32;  resnorm [W] residual norm of s+
+ *   tape: NULL or ostrich_tape_bytes() bytes; receives the Schur factor at s+. */
+int ostrich_step_forward(ostrich_ctx* ctx, const double* q_prev, const double* u_prev, const double* lam_prev,
+                         const double* ctrl, double* q_next, double* u_next, double* lam_next, int32_t* act_slot,
+                         int32_t* n_act, int32_t* status, int32_t* iters, double* resnorm, void* tape,
+                         void* stream);
+
+/* Adjoint of one step (Sec. III-D, Eqs. (16)-(19)): given s-, the controls,
+ * s+ (u_next, lam_next) and the tape written by the forward call, map the
+ * loss cotangents (gq_next [NB*7], gu_next [NB*6]) to gq_prev, gu_prev and
+ * g_ctrl [NCTRL].  The stored factor is back-solved, then `refine` sweeps add
+ * the geometric-stiffness term of the exact Jacobian (params.refine if < 0). */
+int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, const double* u_prev, const double* ctrl,
+                         const double* u_next, const double* lam_next, const void* tape, const double* gq_next,
+                         const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl, int32_t refine,
+                         void* stream);
+
+#define OSTRICH_FORWARD 1
+#define OSTRICH_BACKWARD 2
+
+/* T-step rollout with controls from a spline basis (ctrl_k = basis[k,:] .
+ * knots[c,:], basis [T*K] device, knots [NCTRL*K]) and the loss
+ * |xy(loss_body) - target|^2 at step T (loss_body [W] int32, target [W*2]).
+ * FORWARD writes loss [W], qT, uT and checkpoints into the workspace;
+ * BACKWARD (after a FORWARD with the same arguments and workspace) recomputes
+ * each segment from its checkpoint and runs the adjoint steps in reverse,
+ * writing g_q0, g_u0, g_knots.  status_or [W] ORs the step status bits. */
+int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0, const double* u0, const double* knots,
+                    int32_t K, const double* basis, int32_t T, int32_t ckpt_every, const int32_t* loss_body,
+                    const double* target, double* loss, double* qT, double* uT, double* g_q0, double* g_u0,
+                    double* g_knots, void* workspace, size_t workspace_bytes, int32_t* status_or, void* stream);
+
+/* Natural cubic spline basis on the host: B [T*K] (host), knots at
+ * t_j = j T h / (K - 1), step k samples t = k h. */
+int ostrich_spline_basis(int32_t T, int32_t K, double h, double* B);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,215 @@
+"""MI355X implementation of the batched backward-Euler contact step with
+implicit differentiation (Ostrich, Sec. III).
+
+The compute path is ``libostrich.so`` (HIP, gfx950) behind the C ABI of
+``include/ostrich.h``; this package marshals PyTorch device tensors to it.
+There is no CPU fallback: without the built library every entry point raises.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+
+import numpy as np
+
+from . import _capi
+
+__all__ = ["build", "Simulator", "spline_basis", "OstrichError"]
+
+OstrichError = _capi.OstrichError
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+
+HIP_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libostrich.so for gfx950 in-tree (hipcc)."""
+    out = _capi.SO_PATH
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    src = os.path.join(_HERE, "csrc", "ostrich.hip")
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["hipcc", *HIP_FLAGS, "-I", os.path.join(_ROOT, "include"), "-I", os.path.join(_HERE, "csrc"),
+           "-o", tmp, src]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(tmp, out)
+    return out
+
+
+def spline_basis(T: int, K: int, h: float) -> np.ndarray:
+    """Natural cubic spline basis [T, K] (host): control of step k = B[k] . knots."""
+    L = _capi.load()
+    B = np.zeros((T, K), dtype=np.float64)
+    _capi.check(L.ostrich_spline_basis(T, K, float(h), B.ctypes.data), "ostrich_spline_basis")
+    return B
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Simulator:
+    """A batch of worlds resident on one GPU.
+
+    ``batch`` is any object with the packed arrays of the scene description
+    (see scenes.Batch): offsets and tables as numpy arrays.  All state tensors
+    are float64 on the device; shapes: q [NB, 7], u [NB, 6], lam [NL],
+    ctrl [NCTRL].
+    """
+
+    def __init__(self, batch, params: dict, device="cuda", team: int = 0):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise OstrichError("a ROCm GPU is required (no CPU fallback)")
+        self.lib = _capi.load()
+        self.params = dict(params)
+        self.W = int(batch.n_worlds)
+        self.NB = int(batch.body_off[-1])
+        self.NL = int(batch.lam_off[-1])
+        self.NS = int(batch.slot_off[-1])
+        self.NCTRL = int(batch.ctrl_off[-1])
+        self._dev = {}
+        ptrs = {}
+        for k in _capi.BATCH_ARRAYS:
+            a = np.ascontiguousarray(getattr(batch, k))
+            dt = torch.int32 if a.dtype == np.int32 else torch.float64
+            t = torch.from_numpy(a.astype(np.int32 if a.dtype == np.int32 else np.float64).reshape(-1)).to(
+                self.device, dtype=dt)
+            if t.numel() == 0:
+                t = torch.zeros(1, dtype=dt, device=self.device)
+            self._dev[k] = t
+            ptrs[k] = t.data_ptr()
+        self.body_off = self._dev["body_off"]
+        self._cb = _capi.make_batch(self.W, ptrs, int(batch.hmap_n), float(batch.hmap_spacing))
+        self._cp = _capi.make_params(self.params, team)
+        ctx = _capi.c_vp()
+        torch.cuda.synchronize(self.device)
+        _capi.check(self.lib.ostrich_ctx_create(self._cb, self._cp, ctx), "ostrich_ctx_create")
+        self.ctx = ctx
+        caps = (_capi.ctypes.c_int64 * 6)()
+        _capi.check(self.lib.ostrich_ctx_caps(self.ctx, caps), "ostrich_ctx_caps")
+        self.caps = dict(zip(("bodies", "joints", "slots", "contacts", "rows", "lds_bytes"), list(caps)))
+        self.tape_bytes = int(self.lib.ostrich_tape_bytes(self.ctx))
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                self.lib.ostrich_ctx_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------------- helpers
+    def _stream(self, stream=None):
+        torch = self.torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return s.cuda_stream
+
+    def _f64(self, x, shape=None):
+        torch = self.torch
+        if x is None:
+            return None
+        if not torch.is_tensor(x):
+            x = torch.as_tensor(np.asarray(x, dtype=np.float64), device=self.device)
+        x = x.to(self.device, torch.float64).contiguous()
+        if shape is not None:
+            x = x.reshape(shape)
+        return x
+
+    @staticmethod
+    def _p(t):
+        return None if t is None else t.data_ptr()
+
+    def empty_state(self):
+        torch = self.torch
+        return (torch.empty(self.NB, 7, dtype=torch.float64, device=self.device),
+                torch.empty(self.NB, 6, dtype=torch.float64, device=self.device),
+                torch.empty(max(self.NL, 1), dtype=torch.float64, device=self.device))
+
+    def new_tape(self):
+        return self.torch.empty(self.tape_bytes // 8, dtype=self.torch.float64, device=self.device)
+
+    def _ctrl(self, ctrl):
+        if self.NCTRL == 0:
+            return self.torch.zeros(1, dtype=self.torch.float64, device=self.device)
+        return self._f64(ctrl, (self.NCTRL,))
+
+    # ------------------------------------------------------------------- calls
+    def step_forward(self, q, u, lam, ctrl=None, tape=None, out=None, stream=None):
+        """One backward-Euler step of every world; returns a dict of device tensors."""
+        torch = self.torch
+        q, u, lam = self._f64(q, (self.NB, 7)), self._f64(u, (self.NB, 6)), self._f64(lam)
+        ctrl = self._ctrl(ctrl)
+        if out is None:
+            qn, un, ln = self.empty_state()
+            out = dict(q=qn, u=un, lam=ln,
+                       act_slot=torch.empty(max(self.NS, 1), dtype=torch.int32, device=self.device),
+                       n_act=torch.empty(self.W, dtype=torch.int32, device=self.device),
+                       status=torch.empty(self.W, dtype=torch.int32, device=self.device),
+                       iters=torch.empty(self.W, dtype=torch.int32, device=self.device),
+                       resnorm=torch.empty(self.W, dtype=torch.float64, device=self.device))
+        rc = self.lib.ostrich_step_forward(
+            self.ctx, q.data_ptr(), u.data_ptr(), lam.data_ptr(), ctrl.data_ptr(), out["q"].data_ptr(),
+            out["u"].data_ptr(), out["lam"].data_ptr(), out["act_slot"].data_ptr(), out["n_act"].data_ptr(),
+            out["status"].data_ptr(), out["iters"].data_ptr(), out["resnorm"].data_ptr(), self._p(tape),
+            self._stream(stream))
+        _capi.check(rc, "ostrich_step_forward")
+        return out
+
+    def step_adjoint(self, q, u, ctrl, u_next, lam_next, tape, gq_next, gu_next, refine=-1, stream=None):
+        """Cotangents of (q-, u-, ctrl) from those of (q+, u+)."""
+        torch = self.torch
+        q, u = self._f64(q, (self.NB, 7)), self._f64(u, (self.NB, 6))
+        ctrl = self._ctrl(ctrl)
+        u_next, lam_next = self._f64(u_next, (self.NB, 6)), self._f64(lam_next)
+        gq_next, gu_next = self._f64(gq_next, (self.NB, 7)), self._f64(gu_next, (self.NB, 6))
+        gq = torch.empty_like(q)
+        gu = torch.empty_like(u)
+        gc = torch.zeros(max(self.NCTRL, 1), dtype=torch.float64, device=self.device)
+        rc = self.lib.ostrich_step_adjoint(
+            self.ctx, q.data_ptr(), u.data_ptr(), ctrl.data_ptr(), u_next.data_ptr(), lam_next.data_ptr(),
+            tape.data_ptr(), gq_next.data_ptr(), gu_next.data_ptr(), gq.data_ptr(), gu.data_ptr(), gc.data_ptr(),
+            int(refine), self._stream(stream))
+        _capi.check(rc, "ostrich_step_adjoint")
+        return gq, gu, gc[:self.NCTRL]
+
+    def workspace_bytes(self, T: int, ckpt_every: int) -> int:
+        return int(self.lib.ostrich_rollout_workspace_bytes(self.ctx, int(T), int(ckpt_every)))
+
+    def new_workspace(self, T: int, ckpt_every: int):
+        n = self.workspace_bytes(T, ckpt_every)
+        return self.torch.empty((n + 7) // 8, dtype=self.torch.float64, device=self.device)
+
+    def rollout(self, q0, u0, knots, basis, T, ckpt_every=10, loss_body=None, target=None, phase=3,
+                workspace=None, grads=True, stream=None):
+        """T-step rollout with the final-xy loss; FORWARD (1), BACKWARD (2) or both (3)."""
+        torch = self.torch
+        q0, u0 = self._f64(q0, (self.NB, 7)), self._f64(u0, (self.NB, 6))
+        K = 0
+        if self.NCTRL > 0:
+            knots = self._f64(knots)
+            K = knots.numel() // self.NCTRL
+            knots = knots.reshape(self.NCTRL, K)
+            basis = self._f64(basis, (T, K))
+        lb = torch.as_tensor(np.asarray(loss_body, dtype=np.int32), device=self.device).contiguous()
+        tg = self._f64(target, (self.W, 2))
+        ws = workspace if workspace is not None else self.new_workspace(T, ckpt_every)
+        loss = torch.empty(self.W, dtype=torch.float64, device=self.device)
+        qT, uT, _ = self.empty_state()
+        st = torch.zeros(self.W, dtype=torch.int32, device=self.device)
+        g_q0 = torch.empty_like(q0) if grads else None
+        g_u0 = torch.empty_like(u0) if grads else None
+        g_knots = torch.empty(self.NCTRL, max(K, 1), dtype=torch.float64, device=self.device) if grads else None
+        rc = self.lib.ostrich_rollout(
+            self.ctx, int(phase), q0.data_ptr(), u0.data_ptr(), self._p(knots) if self.NCTRL else None, int(K),
+            self._p(basis) if self.NCTRL else None, int(T), int(ckpt_every), lb.data_ptr(), tg.data_ptr(),
+            loss.data_ptr(), qT.data_ptr(), uT.data_ptr(), self._p(g_q0), self._p(g_u0), self._p(g_knots),
+            ws.data_ptr(), ws.numel() * 8, st.data_ptr(), self._stream(stream))
+        _capi.check(rc, "ostrich_rollout")
+        return dict(loss=loss, qT=qT, uT=uT, g_q0=g_q0, g_u0=g_u0, g_knots=g_knots, status=st, workspace=ws)

@@ -1,0 +1,447 @@
+// Fused per-world forward step (Newton loop with step length and best-iterate
+// selection) and per-world implicit adjoint.
+#pragma once
+
+#include "step.hpp"
+
+namespace ost {
+
+// Tape of one world-step: the LU factor of the Schur matrix at the returned
+// iterate (mr x mr, row stride m), then (regularisation used, m, valid).
+OST_HD size_t tape_doubles(const Caps& c) { return (size_t)c.mr * c.mr + 4; }
+
+// FB argument scales sigma_n = h^2 Abar_nn, sigma_f = h (Abar_t1 + Abar_t2)/2
+// from the Delassus diagonal at the warm start u = u-.
+template <class Team>
+OST_HD void fb_scales(Team& t, const Batch& B, const Params& P, const WorldRef& R, const WorldMem& M,
+                      const double* ctrl) {
+  evaluate(t, B, P, R, M, ctrl, M.um, M.lam, false);
+  const int base = 5 * R.nj + R.nsv;
+  for (int c = t.rank(); c < R.nc; c += t.size()) {
+    double ad[3];
+    for (int k = 0; k < 3; ++k) {
+      int i = base + 3 * c + k;
+      const double* Jr = M.J + 12 * i;
+      double MJ[12], s = 0.0;
+      minv6(M, M.r_a[i], Jr, MJ);
+      for (int q = 0; q < 6; ++q) s += Jr[q] * MJ[q];
+      if (M.r_b[i] >= 0) {
+        minv6(M, M.r_b[i], Jr + 6, MJ + 6);
+        for (int q = 6; q < 12; ++q) s += Jr[q] * MJ[q];
+      }
+      ad[k] = s;
+    }
+    M.c_sn[c] = P.h * P.h * ad[0];
+    M.c_sf[c] = P.h * 0.5 * (ad[1] + ad[2]);
+  }
+  t.sync();
+}
+
+// One backward-Euler step of world w (Sec. III-A..C).
+template <class Team>
+OST_HD void forward_world(Team& t, const Batch& B, const Params& P, const Caps& caps, int w, const double* q_prev,
+                          const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
+                          double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
+                          int32_t* iters_out, double* resnorm, double* tape, WorldMem& M) {
+  WorldRef R = world_ref(B, w);
+  prologue(t, B, P, R, q_prev, u_prev, ctrl, lam_prev, M);
+  clamp_all(t, P, R, M, M.lam);
+  fb_scales(t, B, P, R, M, ctrl);
+  const int nb = R.nb, m = R.m;
+  int st = M.iscal[1] ? ST_OVERFLOW : 0;
+  double nrm = evaluate(t, B, P, R, M, ctrl, M.u, M.lam, true);
+  for (int i = t.rank(); i < 6 * nb; i += t.size()) M.ubest[i] = M.u[i];
+  for (int i = t.rank(); i < m; i += t.size()) M.lambest[i] = M.lam[i];
+  double bn = nrm;
+  bool have = P.kmin == 0, conv = false;
+  int iters = 0;
+  if (!isfinite(nrm)) {
+    st |= ST_NONFINITE | ST_BUDGET;
+  } else if (nrm <= P.tol) {
+    conv = true;
+  } else {
+    for (int k = 1; k <= P.kmax; ++k) {
+      double dreg;
+      if (!factor(t, P, R, M, true, &dreg, &st)) { st |= ST_NONFINITE; break; }
+      for (int i = t.rank(); i < m; i += t.size()) M.dlam[i] = M.rhs[i];
+      t.sync();
+      lu_solve(t, R, M, M.dlam, false);
+      // Eq. (13): du = M~^-1 (h J^T dlambda - r_dyn)
+      for (int b = t.rank(); b < nb; b += t.size()) {
+        double tv[6];
+        for (int q = 0; q < 6; ++q) tv[q] = -M.rdyn[6 * b + q];
+        for (int i = 0; i < m; ++i) {
+          if (M.r_a[i] == b) for (int q = 0; q < 6; ++q) tv[q] += P.h * M.J[12 * i + q] * M.dlam[i];
+          if (M.r_b[i] == b) for (int q = 0; q < 6; ++q) tv[q] += P.h * M.J[12 * i + 6 + q] * M.dlam[i];
+        }
+        minv6(M, b, tv, M.du + 6 * b);
+      }
+      t.sync();
+      // step length: halve until the residual decreases by (1 - 1e-4 alpha), else the best trial
+      double alpha = 1.0, best_a = 1.0, best_n = INFINITY;
+      for (int ls = 0; ls <= P.ls_max; ++ls) {
+        for (int i = t.rank(); i < 6 * nb; i += t.size()) M.ut[i] = M.u[i] + alpha * M.du[i];
+        for (int i = t.rank(); i < m; i += t.size()) M.lamt[i] = M.lam[i] + alpha * M.dlam[i];
+        t.sync();
+        clamp_all(t, P, R, M, M.lamt);
+        double tn = evaluate(t, B, P, R, M, ctrl, M.ut, M.lamt, false);
+        bool ok = tn <= (1.0 - 1e-4 * alpha) * nrm;
+        if (tn < best_n || ok) { best_n = tn; best_a = alpha; }
+        if (ok) break;
+        alpha *= 0.5;
+      }
+      for (int i = t.rank(); i < 6 * nb; i += t.size()) M.u[i] = M.u[i] + best_a * M.du[i];
+      for (int i = t.rank(); i < m; i += t.size()) M.lam[i] = M.lam[i] + best_a * M.dlam[i];
+      t.sync();
+      clamp_all(t, P, R, M, M.lam);
+      nrm = evaluate(t, B, P, R, M, ctrl, M.u, M.lam, true);
+      iters = k;
+      if (!isfinite(nrm)) { st |= ST_NONFINITE; break; }
+      bool take = nrm <= P.tol || (k >= P.kmin && (!have || nrm < bn));
+      if (take) {
+        for (int i = t.rank(); i < 6 * nb; i += t.size()) M.ubest[i] = M.u[i];
+        for (int i = t.rank(); i < m; i += t.size()) M.lambest[i] = M.lam[i];
+        bn = nrm;
+        have = true;
+        t.sync();
+      }
+      if (nrm <= P.tol) { conv = true; break; }
+    }
+  }
+  st |= conv ? ST_CONVERGED : ST_BUDGET;
+  // the tape holds the factor of the Schur matrix at the returned iterate
+  if (tape) {
+    for (int i = t.rank(); i < 6 * nb; i += t.size()) M.u[i] = M.ubest[i];
+    for (int i = t.rank(); i < m; i += t.size()) M.lam[i] = M.lambest[i];
+    t.sync();
+    evaluate(t, B, P, R, M, ctrl, M.u, M.lam, true);
+    double dreg = P.dreg;
+    int fst = 0;
+    bool ok = factor(t, P, R, M, false, &dreg, &fst);
+    double* tw = tape + (size_t)w * tape_doubles(caps);
+    for (int e = t.rank(); e < m * m; e += t.size()) tw[e] = M.A[e];
+    if (t.rank() == 0) {
+      size_t o = (size_t)caps.mr * caps.mr;
+      tw[o] = dreg;
+      tw[o + 1] = m;
+      tw[o + 2] = ok ? 1.0 : 0.0;
+      tw[o + 3] = 0.0;
+    }
+  }
+  // q+ = q- + h G(q-) u* with the quaternion renormalised (Eq. (1))
+  for (int b = t.rank(); b < nb; b += t.size()) {
+    const double* q = M.qm + 7 * b;
+    const double* u = M.ubest + 6 * b;
+    double* qo = q_next + 7 * (R.b0 + b);
+    for (int k = 0; k < 3; ++k) qo[k] = q[k] + P.h * u[k];
+    v3<double> wv{u[3], u[4], u[5]}, qv{q[3], q[4], q[5]};
+    v3<double> dv = wv * q[6] + cross(wv, qv);
+    double dw = -dot(wv, qv);
+    double r4[4] = {q[3] + 0.5 * P.h * dv.x, q[4] + 0.5 * P.h * dv.y, q[5] + 0.5 * P.h * dv.z, q[6] + 0.5 * P.h * dw};
+    double n = ::sqrt(r4[0] * r4[0] + r4[1] * r4[1] + r4[2] * r4[2] + r4[3] * r4[3]);
+    for (int k = 0; k < 4; ++k) qo[3 + k] = r4[k] / n;
+    for (int k = 0; k < 6; ++k) u_next[6 * (R.b0 + b) + k] = u[k];
+  }
+  const int lam_len = B.lam_off[w + 1] - R.l0;
+  for (int i = t.rank(); i < lam_len; i += t.size()) lam_next[R.l0 + i] = 0.0;
+  if (act_slot)
+    for (int s = t.rank(); s < R.ns; s += t.size()) act_slot[R.s0 + s] = -1;
+  t.sync();
+  const int base = 5 * R.nj + R.nsv;
+  for (int i = t.rank(); i < m; i += t.size()) {
+    int ls = i < base ? i : base + 3 * M.c_slot[(i - base) / 3] + (i - base) % 3;
+    lam_next[R.l0 + ls] = M.lambest[i];
+  }
+  if (act_slot)
+    for (int c = t.rank(); c < R.nc; c += t.size()) act_slot[R.s0 + c] = M.c_slot[c];
+  if (t.rank() == 0) {
+    if (n_act) n_act[w] = R.nc;
+    if (status) status[w] = st;
+    if (iters_out) iters_out[w] = iters;
+    if (resnorm) resnorm[w] = bn;
+  }
+  t.sync();
+}
+
+// --------------------------------------------------------------------------
+// Adjoint.
+// --------------------------------------------------------------------------
+
+// Solve the transposed Newton system [[M~, G_u^T], [-h J, G_lambda^T]] [w_u; w_l]
+// = [-b; 0] with the stored factor: A^T w_l = -J M~^-1 b,
+// w_u = -(M~^-1 b + (G_u M~^-1)^T w_l)   (Eqs. (18)-(19)).
+template <class Team>
+OST_HD void adjoint_solve(Team& t, const WorldRef& R, const WorldMem& M, const double* b, double* wu, double* wl) {
+  const int nb = R.nb, m = R.m;
+  for (int q = t.rank(); q < nb; q += t.size()) minv6(M, q, b + 6 * q, M.kg + 6 * q);  // M~^-1 b
+  t.sync();
+  for (int i = t.rank(); i < m; i += t.size()) {
+    const double* Jr = M.J + 12 * i;
+    int a = M.r_a[i], c = M.r_b[i];
+    double s = 0.0;
+    for (int k = 0; k < 6; ++k) s += Jr[k] * M.kg[6 * a + k];
+    if (c >= 0) for (int k = 0; k < 6; ++k) s += Jr[6 + k] * M.kg[6 * c + k];
+    wl[i] = -s;
+  }
+  t.sync();
+  lu_solve(t, R, M, wl, true);
+  for (int q = t.rank(); q < nb; q += t.size()) {
+    double s[6];
+    for (int k = 0; k < 6; ++k) s[k] = M.kg[6 * q + k];
+    for (int i = 0; i < m; ++i) {
+      if (M.r_a[i] == q) for (int k = 0; k < 6; ++k) s[k] += M.Y[12 * i + k] * wl[i];
+      if (M.r_b[i] == q) for (int k = 0; k < 6; ++k) s[k] += M.Y[12 * i + 6 + k] * wl[i];
+    }
+    for (int k = 0; k < 6; ++k) wu[6 * q + k] = -s[k];
+  }
+  t.sync();
+}
+
+// Dual input of a group with body data recomputed from q- (seeded), used by
+// the pose pull-back.  seed_body / seed_comp select the seeded q- component.
+OST_HD void dual_pose(const double* q, int seeded, int comp, v3<dual>& x, m3<dual>& Rm) {
+  dual c[7];
+  for (int k = 0; k < 7; ++k) c[k] = dual(q[k], seeded && comp == k ? 1.0 : 0.0);
+  x = v3<dual>{c[0], c[1], c[2]};
+  Rm = quat_to_R(c[3], c[4], c[5], c[6]);
+}
+
+// Implicit adjoint of one world-step (Sec. III-D): loss cotangents on s+ to
+// cotangents on q-, u- and the controls, through the exact implicit-function
+// Jacobian reached by `refine` sweeps on the stored factor.
+template <class Team>
+OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& caps, int w, const double* q_prev,
+                          const double* u_prev, const double* ctrl, const double* u_next, const double* lam_next,
+                          const double* tape, const double* gq_next, const double* gu_next, double* gq_prev,
+                          double* gu_prev, double* g_ctrl, int refine, WorldMem& M) {
+  WorldRef R = world_ref(B, w);
+  const double h = P.h;
+  prologue(t, B, P, R, q_prev, u_prev, ctrl, lam_next, M);
+  fb_scales(t, B, P, R, M, ctrl);
+  const int nb = R.nb, m = R.m;
+  for (int i = t.rank(); i < 6 * nb; i += t.size()) M.u[i] = u_next[6 * R.b0 + i];
+  t.sync();
+  evaluate(t, B, P, R, M, ctrl, M.u, M.lam, true);
+  const double* tw = tape + (size_t)w * tape_doubles(caps);
+  if (tw[(size_t)caps.mr * caps.mr + 2] == 1.0 && (int)tw[(size_t)caps.mr * caps.mr + 1] == m) {
+    for (int e = t.rank(); e < m * m; e += t.size()) M.A[e] = tw[e];
+    t.sync();
+  } else {  // no usable stored factor: factor here
+    double dreg;
+    int fst = 0;
+    factor(t, P, R, M, false, &dreg, &fst);
+  }
+  // loss cotangent on the raw q+ (through the renormalisation) and the total
+  // velocity cotangent b = g_u + h G(q-)^T g_q
+  for (int b = t.rank(); b < nb; b += t.size()) {
+    const double* q = M.qm + 7 * b;
+    const double* u = M.u + 6 * b;
+    const double* g = gq_next + 7 * (R.b0 + b);
+    v3<double> wv{u[3], u[4], u[5]}, qv{q[3], q[4], q[5]};
+    v3<double> dv = wv * q[6] + cross(wv, qv);
+    double dw = -dot(wv, qv);
+    double r4[4] = {q[3] + 0.5 * h * dv.x, q[4] + 0.5 * h * dv.y, q[5] + 0.5 * h * dv.z, q[6] + 0.5 * h * dw};
+    double n = ::sqrt(r4[0] * r4[0] + r4[1] * r4[1] + r4[2] * r4[2] + r4[3] * r4[3]);
+    double qh[4] = {r4[0] / n, r4[1] / n, r4[2] / n, r4[3] / n};
+    double dq = qh[0] * g[3] + qh[1] * g[4] + qh[2] * g[5] + qh[3] * g[6];
+    double* gr = M.gq + 7 * b;
+    for (int k = 0; k < 3; ++k) gr[k] = g[k];
+    for (int k = 0; k < 4; ++k) gr[3 + k] = (g[3 + k] - qh[k] * dq) / n;
+    const double* gu = gu_next + 6 * (R.b0 + b);
+    double* bb = M.du + 6 * b;  // b
+    for (int k = 0; k < 3; ++k) bb[k] = gu[k] + h * gr[k];
+    v3<double> gv{gr[3], gr[4], gr[5]};
+    v3<double> t3 = gv * q[6] + cross(qv, gv) - qv * gr[6];
+    bb[3] = gu[3] + 0.5 * h * t3.x;
+    bb[4] = gu[4] + 0.5 * h * t3.y;
+    bb[5] = gu[5] + 0.5 * h * t3.z;
+    for (int k = 0; k < 6; ++k) M.rdyn[6 * b + k] = bb[k];  // keep b
+  }
+  t.sync();
+  double* wu = M.ut;
+  double* wl = M.dlam;
+  adjoint_solve(t, R, M, M.du, wu, wl);
+  // refinement towards the exact Jacobian: the factor omits the geometric
+  // stiffness K = d(J(u)^T lambda)/du; w <- Hhat^-T (-[b; 0] + [h K^T w_u; 0])
+  for (int sweep = 0; sweep < refine; ++sweep) {
+    for (int p = t.rank(); p < 6 * nb; p += t.size()) {
+      int beta = p / 6, comp = p % 6;
+      double s = 0.0;
+      const int ng = n_groups(R);
+      for (int g = 0; g < ng; ++g) {
+        int row = group_row(R, g);
+        int a = M.r_a[row], c = M.r_b[row];
+        if (a != beta && c != beta) continue;
+        int kind = M.r_kind[row];
+        int n = kind == RK_CONTACT ? 3 : 1;
+        double target = kind == RK_SERVO ? servo_target(B, R, ctrl, M.r_idx[row]) : 0.0;
+        GroupIn<double> in = group_in_lds(M, row, M.u, M.lam, target);
+        dual ua[6], ub[6], lg[3];
+        for (int k = 0; k < 6; ++k) {
+          ua[k] = dual(M.u[6 * a + k], (a == beta && k == comp) ? 1.0 : 0.0);
+          ub[k] = c >= 0 ? dual(M.u[6 * c + k], (c == beta && k == comp) ? 1.0 : 0.0) : dual(0.0);
+        }
+        for (int k = 0; k < n; ++k) lg[k] = dual(M.lam[row + k]);
+        GroupIn<dual> ind;
+        ind.xa = v3<dual>{in.xa.x, in.xa.y, in.xa.z};
+        ind.xb = v3<dual>{in.xb.x, in.xb.y, in.xb.z};
+        for (int k = 0; k < 9; ++k) { ind.Ra.a[k] = in.Ra.a[k]; ind.Rb.a[k] = in.Rb.a[k]; }
+        ind.ua = ua;
+        ind.ub = c >= 0 ? ub : nullptr;
+        ind.lg = lg;
+        ind.target = dual(target);
+        ind.fr.n = v3<dual>{in.fr.n.x, in.fr.n.y, in.fr.n.z};
+        ind.fr.t1 = v3<dual>{in.fr.t1.x, in.fr.t1.y, in.fr.t1.z};
+        ind.fr.t2 = v3<dual>{in.fr.t2.x, in.fr.t2.y, in.fr.t2.z};
+        ind.fr.noff = dual(in.fr.noff);
+        ind.fr.la = v3<dual>{in.fr.la.x, in.fr.la.y, in.fr.la.z};
+        ind.fr.lb = v3<dual>{in.fr.lb.x, in.fr.lb.y, in.fr.lb.z};
+        dual rd[3], Jd[36];
+        double Dd[3];
+        eval_row_group<dual>(B, P, R, M, row, ind, rd, Jd, Dd);
+        for (int k = 0; k < n; ++k) {
+          double jw = 0.0;
+          for (int q = 0; q < 6; ++q) jw += Jd[12 * k + q].d * wu[6 * a + q];
+          if (c >= 0) for (int q = 0; q < 6; ++q) jw += Jd[12 * k + 6 + q].d * wu[6 * c + q];
+          s += M.lam[row + k] * jw;
+        }
+      }
+      M.kg[p] = s;
+    }
+    t.sync();
+    for (int p = t.rank(); p < 6 * nb; p += t.size()) M.ubest[p] = M.rdyn[p] - h * M.kg[p];
+    t.sync();
+    adjoint_solve(t, R, M, M.ubest, wu, wl);
+  }
+  // pull-back, Eq. (17): dL/dxi = w^T D dF/dxi, plus the direct kinematic term
+  for (int b = t.rank(); b < nb; b += t.size()) {  // u-: -M~ w_u - h (df_gyro/dw-)^T w_u
+    const double* um = M.um + 6 * b;
+    const double* wb = wu + 6 * b;
+    const double* Iw = M.Iw + 9 * b;
+    double* go = gu_prev + 6 * (R.b0 + b);
+    for (int k = 0; k < 3; ++k) go[k] = -M.mass[b] * wb[k];
+    v3<double> wm{um[3], um[4], um[5]}, ww{wb[3], wb[4], wb[5]};
+    auto Iv = [&](const v3<double>& v) {
+      return v3<double>{Iw[0] * v.x + Iw[1] * v.y + Iw[2] * v.z, Iw[3] * v.x + Iw[4] * v.y + Iw[5] * v.z,
+                        Iw[6] * v.x + Iw[7] * v.y + Iw[8] * v.z};
+    };
+    v3<double> mw = Iv(ww);
+    v3<double> gT = cross(ww, Iv(wm)) + Iv(cross(wm, ww));  // (df/dw)^T w, f = -w x (I w)
+    go[3] = -mw.x - h * gT.x;
+    go[4] = -mw.y - h * gT.y;
+    go[5] = -mw.z - h * gT.z;
+  }
+  if (t.rank() == 0 && g_ctrl) {  // controls: torque and servo target
+    int c = 0, sv = 0;
+    for (int j = 0; j < R.nj; ++j) {
+      int act = B.joint_act[R.j0 + j];
+      int a = B.joint_body[2 * (R.j0 + j)], b = B.joint_body[2 * (R.j0 + j) + 1];
+      double g = 0.0;
+      if (act == 1 || act == 3) {
+        v3<double> ax = mul(ldm(M.Rm + 9 * a), ldv(B.joint_frame + 18 * (R.j0 + j) + 15));
+        for (int k = 0; k < 3; ++k) g += -h * at(ax, k) * (wu[6 * b + 3 + k] - wu[6 * a + 3 + k]);
+      }
+      if (act == 2) g = -wl[5 * R.nj + sv];
+      if (act == 2 || act == 3) ++sv;
+      if (act) g_ctrl[R.c0 + c++] = g;
+    }
+  }
+  // q-: forward duals over the 7 components of every body's pose
+  for (int p = t.rank(); p < 7 * nb; p += t.size()) {
+    int beta = p / 7, comp = p % 7;
+    double s = 0.0;
+    // body terms of every body (inertia at q-, gyroscopic term, actuator axes)
+    for (int b = 0; b < nb; ++b) {
+      v3<dual> xb;
+      m3<dual> Rb;
+      dual_pose(M.qm + 7 * b, b == beta, comp, xb, Rb);
+      v3<dual> tq{dual(0.0), dual(0.0), dual(0.0)};
+      int cc = 0;
+      for (int j = 0; j < R.nj; ++j) {
+        int act = B.joint_act[R.j0 + j];
+        if (!act) continue;
+        int ja = B.joint_body[2 * (R.j0 + j)], jb = B.joint_body[2 * (R.j0 + j) + 1];
+        if ((act == 1 || act == 3) && (ja == b || jb == b)) {
+          v3<dual> xa_;
+          m3<dual> Ra_;
+          dual_pose(M.qm + 7 * ja, ja == beta, comp, xa_, Ra_);
+          v3<dual> ax = mul(Ra_, ld3<dual>(B.joint_frame + 18 * (R.j0 + j) + 15));
+          double tau = ctrl[R.c0 + cc];
+          if (jb == b) tq = tq + ax * tau;
+          if (ja == b) tq = tq - ax * tau;
+        }
+        ++cc;
+      }
+      dual um[6], uu[6], out[6];
+      for (int k = 0; k < 6; ++k) { um[k] = dual(M.um[6 * b + k]); uu[k] = dual(M.u[6 * b + k]); }
+      body_terms<dual>(P, M.mass[b], M.inert + 3 * b, Rb, um, uu, tq, out);
+      for (int k = 0; k < 6; ++k) s += wu[6 * b + k] * out[k].d;
+    }
+    // constraint rows and their forces in r_dyn
+    const int ng = n_groups(R);
+    for (int g = 0; g < ng; ++g) {
+      int row = group_row(R, g);
+      int a = M.r_a[row], c = M.r_b[row];
+      if (a != beta && c != beta) continue;
+      int kind = M.r_kind[row];
+      int n = kind == RK_CONTACT ? 3 : 1;
+      double target = kind == RK_SERVO ? servo_target(B, R, ctrl, M.r_idx[row]) : 0.0;
+      GroupIn<dual> ind;
+      dual_pose(M.qm + 7 * a, a == beta, comp, ind.xa, ind.Ra);
+      if (c >= 0) dual_pose(M.qm + 7 * c, c == beta, comp, ind.xb, ind.Rb);
+      else {
+        ind.xb = v3<dual>{dual(0.0), dual(0.0), dual(0.0)};
+        for (int k = 0; k < 9; ++k) ind.Rb.a[k] = dual((k % 4 == 0) ? 1.0 : 0.0);
+      }
+      dual ua[6], ub[6], lg[3];
+      for (int k = 0; k < 6; ++k) {
+        ua[k] = dual(M.u[6 * a + k]);
+        ub[k] = c >= 0 ? dual(M.u[6 * c + k]) : dual(0.0);
+      }
+      for (int k = 0; k < n; ++k) lg[k] = dual(M.lam[row + k]);
+      ind.ua = ua;
+      ind.ub = c >= 0 ? ub : nullptr;
+      ind.lg = lg;
+      ind.target = dual(target);
+      if (kind == RK_CONTACT) {
+        int ci = M.r_idx[row];
+        int s_ = M.c_slot[ci];
+        const int* si = B.slot_int + 4 * (R.s0 + s_);
+        const double* sr = B.slot_real + 6 * (R.s0 + s_);
+        const double* obs = si[0] == 1 ? B.obs_box + 6 * (R.o0 + si[3]) : nullptr;
+        Feature F = M.c_feat[ci];
+        m3<dual> Rb2 = ind.Rb;
+        v3<dual> xb2 = ind.xb;
+        if (si[0] != 2) { Rb2 = ind.Ra; xb2 = v3<dual>{dual(0.0), dual(0.0), dual(0.0)}; }
+        ind.fr = slot_frame<dual>(si[0], sr, obs, ind.xa, ind.Ra, xb2, Rb2, F, false, nullptr);
+      }
+      dual rd[3], Jd[36];
+      double Dd[3];
+      eval_row_group<dual>(B, P, R, M, row, ind, rd, Jd, Dd);
+      for (int k = 0; k < n; ++k) {
+        s += wl[row + k] * M.D[row + k] * rd[k].d;
+        double jw = 0.0;
+        for (int q = 0; q < 6; ++q) jw += Jd[12 * k + q].d * wu[6 * a + q];
+        if (c >= 0) for (int q = 0; q < 6; ++q) jw += Jd[12 * k + 6 + q].d * wu[6 * c + q];
+        s -= h * M.lam[row + k] * jw;
+      }
+    }
+    // direct term of q+ = q- + h G(q-) u*: x -> identity, quaternion -> (I + h/2 L(w))^T
+    const double* gr = M.gq + 7 * beta;
+    double direct;
+    if (comp < 3) {
+      direct = gr[comp];
+    } else {
+      const double* u = M.u + 6 * beta;
+      v3<double> wv{u[3], u[4], u[5]}, gv{gr[3], gr[4], gr[5]};
+      v3<double> tv = -cross(wv, gv) - wv * gr[6];
+      double tw4 = dot(wv, gv);
+      double add = comp == 3 ? tv.x : (comp == 4 ? tv.y : (comp == 5 ? tv.z : tw4));
+      direct = gr[comp] + 0.5 * h * add;
+    }
+    gq_prev[7 * R.b0 + p] = direct + s;
+  }
+  t.sync();
+}
+
+}  // namespace ost

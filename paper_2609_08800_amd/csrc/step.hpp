@@ -1,0 +1,490 @@
+// Team procedures of the fused per-world step: contact refresh, Newton loop
+// with best-iterate selection (Sec. III-C), and the implicit adjoint
+// (Sec. III-D) that back-solves the stored Schur factor.
+#pragma once
+
+#include "world.hpp"
+
+namespace ost {
+
+// ------------------------------------------------------------ small helpers
+OST_HD v3<double> ldv(const double* p) { return v3<double>{p[0], p[1], p[2]}; }
+OST_HD m3<double> ldm(const double* p) {
+  m3<double> R;
+  for (int i = 0; i < 9; ++i) R.a[i] = p[i];
+  return R;
+}
+OST_HD void stv(double* p, const v3<double>& v) { p[0] = v.x; p[1] = v.y; p[2] = v.z; }
+
+struct RowInfo {
+  int kind, a, b, idx, sub, g, n;
+};
+
+OST_HD int n_groups(const WorldRef& R) { return 5 * R.nj + R.nsv + R.nc; }
+OST_HD int group_row(const WorldRef& R, int g) {
+  int base = 5 * R.nj + R.nsv;
+  return g < base ? g : base + 3 * (g - base);
+}
+
+// Input of a group evaluated at (u, lambda) from the LDS copies (double).
+OST_HD GroupIn<double> group_in_lds(const WorldMem& M, int row, const double* u, const double* lam, double target) {
+  GroupIn<double> in;
+  int a = M.r_a[row], b = M.r_b[row];
+  in.xa = ldv(M.xm + 3 * a);
+  in.Ra = ldm(M.Rm + 9 * a);
+  if (b >= 0) {
+    in.xb = ldv(M.xm + 3 * b);
+    in.Rb = ldm(M.Rm + 9 * b);
+  } else {
+    in.xb = v3<double>{0, 0, 0};
+    for (int i = 0; i < 9; ++i) in.Rb.a[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  }
+  in.ua = u + 6 * a;
+  in.ub = b >= 0 ? u + 6 * b : nullptr;
+  in.lg = lam + row;
+  in.target = target;
+  if (M.r_kind[row] == RK_CONTACT) {
+    int c = M.r_idx[row];
+    in.fr.n = ldv(M.c_n + 3 * c);
+    in.fr.t1 = ldv(M.c_t1 + 3 * c);
+    in.fr.t2 = ldv(M.c_t2 + 3 * c);
+    in.fr.noff = M.c_noff[c];
+    in.fr.la = ldv(M.c_la + 3 * c);
+    in.fr.lb = ldv(M.c_lb + 3 * c);
+  }
+  return in;
+}
+
+OST_HD double servo_target(const Batch& B, const WorldRef& R, const double* ctrl, int joint) {
+  int act = B.joint_act[R.j0 + joint];
+  if (act != 2) return 0.0;
+  int c = 0;
+  for (int j = 0; j < joint; ++j)
+    if (B.joint_act[R.j0 + j]) ++c;
+  return ctrl[R.c0 + c];
+}
+
+template <class T>
+OST_HD void eval_row_group(const Batch& B, const Params& P, const WorldRef& R, const WorldMem& M, int row,
+                           const GroupIn<T>& in, T* r, T* J, double* D) {
+  int kind = M.r_kind[row];
+  int c = kind == RK_CONTACT ? M.r_idx[row] : 0;
+  eval_group<T>(B, P, R, kind, M.r_idx[row], M.r_sub[row], M.r_b[row] >= 0, kind == RK_CONTACT ? M.c_r[c] : 0.0,
+                kind == RK_CONTACT ? M.c_mu[c] : 0.0, kind == RK_CONTACT ? M.c_sn[c] : 1.0,
+                kind == RK_CONTACT ? M.c_sf[c] : 1.0, kind == RK_CONTACT ? M.c_kind[c] : 0, in, r, J, D);
+}
+
+// Block reduction of one value per thread, summed in rank order.
+template <class Team> OST_HD double team_sum(Team& t, const WorldMem& M, double v) {
+  M.red[t.rank()] = v;
+  t.sync();
+  double s = 0.0;
+  for (int i = 0; i < t.size(); ++i) s += M.red[i];
+  t.sync();
+  return s;
+}
+
+// --------------------------------------------------------------------------
+// Prologue: bodies at q-, contact refresh (A1), rows, warm start, FB scales.
+// --------------------------------------------------------------------------
+template <class Team>
+OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, const double* q_prev,
+                     const double* u_prev, const double* ctrl, const double* lam_prev, WorldMem& M) {
+  const int nb = R.nb;
+  for (int b = t.rank(); b < nb; b += t.size()) {
+    const double* q = q_prev + 7 * (R.b0 + b);
+    const double* u = u_prev + 6 * (R.b0 + b);
+    for (int k = 0; k < 7; ++k) M.qm[7 * b + k] = q[k];
+    for (int k = 0; k < 6; ++k) { M.um[6 * b + k] = u[k]; M.u[6 * b + k] = u[k]; }
+    for (int k = 0; k < 3; ++k) M.xm[3 * b + k] = q[k];
+    m3<double> Rm = quat_to_R(q[3], q[4], q[5], q[6]);
+    for (int k = 0; k < 9; ++k) M.Rm[9 * b + k] = Rm.a[k];
+    const double* I = B.body_inertia + 3 * (R.b0 + b);
+    M.mass[b] = B.body_mass[R.b0 + b];
+    for (int k = 0; k < 3; ++k) M.inert[3 * b + k] = I[k];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0, si = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          s += Rm.a[3 * i + k] * I[k] * Rm.a[3 * j + k];
+          si += Rm.a[3 * i + k] / I[k] * Rm.a[3 * j + k];
+        }
+        M.Iw[9 * b + 3 * i + j] = s;
+        M.Iwi[9 * b + 3 * i + j] = si;
+      }
+    for (int k = 0; k < 6; ++k) M.fext[6 * b + k] = 0.0;  // actuator torque (angular part)
+  }
+  t.sync();
+  if (t.rank() == 0) {  // actuator torques about the joint axis at q-
+    int c = 0;
+    for (int j = 0; j < R.nj; ++j) {
+      int act = B.joint_act[R.j0 + j];
+      if (!act) continue;
+      if (act == 1 || act == 3) {
+        int a = B.joint_body[2 * (R.j0 + j)], b = B.joint_body[2 * (R.j0 + j) + 1];
+        v3<double> ax = mul(ldm(M.Rm + 9 * a), ldv(B.joint_frame + 18 * (R.j0 + j) + 15));
+        double tau = ctrl[R.c0 + c];
+        for (int k = 0; k < 3; ++k) {
+          M.fext[6 * b + 3 + k] += tau * at(ax, k);
+          M.fext[6 * a + 3 + k] -= tau * at(ax, k);
+        }
+      }
+      ++c;
+    }
+  }
+  // contact refresh: frame and activation of every slot at q-
+  for (int s = t.rank(); s < R.ns; s += t.size()) {
+    const int* si = B.slot_int + 4 * (R.s0 + s);
+    const double* sr = B.slot_real + 6 * (R.s0 + s);
+    int kind = si[0], a = si[1], b = si[2];
+    Feature F{};
+    double gap;
+    v3<double> xb{0, 0, 0};
+    m3<double> Rb = ldm(M.Rm + 9 * a);
+    if (kind == 2) { xb = ldv(M.xm + 3 * b); Rb = ldm(M.Rm + 9 * b); }
+    const double* obs = kind == 1 ? B.obs_box + 6 * (R.o0 + si[3]) : nullptr;
+    Frame<double> C = slot_frame<double>(kind, sr, obs, ldv(M.xm + 3 * a), ldm(M.Rm + 9 * a), xb, Rb, F, true, &gap);
+    // relative velocity of the contact point at q-, approach along n
+    v3<double> pc = ldv(M.xm + 3 * a) + C.la - C.n * sr[3];
+    const double* ua = M.um + 6 * a;
+    v3<double> vr = ldv(ua) + cross(ldv(ua + 3), pc - ldv(M.xm + 3 * a));
+    if (kind == 2) {
+      const double* ub = M.um + 6 * b;
+      vr = vr - (ldv(ub) + cross(ldv(ub + 3), pc - xb));
+    }
+    double vn = dot(C.n, vr);
+    M.s_act[s] = (gap + P.h * (vn < 0.0 ? vn : 0.0) <= P.d0) ? 1 : 0;
+    M.s_feat[s] = F;
+  }
+  t.sync();
+  if (t.rank() == 0) {  // ascending-slot compaction, at most contact_cap
+    int nc = 0, of = 0;
+    for (int s = 0; s < R.ns; ++s)
+      if (M.s_act[s]) {
+        if (nc < R.cap) M.c_slot[nc++] = s;
+        else of = 1;
+      }
+    M.iscal[0] = nc;
+    M.iscal[1] = of;
+  }
+  t.sync();
+  R.nc = M.iscal[0];
+  R.m = 5 * R.nj + R.nsv + 3 * R.nc;
+  for (int c = t.rank(); c < R.nc; c += t.size()) {
+    int s = M.c_slot[c];
+    const int* si = B.slot_int + 4 * (R.s0 + s);
+    const double* sr = B.slot_real + 6 * (R.s0 + s);
+    int kind = si[0], a = si[1], b = si[2];
+    Feature F = M.s_feat[s];
+    v3<double> xb{0, 0, 0};
+    m3<double> Rb = ldm(M.Rm + 9 * a);
+    if (kind == 2) { xb = ldv(M.xm + 3 * b); Rb = ldm(M.Rm + 9 * b); }
+    const double* obs = kind == 1 ? B.obs_box + 6 * (R.o0 + si[3]) : nullptr;
+    Frame<double> C = slot_frame<double>(kind, sr, obs, ldv(M.xm + 3 * a), ldm(M.Rm + 9 * a), xb, Rb, F, false, nullptr);
+    M.c_feat[c] = F;
+    M.c_kind[c] = kind;
+    M.c_a[c] = a;
+    M.c_b[c] = kind == 2 ? b : -1;
+    M.c_r[c] = sr[3];
+    M.c_mu[c] = sr[4];
+    stv(M.c_n + 3 * c, C.n);
+    stv(M.c_t1 + 3 * c, C.t1);
+    stv(M.c_t2 + 3 * c, C.t2);
+    M.c_noff[c] = C.noff;
+    stv(M.c_la + 3 * c, C.la);
+    stv(M.c_lb + 3 * c, C.lb);
+    M.c_sn[c] = 1.0;
+    M.c_sf[c] = 1.0;
+  }
+  // row layout: [5 per revolute joint][servo rows][3 per active contact]
+  const int base = 5 * R.nj + R.nsv;
+  for (int i = t.rank(); i < R.m; i += t.size()) {
+    int kind, a, b, idx, sub, g, lslot;
+    if (i < 5 * R.nj) {
+      idx = i / 5;
+      sub = i % 5;
+      kind = sub < 3 ? RK_ANCHOR : RK_AXIS;
+      if (sub >= 3) sub -= 3;
+      a = B.joint_body[2 * (R.j0 + idx)];
+      b = B.joint_body[2 * (R.j0 + idx) + 1];
+      g = i;
+      lslot = i;
+    } else if (i < base) {
+      int sv = i - 5 * R.nj, c = -1;
+      idx = 0;
+      for (int j = 0; j < R.nj; ++j) {
+        int act = B.joint_act[R.j0 + j];
+        if (act == 2 || act == 3) {
+          if (++c == sv) { idx = j; break; }
+        }
+      }
+      kind = RK_SERVO;
+      sub = 0;
+      a = B.joint_body[2 * (R.j0 + idx)];
+      b = B.joint_body[2 * (R.j0 + idx) + 1];
+      g = i;
+      lslot = i;
+    } else {
+      int c = (i - base) / 3;
+      sub = (i - base) % 3;
+      kind = RK_CONTACT;
+      idx = c;
+      int s = M.c_slot[c];
+      const int* si = B.slot_int + 4 * (R.s0 + s);
+      a = si[1];
+      b = si[0] == 2 ? si[2] : -1;
+      g = base + 3 * c;
+      lslot = base + 3 * s + sub;
+    }
+    M.r_kind[i] = kind;
+    M.r_a[i] = a;
+    M.r_b[i] = b;
+    M.r_idx[i] = idx;
+    M.r_sub[i] = sub;
+    M.r_g[i] = g;
+    M.lam[i] = lam_prev ? lam_prev[R.l0 + lslot] : 0.0;
+  }
+  t.sync();
+}
+
+// Clamp of the friction multipliers to the Coulomb disk of radius
+// max(mu lambda_n, delta_g) (Sec. III-B safeguard).
+template <class Team> OST_HD void clamp_all(Team& t, const Params& P, const WorldRef& R, const WorldMem& M, double* lam) {
+  const int base = 5 * R.nj + R.nsv;
+  for (int c = t.rank(); c < R.nc; c += t.size()) {
+    int i = base + 3 * c;
+    double lim = M.c_mu[c] * lam[i];
+    if (lim < P.dg) lim = P.dg;
+    double n = ::sqrt(lam[i + 1] * lam[i + 1] + lam[i + 2] * lam[i + 2]);
+    if (n > lim) {
+      double s = n > 0.0 ? lim / n : 0.0;
+      lam[i + 1] *= s;
+      lam[i + 2] *= s;
+    }
+  }
+  t.sync();
+}
+
+// M~^-1 applied to a 6-vector of body b.
+OST_HD void minv6(const WorldMem& M, int b, const double* x, double* y) {
+  double im = 1.0 / M.mass[b];
+  y[0] = x[0] * im; y[1] = x[1] * im; y[2] = x[2] * im;
+  const double* Ii = M.Iwi + 9 * b;
+  for (int i = 0; i < 3; ++i) y[3 + i] = Ii[3 * i] * x[3] + Ii[3 * i + 1] * x[4] + Ii[3 * i + 2] * x[5];
+}
+
+// --------------------------------------------------------------------------
+// Residual at (u, lam): J, raw rows, r_dyn, norm; with want_G also the
+// generalized Jacobian of the scaled rows (Y = G_u M~^-1, G_lambda) and the
+// Delassus diagonal.  Returns the residual norm.
+// --------------------------------------------------------------------------
+template <class Team>
+OST_HD double evaluate(Team& t, const Batch& B, const Params& P, const WorldRef& R, const WorldMem& M,
+                       const double* ctrl, const double* u, const double* lam, bool want_G) {
+  const int ng = n_groups(R);
+  for (int g = t.rank(); g < ng; g += t.size()) {
+    int row = group_row(R, g);
+    int kind = M.r_kind[row];
+    int n = kind == RK_CONTACT ? 3 : 1;
+    double target = kind == RK_SERVO ? servo_target(B, R, ctrl, M.r_idx[row]) : 0.0;
+    GroupIn<double> in = group_in_lds(M, row, u, lam, target);
+    double r[3], D[3];
+    eval_row_group<double>(B, P, R, M, row, in, r, M.J + 12 * row, D);
+    for (int k = 0; k < n; ++k) {
+      M.res[row + k] = r[k];
+      M.D[row + k] = D[k];
+    }
+    int a = M.r_a[row], b = M.r_b[row];
+    if (want_G) {
+      // generalized Jacobian of D r by forward duals over the group's local inputs
+      double Gu[3][12], Gl[3][3];
+      int nseed = 12 + n;
+      for (int sd = 0; sd < nseed; ++sd) {
+        if (sd >= 6 && sd < 12 && b < 0) {
+          for (int k = 0; k < n; ++k) Gu[k][sd] = 0.0;
+          continue;
+        }
+        dual ua[6], ub[6], lg[3];
+        for (int k = 0; k < 6; ++k) {
+          ua[k] = dual(u[6 * a + k], sd == k ? 1.0 : 0.0);
+          ub[k] = b >= 0 ? dual(u[6 * b + k], sd == 6 + k ? 1.0 : 0.0) : dual(0.0);
+        }
+        for (int k = 0; k < n; ++k) lg[k] = dual(lam[row + k], sd == 12 + k ? 1.0 : 0.0);
+        GroupIn<dual> ind;
+        ind.xa = v3<dual>{in.xa.x, in.xa.y, in.xa.z};
+        ind.xb = v3<dual>{in.xb.x, in.xb.y, in.xb.z};
+        for (int k = 0; k < 9; ++k) { ind.Ra.a[k] = in.Ra.a[k]; ind.Rb.a[k] = in.Rb.a[k]; }
+        ind.ua = ua;
+        ind.ub = b >= 0 ? ub : nullptr;
+        ind.lg = lg;
+        ind.target = dual(target);
+        ind.fr.n = v3<dual>{in.fr.n.x, in.fr.n.y, in.fr.n.z};
+        ind.fr.t1 = v3<dual>{in.fr.t1.x, in.fr.t1.y, in.fr.t1.z};
+        ind.fr.t2 = v3<dual>{in.fr.t2.x, in.fr.t2.y, in.fr.t2.z};
+        ind.fr.noff = dual(in.fr.noff);
+        ind.fr.la = v3<dual>{in.fr.la.x, in.fr.la.y, in.fr.la.z};
+        ind.fr.lb = v3<dual>{in.fr.lb.x, in.fr.lb.y, in.fr.lb.z};
+        dual rd[3], Jd[36];
+        double Dd[3];
+        eval_row_group<dual>(B, P, R, M, row, ind, rd, Jd, Dd);
+        for (int k = 0; k < n; ++k) {
+          double d = D[k] * rd[k].d;
+          if (sd < 12) Gu[k][sd] = d;
+          else Gl[k][sd - 12] = d;
+        }
+      }
+      for (int k = 0; k < n; ++k) {
+        double* Y = M.Y + 12 * (row + k);
+        minv6(M, a, Gu[k], Y);
+        if (b >= 0) minv6(M, b, Gu[k] + 6, Y + 6);
+        else for (int q = 6; q < 12; ++q) Y[q] = 0.0;
+        for (int q = 0; q < 3; ++q) M.Gl[3 * (row + k) + q] = q < n ? Gl[k][q] : 0.0;
+        const double* Jr = M.J + 12 * (row + k);
+        double MJ[12], s = 0.0;
+        minv6(M, a, Jr, MJ);
+        for (int q = 0; q < 6; ++q) s += Jr[q] * MJ[q];
+        if (b >= 0) {
+          minv6(M, b, Jr + 6, MJ + 6);
+          for (int q = 6; q < 12; ++q) s += Jr[q] * MJ[q];
+        }
+        M.Abar[row + k] = s;
+      }
+    }
+  }
+  t.sync();
+  // r_dyn per body; constraint forces summed over rows in order
+  for (int b = t.rank(); b < R.nb; b += t.size()) {
+    double out[6];
+    v3<double> tq{M.fext[6 * b + 3], M.fext[6 * b + 4], M.fext[6 * b + 5]};
+    body_terms<double>(P, M.mass[b], M.inert + 3 * b, ldm(M.Rm + 9 * b), M.um + 6 * b, u + 6 * b, tq, out);
+    for (int i = 0; i < R.m; ++i) {
+      const double* Jr = M.J + 12 * i;
+      if (M.r_a[i] == b)
+        for (int k = 0; k < 6; ++k) out[k] -= P.h * (Jr[k] * lam[i]);
+      if (M.r_b[i] == b)
+        for (int k = 0; k < 6; ++k) out[k] -= P.h * (Jr[6 + k] * lam[i]);
+    }
+    for (int k = 0; k < 6; ++k) M.rdyn[6 * b + k] = out[k];
+  }
+  t.sync();
+  double s = 0.0;
+  int ntot = 6 * R.nb + R.m;
+  for (int i = t.rank(); i < ntot; i += t.size()) {
+    double v = i < 6 * R.nb ? M.rdyn[i] : M.res[i - 6 * R.nb];
+    s += v * v;
+  }
+  return ::sqrt(team_sum(t, M, s));
+}
+
+// Schur matrix of Eq. (12) with the generalized Jacobian: A = G_u M~^-1 J^T
+// + G_lambda / h + dreg diag(J M~^-1 J^T), and its right-hand side.
+template <class Team>
+OST_HD void assemble(Team& t, const Params& P, const WorldRef& R, const WorldMem& M, double dreg, bool with_rhs) {
+  const int m = R.m;
+  const double ih = 1.0 / P.h;
+  for (int e = t.rank(); e < m * m; e += t.size()) {
+    int i = e / m, j = e - i * m;
+    const double* Y = M.Y + 12 * i;
+    const double* Jj = M.J + 12 * j;
+    int ai = M.r_a[i], bi = M.r_b[i], aj = M.r_a[j], bj = M.r_b[j];
+    double s = 0.0;
+    if (ai == aj) for (int k = 0; k < 6; ++k) s += Y[k] * Jj[k];
+    if (ai == bj) for (int k = 0; k < 6; ++k) s += Y[k] * Jj[6 + k];
+    if (bi >= 0 && bi == aj) for (int k = 0; k < 6; ++k) s += Y[6 + k] * Jj[k];
+    if (bi >= 0 && bi == bj) for (int k = 0; k < 6; ++k) s += Y[6 + k] * Jj[6 + k];
+    int gi = M.r_g[i];
+    if (M.r_g[j] == gi) s += M.Gl[3 * i + (j - gi)] * ih;
+    if (i == j) s += dreg * M.Abar[i];
+    M.A[e] = s;
+  }
+  if (with_rhs)
+    for (int i = t.rank(); i < m; i += t.size()) {
+      const double* Y = M.Y + 12 * i;
+      int a = M.r_a[i], b = M.r_b[i];
+      double s = 0.0;
+      for (int k = 0; k < 6; ++k) s += Y[k] * M.rdyn[6 * a + k];
+      if (b >= 0) for (int k = 0; k < 6; ++k) s += Y[6 + k] * M.rdyn[6 * b + k];
+      M.rhs[i] = (s - M.D[i] * M.res[i]) * ih;
+    }
+  t.sync();
+}
+
+// In-place LU without pivoting; false on a non-finite or tiny pivot.
+template <class Team> OST_HD bool lu_factor(Team& t, const WorldRef& R, const WorldMem& M) {
+  const int m = R.m;
+  double* A = M.A;
+  for (int k = 0; k < m; ++k) {
+    if (t.rank() == 0) {
+      double piv = A[k * m + k], rmax = 0.0;
+      for (int j = k; j < m; ++j) {
+        double v = fabs(A[k * m + j]);
+        rmax = v > rmax ? v : rmax;
+      }
+      M.iscal[2] = (isfinite(piv) && fabs(piv) > 1e-14 * rmax && rmax > 0.0) ? 1 : 0;
+    }
+    t.sync();
+    if (!M.iscal[2]) return false;
+    double ip = 1.0 / A[k * m + k];
+    for (int i = k + 1 + t.rank(); i < m; i += t.size()) A[i * m + k] *= ip;
+    t.sync();
+    int w = m - k - 1;
+    for (int e = t.rank(); e < w * w; e += t.size()) {
+      int i = k + 1 + e / w, j = k + 1 + e % w;
+      A[i * m + j] -= A[i * m + k] * A[k * m + j];
+    }
+    t.sync();
+  }
+  return true;
+}
+
+// Solve A x = b (trans = false) or A^T x = b (trans = true) with the LU in M.A.
+template <class Team> OST_HD void lu_solve(Team& t, const WorldRef& R, const WorldMem& M, double* x, bool trans) {
+  const int m = R.m;
+  const double* A = M.A;
+  if (!trans) {
+    for (int k = 0; k < m; ++k) {  // L y = b (unit lower)
+      double yk = x[k];
+      for (int i = k + 1 + t.rank(); i < m; i += t.size()) x[i] -= A[i * m + k] * yk;
+      t.sync();
+    }
+    for (int k = m - 1; k >= 0; --k) {  // U x = y
+      double xk = x[k] / A[k * m + k];
+      t.sync();
+      if (t.rank() == 0) x[k] = xk;
+      for (int i = t.rank(); i < k; i += t.size()) x[i] -= A[i * m + k] * xk;
+      t.sync();
+    }
+  } else {
+    for (int k = 0; k < m; ++k) {  // U^T z = b
+      double zk = x[k] / A[k * m + k];
+      t.sync();
+      if (t.rank() == 0) x[k] = zk;
+      for (int i = k + 1 + t.rank(); i < m; i += t.size()) x[i] -= A[k * m + i] * zk;
+      t.sync();
+    }
+    for (int k = m - 1; k >= 0; --k) {  // L^T x = z (unit)
+      double xk = x[k];
+      for (int i = t.rank(); i < k; i += t.size()) x[i] -= A[k * m + i] * xk;
+      t.sync();
+    }
+  }
+}
+
+// Assemble and factor with the regularisation raised tenfold on failure.
+template <class Team>
+OST_HD bool factor(Team& t, const Params& P, const WorldRef& R, const WorldMem& M, bool with_rhs, double* dreg_used,
+                   int* status) {
+  double dreg = P.dreg;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    assemble(t, P, R, M, dreg, with_rhs && attempt == 0);
+    if (lu_factor(t, R, M)) {
+      *dreg_used = dreg;
+      return true;
+    }
+    *status |= ST_REGULARIZED;
+    dreg *= 10.0;
+  }
+  return false;
+}
+
+}  // namespace ost

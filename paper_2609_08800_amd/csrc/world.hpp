@@ -1,0 +1,239 @@
+// One world's backward-Euler step and its adjoint, written for a team of
+// threads that share an LDS workspace (one workgroup per world on the GPU).
+//
+// Team interface: rank(), size(), sync().  Work loops are strided by the team
+// size; every reduction runs in a fixed order so results do not depend on
+// scheduling (rollout recomputation is bitwise repeatable).
+#pragma once
+
+#include "model.hpp"
+
+namespace ost {
+
+// Capacities of one launch (maxima over the batch) and the LDS carve-out.
+struct Caps {
+  int nb, nj, ns, nc, mr, nsv;
+};
+
+struct WorldMem {
+  // bodies
+  double *xm, *qm, *Rm, *Iw, *Iwi, *mass, *inert, *fext, *um, *u, *du, *rdyn, *ubest, *ut, *gq, *kg;
+  // contacts
+  int *c_slot, *c_kind, *c_a, *c_b;
+  Feature* c_feat;
+  double *c_n, *c_t1, *c_t2, *c_noff, *c_la, *c_lb, *c_r, *c_mu, *c_sn, *c_sf;
+  // rows
+  int *r_kind, *r_a, *r_b, *r_idx, *r_sub, *r_g;
+  double *J, *Y, *Gl, *D, *res, *lam, *dlam, *lamt, *lambest, *Abar;
+  // Schur matrix and right-hand side
+  double *A, *rhs;
+  // slot scratch
+  int* s_act;
+  Feature* s_feat;
+  // reduction scratch and scalars
+  double* red;
+  int* iscal;
+  double* dscal;
+};
+
+OST_HD size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
+
+// Bytes of LDS one world needs for the given capacities and team size.
+OST_HD size_t world_lds_bytes(const Caps& c, int team) {
+  size_t d = 0, i = 0;
+  d += (size_t)c.nb * (3 + 7 + 9 + 9 + 9 + 1 + 3 + 6 * 7 + 7 + 6);
+  d += (size_t)c.nc * 20;
+  d += (size_t)c.mr * (12 + 12 + 3 + 7);
+  d += (size_t)c.mr * c.mr + c.mr;
+  d += (size_t)team + 8;
+  i += (size_t)c.nc * 4 + (size_t)c.mr * 6 + c.ns + 16;
+  size_t feat = (size_t)(c.nc + c.ns) * sizeof(Feature);
+  return d * 8 + align8(i * 4) + align8(feat);
+}
+
+OST_HD WorldMem carve(char* base, const Caps& c, int team) {
+  WorldMem M;
+  double* p = (double*)base;
+  auto take = [&](size_t n) { double* r = p; p += n; return r; };
+  M.xm = take(3 * c.nb); M.qm = take(7 * c.nb); M.Rm = take(9 * c.nb); M.Iw = take(9 * c.nb);
+  M.Iwi = take(9 * c.nb); M.mass = take(c.nb); M.inert = take(3 * c.nb); M.fext = take(6 * c.nb);
+  M.um = take(6 * c.nb); M.u = take(6 * c.nb); M.du = take(6 * c.nb); M.rdyn = take(6 * c.nb);
+  M.ubest = take(6 * c.nb); M.ut = take(6 * c.nb); M.gq = take(7 * c.nb); M.kg = take(6 * c.nb);
+  M.c_n = take(3 * c.nc); M.c_t1 = take(3 * c.nc); M.c_t2 = take(3 * c.nc); M.c_noff = take(c.nc);
+  M.c_la = take(3 * c.nc); M.c_lb = take(3 * c.nc); M.c_r = take(c.nc); M.c_mu = take(c.nc);
+  M.c_sn = take(c.nc); M.c_sf = take(c.nc);
+  M.J = take(12 * c.mr); M.Y = take(12 * c.mr); M.Gl = take(3 * c.mr); M.D = take(c.mr); M.res = take(c.mr);
+  M.lam = take(c.mr); M.dlam = take(c.mr); M.lamt = take(c.mr); M.lambest = take(c.mr); M.Abar = take(c.mr);
+  M.A = take((size_t)c.mr * c.mr); M.rhs = take(c.mr);
+  M.red = take(team); M.dscal = take(8);
+  int* q = (int*)p;
+  auto itake = [&](size_t n) { int* r = q; q += n; return r; };
+  M.c_slot = itake(c.nc); M.c_kind = itake(c.nc); M.c_a = itake(c.nc); M.c_b = itake(c.nc);
+  M.r_kind = itake(c.mr); M.r_a = itake(c.mr); M.r_b = itake(c.mr); M.r_idx = itake(c.mr);
+  M.r_sub = itake(c.mr); M.r_g = itake(c.mr);
+  M.s_act = itake(c.ns); M.iscal = itake(16);
+  char* f = (char*)(((uintptr_t)q + 7) & ~uintptr_t(7));
+  M.c_feat = (Feature*)f;
+  M.s_feat = M.c_feat + c.nc;
+  return M;
+}
+
+// Per-world view of the packed batch.
+struct WorldRef {
+  int w, b0, nb, j0, nj, s0, ns, o0, l0, c0, cap, nsv, m, nc;
+  int nctrl;
+};
+
+OST_HD WorldRef world_ref(const Batch& B, int w) {
+  WorldRef R;
+  R.w = w;
+  R.b0 = B.body_off[w];
+  R.nb = B.body_off[w + 1] - R.b0;
+  R.j0 = B.joint_off[w];
+  R.nj = B.joint_off[w + 1] - R.j0;
+  R.s0 = B.slot_off[w];
+  R.ns = B.slot_off[w + 1] - R.s0;
+  R.o0 = B.obs_off[w];
+  R.l0 = B.lam_off[w];
+  R.c0 = B.ctrl_off[w];
+  R.nctrl = B.ctrl_off[w + 1] - R.c0;
+  R.cap = B.contact_cap[w];
+  R.nsv = 0;
+  for (int j = 0; j < R.nj; ++j) {
+    int a = B.joint_act[R.j0 + j];
+    if (a == 2 || a == 3) R.nsv++;
+  }
+  R.m = 0;
+  R.nc = 0;
+  return R;
+}
+
+// --------------------------------------------------------------------------
+// Row evaluation.  All inputs that the adjoint differentiates are of type T.
+// --------------------------------------------------------------------------
+template <class T> struct GroupIn {
+  v3<T> xa, xb;      // body positions at q-
+  m3<T> Ra, Rb;      // rotations at q-
+  const T* ua;       // velocity iterate of body a (6)
+  const T* ub;       // velocity iterate of body b (6) or null
+  const T* lg;       // multipliers of the group (1 or 3)
+  Frame<T> fr;       // contact frame (contact groups)
+  T target;          // servo velocity target
+};
+
+// Residual rows r (raw), Jacobian rows J (12 each) and the value of the row
+// scale D of one group: a joint row, a servo row, or a contact (n, t1, t2).
+template <class T>
+OST_HD void eval_group(const Batch& B, const Params& P, const WorldRef& R, int kind, int idx, int sub,
+                       int has_b, double r_prox, double mu, double sn, double sf, int ckind,
+                       const GroupIn<T>& in, T* r, T* J, double* D) {
+  const double h = P.h;
+  const v3<T> zero = mk(T(0.0), T(0.0), T(0.0));
+  T zu[6] = {T(0.0), T(0.0), T(0.0), T(0.0), T(0.0), T(0.0)};
+  BodyIt<T> Ba = body_it(in.xa, in.ua, h);
+  BodyIt<T> Bb = body_it(in.xb, in.ub ? in.ub : zu, h);
+  int n = kind == RK_CONTACT ? 3 : 1;
+  for (int t = 0; t < 12 * n; ++t) J[t] = T(0.0);
+  if (kind == RK_ANCHOR || kind == RK_AXIS) {
+    const double* fr = B.joint_frame + 18 * (R.j0 + idx);
+    if (kind == RK_ANCHOR) {  // Eq. (3): e_i . (x_a + R_a anchor_a - x_b - R_b anchor_b), E = 0
+      v3<T> e = mk(T(sub == 0 ? 1.0 : 0.0), T(sub == 1 ? 1.0 : 0.0), T(sub == 2 ? 1.0 : 0.0));
+      v3<T> aa = mul(in.Ra, ld3<T>(fr));
+      v3<T> ab = mul(in.Rb, ld3<T>(fr + 3));
+      T ca = pos_term(Ba, aa, e, J);
+      T cb = pos_term(Bb, ab, e, J + 6);
+      for (int t = 6; t < 12; ++t) J[t] = -J[t];
+      r[0] = ca - cb;
+    } else {  // axis alignment: (R_a perp) . (R_b axis_b)
+      v3<T> p = mul(in.Ra, ld3<T>(fr + (sub == 0 ? 9 : 12)));
+      v3<T> q = mul(in.Rb, ld3<T>(fr + 6));
+      v3<T> pa = cay(Ba.k, p), qb = cay(Bb.k, q);
+      v3<T> ga = cay_grad(Ba.k, p, qb), gb = cay_grad(Bb.k, q, pa);
+      J[3] = ga.x * 0.5; J[4] = ga.y * 0.5; J[5] = ga.z * 0.5;
+      J[9] = gb.x * 0.5; J[10] = gb.y * 0.5; J[11] = gb.z * 0.5;
+      r[0] = dot(pa, qb);
+    }
+    D[0] = 1.0 / h;
+    return;
+  }
+  if (kind == RK_SERVO) {  // Eq. (8), velocity target, alpha = 1/k_p
+    const double* fr = B.joint_frame + 18 * (R.j0 + idx);
+    double kp = B.joint_kp[R.j0 + idx];
+    v3<T> ax = mul(in.Ra, ld3<T>(fr + 15));
+    J[3] = -ax.x; J[4] = -ax.y; J[5] = -ax.z;
+    J[9] = ax.x; J[10] = ax.y; J[11] = ax.z;
+    r[0] = dot(ax, Bb.w - Ba.w) + in.lg[0] / kp - in.target;
+    D[0] = 1.0;
+    return;
+  }
+  // contact group: normal row (Eq. (4), eps-smoothed FB) and friction rows (Eq. (7))
+  const Frame<T>& F = in.fr;
+  T gap;
+  if (ckind == 2) {
+    gap = pos_term(Ba, F.la, F.n, J) - pos_term(Bb, F.lb, F.n, J + 6) - r_prox;
+    for (int t = 6; t < 12; ++t) J[t] = -J[t];
+  } else {
+    gap = pos_term(Ba, F.la, F.n, J) - F.noff - r_prox;
+  }
+  T Bq = sn * in.lg[0];
+  T S = ssqrt(gap * gap + Bq * Bq + P.eps * P.eps);
+  r[0] = gap + Bq - S;
+  double pa = 1.0 - val(gap) / val(S);
+  D[0] = 1.0 / (h * (pa > P.dg ? pa : P.dg));
+  // tangential velocity of the material points at the contact point at q+
+  v3<T> lev_a = cay(Ba.k, F.la) - F.n * r_prox;
+  v3<T> pc = Ba.x + lev_a;
+  v3<T> lev_b = has_b ? pc - Bb.x : zero;
+  T vt[2];
+  for (int s = 0; s < 2; ++s) {
+    const v3<T>& t = s == 0 ? F.t1 : F.t2;
+    T* Jr = J + 12 * (1 + s);
+    v3<T> wa = cross(lev_a, t);
+    Jr[0] = t.x; Jr[1] = t.y; Jr[2] = t.z;
+    Jr[3] = wa.x; Jr[4] = wa.y; Jr[5] = wa.z;
+    T v = dot(t, Ba.v) + dot(wa, Ba.w);
+    if (has_b) {
+      v3<T> wb = cross(lev_b, t);
+      Jr[6] = -t.x; Jr[7] = -t.y; Jr[8] = -t.z;
+      Jr[9] = -wb.x; Jr[10] = -wb.y; Jr[11] = -wb.z;
+      v = v - dot(t, Bb.v) - dot(wb, Bb.w);
+    }
+    vt[s] = v;
+    D[1 + s] = 1.0;
+  }
+  // compliance weight W = (sqrt(s^2 + beta^2) - beta) / (mu lambda_n), s the
+  // eps-smoothed slip speed, beta = sigma_f (mu lambda_n - |lambda_f|_eps)
+  const T& ln = in.lg[0];
+  T s2 = vt[0] * vt[0] + vt[1] * vt[1] + P.eps * P.eps;
+  T lf = ssqrt(in.lg[1] * in.lg[1] + in.lg[2] * in.lg[2] + P.eps * P.eps);
+  T beta = sf * (mu * ln - lf);
+  T Q = ssqrt(s2 + beta * beta);
+  T den = tmax(ln * mu, T(P.dg));
+  T W = val(beta) > 0.0 ? s2 / ((Q + beta) * den) : (Q - beta) / den;
+  r[1] = vt[0] + W * in.lg[1];
+  r[2] = vt[1] + W * in.lg[2];
+}
+
+// Body-level terms of r_dyn = M~ (u - u-) - h f_ext - h J^T lambda (Eq. (10)),
+// without the constraint forces: mass, world inertia and f_ext at q-.
+template <class T>
+OST_HD void body_terms(const Params& P, double mass, const double* inert, const m3<T>& R, const T* um, const T* u,
+                       const v3<T>& torque, T* out6) {
+  const double h = P.h;
+  for (int k = 0; k < 3; ++k) out6[k] = mass * (u[k] - um[k]) - h * (mass * P.g[k]);
+  v3<T> wm = mk(um[3], um[4], um[5]);
+  v3<T> dw = mk(u[3] - um[3], u[4] - um[4], u[5] - um[5]);
+  auto Iw = [&](const v3<T>& v) {
+    v3<T> l = mulT(R, v);
+    l = mk(l.x * inert[0], l.y * inert[1], l.z * inert[2]);
+    return mul(R, l);
+  };
+  v3<T> gyro = -cross(wm, Iw(wm));
+  v3<T> a = Iw(dw);
+  v3<T> f = gyro + torque;
+  out6[3] = a.x - h * f.x;
+  out6[4] = a.y - h * f.y;
+  out6[5] = a.z - h * f.z;
+}
+
+}  // namespace ost

@@ -1,0 +1,60 @@
+"""Host-side checks of the C-ABI library (no GPU compute)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ostrich.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ostrich_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2609_08800_amd import _capi
+    lib = _capi.load()
+    names = declared_functions()
+    assert "ostrich_step_forward" in names and "ostrich_rollout" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_spline_basis_host_routine_matches_scipy():
+    from scipy.interpolate import CubicSpline
+    from paper_2609_08800_amd import spline_basis
+    for T, K in ((100, 8), (20, 3), (7, 10)):
+        B = spline_basis(T, K, 0.1)
+        tk = np.arange(K) * T * 0.1 / (K - 1)
+        ts = np.arange(T) * 0.1
+        for j in range(K):
+            y = np.zeros(K)
+            y[j] = 1
+            np.testing.assert_allclose(B[:, j], CubicSpline(tk, y, bc_type="natural")(ts), atol=1e-12)
+
+
+def test_batch_struct_layout_matches_header():
+    """The ctypes mirror of ostrich_batch / ostrich_params has the header's field order."""
+    from paper_2609_08800_amd import _capi
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = text[text.index("typedef struct {", text.index("ostrich_st") if False else 0):]
+    batch_fields = re.findall(r"(\w+);", text[text.index("int32_t n_worlds;"):text.index("} ostrich_batch;")])
+    assert [f for f, _ in _capi.OstrichBatch._fields_] == batch_fields
+    pblock = text[text.index("double h;"):text.index("} ostrich_params;")]
+    pfields = [re.sub(r"\[.*\]", "", f) for f in re.findall(r"([\w\[\]0-9]+);", pblock)]
+    assert [f for f, _ in _capi.OstrichParams._fields_] == pfields
+
+
+def test_no_cpu_fallback_without_gpu():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    import scenes
+    from paper_2609_08800_amd import OstrichError, Simulator
+    with pytest.raises(OstrichError):
+        Simulator(scenes.box_batch(1), scenes.solver_params(), device="cuda")
