@@ -95,7 +95,7 @@ typedef struct {
   double delta0;       /* contact activation margin (m) */
   int32_t ls_max;      /* step-length halvings of the residual-decrease test */
   int32_t refine;      /* adjoint refinement sweeps toward the exact Jacobian (0: factor only) */
-  int32_t team;        /* threads per world (64, 128 or 256; 0 = default) */
+  int32_t team;        /* threads per world (64, 128 or 256; 0 = 128) */
 } ostrich_params;
 
 typedef struct ostrich_ctx ostrich_ctx;

@@ -66,35 +66,46 @@ OST_HD void forward_world(Team& t, const Batch& B, const Params& P, const Caps& 
       for (int i = t.rank(); i < m; i += t.size()) M.dlam[i] = M.rhs[i];
       t.sync();
       lu_solve(t, R, M, M.dlam, false);
-      // Eq. (13): du = M~^-1 (h J^T dlambda - r_dyn)
-      for (int b = t.rank(); b < nb; b += t.size()) {
-        double tv[6];
-        for (int q = 0; q < 6; ++q) tv[q] = -M.rdyn[6 * b + q];
+      // Eq. (13): du = M~^-1 (h J^T dlambda - r_dyn), force per (body, component)
+      for (int e = t.rank(); e < 6 * nb; e += t.size()) {
+        int b = e / 6, q = e - 6 * b;
+        double v = -M.rdyn[e];
         for (int i = 0; i < m; ++i) {
-          if (M.r_a[i] == b) for (int q = 0; q < 6; ++q) tv[q] += P.h * M.J[12 * i + q] * M.dlam[i];
-          if (M.r_b[i] == b) for (int q = 0; q < 6; ++q) tv[q] += P.h * M.J[12 * i + 6 + q] * M.dlam[i];
+          if (M.r_a[i] == b) v += P.h * M.J[12 * i + q] * M.dlam[i];
+          if (M.r_b[i] == b) v += P.h * M.J[12 * i + 6 + q] * M.dlam[i];
         }
-        minv6(M, b, tv, M.du + 6 * b);
+        M.kg[e] = v;
       }
       t.sync();
+      for (int b = t.rank(); b < nb; b += t.size()) minv6(M, b, M.kg + 6 * b, M.du + 6 * b);
+      t.sync();
       // step length: halve until the residual decreases by (1 - 1e-4 alpha), else the best trial
+      // (the full step is evaluated with the Newton rows, which are reused when it is accepted)
       double alpha = 1.0, best_a = 1.0, best_n = INFINITY;
+      bool first_ok = false;
       for (int ls = 0; ls <= P.ls_max; ++ls) {
         for (int i = t.rank(); i < 6 * nb; i += t.size()) M.ut[i] = M.u[i] + alpha * M.du[i];
         for (int i = t.rank(); i < m; i += t.size()) M.lamt[i] = M.lam[i] + alpha * M.dlam[i];
         t.sync();
         clamp_all(t, P, R, M, M.lamt);
-        double tn = evaluate(t, B, P, R, M, ctrl, M.ut, M.lamt, false);
+        double tn = evaluate(t, B, P, R, M, ctrl, M.ut, M.lamt, ls == 0);
         bool ok = tn <= (1.0 - 1e-4 * alpha) * nrm;
         if (tn < best_n || ok) { best_n = tn; best_a = alpha; }
-        if (ok) break;
+        if (ok) { first_ok = ls == 0; break; }
         alpha *= 0.5;
       }
-      for (int i = t.rank(); i < 6 * nb; i += t.size()) M.u[i] = M.u[i] + best_a * M.du[i];
-      for (int i = t.rank(); i < m; i += t.size()) M.lam[i] = M.lam[i] + best_a * M.dlam[i];
-      t.sync();
-      clamp_all(t, P, R, M, M.lam);
-      nrm = evaluate(t, B, P, R, M, ctrl, M.u, M.lam, true);
+      if (first_ok) {
+        for (int i = t.rank(); i < 6 * nb; i += t.size()) M.u[i] = M.ut[i];
+        for (int i = t.rank(); i < m; i += t.size()) M.lam[i] = M.lamt[i];
+        t.sync();
+        nrm = best_n;
+      } else {
+        for (int i = t.rank(); i < 6 * nb; i += t.size()) M.u[i] = M.u[i] + best_a * M.du[i];
+        for (int i = t.rank(); i < m; i += t.size()) M.lam[i] = M.lam[i] + best_a * M.dlam[i];
+        t.sync();
+        clamp_all(t, P, R, M, M.lam);
+        nrm = evaluate(t, B, P, R, M, ctrl, M.u, M.lam, true);
+      }
       iters = k;
       if (!isfinite(nrm)) { st |= ST_NONFINITE; break; }
       bool take = nrm <= P.tol || (k >= P.kmin && (!have || nrm < bn));
@@ -185,14 +196,14 @@ OST_HD void adjoint_solve(Team& t, const WorldRef& R, const WorldMem& M, const d
   }
   t.sync();
   lu_solve(t, R, M, wl, true);
-  for (int q = t.rank(); q < nb; q += t.size()) {
-    double s[6];
-    for (int k = 0; k < 6; ++k) s[k] = M.kg[6 * q + k];
+  for (int e = t.rank(); e < 6 * nb; e += t.size()) {
+    int q = e / 6, k = e - 6 * q;
+    double s = M.kg[e];
     for (int i = 0; i < m; ++i) {
-      if (M.r_a[i] == q) for (int k = 0; k < 6; ++k) s[k] += M.Y[12 * i + k] * wl[i];
-      if (M.r_b[i] == q) for (int k = 0; k < 6; ++k) s[k] += M.Y[12 * i + 6 + k] * wl[i];
+      if (M.r_a[i] == q) s += M.Y[12 * i + k] * wl[i];
+      if (M.r_b[i] == q) s += M.Y[12 * i + 6 + k] * wl[i];
     }
-    for (int k = 0; k < 6; ++k) wu[6 * q + k] = -s[k];
+    wu[e] = -s;
   }
   t.sync();
 }

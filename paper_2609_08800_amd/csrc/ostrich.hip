@@ -34,9 +34,22 @@ struct GpuTeam {
   __device__ int rank() const { return threadIdx.x; }
   __device__ int size() const { return blockDim.x; }
   __device__ void sync() const { __syncthreads(); }
+  // Sum over the team: a butterfly within each 64-lane wavefront, then the
+  // wavefront sums in wavefront order; every thread returns the same value.
+  __device__ double sum(double v, double* scratch) const {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    int nw = (blockDim.x + 63) >> 6;
+    if (nw == 1) return v;
+    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += scratch[i];
+    __syncthreads();
+    return s;
+  }
 };
 
-__global__ void k_forward(ost::Batch B, ost::Params P, ost::Caps caps, const double* q_prev, const double* u_prev,
+__global__ void __launch_bounds__(256) k_forward(ost::Batch B, ost::Params P, ost::Caps caps, const double* q_prev, const double* u_prev,
                           const double* lam_prev, const double* ctrl, double* q_next, double* u_next,
                           double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status, int32_t* iters,
                           double* resnorm, double* tape) {
@@ -50,7 +63,7 @@ __global__ void k_forward(ost::Batch B, ost::Params P, ost::Caps caps, const dou
   }
 }
 
-__global__ void k_adjoint(ost::Batch B, ost::Params P, ost::Caps caps, const double* q_prev, const double* u_prev,
+__global__ void __launch_bounds__(256) k_adjoint(ost::Batch B, ost::Params P, ost::Caps caps, const double* q_prev, const double* u_prev,
                           const double* ctrl, const double* u_next, const double* lam_next, const double* tape,
                           const double* gq_next, const double* gu_next, double* gq_prev, double* gu_prev,
                           double* g_ctrl, int refine) {
@@ -164,7 +177,7 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   c.nc = std::max(c.nc, 1);
   c.mr = std::max(c.mr, 1);
   c.ns = std::max(c.ns, 1);
-  int team = p->team > 0 ? p->team : 64;
+  int team = p->team > 0 ? p->team : 128;
   if (team != 64 && team != 128 && team != 256) return fail(OSTRICH_E_ARG, "team must be 64, 128 or 256");
   size_t lds = ost::world_lds_bytes(c, team);
   hipDeviceProp_t prop;

@@ -74,16 +74,6 @@ OST_HD void eval_row_group(const Batch& B, const Params& P, const WorldRef& R, c
                 kind == RK_CONTACT ? M.c_sf[c] : 1.0, kind == RK_CONTACT ? M.c_kind[c] : 0, in, r, J, D);
 }
 
-// Block reduction of one value per thread, summed in rank order.
-template <class Team> OST_HD double team_sum(Team& t, const WorldMem& M, double v) {
-  M.red[t.rank()] = v;
-  t.sync();
-  double s = 0.0;
-  for (int i = 0; i < t.size(); ++i) s += M.red[i];
-  t.sync();
-  return s;
-}
-
 // --------------------------------------------------------------------------
 // Prologue: bodies at q-, contact refresh (A1), rows, warm start, FB scales.
 // --------------------------------------------------------------------------
@@ -289,82 +279,52 @@ OST_HD double evaluate(Team& t, const Batch& B, const Params& P, const WorldRef&
     double target = kind == RK_SERVO ? servo_target(B, R, ctrl, M.r_idx[row]) : 0.0;
     GroupIn<double> in = group_in_lds(M, row, u, lam, target);
     double r[3], D[3];
-    eval_row_group<double>(B, P, R, M, row, in, r, M.J + 12 * row, D);
+    double* Jg = M.J + 12 * row;
+    eval_row_group<double>(B, P, R, M, row, in, r, Jg, D);
     for (int k = 0; k < n; ++k) {
       M.res[row + k] = r[k];
       M.D[row + k] = D[k];
     }
+    if (!want_G) continue;
     int a = M.r_a[row], b = M.r_b[row];
-    if (want_G) {
-      // generalized Jacobian of D r by forward duals over the group's local inputs
-      double Gu[3][12], Gl[3][3];
-      int nseed = 12 + n;
-      for (int sd = 0; sd < nseed; ++sd) {
-        if (sd >= 6 && sd < 12 && b < 0) {
-          for (int k = 0; k < n; ++k) Gu[k][sd] = 0.0;
-          continue;
-        }
-        dual ua[6], ub[6], lg[3];
-        for (int k = 0; k < 6; ++k) {
-          ua[k] = dual(u[6 * a + k], sd == k ? 1.0 : 0.0);
-          ub[k] = b >= 0 ? dual(u[6 * b + k], sd == 6 + k ? 1.0 : 0.0) : dual(0.0);
-        }
-        for (int k = 0; k < n; ++k) lg[k] = dual(lam[row + k], sd == 12 + k ? 1.0 : 0.0);
-        GroupIn<dual> ind;
-        ind.xa = v3<dual>{in.xa.x, in.xa.y, in.xa.z};
-        ind.xb = v3<dual>{in.xb.x, in.xb.y, in.xb.z};
-        for (int k = 0; k < 9; ++k) { ind.Ra.a[k] = in.Ra.a[k]; ind.Rb.a[k] = in.Rb.a[k]; }
-        ind.ua = ua;
-        ind.ub = b >= 0 ? ub : nullptr;
-        ind.lg = lg;
-        ind.target = dual(target);
-        ind.fr.n = v3<dual>{in.fr.n.x, in.fr.n.y, in.fr.n.z};
-        ind.fr.t1 = v3<dual>{in.fr.t1.x, in.fr.t1.y, in.fr.t1.z};
-        ind.fr.t2 = v3<dual>{in.fr.t2.x, in.fr.t2.y, in.fr.t2.z};
-        ind.fr.noff = dual(in.fr.noff);
-        ind.fr.la = v3<dual>{in.fr.la.x, in.fr.la.y, in.fr.la.z};
-        ind.fr.lb = v3<dual>{in.fr.lb.x, in.fr.lb.y, in.fr.lb.z};
-        dual rd[3], Jd[36];
-        double Dd[3];
-        eval_row_group<dual>(B, P, R, M, row, ind, rd, Jd, Dd);
-        for (int k = 0; k < n; ++k) {
-          double d = D[k] * rd[k].d;
-          if (sd < 12) Gu[k][sd] = d;
-          else Gl[k][sd - 12] = d;
-        }
+    double Gu[36], Gl[9];
+    if (kind == RK_CONTACT) {
+      int c = M.r_idx[row];
+      contact_G(P, in, b >= 0, M.c_r[c], M.c_mu[c], M.c_sn[c], M.c_sf[c], M.c_kind[c], Jg, D, Gu, Gl);
+    } else {  // joint rows: D r = c(q(u)) / h, so D dr/du = J; servo rows: dr/du = J, dr/dlambda = 1/k_p
+      for (int q = 0; q < 12; ++q) Gu[q] = Jg[q];
+      Gl[0] = kind == RK_SERVO ? 1.0 / B.joint_kp[R.j0 + M.r_idx[row]] : 0.0;
+    }
+    for (int k = 0; k < n; ++k) {
+      double* Y = M.Y + 12 * (row + k);
+      minv6(M, a, Gu + 12 * k, Y);
+      if (b >= 0) minv6(M, b, Gu + 12 * k + 6, Y + 6);
+      else for (int q = 6; q < 12; ++q) Y[q] = 0.0;
+      for (int q = 0; q < 3; ++q) M.Gl[3 * (row + k) + q] = q < n ? Gl[3 * k + q] : 0.0;
+      const double* Jr = Jg + 12 * k;
+      double MJ[12], s = 0.0;
+      minv6(M, a, Jr, MJ);
+      for (int q = 0; q < 6; ++q) s += Jr[q] * MJ[q];
+      if (b >= 0) {
+        minv6(M, b, Jr + 6, MJ + 6);
+        for (int q = 6; q < 12; ++q) s += Jr[q] * MJ[q];
       }
-      for (int k = 0; k < n; ++k) {
-        double* Y = M.Y + 12 * (row + k);
-        minv6(M, a, Gu[k], Y);
-        if (b >= 0) minv6(M, b, Gu[k] + 6, Y + 6);
-        else for (int q = 6; q < 12; ++q) Y[q] = 0.0;
-        for (int q = 0; q < 3; ++q) M.Gl[3 * (row + k) + q] = q < n ? Gl[k][q] : 0.0;
-        const double* Jr = M.J + 12 * (row + k);
-        double MJ[12], s = 0.0;
-        minv6(M, a, Jr, MJ);
-        for (int q = 0; q < 6; ++q) s += Jr[q] * MJ[q];
-        if (b >= 0) {
-          minv6(M, b, Jr + 6, MJ + 6);
-          for (int q = 6; q < 12; ++q) s += Jr[q] * MJ[q];
-        }
-        M.Abar[row + k] = s;
-      }
+      M.Abar[row + k] = s;
     }
   }
   t.sync();
-  // r_dyn per body; constraint forces summed over rows in order
-  for (int b = t.rank(); b < R.nb; b += t.size()) {
+  // r_dyn per (body, component); constraint forces summed over rows in order
+  for (int e = t.rank(); e < 6 * R.nb; e += t.size()) {
+    int b = e / 6, comp = e - 6 * b;
     double out[6];
     v3<double> tq{M.fext[6 * b + 3], M.fext[6 * b + 4], M.fext[6 * b + 5]};
     body_terms<double>(P, M.mass[b], M.inert + 3 * b, ldm(M.Rm + 9 * b), M.um + 6 * b, u + 6 * b, tq, out);
+    double v = out[comp];
     for (int i = 0; i < R.m; ++i) {
-      const double* Jr = M.J + 12 * i;
-      if (M.r_a[i] == b)
-        for (int k = 0; k < 6; ++k) out[k] -= P.h * (Jr[k] * lam[i]);
-      if (M.r_b[i] == b)
-        for (int k = 0; k < 6; ++k) out[k] -= P.h * (Jr[6 + k] * lam[i]);
+      if (M.r_a[i] == b) v -= P.h * (M.J[12 * i + comp] * lam[i]);
+      if (M.r_b[i] == b) v -= P.h * (M.J[12 * i + 6 + comp] * lam[i]);
     }
-    for (int k = 0; k < 6; ++k) M.rdyn[6 * b + k] = out[k];
+    M.rdyn[e] = v;
   }
   t.sync();
   double s = 0.0;
@@ -373,7 +333,7 @@ OST_HD double evaluate(Team& t, const Batch& B, const Params& P, const WorldRef&
     double v = i < 6 * R.nb ? M.rdyn[i] : M.res[i - 6 * R.nb];
     s += v * v;
   }
-  return ::sqrt(team_sum(t, M, s));
+  return ::sqrt(t.sum(s, M.red));
 }
 
 // Schur matrix of Eq. (12) with the generalized Jacobian: A = G_u M~^-1 J^T

@@ -214,6 +214,84 @@ OST_HD void eval_group(const Batch& B, const Params& P, const WorldRef& R, int k
   r[2] = vt[1] + W * in.lg[2];
 }
 
+// Generalized Jacobian of the scaled rows of a contact group (Newton matrix
+// rows): G_u = D dr/du (3 x 12) and G_lambda = D dr/d(lambda_n, lambda_t1,
+// lambda_t2) (3 x 3), in closed form.  J and D are the outputs of eval_group
+// at the same point.
+OST_HD void contact_G(const Params& P, const GroupIn<double>& in, int has_b, double r_prox, double mu, double sn,
+                      double sf, int ckind, const double* J, const double* D, double* Gu, double* Gl) {
+  const double h = P.h;
+  double zu[6] = {0, 0, 0, 0, 0, 0};
+  BodyIt<double> Ba = body_it(in.xa, in.ua, h);
+  BodyIt<double> Bb = body_it(in.xb, in.ub ? in.ub : zu, h);
+  const Frame<double>& F = in.fr;
+  // normal row: r_n = gap + B - S, S = sqrt(gap^2 + B^2 + eps^2), B = sigma_n lambda_n
+  double gap = dot(F.n, Ba.x + cay(Ba.k, F.la));
+  if (ckind == 2) gap -= dot(F.n, Bb.x + cay(Bb.k, F.lb));
+  else gap -= F.noff;
+  gap -= r_prox;
+  double Bq = sn * in.lg[0];
+  double S = ::sqrt(gap * gap + Bq * Bq + P.eps * P.eps);
+  double pa = 1.0 - gap / S, pb = 1.0 - Bq / S;
+  double c = pa / (pa > P.dg ? pa : P.dg);
+  for (int q = 0; q < 12; ++q) Gu[q] = c * J[q];
+  Gl[0] = D[0] * sn * pb;
+  Gl[1] = 0.0;
+  Gl[2] = 0.0;
+  // friction rows: r_f = v_t + W lambda_f
+  v3<double> lev_a = cay(Ba.k, F.la) - F.n * r_prox;
+  v3<double> pc = Ba.x + lev_a;
+  v3<double> lev_b = has_b ? pc - Bb.x : v3<double>{0, 0, 0};
+  double vt[2], dv[2][12];
+  for (int s = 0; s < 2; ++s) {
+    const v3<double>& t = s == 0 ? F.t1 : F.t2;
+    const double* Jr = J + 12 * (1 + s);
+    double v = 0.0;
+    for (int q = 0; q < 6; ++q) v += Jr[q] * in.ua[q];
+    if (has_b) for (int q = 0; q < 6; ++q) v += Jr[6 + q] * in.ub[q];
+    vt[s] = v;
+    // d v_t / du, including the dependence of the lever arms on the iterate
+    v3<double> twa = cross(t, Ba.w);
+    v3<double> gwa = cay_grad(Ba.k, F.la, twa) * (0.5 * h);
+    v3<double> dva = t, dwa = cross(lev_a, t) + gwa;
+    for (int q = 6; q < 12; ++q) dv[s][q] = 0.0;
+    if (has_b) {
+      v3<double> twb = cross(t, Bb.w);
+      dva = dva - twb * h;
+      dwa = dwa - cay_grad(Ba.k, F.la, twb) * (0.5 * h);
+      v3<double> dvb = twb * h - t, dwb = -cross(lev_b, t);
+      dv[s][6] = dvb.x; dv[s][7] = dvb.y; dv[s][8] = dvb.z;
+      dv[s][9] = dwb.x; dv[s][10] = dwb.y; dv[s][11] = dwb.z;
+    }
+    dv[s][0] = dva.x; dv[s][1] = dva.y; dv[s][2] = dva.z;
+    dv[s][3] = dwa.x; dv[s][4] = dwa.y; dv[s][5] = dwa.z;
+  }
+  const double ln = in.lg[0], l1 = in.lg[1], l2 = in.lg[2];
+  double s2 = vt[0] * vt[0] + vt[1] * vt[1] + P.eps * P.eps;
+  double lf = ::sqrt(l1 * l1 + l2 * l2 + P.eps * P.eps);
+  double beta = sf * (mu * ln - lf);
+  double Q = ::sqrt(s2 + beta * beta);
+  bool den_act = ln * mu >= P.dg;
+  double den = den_act ? ln * mu : P.dg;
+  double W = beta > 0.0 ? s2 / ((Q + beta) * den) : (Q - beta) / den;
+  double dW_ds2 = 0.5 / (Q * den);
+  double dW_db = -W / Q;
+  double dW_dln = dW_db * sf * mu + (den_act ? -W / den * mu : 0.0);
+  double dW_dl1 = dW_db * (-sf * l1 / lf), dW_dl2 = dW_db * (-sf * l2 / lf);
+  double lt[2] = {l1, l2};
+  for (int s = 0; s < 2; ++s) {
+    double* G = Gu + 12 * (1 + s);
+    for (int q = 0; q < 12; ++q) {
+      double dW = dW_ds2 * 2.0 * (vt[0] * dv[0][q] + vt[1] * dv[1][q]);
+      G[q] = dv[s][q] + lt[s] * dW;
+    }
+    double* Gs = Gl + 3 * (1 + s);
+    Gs[0] = lt[s] * dW_dln;
+    Gs[1] = (s == 0 ? W : 0.0) + lt[s] * dW_dl1;
+    Gs[2] = (s == 1 ? W : 0.0) + lt[s] * dW_dl2;
+  }
+}
+
 // Body-level terms of r_dyn = M~ (u - u-) - h f_ext - h J^T lambda (Eq. (10)),
 // without the constraint forces: mass, world inertia and f_ext at q-.
 template <class T>
