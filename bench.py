@@ -55,7 +55,7 @@ def _oracle_worker(args):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(T=20, worlds_per_core=4):
+def cpu_baseline(T=100, worlds_per_core=24):
     cores = max(1, min(16, os.cpu_count() or 1))
     jobs = [(1000 + i, worlds_per_core, T) for i in range(cores)]
     t0 = time.perf_counter()
@@ -72,14 +72,27 @@ def cpu_baseline(T=20, worlds_per_core=4):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--worlds", type=int, default=8192)
     ap.add_argument("--T", type=int, default=100)
     ap.add_argument("--ckpt", type=int, default=10)
     ap.add_argument("--team", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="skip the timed rollouts; run only the per-launch forward measurement "
+                         "(for hardware-counter runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain device copy of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        torch.cuda.synchronize()
+        y = x.clone()
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8}))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU kernel "
               "(worlds are independent; multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
@@ -108,18 +121,20 @@ def main():
         return sim.rollout(q0, u0, knots, basis, T, ckpt_every=args.ckpt, loss_body=lb, target=tg,
                            phase=3, workspace=ws)
 
+    if args.roofline_only:
+        args.steps, args.warmup = 1, 0
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
     torch.cuda.reset_peak_memory_stats(dev)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        out = one_step()
+        out = one_step() if not args.roofline_only else {"status": torch.zeros(W, dtype=torch.int32)}
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = dt / args.steps * 1e3
     world_steps = W * T * args.steps
-    value = world_steps / dt
+    value = world_steps / dt if not args.roofline_only else float("nan")
     status = out["status"].cpu().numpy()
     peak_gb = (torch.cuda.max_memory_allocated(dev)) / 1e9
 
@@ -157,7 +172,7 @@ def main():
     iters_all = np.array(iters_all)
     line = {
         "metric": "fwd+adjoint world-steps/s at 8192 worlds (FP64)",
-        "value": round(value, 2),
+        "value": round(value, 2) if not args.roofline_only else None,
         "unit": "world-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
