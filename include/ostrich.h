@@ -95,8 +95,17 @@ typedef struct {
   double delta0;       /* contact activation margin (m) */
   int32_t ls_max;      /* step-length halvings of the residual-decrease test */
   int32_t refine;      /* adjoint refinement sweeps toward the exact Jacobian (0: factor only) */
-  int32_t team;        /* threads per world (64, 128 or 256; 0 = 128) */
+  int32_t team;        /* threads per world (64, 128 or 256; 0 = 128) before autotuning */
+  int32_t schedule;    /* OSTRICH_SCHED_FIXED or OSTRICH_SCHED_BUCKETED */
 } ostrich_params;
+
+/* Launch schedules.  FIXED: every world in one launch shaped for the largest
+ * world of the batch.  BUCKETED: worlds grouped by row capacity (edges 16, 32,
+ * 64, 96, 128, 192, 256, 384), one launch per group, each shaped for its own
+ * worlds and tunable by ostrich_autotune.  The per-world arithmetic, and so
+ * every result, is identical under both. */
+#define OSTRICH_SCHED_FIXED 0
+#define OSTRICH_SCHED_BUCKETED 1
 
 typedef struct ostrich_ctx ostrich_ctx;
 
@@ -104,21 +113,41 @@ typedef struct ostrich_ctx ostrich_ctx;
 const char* ostrich_last_error(void);
 
 /* Create a context for a packed batch.  Reads body/joint/slot offsets,
- * joint_act and contact_cap to the host once to size the launches.  Fails
- * with OSTRICH_E_UNSUPPORTED if one world needs more on-chip memory than a
- * workgroup has. */
+ * joint_act and contact_cap to the host once to size the launches, and
+ * allocates its own small tables (per-bucket world lists, per-world tape
+ * offsets) and, for worlds whose Schur matrix does not fit on chip, one slice
+ * of device memory per resident workgroup.  Fails with OSTRICH_E_UNSUPPORTED
+ * if a world does not fit a workgroup even then. */
 int ostrich_ctx_create(const ostrich_batch* batch, const ostrich_params* params, ostrich_ctx** out);
 int ostrich_ctx_destroy(ostrich_ctx* ctx);
 
-/* Sizes the caller allocates: the per-step tape of all worlds (bytes), and
+/* Sizes the caller allocates: the per-step tape of all worlds (bytes; world w
+ * holds mr_w^2 + 4 doubles, mr_w its row capacity), and
  * the rollout workspace for horizon T and checkpoint interval k (0: keep every
  * state and tape; k >= 1: keep every k-th state and recompute segments). */
 size_t ostrich_tape_bytes(const ostrich_ctx* ctx);
 size_t ostrich_rollout_workspace_bytes(const ostrich_ctx* ctx, int32_t T, int32_t ckpt_every);
 
 /* Capacities used for the launches: bodies, joints, slots, contacts, rows
- * per world, and the LDS bytes of one world.  out[6]. */
+ * per world (maxima over the batch), and the largest LDS bytes of one
+ * workgroup.  out[6]. */
 int ostrich_ctx_caps(const ostrich_ctx* ctx, int64_t* out);
+
+/* Launch schedule: returns the number of buckets and, if out is not NULL,
+ * writes for each of the first max_buckets buckets six int32 (row capacity,
+ * number of worlds, threads per world, storage split: 0 on chip / 1 Schur
+ * matrix and Jacobian blocks in device memory, LDS bytes per workgroup,
+ * tuned flag). */
+int ostrich_ctx_schedule(const ostrich_ctx* ctx, int32_t* out, int32_t max_buckets);
+
+/* Autotuner of the batching system: times `reps` forward steps of every bucket
+ * from the given state (device pointers, as for ostrich_step_forward) under
+ * each candidate launch (64, 128 or 256 threads per world; Schur matrix on
+ * chip or in device memory) and keeps the fastest.  Synchronises the stream and
+ * allocates temporary device memory: a set-up call, not for the hot path.
+ * Results of later steps do not depend on the choice. */
+int ostrich_autotune(ostrich_ctx* ctx, const double* q, const double* u, const double* lam, const double* ctrl,
+                     int32_t reps, void* stream);
 
 /* One backward-Euler step of every world (Sec. III-A..C, A1-A8 of the hot
  * path): contact refresh at q-, fused Newton loop, best iterate, q+.
@@ -145,17 +174,22 @@ int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, const double* u
 #define OSTRICH_FORWARD 1
 #define OSTRICH_BACKWARD 2
 
-/* T-step rollout with controls from a spline basis (ctrl_k = basis[k,:] .
- * knots[c,:], basis [T*K] device, knots [NCTRL*K]) and the loss
- * |xy(loss_body) - target|^2 at step T (loss_body [W] int32, target [W*2]).
+/* T-step rollout (the optimisation workload of Sec. IV: a rollout, its loss
+ * and the adjoint of Sec. III-D over all steps) with controls from a spline
+ * basis (ctrl_k = basis[k,:] . knots[c,:], basis [T*K] device, knots
+ * [NCTRL*K]) and the loss |xy(loss_body) - target|^2 at step T (loss_body [W]
+ * int32, target [W*2]).
  * FORWARD writes loss [W], qT, uT and checkpoints into the workspace;
  * BACKWARD (after a FORWARD with the same arguments and workspace) recomputes
  * each segment from its checkpoint and runs the adjoint steps in reverse,
- * writing g_q0, g_u0, g_knots.  status_or [W] ORs the step status bits. */
+ * writing g_q0, g_u0, g_knots: the gradients of sum_w loss_grad[w] loss[w]
+ * (loss_grad [W] device, NULL for all ones).  status_or [W] ORs the step
+ * status bits. */
 int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0, const double* u0, const double* knots,
                     int32_t K, const double* basis, int32_t T, int32_t ckpt_every, const int32_t* loss_body,
-                    const double* target, double* loss, double* qT, double* uT, double* g_q0, double* g_u0,
-                    double* g_knots, void* workspace, size_t workspace_bytes, int32_t* status_or, void* stream);
+                    const double* target, const double* loss_grad, double* loss, double* qT, double* uT,
+                    double* g_q0, double* g_u0, double* g_knots, void* workspace, size_t workspace_bytes,
+                    int32_t* status_or, void* stream);
 
 /* Natural cubic spline basis on the host: B [T*K] (host), knots at
  * t_j = j T h / (K - 1), step k samples t = k h. */

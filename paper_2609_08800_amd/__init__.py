@@ -14,7 +14,7 @@ import numpy as np
 
 from . import _capi
 
-__all__ = ["build", "Simulator", "spline_basis", "OstrichError"]
+__all__ = ["build", "Simulator", "GraphRollout", "spline_basis", "OstrichError"]
 
 OstrichError = _capi.OstrichError
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -61,7 +61,7 @@ class Simulator:
     ctrl [NCTRL].
     """
 
-    def __init__(self, batch, params: dict, device="cuda", team: int = 0):
+    def __init__(self, batch, params: dict, device="cuda", team: int = 0, schedule: str = "bucketed"):
         torch = _torch()
         self.torch = torch
         self.device = torch.device(device)
@@ -87,7 +87,10 @@ class Simulator:
             ptrs[k] = t.data_ptr()
         self.body_off = self._dev["body_off"]
         self._cb = _capi.make_batch(self.W, ptrs, int(batch.hmap_n), float(batch.hmap_spacing))
-        self._cp = _capi.make_params(self.params, team)
+        if schedule not in ("fixed", "bucketed"):
+            raise OstrichError("schedule must be 'fixed' or 'bucketed'")
+        self._cp = _capi.make_params(self.params, team,
+                                     _capi.SCHED_FIXED if schedule == "fixed" else _capi.SCHED_BUCKETED)
         ctx = _capi.c_vp()
         torch.cuda.synchronize(self.device)
         _capi.check(self.lib.ostrich_ctx_create(self._cb, self._cp, ctx), "ostrich_ctx_create")
@@ -104,6 +107,25 @@ class Simulator:
                 self.ctx = None
         except Exception:
             pass
+
+    def schedule(self):
+        """Buckets of the launch schedule: list of dicts (rows, worlds, team, split, lds, tuned)."""
+        n = int(self.lib.ostrich_ctx_schedule(self.ctx, None, 0))
+        buf = np.zeros(6 * max(n, 1), dtype=np.int32)
+        self.lib.ostrich_ctx_schedule(self.ctx, buf.ctypes.data, n)
+        keys = ("rows", "worlds", "team", "split", "lds", "tuned")
+        return [dict(zip(keys, map(int, buf[6 * i:6 * i + 6]))) for i in range(n)]
+
+    def autotune(self, q, u, lam=None, ctrl=None, reps: int = 2, stream=None):
+        """Pick each bucket's launch by timing forward steps from (q, u, lam, ctrl)."""
+        q, u = self._f64(q, (self.NB, 7)), self._f64(u, (self.NB, 6))
+        lam = self._f64(lam) if lam is not None else self.torch.zeros(max(self.NL, 1), dtype=self.torch.float64,
+                                                                      device=self.device)
+        ctrl = self._ctrl(ctrl)
+        _capi.check(self.lib.ostrich_autotune(self.ctx, q.data_ptr(), u.data_ptr(), lam.data_ptr(),
+                                              ctrl.data_ptr(), int(reps), self._stream(stream)),
+                    "ostrich_autotune")
+        return self.schedule()
 
     # ----------------------------------------------------------------- helpers
     def _stream(self, stream=None):
@@ -187,8 +209,9 @@ class Simulator:
         return self.torch.empty((n + 7) // 8, dtype=self.torch.float64, device=self.device)
 
     def rollout(self, q0, u0, knots, basis, T, ckpt_every=10, loss_body=None, target=None, phase=3,
-                workspace=None, grads=True, stream=None):
-        """T-step rollout with the final-xy loss; FORWARD (1), BACKWARD (2) or both (3)."""
+                workspace=None, grads=True, loss_grad=None, stream=None):
+        """T-step rollout with the final-xy loss; FORWARD (1), BACKWARD (2) or both (3).
+        Gradients are those of sum_w loss_grad[w] loss[w] (all ones by default)."""
         torch = self.torch
         q0, u0 = self._f64(q0, (self.NB, 7)), self._f64(u0, (self.NB, 6))
         K = 0
@@ -197,8 +220,12 @@ class Simulator:
             K = knots.numel() // self.NCTRL
             knots = knots.reshape(self.NCTRL, K)
             basis = self._f64(basis, (T, K))
-        lb = torch.as_tensor(np.asarray(loss_body, dtype=np.int32), device=self.device).contiguous()
+        if torch.is_tensor(loss_body):
+            lb = loss_body.to(self.device, torch.int32).contiguous()
+        else:
+            lb = torch.as_tensor(np.asarray(loss_body, dtype=np.int32), device=self.device).contiguous()
         tg = self._f64(target, (self.W, 2))
+        lg = self._f64(loss_grad, (self.W,)) if loss_grad is not None else None
         ws = workspace if workspace is not None else self.new_workspace(T, ckpt_every)
         loss = torch.empty(self.W, dtype=torch.float64, device=self.device)
         qT, uT, _ = self.empty_state()
@@ -209,7 +236,52 @@ class Simulator:
         rc = self.lib.ostrich_rollout(
             self.ctx, int(phase), q0.data_ptr(), u0.data_ptr(), self._p(knots) if self.NCTRL else None, int(K),
             self._p(basis) if self.NCTRL else None, int(T), int(ckpt_every), lb.data_ptr(), tg.data_ptr(),
-            loss.data_ptr(), qT.data_ptr(), uT.data_ptr(), self._p(g_q0), self._p(g_u0), self._p(g_knots),
+            self._p(lg), loss.data_ptr(), qT.data_ptr(), uT.data_ptr(), self._p(g_q0), self._p(g_u0), self._p(g_knots),
             ws.data_ptr(), ws.numel() * 8, st.data_ptr(), self._stream(stream))
         _capi.check(rc, "ostrich_rollout")
         return dict(loss=loss, qT=qT, uT=uT, g_q0=g_q0, g_u0=g_u0, g_knots=g_knots, status=st, workspace=ws)
+
+
+class GraphRollout:
+    """A rollout with its adjoint (both phases of ``Simulator.rollout``) captured
+    once into a HIP graph and replayed: one graph launch per rollout instead of
+    one host launch per kernel.  Inputs live in static device tensors that
+    ``replay`` overwrites; outputs are the same tensors on every replay.
+    """
+
+    def __init__(self, sim: "Simulator", q0, u0, knots, basis, T: int, ckpt_every: int, loss_body, target,
+                 warmup: int = 1):
+        torch = sim.torch
+        self.sim = sim
+        self.q0 = sim._f64(q0, (sim.NB, 7)).clone()
+        self.u0 = sim._f64(u0, (sim.NB, 6)).clone()
+        self.knots = sim._f64(knots).clone() if sim.NCTRL else None
+        self.basis = sim._f64(basis).clone() if sim.NCTRL else None
+        self.lb = torch.as_tensor(np.asarray(loss_body, dtype=np.int32), device=sim.device).contiguous()
+        self.tg = sim._f64(target, (sim.W, 2)).clone()
+        self.ws = sim.new_workspace(T, ckpt_every)
+        self.T, self.ck = int(T), int(ckpt_every)
+        side = torch.cuda.Stream(device=sim.device)
+        side.wait_stream(torch.cuda.current_stream(sim.device))
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                self._run()
+        torch.cuda.current_stream(sim.device).wait_stream(side)
+        torch.cuda.synchronize(sim.device)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.out = self._run()
+
+    def _run(self):
+        return self.sim.rollout(self.q0, self.u0, self.knots, self.basis, self.T, ckpt_every=self.ck,
+                                loss_body=self.lb, target=self.tg, phase=3, workspace=self.ws)
+
+    def replay(self, knots=None, q0=None, u0=None):
+        if knots is not None:
+            self.knots.copy_(self.sim._f64(knots).reshape(self.knots.shape))
+        if q0 is not None:
+            self.q0.copy_(self.sim._f64(q0, (self.sim.NB, 7)))
+        if u0 is not None:
+            self.u0.copy_(self.sim._f64(u0, (self.sim.NB, 6)))
+        self.graph.replay()
+        return self.out

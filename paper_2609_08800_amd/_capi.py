@@ -19,6 +19,7 @@ c_size = ctypes.c_size_t
 E_ARG, E_HIP, E_WORKSPACE, E_UNSUPPORTED = -1, -2, -3, -4
 ST_CONVERGED, ST_BUDGET, ST_NONFINITE, ST_REGULARIZED, ST_OVERFLOW = 1, 2, 4, 8, 16
 FORWARD, BACKWARD = 1, 2
+SCHED_FIXED, SCHED_BUCKETED = 0, 1
 
 
 class OstrichBatch(ctypes.Structure):
@@ -33,7 +34,7 @@ class OstrichBatch(ctypes.Structure):
 class OstrichParams(ctypes.Structure):
     _fields_ = [("h", c_dbl), ("gravity", c_dbl * 3), ("tol", c_dbl), ("k_max", c_int), ("k_min", c_int),
                 ("eps", c_dbl), ("delta_g", c_dbl), ("delta_reg", c_dbl), ("delta0", c_dbl),
-                ("ls_max", c_int), ("refine", c_int), ("team", c_int)]
+                ("ls_max", c_int), ("refine", c_int), ("team", c_int), ("schedule", c_int)]
 
 
 BATCH_ARRAYS = ("body_off", "body_mass", "body_inertia", "joint_off", "joint_body", "joint_frame", "joint_act",
@@ -72,8 +73,12 @@ def load() -> ctypes.CDLL:
     L.ostrich_step_adjoint.argtypes = [c_vp] + [c_vp] * 11 + [c_int, c_vp]
     L.ostrich_step_adjoint.restype = c_int
     L.ostrich_rollout.argtypes = ([c_vp, c_int, c_vp, c_vp, c_vp, c_int, c_vp, c_int, c_int, c_vp, c_vp, c_vp,
-                                   c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp, c_vp])
+                                   c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp, c_vp])
     L.ostrich_rollout.restype = c_int
+    L.ostrich_ctx_schedule.argtypes = [c_vp, c_vp, c_int]
+    L.ostrich_ctx_schedule.restype = c_int
+    L.ostrich_autotune.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp, c_int, c_vp]
+    L.ostrich_autotune.restype = c_int
     L.ostrich_spline_basis.argtypes = [c_int, c_int, c_dbl, c_vp]
     L.ostrich_spline_basis.restype = c_int
     _lib = L
@@ -86,7 +91,7 @@ def check(rc: int, what: str):
         raise OstrichError(f"{what} failed ({rc}): {msg}")
 
 
-def make_params(p: dict, team: int = 0) -> OstrichParams:
+def make_params(p: dict, team: int = 0, schedule: int = SCHED_BUCKETED) -> OstrichParams:
     cp = OstrichParams()
     cp.h = float(p["h"])
     for k in range(3):
@@ -101,6 +106,7 @@ def make_params(p: dict, team: int = 0) -> OstrichParams:
     cp.ls_max = int(p.get("ls_max", 0))
     cp.refine = int(p.get("refine", 8))
     cp.team = int(team)
+    cp.schedule = int(schedule)
     return cp
 
 

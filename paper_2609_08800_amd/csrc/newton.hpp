@@ -7,8 +7,23 @@
 namespace ost {
 
 // Tape of one world-step: the LU factor of the Schur matrix at the returned
-// iterate (mr x mr, row stride m), then (regularisation used, m, valid).
-OST_HD size_t tape_doubles(const Caps& c) { return (size_t)c.mr * c.mr + 4; }
+// iterate (band entries of an m x m array with row stride m, inside the
+// world's mr_w x mr_w slice), then (regularisation used, m, valid, band).
+// World w's tape starts at tape_off[w]; tape_off[w+1] - tape_off[w] = mr_w^2 + 4.
+OST_HD size_t tape_doubles_world(int mr_w) { return (size_t)mr_w * mr_w + 4; }
+
+// Visit the band entries (|i - j| <= bw) of an m x m row-major array.
+template <class Team, class F> OST_HD void for_band(Team& t, int m, int bw, F f) {
+  const int wd = 2 * bw + 1;
+  if (wd >= m) {
+    for (int e = t.rank(); e < m * m; e += t.size()) f(e);
+  } else {
+    for (int e = t.rank(); e < m * wd; e += t.size()) {
+      int i = e / wd, j = i - bw + (e - i * wd);
+      if (j >= 0 && j < m) f(i * m + j);
+    }
+  }
+}
 
 // FB argument scales sigma_n = h^2 Abar_nn, sigma_f = h (Abar_t1 + Abar_t2)/2
 // from the Delassus diagonal at the warm start u = u-.
@@ -42,7 +57,8 @@ template <class Team>
 OST_HD void forward_world(Team& t, const Batch& B, const Params& P, const Caps& caps, int w, const double* q_prev,
                           const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
                           double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
-                          int32_t* iters_out, double* resnorm, double* tape, WorldMem& M) {
+                          int32_t* iters_out, double* resnorm, double* tape, const int64_t* tape_off,
+                          WorldMem& M) {
   WorldRef R = world_ref(B, w);
   prologue(t, B, P, R, q_prev, u_prev, ctrl, lam_prev, M);
   clamp_all(t, P, R, M, M.lam);
@@ -129,14 +145,14 @@ OST_HD void forward_world(Team& t, const Batch& B, const Params& P, const Caps& 
     double dreg = P.dreg;
     int fst = 0;
     bool ok = factor(t, P, R, M, false, &dreg, &fst);
-    double* tw = tape + (size_t)w * tape_doubles(caps);
-    for (int e = t.rank(); e < m * m; e += t.size()) tw[e] = M.A[e];
+    double* tw = tape + tape_off[w];
+    for_band(t, m, R.bw, [&](int e) { tw[e] = M.A[e]; });
     if (t.rank() == 0) {
-      size_t o = (size_t)caps.mr * caps.mr;
-      tw[o] = dreg;
-      tw[o + 1] = m;
-      tw[o + 2] = ok ? 1.0 : 0.0;
-      tw[o + 3] = 0.0;
+      double* tr = tape + tape_off[w + 1] - 4;
+      tr[0] = dreg;
+      tr[1] = m;
+      tr[2] = ok ? 1.0 : 0.0;
+      tr[3] = R.bw;
     }
   }
   // q+ = q- + h G(q-) u* with the quaternion renormalised (Eq. (1))
@@ -223,8 +239,9 @@ OST_HD void dual_pose(const double* q, int seeded, int comp, v3<dual>& x, m3<dua
 template <class Team>
 OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& caps, int w, const double* q_prev,
                           const double* u_prev, const double* ctrl, const double* u_next, const double* lam_next,
-                          const double* tape, const double* gq_next, const double* gu_next, double* gq_prev,
-                          double* gu_prev, double* g_ctrl, int refine, WorldMem& M) {
+                          const double* tape, const int64_t* tape_off, const double* gq_next,
+                          const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl, int refine,
+                          WorldMem& M) {
   WorldRef R = world_ref(B, w);
   const double h = P.h;
   prologue(t, B, P, R, q_prev, u_prev, ctrl, lam_next, M);
@@ -233,9 +250,10 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
   for (int i = t.rank(); i < 6 * nb; i += t.size()) M.u[i] = u_next[6 * R.b0 + i];
   t.sync();
   evaluate(t, B, P, R, M, ctrl, M.u, M.lam, true);
-  const double* tw = tape + (size_t)w * tape_doubles(caps);
-  if (tw[(size_t)caps.mr * caps.mr + 2] == 1.0 && (int)tw[(size_t)caps.mr * caps.mr + 1] == m) {
-    for (int e = t.rank(); e < m * m; e += t.size()) M.A[e] = tw[e];
+  const double* tw = tape + tape_off[w];
+  const double* tr = tape + tape_off[w + 1] - 4;
+  if (tr[2] == 1.0 && (int)tr[1] == m && (int)tr[3] == R.bw) {
+    for_band(t, m, R.bw, [&](int e) { M.A[e] = tw[e]; });
     t.sync();
   } else {  // no usable stored factor: factor here
     double dreg;
@@ -292,7 +310,8 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
           ua[k] = dual(M.u[6 * a + k], (a == beta && k == comp) ? 1.0 : 0.0);
           ub[k] = c >= 0 ? dual(M.u[6 * c + k], (c == beta && k == comp) ? 1.0 : 0.0) : dual(0.0);
         }
-        for (int k = 0; k < n; ++k) lg[k] = dual(M.lam[row + k]);
+        #pragma unroll
+        for (int k = 0; k < 3; ++k) if (k < n) lg[k] = dual(M.lam[row + k]);
         GroupIn<dual> ind;
         ind.xa = v3<dual>{in.xa.x, in.xa.y, in.xa.z};
         ind.xb = v3<dual>{in.xb.x, in.xb.y, in.xb.z};
@@ -310,7 +329,8 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
         dual rd[3], Jd[36];
         double Dd[3];
         eval_row_group<dual>(B, P, R, M, row, ind, rd, Jd, Dd);
-        for (int k = 0; k < n; ++k) {
+        #pragma unroll
+        for (int k = 0; k < 3; ++k) if (k < n) {
           double jw = 0.0;
           for (int q = 0; q < 6; ++q) jw += Jd[12 * k + q].d * wu[6 * a + q];
           if (c >= 0) for (int q = 0; q < 6; ++q) jw += Jd[12 * k + 6 + q].d * wu[6 * c + q];
@@ -409,7 +429,8 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
         ua[k] = dual(M.u[6 * a + k]);
         ub[k] = c >= 0 ? dual(M.u[6 * c + k]) : dual(0.0);
       }
-      for (int k = 0; k < n; ++k) lg[k] = dual(M.lam[row + k]);
+      #pragma unroll
+      for (int k = 0; k < 3; ++k) if (k < n) lg[k] = dual(M.lam[row + k]);
       ind.ua = ua;
       ind.ub = c >= 0 ? ub : nullptr;
       ind.lg = lg;
@@ -429,7 +450,8 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
       dual rd[3], Jd[36];
       double Dd[3];
       eval_row_group<dual>(B, P, R, M, row, ind, rd, Jd, Dd);
-      for (int k = 0; k < n; ++k) {
+      #pragma unroll
+      for (int k = 0; k < 3; ++k) if (k < n) {
         s += wl[row + k] * M.D[row + k] * rd[k].d;
         double jw = 0.0;
         for (int q = 0; q < 6; ++q) jw += Jd[12 * k + q].d * wu[6 * a + q];

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -47,32 +48,71 @@ struct GpuTeam {
     __syncthreads();
     return s;
   }
+  // Butterfly sum of the values held by the first wavefront (threads 0..63),
+  // broadcast to the team: the result does not depend on the team size.
+  __device__ double sum64(double v, double* scratch) const {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (blockDim.x == 64) return v;
+    if (threadIdx.x == 0) scratch[0] = v;
+    __syncthreads();
+    double r = scratch[0];
+    __syncthreads();
+    return r;
+  }
+  __device__ int imax(int v, double* scratch) const {
+    for (int off = 32; off > 0; off >>= 1) {
+      int o = __shfl_xor(v, off, 64);
+      v = o > v ? o : v;
+    }
+    int nw = (blockDim.x + 63) >> 6;
+    if (nw == 1) return v;
+    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = (double)v;
+    __syncthreads();
+    int r = v;
+    for (int i = 0; i < nw; ++i) r = (int)scratch[i] > r ? (int)scratch[i] : r;
+    __syncthreads();
+    return r;
+  }
 };
 
-__global__ void __launch_bounds__(256) k_forward(ost::Batch B, ost::Params P, ost::Caps caps, const double* q_prev, const double* u_prev,
-                          const double* lam_prev, const double* ctrl, double* q_next, double* u_next,
-                          double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status, int32_t* iters,
-                          double* resnorm, double* tape) {
+// Launch shape of one bucket of worlds: the worlds of the list are taken by
+// workgroups in turn (persistent when the grid is smaller than the list).
+struct Launch {
+  const int32_t* wlist;  // world ids of the bucket
+  int nlist;
+  int split;             // ost::SPLIT_LDS or ost::SPLIT_GLOBAL
+  double* gscr;          // SPLIT_GLOBAL: per-workgroup slices of gstride doubles
+  size_t gstride;
+};
+
+__global__ void __launch_bounds__(256) k_forward(ost::Batch B, ost::Params P, ost::Caps caps, Launch L,
+                                                 const double* q_prev, const double* u_prev, const double* lam_prev,
+                                                 const double* ctrl, double* q_next, double* u_next,
+                                                 double* lam_next, int32_t* act_slot, int32_t* n_act,
+                                                 int32_t* status, int32_t* iters, double* resnorm, double* tape,
+                                                 const int64_t* tape_off) {
   extern __shared__ __align__(16) char smem[];
   GpuTeam t;
-  ost::WorldMem M = ost::carve(smem, caps, blockDim.x);
-  for (int w = blockIdx.x; w < B.n_worlds; w += gridDim.x) {
-    ost::forward_world(t, B, P, caps, w, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot,
-                       n_act, status, iters, resnorm, tape, M);
+  ost::WorldMem M = ost::carve(smem, caps, blockDim.x, L.split, L.gscr ? L.gscr + blockIdx.x * L.gstride : nullptr);
+  for (int i = blockIdx.x; i < L.nlist; i += gridDim.x) {
+    ost::forward_world(t, B, P, caps, L.wlist[i], q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
+                       act_slot, n_act, status, iters, resnorm, tape, tape_off, M);
     __syncthreads();
   }
 }
 
-__global__ void __launch_bounds__(256) k_adjoint(ost::Batch B, ost::Params P, ost::Caps caps, const double* q_prev, const double* u_prev,
-                          const double* ctrl, const double* u_next, const double* lam_next, const double* tape,
-                          const double* gq_next, const double* gu_next, double* gq_prev, double* gu_prev,
-                          double* g_ctrl, int refine) {
+__global__ void __launch_bounds__(256) k_adjoint(ost::Batch B, ost::Params P, ost::Caps caps, Launch L,
+                                                 const double* q_prev, const double* u_prev, const double* ctrl,
+                                                 const double* u_next, const double* lam_next, const double* tape,
+                                                 const int64_t* tape_off, const double* gq_next,
+                                                 const double* gu_next, double* gq_prev, double* gu_prev,
+                                                 double* g_ctrl, int refine) {
   extern __shared__ __align__(16) char smem[];
   GpuTeam t;
-  ost::WorldMem M = ost::carve(smem, caps, blockDim.x);
-  for (int w = blockIdx.x; w < B.n_worlds; w += gridDim.x) {
-    ost::adjoint_world(t, B, P, caps, w, q_prev, u_prev, ctrl, u_next, lam_next, tape, gq_next, gu_next, gq_prev,
-                       gu_prev, g_ctrl, refine, M);
+  ost::WorldMem M = ost::carve(smem, caps, blockDim.x, L.split, L.gscr ? L.gscr + blockIdx.x * L.gstride : nullptr);
+  for (int i = blockIdx.x; i < L.nlist; i += gridDim.x) {
+    ost::adjoint_world(t, B, P, caps, L.wlist[i], q_prev, u_prev, ctrl, u_next, lam_next, tape, tape_off,
+                       gq_next, gu_next, gq_prev, gu_prev, g_ctrl, refine, M);
     __syncthreads();
   }
 }
@@ -94,15 +134,16 @@ __global__ void k_fill(double* p, long n, double v) {
 
 // loss |xy(loss_body) - target|^2 and its cotangent on q_T
 __global__ void k_loss(const int32_t* body_off, int W, const double* qT, const int32_t* loss_body,
-                       const double* target, double* loss, double* gq) {
+                       const double* target, const double* loss_grad, double* loss, double* gq) {
   int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
   int b = body_off[w] + loss_body[w];
   double dx = qT[7 * b] - target[2 * w], dy = qT[7 * b + 1] - target[2 * w + 1];
   if (loss) loss[w] = dx * dx + dy * dy;
   if (gq) {
-    gq[7 * b] = 2.0 * dx;
-    gq[7 * b + 1] = 2.0 * dy;
+    double g = loss_grad ? loss_grad[w] : 1.0;
+    gq[7 * b] = 2.0 * dx * g;
+    gq[7 * b + 1] = 2.0 * dy * g;
   }
 }
 
@@ -127,30 +168,116 @@ inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
 
+namespace {
+// One bucket of worlds with similar row capacity, and its launch choice.
+struct Bucket {
+  ost::Caps caps{0, 0, 0, 0, 0, 0};
+  std::vector<int32_t> worlds;  // host copy of the world ids
+  int32_t* d_worlds = nullptr;
+  int team = 128;
+  int split = ost::SPLIT_LDS;
+  size_t lds = 0;
+  int slots = 0;                // SPLIT_GLOBAL: workgroups of the persistent grid
+  double* gscr = nullptr;
+  size_t gstride = 0;
+  bool tuned = false;
+};
+
+// Row capacity edges of the buckets: a world with row cap mr goes to the first
+// bucket whose edge is >= mr.
+const int kEdges[] = {16, 32, 64, 96, 128, 192, 256, 384, 1 << 30};
+}  // namespace
+
 struct ostrich_ctx {
   ost::Batch B;
   ost::Params P;
-  ost::Caps caps;
+  ost::Caps caps;  // maxima over the batch
   int team;
-  size_t lds;
+  int schedule;
+  size_t lds_limit;
+  int n_cu;
   int W, NB, NL, NS, NCTRL;
   int refine;
   std::vector<int32_t> body_off_h;
+  std::vector<ost::Caps> wcaps;  // per world
+  std::vector<Bucket> buckets;
+  int64_t* d_tape_off = nullptr;
+  size_t tape_total = 0;  // doubles
+  ~ostrich_ctx() {
+    for (auto& b : buckets) {
+      if (b.d_worlds) (void)hipFree(b.d_worlds);
+      if (b.gscr) (void)hipFree(b.gscr);
+    }
+    if (d_tape_off) (void)hipFree(d_tape_off);
+  }
 };
 
 extern "C" const char* ostrich_last_error(void) { return g_err.c_str(); }
 
 static bool is_ptr_ok(const void* p) { return p != nullptr; }
 
+static ost::Caps caps_max(const ost::Caps& a, const ost::Caps& b) {
+  return ost::Caps{std::max(a.nb, b.nb), std::max(a.nj, b.nj), std::max(a.ns, b.ns),
+                   std::max(a.nc, b.nc), std::max(a.mr, b.mr), std::max(a.nsv, b.nsv)};
+}
+
+static bool team_ok(int t) { return t == 64 || t == 128 || t == 256; }
+
+// Decide the storage split of a bucket for a team size and (re)allocate its
+// device scratch; fails if the world does not fit either way.
+static int configure_bucket(ostrich_ctx* ctx, Bucket& bk, int team, int split) {
+  size_t lds = ost::world_lds_bytes(bk.caps, team, split);
+  if (lds > ctx->lds_limit) return fail(OSTRICH_E_UNSUPPORTED, "bucket does not fit in LDS");
+  bk.team = team;
+  bk.split = split;
+  bk.lds = lds;
+  if (split == ost::SPLIT_GLOBAL) {
+    size_t per_cu = std::max<size_t>(1, ctx->lds_limit / std::max<size_t>(lds, 1));
+    per_cu = std::min<size_t>(per_cu, 2048 / team);
+    int slots = (int)std::min<size_t>(bk.worlds.size(), per_cu * ctx->n_cu);
+    size_t stride = (ost::world_glob_doubles(bk.caps, split) + 31) & ~size_t(31);
+    if (!bk.gscr || slots * stride > (size_t)bk.slots * bk.gstride) {
+      if (bk.gscr) HIP_OK(hipFree(bk.gscr));
+      bk.gscr = nullptr;
+      HIP_OK(hipMalloc(&bk.gscr, sizeof(double) * stride * slots));
+    }
+    bk.slots = slots;
+    bk.gstride = stride;
+  }
+  return 0;
+}
+
+// Default launch choice: the requested team (or 128), on chip when it fits.
+static int default_config(ostrich_ctx* ctx, Bucket& bk) {
+  int team = ctx->team;
+  if (ost::world_lds_bytes(bk.caps, team, ost::SPLIT_LDS) <= ctx->lds_limit)
+    return configure_bucket(ctx, bk, team, ost::SPLIT_LDS);
+  return configure_bucket(ctx, bk, team, ost::SPLIT_GLOBAL);
+}
+
+static Launch launch_of(const Bucket& bk) {
+  return Launch{bk.d_worlds, (int)bk.worlds.size(), bk.split, bk.split == ost::SPLIT_GLOBAL ? bk.gscr : nullptr,
+                bk.gstride};
+}
+
+static int grid_of(const Bucket& bk) {
+  int n = (int)bk.worlds.size();
+  return bk.split == ost::SPLIT_GLOBAL ? std::max(1, std::min(n, bk.slots)) : n;
+}
+
 extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* p, ostrich_ctx** out) {
   if (!b || !p || !out) return fail(OSTRICH_E_ARG, "null argument");
   if (b->n_worlds < 1) return fail(OSTRICH_E_ARG, "n_worlds must be >= 1");
   if (!(p->h > 0.0) || p->k_max < 0 || p->k_min < 0 || p->ls_max < 0 || !(p->tol >= 0.0) || !(p->eps > 0.0))
     return fail(OSTRICH_E_ARG, "invalid solver parameters");
+  if (p->schedule != OSTRICH_SCHED_FIXED && p->schedule != OSTRICH_SCHED_BUCKETED)
+    return fail(OSTRICH_E_ARG, "schedule must be OSTRICH_SCHED_FIXED or OSTRICH_SCHED_BUCKETED");
   const void* need[] = {b->body_off, b->body_mass, b->body_inertia, b->joint_off, b->ctrl_off, b->slot_off,
                         b->obs_off, b->lam_off, b->contact_cap};
   for (const void* q : need)
     if (!is_ptr_ok(q)) return fail(OSTRICH_E_ARG, "null array in batch");
+  int team = p->team > 0 ? p->team : 128;
+  if (!team_ok(team)) return fail(OSTRICH_E_ARG, "team must be 64, 128 or 256");
   const int W = b->n_worlds;
   std::vector<int32_t> bo(W + 1), jo(W + 1), so(W + 1), co(W + 1), lo(W + 1), cap(W);
   HIP_OK(hipMemcpy(bo.data(), b->body_off, (W + 1) * 4, hipMemcpyDeviceToHost));
@@ -161,35 +288,30 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   HIP_OK(hipMemcpy(cap.data(), b->contact_cap, W * 4, hipMemcpyDeviceToHost));
   std::vector<int32_t> act(std::max(jo[W], 1), 0);
   if (jo[W] > 0) HIP_OK(hipMemcpy(act.data(), b->joint_act, jo[W] * 4, hipMemcpyDeviceToHost));
+  std::unique_ptr<ostrich_ctx> ctx(new ostrich_ctx());
+  ctx->wcaps.resize(W);
   ost::Caps c{0, 0, 0, 0, 0, 0};
+  std::vector<int64_t> toff(W + 1, 0);
   for (int w = 0; w < W; ++w) {
     int nb = bo[w + 1] - bo[w], nj = jo[w + 1] - jo[w], ns = so[w + 1] - so[w];
-    if (nb < 1 || nj < 0 || ns < 0 || cap[w] < 0) return fail(OSTRICH_E_ARG, "malformed offsets");
+    if (nb < 1 || nj < 0 || ns < 0 || cap[w] < 0 || co[w + 1] < co[w] || lo[w + 1] < lo[w])
+      return fail(OSTRICH_E_ARG, "malformed offsets");
     int nsv = 0;
     for (int j = jo[w]; j < jo[w + 1]; ++j) nsv += (act[j] == 2 || act[j] == 3);
-    c.nb = std::max(c.nb, nb);
-    c.nj = std::max(c.nj, nj);
-    c.ns = std::max(c.ns, ns);
-    c.nc = std::max(c.nc, std::min(cap[w], ns));
-    c.nsv = std::max(c.nsv, nsv);
-    c.mr = std::max(c.mr, 5 * nj + nsv + 3 * std::min(cap[w], ns));
+    int nc = std::min(cap[w], ns);
+    ost::Caps wc{nb, nj, std::max(ns, 1), std::max(nc, 1), std::max(5 * nj + nsv + 3 * nc, 1), nsv};
+    ctx->wcaps[w] = wc;
+    c = caps_max(c, wc);
+    toff[w + 1] = toff[w] + (int64_t)ost::tape_doubles_world(wc.mr);
   }
-  c.nc = std::max(c.nc, 1);
-  c.mr = std::max(c.mr, 1);
-  c.ns = std::max(c.ns, 1);
-  int team = p->team > 0 ? p->team : 128;
-  if (team != 64 && team != 128 && team != 256) return fail(OSTRICH_E_ARG, "team must be 64, 128 or 256");
-  size_t lds = ost::world_lds_bytes(c, team);
   hipDeviceProp_t prop;
   int dev = 0;
   HIP_OK(hipGetDevice(&dev));
   HIP_OK(hipGetDeviceProperties(&prop, dev));
-  if (lds > (size_t)prop.sharedMemPerBlock)
-    return fail(OSTRICH_E_UNSUPPORTED, "a world needs " + std::to_string(lds) + " B of LDS, more than " +
-                                           std::to_string(prop.sharedMemPerBlock));
-  HIP_OK(hipFuncSetAttribute((const void*)k_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  HIP_OK(hipFuncSetAttribute((const void*)k_adjoint, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  ostrich_ctx* ctx = new ostrich_ctx();
+  ctx->lds_limit = prop.sharedMemPerBlock;
+  ctx->n_cu = std::max(1, prop.multiProcessorCount);
+  for (auto f : {(const void*)k_forward, (const void*)k_adjoint})
+    HIP_OK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctx->lds_limit));
   std::memcpy(&ctx->B, b, sizeof(ost::Batch));
   static_assert(sizeof(ost::Batch) == sizeof(ostrich_batch), "batch layouts differ");
   ctx->P.h = p->h;
@@ -206,14 +328,41 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   ctx->refine = p->refine;
   ctx->caps = c;
   ctx->team = team;
-  ctx->lds = lds;
+  ctx->schedule = p->schedule;
   ctx->W = W;
   ctx->NB = bo[W];
   ctx->NL = lo[W];
   ctx->NS = so[W];
   ctx->NCTRL = co[W];
   ctx->body_off_h = bo;
-  *out = ctx;
+  ctx->tape_total = (size_t)toff[W];
+  // buckets: one for the fixed schedule, else by row capacity
+  if (p->schedule == OSTRICH_SCHED_FIXED) {
+    ctx->buckets.resize(1);
+    for (int w = 0; w < W; ++w) ctx->buckets[0].worlds.push_back(w);
+    ctx->buckets[0].caps = c;
+  } else {
+    const int ne = sizeof(kEdges) / sizeof(kEdges[0]);
+    std::vector<Bucket> bk(ne);
+    for (int w = 0; w < W; ++w) {
+      int e = 0;
+      while (kEdges[e] < ctx->wcaps[w].mr) ++e;
+      bk[e].worlds.push_back(w);
+      bk[e].caps = caps_max(bk[e].caps, ctx->wcaps[w]);
+    }
+    for (auto& x : bk)
+      if (!x.worlds.empty()) ctx->buckets.push_back(std::move(x));
+  }
+  for (auto& x : ctx->buckets) {
+    HIP_OK(hipMalloc(&x.d_worlds, x.worlds.size() * sizeof(int32_t)));
+    HIP_OK(hipMemcpy(x.d_worlds, x.worlds.data(), x.worlds.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    int rc = default_config(ctx.get(), x);
+    if (rc) return fail(OSTRICH_E_UNSUPPORTED, "a world with " + std::to_string(x.caps.mr) +
+                                                   " rows needs more LDS than a workgroup has");
+  }
+  HIP_OK(hipMalloc(&ctx->d_tape_off, (W + 1) * sizeof(int64_t)));
+  HIP_OK(hipMemcpy(ctx->d_tape_off, toff.data(), (W + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  *out = ctx.release();
   return 0;
 }
 
@@ -224,17 +373,43 @@ extern "C" int ostrich_ctx_destroy(ostrich_ctx* ctx) {
 
 extern "C" int ostrich_ctx_caps(const ostrich_ctx* ctx, int64_t* out) {
   if (!ctx || !out) return fail(OSTRICH_E_ARG, "null argument");
+  size_t lds = 0;
+  for (const auto& b : ctx->buckets) lds = std::max(lds, b.lds);
   out[0] = ctx->caps.nb;
   out[1] = ctx->caps.nj;
   out[2] = ctx->caps.ns;
   out[3] = ctx->caps.nc;
   out[4] = ctx->caps.mr;
-  out[5] = (int64_t)ctx->lds;
+  out[5] = (int64_t)lds;
   return 0;
 }
 
-extern "C" size_t ostrich_tape_bytes(const ostrich_ctx* ctx) {
-  return ctx ? (size_t)ctx->W * ost::tape_doubles(ctx->caps) * sizeof(double) : 0;
+extern "C" int ostrich_ctx_schedule(const ostrich_ctx* ctx, int32_t* out, int32_t max_buckets) {
+  if (!ctx) return fail(OSTRICH_E_ARG, "null argument");
+  int n = (int)ctx->buckets.size();
+  if (out)
+    for (int i = 0; i < std::min(n, (int)max_buckets); ++i) {
+      const Bucket& b = ctx->buckets[i];
+      int32_t* o = out + 6 * i;
+      o[0] = b.caps.mr;
+      o[1] = (int32_t)b.worlds.size();
+      o[2] = b.team;
+      o[3] = b.split;
+      o[4] = (int32_t)b.lds;
+      o[5] = b.tuned ? 1 : 0;
+    }
+  return n;
+}
+
+extern "C" size_t ostrich_tape_bytes(const ostrich_ctx* ctx) { return ctx ? ctx->tape_total * sizeof(double) : 0; }
+
+static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, const double* q_prev,
+                           const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
+                           double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
+                           int32_t* iters, double* resnorm, double* tape) {
+  hipLaunchKernelGGL(k_forward, dim3(grid_of(bk)), dim3(bk.team), bk.lds, st, ctx->B, ctx->P, bk.caps,
+                     launch_of(bk), q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act,
+                     status, iters, resnorm, tape, (const int64_t*)ctx->d_tape_off);
 }
 
 extern "C" int ostrich_step_forward(ostrich_ctx* ctx, const double* q_prev, const double* u_prev,
@@ -244,9 +419,9 @@ extern "C" int ostrich_step_forward(ostrich_ctx* ctx, const double* q_prev, cons
   if (!ctx || !q_prev || !u_prev || !lam_prev || !q_next || !u_next || !lam_next)
     return fail(OSTRICH_E_ARG, "null state pointer");
   if (ctx->NCTRL > 0 && !ctrl) return fail(OSTRICH_E_ARG, "controls required");
-  hipLaunchKernelGGL(k_forward, dim3(ctx->W), dim3(ctx->team), ctx->lds, (hipStream_t)stream, ctx->B, ctx->P,
-                     ctx->caps, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status,
-                     iters, resnorm, (double*)tape);
+  for (const Bucket& bk : ctx->buckets)
+    launch_forward(ctx, bk, (hipStream_t)stream, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
+                   act_slot, n_act, status, iters, resnorm, (double*)tape);
   HIP_OK(hipGetLastError());
   return 0;
 }
@@ -259,11 +434,72 @@ extern "C" int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, cons
     return fail(OSTRICH_E_ARG, "null pointer");
   if (ctx->NCTRL > 0 && (!ctrl || !g_ctrl)) return fail(OSTRICH_E_ARG, "controls required");
   int rf = refine < 0 ? ctx->refine : refine;
-  hipLaunchKernelGGL(k_adjoint, dim3(ctx->W), dim3(ctx->team), ctx->lds, (hipStream_t)stream, ctx->B, ctx->P,
-                     ctx->caps, q_prev, u_prev, ctrl, u_next, lam_next, (const double*)tape, gq_next, gu_next,
-                     gq_prev, gu_prev, g_ctrl, rf);
+  for (const Bucket& bk : ctx->buckets)
+    hipLaunchKernelGGL(k_adjoint, dim3(grid_of(bk)), dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
+                       bk.caps, launch_of(bk), q_prev, u_prev, ctrl, u_next, lam_next, (const double*)tape,
+                       (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf);
   HIP_OK(hipGetLastError());
   return 0;
+}
+
+// Autotuner: for every bucket, time one forward step of its worlds under each
+// candidate launch (team 64 / 128 / 256, Schur matrix on chip or in device
+// memory) and keep the fastest.  The per-world arithmetic is the same under
+// every candidate, so the choice changes only the time.
+extern "C" int ostrich_autotune(ostrich_ctx* ctx, const double* q, const double* u, const double* lam,
+                                const double* ctrl, int32_t reps, void* stream) {
+  if (!ctx || !q || !u || !lam) return fail(OSTRICH_E_ARG, "null argument");
+  if (ctx->NCTRL > 0 && !ctrl) return fail(OSTRICH_E_ARG, "controls required");
+  if (reps < 1) reps = 1;
+  hipStream_t st = (hipStream_t)stream;
+  const int W = ctx->W, NB = ctx->NB;
+  double *qn = nullptr, *un = nullptr, *ln = nullptr, *rn = nullptr;
+  int32_t *as = nullptr, *na = nullptr, *ss = nullptr, *it = nullptr;
+  auto cleanup = [&]() {
+    for (void* p : {(void*)qn, (void*)un, (void*)ln, (void*)rn, (void*)as, (void*)na, (void*)ss, (void*)it})
+      if (p) (void)hipFree(p);
+  };
+  hipEvent_t e0, e1;
+  int rc = 0;
+  if (hipMalloc(&qn, sizeof(double) * 7 * NB) || hipMalloc(&un, sizeof(double) * 6 * NB) ||
+      hipMalloc(&ln, sizeof(double) * std::max(ctx->NL, 1)) || hipMalloc(&rn, sizeof(double) * W) ||
+      hipMalloc(&as, sizeof(int32_t) * std::max(ctx->NS, 1)) || hipMalloc(&na, sizeof(int32_t) * W) ||
+      hipMalloc(&ss, sizeof(int32_t) * W) || hipMalloc(&it, sizeof(int32_t) * W)) {
+    cleanup();
+    return fail(OSTRICH_E_HIP, "autotune scratch allocation failed");
+  }
+  if (hipEventCreate(&e0) || hipEventCreate(&e1)) {
+    cleanup();
+    return fail(OSTRICH_E_HIP, "hipEventCreate failed");
+  }
+  for (Bucket& bk : ctx->buckets) {
+    float best = 1e30f;
+    int bt = bk.team, bs = bk.split;
+    for (int split : {ost::SPLIT_LDS, ost::SPLIT_GLOBAL})
+      for (int team : {64, 128, 256}) {
+        if (ost::world_lds_bytes(bk.caps, team, split) > ctx->lds_limit) continue;
+        if ((rc = configure_bucket(ctx, bk, team, split))) break;
+        launch_forward(ctx, bk, st, q, u, lam, ctrl, qn, un, ln, as, na, ss, it, rn, nullptr);  // warm
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps; ++r)
+          launch_forward(ctx, bk, st, q, u, lam, ctrl, qn, un, ln, as, na, ss, it, rn, nullptr);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess || hipGetLastError() != hipSuccess) {
+          rc = fail(OSTRICH_E_HIP, "autotune launch failed");
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) { best = ms; bt = team; bs = split; }
+      }
+    if (rc) break;
+    if ((rc = configure_bucket(ctx, bk, bt, bs))) break;
+    bk.tuned = true;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  cleanup();
+  return rc;
 }
 
 // ------------------------------------------------------------------ rollout
@@ -277,7 +513,7 @@ inline size_t al(size_t x) { return (x + 31) & ~size_t(31); }
 RollLayout roll_layout(const ostrich_ctx* c, int T, int ck) {
   RollLayout L;
   L.S = (size_t)7 * c->NB + 6 * c->NB + c->NL;
-  L.tape = (size_t)c->W * ost::tape_doubles(c->caps);
+  L.tape = c->tape_total;
   L.ctrl = al((size_t)T * std::max(c->NCTRL, 1));
   if (ck <= 0) {
     L.n_seg = 0;
@@ -305,7 +541,8 @@ extern "C" size_t ostrich_rollout_workspace_bytes(const ostrich_ctx* ctx, int32_
 
 extern "C" int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0, const double* u0,
                                const double* knots, int32_t K, const double* basis, int32_t T, int32_t ckpt_every,
-                               const int32_t* loss_body, const double* target, double* loss, double* qT,
+                               const int32_t* loss_body, const double* target, const double* loss_grad,
+                               double* loss, double* qT,
                                double* uT, double* g_q0, double* g_u0, double* g_knots, void* workspace,
                                size_t workspace_bytes, int32_t* status_or, void* stream_) {
   if (!ctx || !q0 || !u0 || T < 1 || !workspace || !loss_body || !target)
@@ -377,7 +614,7 @@ extern "C" int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0
       if (cur != fin) HIP_OK(hipMemcpyAsync(fin, cur, sizeof(double) * L.S, hipMemcpyDeviceToDevice, st));
     }
     hipLaunchKernelGGL(k_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.body_off, W, st_q(cur), loss_body,
-                       target, loss, (double*)nullptr);
+                       target, (const double*)nullptr, loss, (double*)nullptr);
   }
   if (phase & OSTRICH_BACKWARD) {
     if (!g_q0 || !g_u0 || (ctx->NCTRL > 0 && !g_knots)) return fail(OSTRICH_E_ARG, "gradient outputs required");
@@ -388,7 +625,7 @@ extern "C" int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0
       hipLaunchKernelGGL(k_fill, dim3(nblk((long)ctx->NCTRL * K, 256)), dim3(256), 0, st, g_knots,
                          (long)ctx->NCTRL * K, 0.0);
     hipLaunchKernelGGL(k_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.body_off, W, st_q(fin), loss_body,
-                       target, (double*)nullptr, gqa);
+                       target, loss_grad, (double*)nullptr, gqa);
     double *gq = gqa, *gq2 = gqb, *gu = gua, *gu2 = gub;
     auto adj = [&](double* sm, double* sp, double* tp, int k) -> int {
       int r = ostrich_step_adjoint(ctx, st_q(sm), st_u(sm), ctrl_at(k), st_u(sp), st_l(sp), tp, gq, gu, gq2, gu2,

@@ -235,6 +235,23 @@ OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
     M.lam[i] = lam_prev ? lam_prev[R.l0 + lslot] : 0.0;
   }
   t.sync();
+  // Band of the Schur matrix: entry (i, j) is structurally non-zero only if
+  // rows i and j act on a common body, so rows couple back to the first row
+  // that touches one of their bodies.
+  for (int b = t.rank(); b < nb; b += t.size()) {
+    int f = R.m;
+    for (int i = 0; i < R.m; ++i)
+      if (M.r_a[i] == b || M.r_b[i] == b) { f = i; break; }
+    M.b_first[b] = f;
+  }
+  t.sync();
+  int bw = 0;
+  for (int i = t.rank(); i < R.m; i += t.size()) {
+    int f = M.b_first[M.r_a[i]];
+    if (M.r_b[i] >= 0 && M.b_first[M.r_b[i]] < f) f = M.b_first[M.r_b[i]];
+    if (i - f > bw) bw = i - f;
+  }
+  R.bw = t.imax(bw, M.red);
 }
 
 // Clamp of the friction multipliers to the Coulomb disk of radius
@@ -281,7 +298,8 @@ OST_HD double evaluate(Team& t, const Batch& B, const Params& P, const WorldRef&
     double r[3], D[3];
     double* Jg = M.J + 12 * row;
     eval_row_group<double>(B, P, R, M, row, in, r, Jg, D);
-    for (int k = 0; k < n; ++k) {
+    #pragma unroll
+    for (int k = 0; k < 3; ++k) if (k < n) {
       M.res[row + k] = r[k];
       M.D[row + k] = D[k];
     }
@@ -295,7 +313,8 @@ OST_HD double evaluate(Team& t, const Batch& B, const Params& P, const WorldRef&
       for (int q = 0; q < 12; ++q) Gu[q] = Jg[q];
       Gl[0] = kind == RK_SERVO ? 1.0 / B.joint_kp[R.j0 + M.r_idx[row]] : 0.0;
     }
-    for (int k = 0; k < n; ++k) {
+    #pragma unroll
+    for (int k = 0; k < 3; ++k) if (k < n) {
       double* Y = M.Y + 12 * (row + k);
       minv6(M, a, Gu + 12 * k, Y);
       if (b >= 0) minv6(M, b, Gu + 12 * k + 6, Y + 6);
@@ -327,23 +346,34 @@ OST_HD double evaluate(Team& t, const Batch& B, const Params& P, const WorldRef&
     M.rdyn[e] = v;
   }
   t.sync();
+  // sum of squares over a fixed partition into 64 lanes, so the value does not
+  // depend on the team size
   double s = 0.0;
   int ntot = 6 * R.nb + R.m;
-  for (int i = t.rank(); i < ntot; i += t.size()) {
-    double v = i < 6 * R.nb ? M.rdyn[i] : M.res[i - 6 * R.nb];
-    s += v * v;
-  }
-  return ::sqrt(t.sum(s, M.red));
+  for (int l = t.rank(); l < 64; l += t.size())
+    for (int i = l; i < ntot; i += 64) {
+      double v = i < 6 * R.nb ? M.rdyn[i] : M.res[i - 6 * R.nb];
+      s += v * v;
+    }
+  return ::sqrt(t.sum64(s, M.red));
 }
 
 // Schur matrix of Eq. (12) with the generalized Jacobian: A = G_u M~^-1 J^T
 // + G_lambda / h + dreg diag(J M~^-1 J^T), and its right-hand side.
 template <class Team>
 OST_HD void assemble(Team& t, const Params& P, const WorldRef& R, const WorldMem& M, double dreg, bool with_rhs) {
-  const int m = R.m;
+  const int m = R.m, bw = R.bw, wd = 2 * bw + 1;
+  const bool dense = wd >= m;
   const double ih = 1.0 / P.h;
-  for (int e = t.rank(); e < m * m; e += t.size()) {
-    int i = e / m, j = e - i * m;
+  const int n_e = dense ? m * m : m * wd;
+  for (int e = t.rank(); e < n_e; e += t.size()) {
+    int i, j;
+    if (dense) { i = e / m; j = e - i * m; }
+    else {
+      i = e / wd;
+      j = i - bw + (e - i * wd);
+      if (j < 0 || j >= m) continue;
+    }
     const double* Y = M.Y + 12 * i;
     const double* Jj = M.J + 12 * j;
     int ai = M.r_a[i], bi = M.r_b[i], aj = M.r_a[j], bj = M.r_b[j];
@@ -355,7 +385,7 @@ OST_HD void assemble(Team& t, const Params& P, const WorldRef& R, const WorldMem
     int gi = M.r_g[i];
     if (M.r_g[j] == gi) s += M.Gl[3 * i + (j - gi)] * ih;
     if (i == j) s += dreg * M.Abar[i];
-    M.A[e] = s;
+    M.A[i * m + j] = s;
   }
   if (with_rhs)
     for (int i = t.rank(); i < m; i += t.size()) {
@@ -369,14 +399,17 @@ OST_HD void assemble(Team& t, const Params& P, const WorldRef& R, const WorldMem
   t.sync();
 }
 
-// In-place LU without pivoting; false on a non-finite or tiny pivot.
+// In-place LU without pivoting, restricted to the band |i - j| <= bw (no
+// fill-in leaves the band without pivoting); false on a non-finite or tiny
+// pivot.
 template <class Team> OST_HD bool lu_factor(Team& t, const WorldRef& R, const WorldMem& M) {
-  const int m = R.m;
+  const int m = R.m, bw = R.bw;
   double* A = M.A;
   for (int k = 0; k < m; ++k) {
+    const int hi = k + bw + 1 < m ? k + bw + 1 : m;
     if (t.rank() == 0) {
       double piv = A[k * m + k], rmax = 0.0;
-      for (int j = k; j < m; ++j) {
+      for (int j = k; j < hi; ++j) {
         double v = fabs(A[k * m + j]);
         rmax = v > rmax ? v : rmax;
       }
@@ -385,9 +418,9 @@ template <class Team> OST_HD bool lu_factor(Team& t, const WorldRef& R, const Wo
     t.sync();
     if (!M.iscal[2]) return false;
     double ip = 1.0 / A[k * m + k];
-    for (int i = k + 1 + t.rank(); i < m; i += t.size()) A[i * m + k] *= ip;
+    for (int i = k + 1 + t.rank(); i < hi; i += t.size()) A[i * m + k] *= ip;
     t.sync();
-    int w = m - k - 1;
+    int w = hi - k - 1;
     for (int e = t.rank(); e < w * w; e += t.size()) {
       int i = k + 1 + e / w, j = k + 1 + e % w;
       A[i * m + j] -= A[i * m + k] * A[k * m + j];
@@ -397,34 +430,36 @@ template <class Team> OST_HD bool lu_factor(Team& t, const WorldRef& R, const Wo
   return true;
 }
 
-// Solve A x = b (trans = false) or A^T x = b (trans = true) with the LU in M.A.
+// Solve A x = b (trans = false) or A^T x = b (trans = true) with the banded LU in M.A.
 template <class Team> OST_HD void lu_solve(Team& t, const WorldRef& R, const WorldMem& M, double* x, bool trans) {
-  const int m = R.m;
+  const int m = R.m, bw = R.bw;
   const double* A = M.A;
   if (!trans) {
     for (int k = 0; k < m; ++k) {  // L y = b (unit lower)
       double yk = x[k];
-      for (int i = k + 1 + t.rank(); i < m; i += t.size()) x[i] -= A[i * m + k] * yk;
+      const int hi = k + bw + 1 < m ? k + bw + 1 : m;
+      for (int i = k + 1 + t.rank(); i < hi; i += t.size()) x[i] -= A[i * m + k] * yk;
       t.sync();
     }
     for (int k = m - 1; k >= 0; --k) {  // U x = y
       double xk = x[k] / A[k * m + k];
       t.sync();
       if (t.rank() == 0) x[k] = xk;
-      for (int i = t.rank(); i < k; i += t.size()) x[i] -= A[i * m + k] * xk;
+      for (int i = (k - bw > 0 ? k - bw : 0) + t.rank(); i < k; i += t.size()) x[i] -= A[i * m + k] * xk;
       t.sync();
     }
   } else {
     for (int k = 0; k < m; ++k) {  // U^T z = b
       double zk = x[k] / A[k * m + k];
+      const int hi = k + bw + 1 < m ? k + bw + 1 : m;
       t.sync();
       if (t.rank() == 0) x[k] = zk;
-      for (int i = k + 1 + t.rank(); i < m; i += t.size()) x[i] -= A[k * m + i] * zk;
+      for (int i = k + 1 + t.rank(); i < hi; i += t.size()) x[i] -= A[k * m + i] * zk;
       t.sync();
     }
     for (int k = m - 1; k >= 0; --k) {  // L^T x = z (unit)
       double xk = x[k];
-      for (int i = t.rank(); i < k; i += t.size()) x[i] -= A[k * m + i] * xk;
+      for (int i = (k - bw > 0 ? k - bw : 0) + t.rank(); i < k; i += t.size()) x[i] -= A[k * m + i] * xk;
       t.sync();
     }
   }

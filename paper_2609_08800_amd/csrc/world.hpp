@@ -27,8 +27,9 @@ struct WorldMem {
   double *J, *Y, *Gl, *D, *res, *lam, *dlam, *lamt, *lambest, *Abar;
   // Schur matrix and right-hand side
   double *A, *rhs;
-  // slot scratch
+  // slot scratch; first row touching each body (band of the Schur matrix)
   int* s_act;
+  int* b_first;
   Feature* s_feat;
   // reduction scratch and scalars
   double* red;
@@ -38,23 +39,40 @@ struct WorldMem {
 
 OST_HD size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
 
-// Bytes of LDS one world needs for the given capacities and team size.
-OST_HD size_t world_lds_bytes(const Caps& c, int team) {
+// Storage split of one world's workspace.  SPLIT_LDS keeps everything in LDS;
+// SPLIT_GLOBAL moves the m x m Schur matrix and the per-row Jacobian blocks
+// (J, Y, G_lambda: 27 m doubles) to a per-workgroup slice of device memory,
+// for worlds whose rows do not fit on chip.
+enum { SPLIT_LDS = 0, SPLIT_GLOBAL = 1 };
+
+OST_HD size_t world_glob_doubles(const Caps& c, int split) {
+  return split == SPLIT_GLOBAL ? (size_t)c.mr * c.mr + (size_t)27 * c.mr : 0;
+}
+
+// Bytes of LDS one world needs for the given capacities, team size and split.
+OST_HD size_t world_lds_bytes(const Caps& c, int team, int split = SPLIT_LDS) {
   size_t d = 0, i = 0;
   d += (size_t)c.nb * (3 + 7 + 9 + 9 + 9 + 1 + 3 + 6 * 7 + 7 + 6);
   d += (size_t)c.nc * 20;
-  d += (size_t)c.mr * (12 + 12 + 3 + 7);
-  d += (size_t)c.mr * c.mr + c.mr;
+  d += (size_t)c.mr * 7;
+  if (split == SPLIT_LDS) d += (size_t)c.mr * 27 + (size_t)c.mr * c.mr;
+  d += c.mr;
   d += (size_t)team + 8;
-  i += (size_t)c.nc * 4 + (size_t)c.mr * 6 + c.ns + 16;
+  i += (size_t)c.nc * 4 + (size_t)c.mr * 6 + c.ns + c.nb + 16;
   size_t feat = (size_t)(c.nc + c.ns) * sizeof(Feature);
   return d * 8 + align8(i * 4) + align8(feat);
 }
 
-OST_HD WorldMem carve(char* base, const Caps& c, int team) {
+// Carve one world's workspace from LDS (and, with SPLIT_GLOBAL, from `glob`).
+OST_HD WorldMem carve(char* base, const Caps& c, int team, int split = SPLIT_LDS, double* glob = nullptr) {
   WorldMem M;
   double* p = (double*)base;
   auto take = [&](size_t n) { double* r = p; p += n; return r; };
+  double* g = glob;
+  auto gtake = [&](size_t n) {
+    if (split == SPLIT_LDS) return take(n);
+    double* r = g; g += n; return r;
+  };
   M.xm = take(3 * c.nb); M.qm = take(7 * c.nb); M.Rm = take(9 * c.nb); M.Iw = take(9 * c.nb);
   M.Iwi = take(9 * c.nb); M.mass = take(c.nb); M.inert = take(3 * c.nb); M.fext = take(6 * c.nb);
   M.um = take(6 * c.nb); M.u = take(6 * c.nb); M.du = take(6 * c.nb); M.rdyn = take(6 * c.nb);
@@ -62,16 +80,17 @@ OST_HD WorldMem carve(char* base, const Caps& c, int team) {
   M.c_n = take(3 * c.nc); M.c_t1 = take(3 * c.nc); M.c_t2 = take(3 * c.nc); M.c_noff = take(c.nc);
   M.c_la = take(3 * c.nc); M.c_lb = take(3 * c.nc); M.c_r = take(c.nc); M.c_mu = take(c.nc);
   M.c_sn = take(c.nc); M.c_sf = take(c.nc);
-  M.J = take(12 * c.mr); M.Y = take(12 * c.mr); M.Gl = take(3 * c.mr); M.D = take(c.mr); M.res = take(c.mr);
+  M.J = gtake(12 * c.mr); M.Y = gtake(12 * c.mr); M.Gl = gtake(3 * c.mr);
+  M.D = take(c.mr); M.res = take(c.mr);
   M.lam = take(c.mr); M.dlam = take(c.mr); M.lamt = take(c.mr); M.lambest = take(c.mr); M.Abar = take(c.mr);
-  M.A = take((size_t)c.mr * c.mr); M.rhs = take(c.mr);
+  M.A = gtake((size_t)c.mr * c.mr); M.rhs = take(c.mr);
   M.red = take(team); M.dscal = take(8);
   int* q = (int*)p;
   auto itake = [&](size_t n) { int* r = q; q += n; return r; };
   M.c_slot = itake(c.nc); M.c_kind = itake(c.nc); M.c_a = itake(c.nc); M.c_b = itake(c.nc);
   M.r_kind = itake(c.mr); M.r_a = itake(c.mr); M.r_b = itake(c.mr); M.r_idx = itake(c.mr);
   M.r_sub = itake(c.mr); M.r_g = itake(c.mr);
-  M.s_act = itake(c.ns); M.iscal = itake(16);
+  M.s_act = itake(c.ns); M.b_first = itake(c.nb); M.iscal = itake(16);
   char* f = (char*)(((uintptr_t)q + 7) & ~uintptr_t(7));
   M.c_feat = (Feature*)f;
   M.s_feat = M.c_feat + c.nc;
@@ -81,6 +100,7 @@ OST_HD WorldMem carve(char* base, const Caps& c, int team) {
 // Per-world view of the packed batch.
 struct WorldRef {
   int w, b0, nb, j0, nj, s0, ns, o0, l0, c0, cap, nsv, m, nc;
+  int bw;  // half band width of the Schur matrix (rows i, j couple only if |i - j| <= bw)
   int nctrl;
 };
 
@@ -105,6 +125,7 @@ OST_HD WorldRef world_ref(const Batch& B, int w) {
   }
   R.m = 0;
   R.nc = 0;
+  R.bw = 0;
   return R;
 }
 
@@ -133,7 +154,8 @@ OST_HD void eval_group(const Batch& B, const Params& P, const WorldRef& R, int k
   BodyIt<T> Ba = body_it(in.xa, in.ua, h);
   BodyIt<T> Bb = body_it(in.xb, in.ub ? in.ub : zu, h);
   int n = kind == RK_CONTACT ? 3 : 1;
-  for (int t = 0; t < 12 * n; ++t) J[t] = T(0.0);
+#pragma unroll
+  for (int t = 0; t < 36; ++t) if (t < 12 * n) J[t] = T(0.0);
   if (kind == RK_ANCHOR || kind == RK_AXIS) {
     const double* fr = B.joint_frame + 18 * (R.j0 + idx);
     if (kind == RK_ANCHOR) {  // Eq. (3): e_i . (x_a + R_a anchor_a - x_b - R_b anchor_b), E = 0
