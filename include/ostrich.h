@@ -171,6 +171,19 @@ int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, const double* u
                          const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl, int32_t refine,
                          void* stream);
 
+/* The same two steps restricted to the worlds listed in `worlds` (device
+ * int32 [n], distinct ids): only those worlds' entries of the state, status
+ * and tape arrays are read or written.  The serving loop uses them to advance
+ * the worlds of many requests, each at its own step, in one launch. */
+int ostrich_step_forward_list(ostrich_ctx* ctx, const int32_t* worlds, int32_t n, const double* q_prev,
+                              const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
+                              double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
+                              int32_t* iters, double* resnorm, void* tape, void* stream);
+int ostrich_step_adjoint_list(ostrich_ctx* ctx, const int32_t* worlds, int32_t n, const double* q_prev,
+                              const double* u_prev, const double* ctrl, const double* u_next, const double* lam_next,
+                              const void* tape, const double* gq_next, const double* gu_next, double* gq_prev,
+                              double* gu_prev, double* g_ctrl, int32_t refine, void* stream);
+
 #define OSTRICH_FORWARD 1
 #define OSTRICH_BACKWARD 2
 
@@ -190,6 +203,27 @@ int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0, const dou
                     const double* target, const double* loss_grad, double* loss, double* qT, double* uT,
                     double* g_q0, double* g_u0, double* g_knots, void* workspace, size_t workspace_bytes,
                     int32_t* status_or, void* stream);
+
+/* Device helpers of the trajectory-optimisation loop (Sec. IV: spline
+ * controls, the final-position loss, Adam on the knots), all asynchronous on
+ * `stream`, device pointers:
+ *   ostrich_spline_controls: ctrl[k*nctrl + c] = sum_j basis[k*K + j] knots[c*K + j], k < T.
+ *   ostrich_final_loss: for the n_worlds worlds whose body offsets start at
+ *     body_off (body_off[i] indexes qT rows), loss[i] = |xy - target[i]|^2 of
+ *     body loss_body[i] (loss may be NULL), and, if gq is not NULL, its
+ *     cotangent 2 (xy - target) loss_grad[i] (loss_grad NULL: 1) written into
+ *     the x, y entries of gq (other entries untouched).
+ *   ostrich_knot_grad_accumulate: g_knots[c*K + j] += basis[k*K + j] g_ctrl[c].
+ *   ostrich_adam: x -= lr mhat / (sqrt(vhat) + eps) with the moments m, v
+ *     updated in place from g, bias corrections of step t >= 1. */
+int ostrich_spline_controls(const double* basis, const double* knots, int32_t T, int32_t K, int32_t nctrl,
+                            double* ctrl, void* stream);
+int ostrich_final_loss(const int32_t* body_off, int32_t n_worlds, const double* qT, const int32_t* loss_body,
+                       const double* target, const double* loss_grad, double* loss, double* gq, void* stream);
+int ostrich_knot_grad_accumulate(const double* basis, const double* g_ctrl, int32_t k, int32_t K, int32_t nctrl,
+                                 double* g_knots, void* stream);
+int ostrich_adam(double* x, const double* g, double* m, double* v, int64_t n, double lr, double beta1, double beta2,
+                 double eps, int32_t t, void* stream);
 
 /* Natural cubic spline basis on the host: B [T*K] (host), knots at
  * t_j = j T h / (K - 1), step k samples t = k h. */

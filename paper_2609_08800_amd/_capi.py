@@ -79,6 +79,18 @@ def load() -> ctypes.CDLL:
     L.ostrich_ctx_schedule.restype = c_int
     L.ostrich_autotune.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp, c_int, c_vp]
     L.ostrich_autotune.restype = c_int
+    L.ostrich_step_forward_list.argtypes = [c_vp, c_vp, c_int] + [c_vp] * 13 + [c_vp]
+    L.ostrich_step_forward_list.restype = c_int
+    L.ostrich_step_adjoint_list.argtypes = [c_vp, c_vp, c_int] + [c_vp] * 11 + [c_int, c_vp]
+    L.ostrich_step_adjoint_list.restype = c_int
+    L.ostrich_spline_controls.argtypes = [c_vp, c_vp, c_int, c_int, c_int, c_vp, c_vp]
+    L.ostrich_spline_controls.restype = c_int
+    L.ostrich_final_loss.argtypes = [c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]
+    L.ostrich_final_loss.restype = c_int
+    L.ostrich_knot_grad_accumulate.argtypes = [c_vp, c_vp, c_int, c_int, c_int, c_vp, c_vp]
+    L.ostrich_knot_grad_accumulate.restype = c_int
+    L.ostrich_adam.argtypes = [c_vp, c_vp, c_vp, c_vp, ctypes.c_int64, c_dbl, c_dbl, c_dbl, c_dbl, c_int, c_vp]
+    L.ostrich_adam.restype = c_int
     L.ostrich_spline_basis.argtypes = [c_int, c_int, c_dbl, c_vp]
     L.ostrich_spline_basis.restype = c_int
     _lib = L

@@ -169,18 +169,22 @@ OST_HD void forward_world(Team& t, const Batch& B, const Params& P, const Caps& 
     for (int k = 0; k < 4; ++k) qo[3 + k] = r4[k] / n;
     for (int k = 0; k < 6; ++k) u_next[6 * (R.b0 + b) + k] = u[k];
   }
+  // every output entry is written exactly once: multipliers of inactive slots
+  // are zero, active slots take their row of the returned iterate
   const int lam_len = B.lam_off[w + 1] - R.l0;
-  for (int i = t.rank(); i < lam_len; i += t.size()) lam_next[R.l0 + i] = 0.0;
-  if (act_slot)
-    for (int s = t.rank(); s < R.ns; s += t.size()) act_slot[R.s0 + s] = -1;
-  t.sync();
   const int base = 5 * R.nj + R.nsv;
-  for (int i = t.rank(); i < m; i += t.size()) {
-    int ls = i < base ? i : base + 3 * M.c_slot[(i - base) / 3] + (i - base) % 3;
-    lam_next[R.l0 + ls] = M.lambest[i];
+  for (int i = t.rank(); i < lam_len; i += t.size()) {
+    double v = 0.0;
+    if (i < base) {
+      v = M.lambest[i];
+    } else {
+      int s = (i - base) / 3, c = M.s_act[s];
+      if (c >= 0) v = M.lambest[base + 3 * c + (i - base) % 3];
+    }
+    lam_next[R.l0 + i] = v;
   }
   if (act_slot)
-    for (int c = t.rank(); c < R.nc; c += t.size()) act_slot[R.s0 + c] = M.c_slot[c];
+    for (int c = t.rank(); c < R.ns; c += t.size()) act_slot[R.s0 + c] = c < R.nc ? M.c_slot[c] : -1;
   if (t.rank() == 0) {
     if (n_act) n_act[w] = R.nc;
     if (status) status[w] = st;

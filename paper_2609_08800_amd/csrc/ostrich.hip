@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <memory>
 #include <cstring>
 #include <string>
@@ -201,6 +202,7 @@ struct ostrich_ctx {
   std::vector<int32_t> body_off_h;
   std::vector<ost::Caps> wcaps;  // per world
   std::vector<Bucket> buckets;
+  Bucket all;  // every world, shaped for the largest: launches over caller-given world lists
   int64_t* d_tape_off = nullptr;
   size_t tape_total = 0;  // doubles
   ~ostrich_ctx() {
@@ -208,6 +210,7 @@ struct ostrich_ctx {
       if (b.d_worlds) (void)hipFree(b.d_worlds);
       if (b.gscr) (void)hipFree(b.gscr);
     }
+    if (all.gscr) (void)hipFree(all.gscr);
     if (d_tape_off) (void)hipFree(d_tape_off);
   }
 };
@@ -360,6 +363,10 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
     if (rc) return fail(OSTRICH_E_UNSUPPORTED, "a world with " + std::to_string(x.caps.mr) +
                                                    " rows needs more LDS than a workgroup has");
   }
+  for (int w = 0; w < W; ++w) ctx->all.worlds.push_back(w);
+  ctx->all.caps = c;
+  if (default_config(ctx.get(), ctx->all))
+    return fail(OSTRICH_E_UNSUPPORTED, "the batch does not fit a workgroup");
   HIP_OK(hipMalloc(&ctx->d_tape_off, (W + 1) * sizeof(int64_t)));
   HIP_OK(hipMemcpy(ctx->d_tape_off, toff.data(), (W + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
   *out = ctx.release();
@@ -438,6 +445,52 @@ extern "C" int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, cons
     hipLaunchKernelGGL(k_adjoint, dim3(grid_of(bk)), dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
                        bk.caps, launch_of(bk), q_prev, u_prev, ctrl, u_next, lam_next, (const double*)tape,
                        (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf);
+  HIP_OK(hipGetLastError());
+  return 0;
+}
+
+static Launch list_launch(const ostrich_ctx* ctx, const int32_t* worlds, int n) {
+  return Launch{worlds, n, ctx->all.split, ctx->all.split == ost::SPLIT_GLOBAL ? ctx->all.gscr : nullptr,
+                ctx->all.gstride};
+}
+static int list_grid(const ostrich_ctx* ctx, int n) {
+  return ctx->all.split == ost::SPLIT_GLOBAL ? std::max(1, std::min(n, ctx->all.slots)) : n;
+}
+
+extern "C" int ostrich_step_forward_list(ostrich_ctx* ctx, const int32_t* worlds, int32_t n, const double* q_prev,
+                                         const double* u_prev, const double* lam_prev, const double* ctrl,
+                                         double* q_next, double* u_next, double* lam_next, int32_t* act_slot,
+                                         int32_t* n_act, int32_t* status, int32_t* iters, double* resnorm,
+                                         void* tape, void* stream) {
+  if (!ctx || !worlds || n < 0 || n > ctx->W) return fail(OSTRICH_E_ARG, "world list");
+  if (!q_prev || !u_prev || !lam_prev || !q_next || !u_next || !lam_next)
+    return fail(OSTRICH_E_ARG, "null state pointer");
+  if (ctx->NCTRL > 0 && !ctrl) return fail(OSTRICH_E_ARG, "controls required");
+  if (n == 0) return 0;
+  const Bucket& bk = ctx->all;
+  hipLaunchKernelGGL(k_forward, dim3(list_grid(ctx, n)), dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
+                     bk.caps, list_launch(ctx, worlds, n), q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
+                     act_slot, n_act, status, iters, resnorm, (double*)tape, (const int64_t*)ctx->d_tape_off);
+  HIP_OK(hipGetLastError());
+  return 0;
+}
+
+extern "C" int ostrich_step_adjoint_list(ostrich_ctx* ctx, const int32_t* worlds, int32_t n, const double* q_prev,
+                                         const double* u_prev, const double* ctrl, const double* u_next,
+                                         const double* lam_next, const void* tape, const double* gq_next,
+                                         const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl,
+                                         int32_t refine, void* stream) {
+  if (!ctx || !worlds || n < 0 || n > ctx->W) return fail(OSTRICH_E_ARG, "world list");
+  if (!q_prev || !u_prev || !u_next || !lam_next || !tape || !gq_next || !gu_next || !gq_prev || !gu_prev)
+    return fail(OSTRICH_E_ARG, "null pointer");
+  if (ctx->NCTRL > 0 && (!ctrl || !g_ctrl)) return fail(OSTRICH_E_ARG, "controls required");
+  if (n == 0) return 0;
+  const Bucket& bk = ctx->all;
+  int rf = refine < 0 ? ctx->refine : refine;
+  hipLaunchKernelGGL(k_adjoint, dim3(list_grid(ctx, n)), dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
+                     bk.caps, list_launch(ctx, worlds, n), q_prev, u_prev, ctrl, u_next, lam_next,
+                     (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev,
+                     g_ctrl, rf);
   HIP_OK(hipGetLastError());
   return 0;
 }
@@ -663,6 +716,60 @@ extern "C" int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0
     HIP_OK(hipMemcpyAsync(g_q0, gq, sizeof(double) * 7 * NB, hipMemcpyDeviceToDevice, st));
     HIP_OK(hipMemcpyAsync(g_u0, gu, sizeof(double) * 6 * NB, hipMemcpyDeviceToDevice, st));
   }
+  return 0;
+}
+
+__global__ void k_adam(double* x, const double* g, double* m, double* v, long n, double lr, double b1, double b2,
+                       double eps, double c1, double c2) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double gi = g[i];
+  double mi = b1 * m[i] + (1.0 - b1) * gi;
+  double vi = b2 * v[i] + (1.0 - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  x[i] -= lr * (mi / c1) / (::sqrt(vi / c2) + eps);
+}
+
+extern "C" int ostrich_spline_controls(const double* basis, const double* knots, int32_t T, int32_t K, int32_t nctrl,
+                                       double* ctrl, void* stream) {
+  if (!basis || !knots || !ctrl || T < 1 || K < 1 || nctrl < 0) return fail(OSTRICH_E_ARG, "spline controls");
+  if (nctrl == 0) return 0;
+  hipLaunchKernelGGL(k_ctrl, dim3(nblk((long)T * nctrl, 256)), dim3(256), 0, (hipStream_t)stream, basis, knots, T, K,
+                     nctrl, ctrl);
+  HIP_OK(hipGetLastError());
+  return 0;
+}
+
+extern "C" int ostrich_final_loss(const int32_t* body_off, int32_t n_worlds, const double* qT,
+                                  const int32_t* loss_body, const double* target, const double* loss_grad,
+                                  double* loss, double* gq, void* stream) {
+  if (!body_off || !qT || !loss_body || !target || n_worlds < 0) return fail(OSTRICH_E_ARG, "final loss");
+  if (n_worlds == 0) return 0;
+  hipLaunchKernelGGL(k_loss, dim3(nblk(n_worlds, 256)), dim3(256), 0, (hipStream_t)stream, body_off, n_worlds, qT,
+                     loss_body, target, loss_grad, loss, gq);
+  HIP_OK(hipGetLastError());
+  return 0;
+}
+
+extern "C" int ostrich_knot_grad_accumulate(const double* basis, const double* g_ctrl, int32_t k, int32_t K,
+                                            int32_t nctrl, double* g_knots, void* stream) {
+  if (!basis || !g_ctrl || !g_knots || k < 0 || K < 1 || nctrl < 0) return fail(OSTRICH_E_ARG, "knot gradient");
+  if (nctrl == 0) return 0;
+  hipLaunchKernelGGL(k_gknots, dim3(nblk((long)nctrl * K, 256)), dim3(256), 0, (hipStream_t)stream, basis, g_ctrl, k,
+                     K, nctrl, g_knots);
+  HIP_OK(hipGetLastError());
+  return 0;
+}
+
+extern "C" int ostrich_adam(double* x, const double* g, double* m, double* v, int64_t n, double lr, double beta1,
+                            double beta2, double eps, int32_t t, void* stream) {
+  if (!x || !g || !m || !v || n < 0 || t < 1) return fail(OSTRICH_E_ARG, "adam");
+  if (n == 0) return 0;
+  double c1 = 1.0 - std::pow(beta1, t), c2 = 1.0 - std::pow(beta2, t);
+  hipLaunchKernelGGL(k_adam, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, x, g, m, v, (long)n, lr, beta1,
+                     beta2, eps, c1, c2);
+  HIP_OK(hipGetLastError());
   return 0;
 }
 

@@ -147,12 +147,19 @@ OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
     M.s_feat[s] = F;
   }
   t.sync();
-  if (t.rank() == 0) {  // ascending-slot compaction, at most contact_cap
+  if (t.rank() == 0) {  // ascending-slot compaction, at most contact_cap; s_act becomes the position or -1
     int nc = 0, of = 0;
     for (int s = 0; s < R.ns; ++s)
       if (M.s_act[s]) {
-        if (nc < R.cap) M.c_slot[nc++] = s;
-        else of = 1;
+        if (nc < R.cap) {
+          M.c_slot[nc] = s;
+          M.s_act[s] = nc++;
+        } else {
+          of = 1;
+          M.s_act[s] = -1;
+        }
+      } else {
+        M.s_act[s] = -1;
       }
     M.iscal[0] = nc;
     M.iscal[1] = of;

@@ -1,0 +1,94 @@
+"""Serving scheduler on the host (fake backend, virtual clock): admission by
+free slots and HBM budget, continuous batching, completion and latency
+accounting."""
+import numpy as np
+import pytest
+
+from paper_2609_08800_amd.serving import FakeBackend, Request, ServingEngine, SlotAllocator, percentile, \
+    poisson_arrivals
+
+
+class B:  # minimal packed-batch stand-in: only the world count matters to the fake backend
+    def __init__(self, n):
+        self.n_worlds = n
+
+
+def run(reqs, capacity=16, budget=1e12, tick=0.01):
+    be = FakeBackend(capacity, tick_seconds=tick)
+    eng = ServingEngine(be, budget, clock=be.clock)
+    out = eng.run(reqs)
+    return be, eng, out
+
+
+def test_slot_allocator_first_fit_and_merge():
+    a = SlotAllocator(10)
+    assert a.alloc(4) == 0 and a.alloc(4) == 4 and a.alloc(4) == -1
+    a.release(0, 4)
+    assert a.alloc(3) == 0
+    a.release(4, 4)
+    a.release(0, 3)
+    assert a.free == [(0, 10)]
+
+
+def test_every_request_completes_all_iterations():
+    reqs = [Request(i, B(2 + i), T=3 + i, iters=4, arrival=0.005 * i) for i in range(5)]
+    be, eng, out = run(reqs)
+    assert len(out["requests"]) == 5
+    for r in out["requests"]:
+        assert len(r.iter_latency) == 4 and len(r.losses) == 4
+        assert r.finished_at >= r.admitted_at >= r.arrival
+        # an iteration is T forward ticks and T backward ticks
+        assert min(r.iter_latency) >= 2 * r.T * 0.01 - 1e-12
+
+
+def test_admission_waits_for_free_slots():
+    reqs = [Request(i, B(6), T=2, iters=1, arrival=0.0) for i in range(3)]
+    be, eng, out = run(reqs, capacity=12)
+    admitted = sorted((r.admitted_at, r.rid) for r in out["requests"])
+    assert admitted[0][0] == admitted[1][0] == 0.0
+    assert admitted[2][0] > 0.0   # the third waits until a range of 6 slots frees up
+    assert max(n_f + n_b for _, n_f, n_b, _ in eng.ticks) <= 12
+
+
+def test_admission_respects_hbm_budget():
+    reqs = [Request(i, B(2), T=4, iters=1, arrival=0.0) for i in range(3)]
+    per = 1.0 * 2 * 5
+    be, eng, out = run(reqs, capacity=64, budget=per * 1.5)
+    # only one request fits the budget at a time: their lifetimes do not overlap
+    spans = sorted((r.admitted_at, r.finished_at) for r in out["requests"])
+    for (a0, f0), (a1, f1) in zip(spans, spans[1:]):
+        assert a1 >= f0
+    with pytest.raises(ValueError):
+        run([Request(9, B(2), T=4, iters=1)], budget=per * 0.5)
+
+
+def test_continuous_batching_admits_while_others_run():
+    early = Request(0, B(4), T=20, iters=2, arrival=0.0)
+    late = Request(1, B(4), T=5, iters=1, arrival=0.1)
+    be, eng, out = run([early, late], capacity=16)
+    # the late request joins ticks in which the early one is still in flight
+    shared = [rids for _, _, _, rids in eng.ticks if rids == (0, 1)]
+    assert shared
+    assert late.admitted_at < early.finished_at
+    assert late.finished_at < early.finished_at   # a short request overtakes a long one in flight
+    # some tick mixes a forward phase and a backward phase
+    assert any(f and b for f, b in be.log)
+
+
+def test_results_do_not_depend_on_the_mix():
+    alone = Request(7, B(3), T=6, iters=3)
+    _, _, o1 = run([alone])
+    mixed = Request(7, B(3), T=6, iters=3, arrival=0.02)
+    others = [Request(i, B(2), T=4 + i, iters=2, arrival=0.01 * i) for i in range(4)]
+    _, _, o2 = run([mixed] + others)
+    assert np.array_equal(alone.knots, mixed.knots)
+    assert all(np.array_equal(a, b) for a, b in zip(alone.losses, mixed.losses))
+
+
+def test_percentiles_and_arrivals():
+    assert percentile([1, 2, 3, 4], 50) == 2.5
+    a = poisson_arrivals(100.0, 2.0, seed=1)
+    assert all(0 < x < 2.0 for x in a) and a == sorted(a)
+    assert 120 < len(a) < 280
+    _, _, out = run([Request(i, B(1), T=2, iters=2, arrival=t) for i, t in enumerate(a[:20])])
+    assert out["iter_latency_p50_s"] <= out["iter_latency_p99_s"]

@@ -1,0 +1,87 @@
+"""Serving system on the GPU: a served request computes what the rollout
+entry point and Adam compute, and its results are the same alone and in a mix
+of requests of other sizes and horizons arriving while it runs."""
+import numpy as np
+import pytest
+
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    t = pytest.importorskip("torch")
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+K = scenes.ROBOT_KNOTS
+
+
+def engine(capacity=64, budget=8e9):
+    from paper_2609_08800_amd.serving import GpuBackend, ServingEngine
+    P = scenes.solver_params()
+    tmpl = scenes.robot_batch(1, seed=0).worlds[0]
+    be = GpuBackend(tmpl, capacity, P, K)
+    return be, ServingEngine(be, budget)
+
+
+def adam_ref(x, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    x = x - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+    return x, m, v
+
+
+def test_served_request_matches_rollout_and_adam(torch):
+    from paper_2609_08800_amd import Simulator, spline_basis
+    from paper_2609_08800_amd.serving import Request
+    b = scenes.robot_batch(3, seed=41)
+    T, iters, lr = 8, 3, 0.1
+    be, eng = engine(capacity=8)
+    r = Request(0, b, T=T, iters=iters, lr=lr)
+    out = eng.run([r])
+    assert len(out["requests"]) == 1 and len(r.iter_latency) == iters
+    P = scenes.solver_params()
+    sim = Simulator(b, P, device="cuda:0")
+    basis = spline_basis(T, K, P["h"])
+    x = scenes.knots_array(b, K)
+    m, v = np.zeros_like(x), np.zeros_like(x)
+    for it in range(iters):
+        ref = sim.rollout(b.q0, b.u0, x, basis, T, ckpt_every=0, loss_body=b.loss_body, target=b.target)
+        np.testing.assert_allclose(r.losses[it], ref["loss"].cpu().numpy(), rtol=1e-12, atol=0)
+        x, m, v = adam_ref(x, ref["g_knots"].cpu().numpy(), m, v, it + 1, lr)
+    np.testing.assert_allclose(r.knots.reshape(x.shape), x, rtol=1e-12, atol=1e-14)
+
+
+def test_results_same_alone_and_in_the_mix(torch):
+    from paper_2609_08800_amd.serving import Request
+    mine = scenes.robot_batch(5, seed=50)
+    be, eng = engine(capacity=48)
+    alone = Request(0, mine, T=10, iters=3)
+    eng.run([alone])
+    be2, eng2 = engine(capacity=48)
+    mixed = Request(0, mine, T=10, iters=3, arrival=0.05)
+    others = [Request(1 + i, scenes.robot_batch(n, seed=60 + i), T=t, iters=2, arrival=0.02 * i)
+              for i, (n, t) in enumerate(((7, 6), (3, 14), (11, 9), (2, 5)))]
+    out = eng2.run([mixed] + others)
+    assert len(out["requests"]) == 5
+    assert any(len(rids) >= 3 for _, _, _, rids in eng2.ticks), "requests never shared a launch"
+    assert any(f and b_ for _, f, b_, _ in eng2.ticks), "no tick mixed forward and adjoint work"
+    assert np.array_equal(alone.knots, mixed.knots)
+    for a, c in zip(alone.losses, mixed.losses):
+        assert np.array_equal(a, c)
+
+
+def test_hbm_budget_serialises_requests(torch):
+    from paper_2609_08800_amd.serving import Request
+    be, eng = engine(capacity=32)
+    reqs = [Request(i, scenes.robot_batch(4, seed=70 + i), T=6, iters=1) for i in range(3)]
+    need = be.request_bytes(reqs[0])
+    eng.budget = 1.5 * need
+    out = eng.run(reqs)
+    spans = sorted((r.admitted_at, r.finished_at) for r in out["requests"])
+    for (a0, f0), (a1, f1) in zip(spans, spans[1:]):
+        assert a1 >= f0
