@@ -8,8 +8,9 @@
 // constraint is d c(q(u)) / du / h, the exact implicit-function Jacobian is
 // dF/d(u, lambda), and the pull-back is dF/d(q-, u-, a).
 //
-// Parity unpinned: the heightmap narrow phase (slot kind 3) is not part of
-// this oracle.
+// The terrain narrow phase searches every feature of the mesh (brute force);
+// its pins are the flat heightmap, which must reproduce the plane z = h0, and
+// hand-placed points over single features.
 #include "ostrich_ref.h"
 
 #include <algorithm>
@@ -115,8 +116,18 @@ struct SlotD {
   int kind, a, b, feat;
   double loc[3], r, mu, face_h;
 };
+// Heightmap terrain: an n x n vertex grid, vertex (i, j) at (ox + i sp,
+// oy + j sp, z[i n + j]); each grid cell is cut along the diagonal from
+// (i, j) to (i+1, j+1).
+struct HmapD {
+  const double* z = nullptr;
+  int n = 0;
+  double sp = 0, ox = 0, oy = 0;
+  V3<double> vert(int i, int j) const { return {ox + sp * i, oy + sp * j, z[i * n + j]}; }
+};
 struct WorldD {
   int nb = 0, nctrl = 0, nservo = 0, lam_len = 0, cap = 0;
+  HmapD hm;
   const double* mass = nullptr;
   const double* inertia = nullptr;
   std::vector<JointD> joints;
@@ -164,6 +175,14 @@ WorldD load_world(const ostrich_ref_batch* B, int w) {
     S.mu = r[4];
     S.face_h = r[5];
     W.slots.push_back(S);
+  }
+  if (B->world_hmap && B->world_hmap[w] >= 0 && B->hmap_n >= 2) {
+    int k = B->world_hmap[w];
+    W.hm.n = B->hmap_n;
+    W.hm.sp = B->hmap_spacing;
+    W.hm.z = B->hmap_heights + (size_t)k * B->hmap_n * B->hmap_n;
+    W.hm.ox = B->hmap_origin[2 * k];
+    W.hm.oy = B->hmap_origin[2 * k + 1];
   }
   W.obs = B->obs_box + 6 * B->obs_off[w];
   W.no = B->obs_off[w + 1] - B->obs_off[w];
@@ -229,8 +248,122 @@ template <class T> V3<T> inertia_apply(const Q4<T>& R, const double* I, const V3
 // ------------------------------------------------- contact front end -----
 // Active set and contact frame are fixed from q- for the whole step; the
 // active set evolves only between steps.
+// Terrain contacts (slot kind 3).  The mesh's local features are its
+// vertices, its edges (open segments) and its triangles (open faces).  A
+// feature is a candidate contact for the point P if the point of the feature
+// nearest to P is a local minimum of the distance from P to the mesh surface:
+// for a triangle, P projects into its interior; for an edge, P projects into
+// the open segment and, in the plane of each triangle on the edge, lies on the
+// far side of the edge from that triangle; for a vertex, P makes an obtuse
+// angle with every edge leaving the vertex.  Candidates farther than the
+// search radius are dropped, and slot k of a proxy takes the k-th candidate
+// ordered by distance (quantised to 1e-9 m) and then by key.  Every feature is
+// named by the vertex (i, j) that owns it and a kind: 0 the vertex, 1 edge to
+// (i+1, j), 2 edge to (i, j+1), 3 edge to (i+1, j+1), 4 triangle
+// (i,j),(i+1,j),(i+1,j+1), 5 triangle (i,j),(i+1,j+1),(i,j+1);
+// key = 6 (i n + j) + kind.
+constexpr double kDistQuantum = 1e-9;
+
+// Barycentric coordinates of the projection of p onto the plane of (a, b, c).
+void barycentric(const V3<double>& a, const V3<double>& b, const V3<double>& c, const V3<double>& p,
+                 double& ua, double& ub, double& uc) {
+  V3<double> e0 = b - a, e1 = c - a, e2 = p - a;
+  double d00 = dot(e0, e0), d01 = dot(e0, e1), d11 = dot(e1, e1), d20 = dot(e2, e0), d21 = dot(e2, e1);
+  double den = d00 * d11 - d01 * d01;
+  ub = (d11 * d20 - d01 * d21) / den;
+  uc = (d00 * d21 - d01 * d20) / den;
+  ua = 1.0 - ub - uc;
+}
+
+// Normal n and plane offset noff = n . C of feature `key` for the point P
+// (C the feature's point nearest to P), or false if it is not a candidate.
+template <class T>
+bool terrain_feature(const HmapD& H, int key, const V3<T>& P, V3<T>& n, T& noff, double* dist) {
+  const int kind = key % 6, i = (key / 6) / H.n, j = (key / 6) % H.n, last = H.n - 1;
+  const V3<double> A = H.vert(i, j);
+  const V3<double> p{val(P.x), val(P.y), val(P.z)};
+  auto exists = [&](int a, int b) { return a >= 0 && b >= 0 && a <= last && b <= last; };
+  if (kind == 0) {
+    const int nbr[6][2] = {{1, 0}, {0, 1}, {1, 1}, {-1, 0}, {0, -1}, {-1, -1}};
+    for (const auto& d : nbr)
+      if (exists(i + d[0], j + d[1]) && dot(H.vert(i + d[0], j + d[1]) - A, p - A) >= 0.0) return false;
+    V3<T> d = P - cst3<T>(A.x, A.y, A.z);
+    T len = norm(d);
+    if (val(len) <= 1e-12) return false;
+    n = d * (1.0 / len);
+    noff = dot(n, cst3<T>(A.x, A.y, A.z));
+    if (dist) *dist = val(len);
+    return true;
+  }
+  if (kind <= 3) {
+    const int bi = kind == 2 ? i : i + 1, bj = kind == 1 ? j : j + 1;
+    const V3<double> B = H.vert(bi, bj);
+    // third vertices of the (one or two) triangles on this edge
+    int third[2][2], nt = 0;
+    if (kind == 1) {
+      if (exists(i + 1, j + 1)) { third[nt][0] = i + 1; third[nt][1] = j + 1; ++nt; }
+      if (exists(i, j - 1)) { third[nt][0] = i; third[nt][1] = j - 1; ++nt; }
+    } else if (kind == 2) {
+      if (exists(i + 1, j + 1)) { third[nt][0] = i + 1; third[nt][1] = j + 1; ++nt; }
+      if (exists(i - 1, j)) { third[nt][0] = i - 1; third[nt][1] = j; ++nt; }
+    } else {
+      third[0][0] = i + 1; third[0][1] = j;
+      third[1][0] = i; third[1][1] = j + 1;
+      nt = 2;
+    }
+    for (int k = 0; k < nt; ++k) {
+      double ua, ub, uc;
+      barycentric(A, B, H.vert(third[k][0], third[k][1]), p, ua, ub, uc);
+      if (!(uc < 0.0)) return false;   // P is not beyond the edge in this triangle
+    }
+    const V3<double> e = B - A;
+    T s = dot(P - cst3<T>(A.x, A.y, A.z), cst3<T>(e.x, e.y, e.z)) / dot(e, e);
+    if (!(val(s) > 0.0 && val(s) < 1.0)) return false;
+    V3<T> C = cst3<T>(A.x, A.y, A.z) + cst3<T>(e.x, e.y, e.z) * s;
+    V3<T> d = P - C;
+    T len = norm(d);
+    if (val(len) <= 1e-12) return false;
+    n = d * (1.0 / len);
+    noff = dot(n, C);
+    if (dist) *dist = val(len);
+    return true;
+  }
+  const V3<double> B = kind == 4 ? H.vert(i + 1, j) : H.vert(i + 1, j + 1);
+  const V3<double> Cv = kind == 4 ? H.vert(i + 1, j + 1) : H.vert(i, j + 1);
+  V3<double> N = cross(B - A, Cv - A);
+  N = N * (1.0 / norm(N));
+  double ua, ub, uc;
+  barycentric(A, B, Cv, p, ua, ub, uc);
+  if (!(ua > 0.0 && ub > 0.0 && uc > 0.0)) return false;
+  n = cst3<T>(N.x, N.y, N.z);
+  noff = T(dot(N, A));
+  if (dist) *dist = std::fabs(dot(N, p - A));
+  return true;
+}
+
+// Brute force over every feature of the mesh: the rank-th candidate within rc.
+int terrain_select(const HmapD& H, const V3<double>& P, double rc, int rank) {
+  struct Cand { long long qd; int key; };
+  std::vector<Cand> cands;
+  for (int i = 0; i < H.n; ++i)
+    for (int j = 0; j < H.n; ++j)
+      for (int kind = 0; kind < 6; ++kind) {
+        bool need_i = kind == 1 || kind == 3 || kind >= 4, need_j = kind == 2 || kind == 3 || kind >= 4;
+        if ((need_i && i + 1 >= H.n) || (need_j && j + 1 >= H.n)) continue;
+        int key = 6 * (i * H.n + j) + kind;
+        V3<double> n;
+        double noff, d;
+        if (!terrain_feature<double>(H, key, P, n, noff, &d) || d > rc) continue;
+        cands.push_back({(long long)std::floor(d / kDistQuantum), key});
+      }
+  std::sort(cands.begin(), cands.end(),
+            [](const Cand& a, const Cand& b) { return a.qd < b.qd || (a.qd == b.qd && a.key < b.key); });
+  return rank >= 0 && rank < (int)cands.size() ? cands[rank].key : -1;
+}
+
 struct Feature {
   int slot;
+  int tkey;      // terrain: feature key, -1 if the slot has no candidate
   int flags[3];  // box: -1 clamped low, +1 clamped high, 0 free
   int inside;    // box: 1 if the proxy centre is inside (or on) the box
   int in_axis, in_side;
@@ -262,7 +395,16 @@ Contact<T> contact_frame(const WorldD& W, const T* qprev, Feature& F, bool decid
   T gap;
   C.noff = T(0.0);
   C.lb = cst3<T>(0, 0, 0);
-  if (S.kind == 0) {  // ground plane z = 0
+  if (S.kind == 3) {  // terrain feature, chosen at q- (search radius given by the caller)
+    bool ok = F.tkey >= 0 && terrain_feature<T>(W.hm, F.tkey, P, C.n, C.noff, nullptr);
+    if (!ok) {
+      C.n = cst3<T>(0, 0, 1);
+      C.noff = T(-1e30);
+      gap = T(1e30);
+    } else {
+      gap = dot(C.n, P) - C.noff - S.r;
+    }
+  } else if (S.kind == 0) {  // ground plane z = 0
     C.n = cst3<T>(0, 0, 1);
     gap = P.z - S.r;
   } else if (S.kind == 1) {  // static axis-aligned box
@@ -341,10 +483,20 @@ void select_active(const WorldD& W, const Prm& P, const double* qm, const double
   for (int s = 0; s < (int)W.slots.size(); ++s) {
     Feature F{};
     F.slot = s;
+    F.tkey = -1;
+    const SlotD& S = W.slots[s];
+    if (S.kind == 3 && W.hm.n >= 2) {
+      // search radius: proxy radius, activation margin and one step at the proxy centre's speed
+      const double* q = qm + 7 * S.a;
+      const double* ua = um + 6 * S.a;
+      V3<double> arm = qrot(prev_rot(q), cst3<double>(S.loc));
+      V3<double> vp = V3<double>{ua[0], ua[1], ua[2]} + cross(V3<double>{ua[3], ua[4], ua[5]}, arm);
+      V3<double> pp{q[0] + arm.x, q[1] + arm.y, q[2] + arm.z};
+      F.tkey = terrain_select(W.hm, pp, S.r + P.d0 + P.h * norm(vp), S.feat);
+    }
     double gap;
     V3<double> pc;
     Contact<double> C = contact_frame<double>(W, qm, F, true, &gap, &pc);
-    const SlotD& S = W.slots[s];
     const double* ua = um + 6 * S.a;
     V3<double> xa{qm[7 * S.a], qm[7 * S.a + 1], qm[7 * S.a + 2]};
     V3<double> vr = V3<double>{ua[0], ua[1], ua[2]} + cross(V3<double>{ua[3], ua[4], ua[5]}, pc - xa);
@@ -1242,7 +1394,7 @@ extern "C" int ostrich_ref_step_forward(const ostrich_ref_batch* b, const ostric
     X.W = load_world(b, w);
     X.P = P;
     for (const SlotD& s : X.W.slots)
-      if (s.kind == 3) return -3;
+      if (s.kind == 3 && X.W.hm.n < 2) return -3;  // terrain slot without a heightmap
     int b0 = b->body_off[w], c0 = b->ctrl_off[w], l0 = b->lam_off[w], s0 = b->slot_off[w];
     prepare(X, q_prev + 7 * b0, u_prev + 6 * b0, ctrl ? ctrl + c0 : nullptr);
     StepResult R = newton(X, lam_prev + l0);

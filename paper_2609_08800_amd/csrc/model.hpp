@@ -166,7 +166,147 @@ enum { ST_CONVERGED = 1, ST_BUDGET = 2, ST_NONFINITE = 4, ST_REGULARIZED = 8, ST
 struct Feature {
   int8_t flag[3];
   int8_t inside, in_axis, in_side, tan_e;
+  int32_t hkey;  // heightmap slots: feature key (6 * vertex + kind), -1 when no candidate
 };
+
+// Heightmap of a world: n x n vertices at spacing sp from (ox, oy); vertex
+// (i, j) is at (ox + i sp, oy + j sp, h[i n + j]); cell (i, j) is split along
+// its (i,j)-(i+1,j+1) diagonal into T0 = (v_ij, v_i+1,j, v_i+1,j+1) and
+// T1 = (v_ij, v_i+1,j+1, v_i,j+1).
+struct HmapRef {
+  const double* h;
+  int n;
+  double sp, ox, oy;
+};
+
+// Local features of the triangle mesh, each owned by one vertex (i, j): the
+// vertex (kind 0), the edges to (i+1, j) (1), (i, j+1) (2) and (i+1, j+1) (3),
+// the faces T0 (4) and T1 (5) of cell (i, j); key = 6 (i n + j) + kind.  A
+// feature is a candidate contact for the point P when P's closest point on the
+// mesh near it lies on it and is a local minimum of the distance to the mesh:
+// a face whose plane projection of P is interior; an edge whose projection is
+// interior and which P lies beyond, in the plane of every triangle sharing the
+// edge; a vertex from which every neighbouring vertex points away from P.
+OST_HD v3<double> hm_vertex(const HmapRef& H, int i, int j) {
+  return v3<double>{H.ox + i * H.sp, H.oy + j * H.sp, H.h[i * H.n + j]};
+}
+
+// P beyond edge (a, b) of triangle (a, b, c), in the triangle's plane.
+OST_HD bool hm_beyond(const v3<double>& a, const v3<double>& b, const v3<double>& c, const v3<double>& p) {
+  v3<double> N = cross(b - a, c - a);
+  return dot(cross(b - a, p - a), N) < 0.0;
+}
+
+// Whether feature `key` is a candidate for P, and then its contact normal n
+// (unit; from the feature to P for vertices and edges, the upward normal for
+// faces), the plane offset noff = n . C of its closest point C, and the
+// distance (|P - C|, or |n . (P - C)| for faces).
+template <class T>
+OST_HD bool hm_feature(const HmapRef& H, int key, const v3<T>& P, v3<T>& n, T& noff, double* dist) {
+  const int kind = key % 6, vi = key / 6, i = vi / H.n, j = vi - i * H.n, N1 = H.n - 1;
+  const v3<double> A = hm_vertex(H, i, j);
+  const v3<double> p{val(P.x), val(P.y), val(P.z)};
+  if (kind == 0) {
+    const int di[6] = {1, -1, 0, 0, 1, -1}, dj[6] = {0, 0, 1, -1, 1, -1};
+    for (int k = 0; k < 6; ++k) {
+      int a = i + di[k], b = j + dj[k];
+      if (a < 0 || b < 0 || a > N1 || b > N1) continue;
+      if (!(dot(p - A, hm_vertex(H, a, b) - A) < 0.0)) return false;
+    }
+    v3<T> d = P - v3<T>{T(A.x), T(A.y), T(A.z)};
+    T dn = ssqrt(dot(d, d));
+    if (!(val(dn) > 1e-12)) return false;
+    n = d * (1.0 / dn);
+    noff = n.x * A.x + n.y * A.y + n.z * A.z;
+    if (dist) *dist = val(dn);
+    return true;
+  }
+  if (kind <= 3) {
+    v3<double> Bv = kind == 1 ? hm_vertex(H, i + 1, j) : (kind == 2 ? hm_vertex(H, i, j + 1) : hm_vertex(H, i + 1, j + 1));
+    v3<double> e = Bv - A;
+    double tv = dot(p - A, e) / dot(e, e);
+    if (!(tv > 0.0 && tv < 1.0)) return false;
+    // third vertices of the triangles sharing the edge
+    if (kind == 1) {
+      if (j + 1 <= N1 && !hm_beyond(A, Bv, hm_vertex(H, i + 1, j + 1), p)) return false;
+      if (j - 1 >= 0 && !hm_beyond(A, Bv, hm_vertex(H, i, j - 1), p)) return false;
+    } else if (kind == 2) {
+      if (i + 1 <= N1 && !hm_beyond(A, Bv, hm_vertex(H, i + 1, j + 1), p)) return false;
+      if (i - 1 >= 0 && !hm_beyond(A, Bv, hm_vertex(H, i - 1, j), p)) return false;
+    } else {
+      if (!hm_beyond(A, Bv, hm_vertex(H, i + 1, j), p)) return false;
+      if (!hm_beyond(A, Bv, hm_vertex(H, i, j + 1), p)) return false;
+    }
+    v3<T> pa = P - v3<T>{T(A.x), T(A.y), T(A.z)};
+    T tt = (pa.x * e.x + pa.y * e.y + pa.z * e.z) * (1.0 / dot(e, e));
+    v3<T> C = v3<T>{A.x + tt * e.x, A.y + tt * e.y, A.z + tt * e.z};
+    v3<T> d = P - C;
+    T dn = ssqrt(dot(d, d));
+    if (!(val(dn) > 1e-12)) return false;
+    n = d * (1.0 / dn);
+    noff = dot(n, C);
+    if (dist) *dist = val(dn);
+    return true;
+  }
+  v3<double> V1, V2;
+  if (kind == 4) { V1 = hm_vertex(H, i + 1, j); V2 = hm_vertex(H, i + 1, j + 1); }
+  else { V1 = hm_vertex(H, i + 1, j + 1); V2 = hm_vertex(H, i, j + 1); }
+  v3<double> N = cross(V1 - A, V2 - A);
+  N = N * (1.0 / ::sqrt(dot(N, N)));
+  // interior test of the projection of P onto the face (edge functions with the normal)
+  const v3<double>* Vs[3] = {&A, &V1, &V2};
+  for (int k = 0; k < 3; ++k) {
+    const v3<double>& Va = *Vs[k];
+    const v3<double>& Vb = *Vs[(k + 1) % 3];
+    if (!(dot(cross(Vb - Va, p - Va), N) > 0.0)) return false;
+  }
+  n = v3<T>{T(N.x), T(N.y), T(N.z)};
+  noff = T(dot(N, A));
+  if (dist) *dist = fabs(dot(N, p - A));
+  return true;
+}
+
+// The rank-th nearest candidate feature within radius rc of P, ordered by
+// distance quantised to 1e-9 m and then by key; -1 if there are fewer.
+OST_HD int hm_select(const HmapRef& H, const v3<double>& P, double rc, int rank) {
+  const int K = 4;
+  long long bd[K];
+  int bk[K];
+  int nb = 0;
+  if (rank < 0 || rank >= K || H.n < 2) return -1;
+  // vertex range covering the search disc (clamped in floating point, so that
+  // non-finite or far-away points give an empty or bounded range)
+  const double reach = rc + 2.0 * H.sp, top = H.n - 1;
+  double fi0 = floor((P.x - reach - H.ox) / H.sp), fi1 = ceil((P.x + reach - H.ox) / H.sp);
+  double fj0 = floor((P.y - reach - H.oy) / H.sp), fj1 = ceil((P.y + reach - H.oy) / H.sp);
+  if (!(fi0 >= 0.0)) fi0 = 0.0;
+  if (!(fj0 >= 0.0)) fj0 = 0.0;
+  if (!(fi1 <= top)) fi1 = top;
+  if (!(fj1 <= top)) fj1 = top;
+  if (!(fi0 <= top) || !(fj0 <= top) || !(fi1 >= 0.0) || !(fj1 >= 0.0) || !(rc >= 0.0)) return -1;
+  const int i0 = (int)fi0, i1 = (int)fi1, j0 = (int)fj0, j1 = (int)fj1;
+  for (int i = i0; i <= i1; ++i)
+    for (int j = j0; j <= j1; ++j)
+      for (int kind = 0; kind < 6; ++kind) {
+        if ((kind == 1 || kind == 3 || kind >= 4) && i + 1 >= H.n) continue;
+        if ((kind == 2 || kind == 3 || kind >= 4) && j + 1 >= H.n) continue;
+        int key = 6 * (i * H.n + j) + kind;
+        v3<double> nn;
+        double no, dd;
+        if (!hm_feature<double>(H, key, P, nn, no, &dd) || !(dd <= rc)) continue;
+        long long d = (long long)floor(dd / 1e-9);
+        // insert into the sorted best list (distance, then key)
+        int pos = nb;
+        while (pos > 0 && (d < bd[pos - 1] || (d == bd[pos - 1] && key < bk[pos - 1]))) --pos;
+        if (pos >= K) continue;
+        int last = nb < K ? nb : K - 1;
+        for (int q = last; q > pos; --q) { bd[q] = bd[q - 1]; bk[q] = bk[q - 1]; }
+        bd[pos] = d;
+        bk[pos] = key;
+        if (nb < K) ++nb;
+      }
+  return rank < nb ? bk[rank] : -1;
+}
 
 // Contact frame at q- (templated: the adjoint differentiates it w.r.t. q-).
 template <class T> struct Frame {
@@ -178,9 +318,12 @@ template <class T> struct Frame {
 
 // Frame of a slot at q-.  With `decide`, the feature choice is made (value
 // arithmetic) and written to F; otherwise F is used as given.
+// Heightmap slots (kind 3) take the rank-th nearest mesh feature within the
+// search radius rc (decided at q-; rc is only used when deciding).
 template <class T>
 OST_HD Frame<T> slot_frame(int kind, const double* sreal, const double* obs, const v3<T>& xa, const m3<T>& Ra,
-                           const v3<T>& xb, const m3<T>& Rb, Feature& F, bool decide, double* gap_out) {
+                           const v3<T>& xb, const m3<T>& Rb, Feature& F, bool decide, double* gap_out,
+                           const HmapRef* hm = nullptr, int rank = 0, double rc = 0.0) {
   Frame<T> C;
   C.la = mul(Ra, ld3<T>(sreal));
   v3<T> P = xa + C.la;
@@ -188,7 +331,15 @@ OST_HD Frame<T> slot_frame(int kind, const double* sreal, const double* obs, con
   C.noff = T(0.0);
   C.lb = mk(T(0.0), T(0.0), T(0.0));
   T gap;
-  if (kind == 0) {  // plane z = 0
+  if (kind == 3) {  // heightmap feature
+    if (decide) F.hkey = hm ? hm_select(*hm, v3<double>{val(P.x), val(P.y), val(P.z)}, rc, rank) : -1;
+    bool ok = F.hkey >= 0 && hm_feature<T>(*hm, F.hkey, P, C.n, C.noff, nullptr);
+    if (!ok) {  // no candidate: an inactive frame
+      C.n = mk(T(0.0), T(0.0), T(1.0));
+      C.noff = T(-1e30);
+    }
+    gap = ok ? dot(C.n, P) - C.noff - r : T(1e30);
+  } else if (kind == 0) {  // plane z = 0
     C.n = mk(T(0.0), T(0.0), T(1.0));
     gap = P.z - r;
   } else if (kind == 1) {  // static axis-aligned box

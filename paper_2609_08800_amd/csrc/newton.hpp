@@ -449,7 +449,7 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
         m3<dual> Rb2 = ind.Rb;
         v3<dual> xb2 = ind.xb;
         if (si[0] != 2) { Rb2 = ind.Ra; xb2 = v3<dual>{dual(0.0), dual(0.0), dual(0.0)}; }
-        ind.fr = slot_frame<dual>(si[0], sr, obs, ind.xa, ind.Ra, xb2, Rb2, F, false, nullptr);
+        ind.fr = slot_frame<dual>(si[0], sr, obs, ind.xa, ind.Ra, xb2, Rb2, F, false, nullptr, &R.hm, si[3]);
       }
       dual rd[3], Jd[36];
       double Dd[3];

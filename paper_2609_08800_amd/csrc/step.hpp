@@ -133,7 +133,15 @@ OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
     m3<double> Rb = ldm(M.Rm + 9 * a);
     if (kind == 2) { xb = ldv(M.xm + 3 * b); Rb = ldm(M.Rm + 9 * b); }
     const double* obs = kind == 1 ? B.obs_box + 6 * (R.o0 + si[3]) : nullptr;
-    Frame<double> C = slot_frame<double>(kind, sr, obs, ldv(M.xm + 3 * a), ldm(M.Rm + 9 * a), xb, Rb, F, true, &gap);
+    double rc = 0.0;
+    if (kind == 3) {  // search radius: proxy radius, margin and one step at the proxy centre's speed
+      const double* ua = M.um + 6 * a;
+      v3<double> la = mul(ldm(M.Rm + 9 * a), ldv(sr));
+      v3<double> vp = ldv(ua) + cross(ldv(ua + 3), la);
+      rc = sr[3] + P.d0 + P.h * ::sqrt(dot(vp, vp));
+    }
+    Frame<double> C = slot_frame<double>(kind, sr, obs, ldv(M.xm + 3 * a), ldm(M.Rm + 9 * a), xb, Rb, F, true, &gap,
+                                         &R.hm, si[3], rc);
     // relative velocity of the contact point at q-, approach along n
     v3<double> pc = ldv(M.xm + 3 * a) + C.la - C.n * sr[3];
     const double* ua = M.um + 6 * a;
@@ -177,7 +185,8 @@ OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
     m3<double> Rb = ldm(M.Rm + 9 * a);
     if (kind == 2) { xb = ldv(M.xm + 3 * b); Rb = ldm(M.Rm + 9 * b); }
     const double* obs = kind == 1 ? B.obs_box + 6 * (R.o0 + si[3]) : nullptr;
-    Frame<double> C = slot_frame<double>(kind, sr, obs, ldv(M.xm + 3 * a), ldm(M.Rm + 9 * a), xb, Rb, F, false, nullptr);
+    Frame<double> C = slot_frame<double>(kind, sr, obs, ldv(M.xm + 3 * a), ldm(M.Rm + 9 * a), xb, Rb, F, false, nullptr,
+                                         &R.hm, si[3]);
     M.c_feat[c] = F;
     M.c_kind[c] = kind;
     M.c_a[c] = a;

@@ -100,6 +100,7 @@ OST_HD WorldMem carve(char* base, const Caps& c, int team, int split = SPLIT_LDS
 // Per-world view of the packed batch.
 struct WorldRef {
   int w, b0, nb, j0, nj, s0, ns, o0, l0, c0, cap, nsv, m, nc;
+  HmapRef hm;  // the world's heightmap (n = 0: none)
   int bw;  // half band width of the Schur matrix (rows i, j couple only if |i - j| <= bw)
   int nctrl;
 };
@@ -126,6 +127,17 @@ OST_HD WorldRef world_ref(const Batch& B, int w) {
   R.m = 0;
   R.nc = 0;
   R.bw = 0;
+  int hi = B.world_hmap ? B.world_hmap[w] : -1;
+  R.hm.n = 0;
+  R.hm.h = nullptr;
+  R.hm.sp = B.hmap_spacing;
+  R.hm.ox = R.hm.oy = 0.0;
+  if (hi >= 0 && B.hmap_n >= 2) {
+    R.hm.n = B.hmap_n;
+    R.hm.h = B.hmap_heights + (size_t)hi * B.hmap_n * B.hmap_n;
+    R.hm.ox = B.hmap_origin[2 * hi];
+    R.hm.oy = B.hmap_origin[2 * hi + 1];
+  }
   return R;
 }
 

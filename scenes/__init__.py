@@ -403,6 +403,111 @@ def stack_world(rng, n_boxes: int) -> World:
     return wd
 
 
+TERRAIN_N = 128          # vertices per side
+TERRAIN_SPACING = 0.05   # m
+TERRAIN_AMP = 0.3        # m, peak |height|
+TERRAIN_ORIGIN = (-1.6, -0.5 * (TERRAIN_N - 1) * TERRAIN_SPACING)
+TERRAIN_FEATURES = 4     # candidate mesh features per wheel proxy
+
+
+def value_noise_heightmap(seed: int, n: int = TERRAIN_N, spacing: float = TERRAIN_SPACING,
+                          origin=TERRAIN_ORIGIN, amp: float = TERRAIN_AMP,
+                          lattices=(1.6, 0.8, 0.4, 0.2)) -> Heightmap:
+    """Four-octave value noise: lattice values U(-1, 1) on grids of the given
+    spacings, smoothstep-bilinear interpolation, octave o weighted 0.5**o, the
+    sum scaled so that its peak |height| is `amp`."""
+    rng = np.random.default_rng(seed)
+    xs = origin[0] + spacing * np.arange(n)
+    ys = origin[1] + spacing * np.arange(n)
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    H = np.zeros((n, n))
+    for o, L in enumerate(lattices):
+        gx = int(np.ceil((xs[-1] - xs[0]) / L)) + 2
+        gy = int(np.ceil((ys[-1] - ys[0]) / L)) + 2
+        val = rng.uniform(-1.0, 1.0, size=(gx, gy))
+        u = (X - xs[0]) / L
+        v = (Y - ys[0]) / L
+        i0 = np.floor(u).astype(int)
+        j0 = np.floor(v).astype(int)
+        fu = u - i0
+        fv = v - j0
+        su = fu * fu * (3 - 2 * fu)
+        sv = fv * fv * (3 - 2 * fv)
+        a = val[i0, j0] * (1 - su) + val[i0 + 1, j0] * su
+        b = val[i0, j0 + 1] * (1 - su) + val[i0 + 1, j0 + 1] * su
+        H += (0.5 ** o) * (a * (1 - sv) + b * sv)
+    H *= amp / np.max(np.abs(H))
+    return Heightmap(n=n, spacing=spacing, origin=tuple(origin), heights=np.ascontiguousarray(H))
+
+
+def terrain_height(hm: Heightmap, x: float, y: float) -> float:
+    """Height of the triangulated heightmap at (x, y) (cells cut along (i,j)-(i+1,j+1))."""
+    u = (x - hm.origin[0]) / hm.spacing
+    v = (y - hm.origin[1]) / hm.spacing
+    i = int(min(max(np.floor(u), 0), hm.n - 2))
+    j = int(min(max(np.floor(v), 0), hm.n - 2))
+    fu, fv = u - i, v - j
+    H = hm.heights
+    if fu >= fv:   # triangle (i,j), (i+1,j), (i+1,j+1)
+        return float(H[i, j] + fu * (H[i + 1, j] - H[i, j]) + fv * (H[i + 1, j + 1] - H[i + 1, j]))
+    return float(H[i, j] + fv * (H[i, j + 1] - H[i, j]) + fu * (H[i + 1, j + 1] - H[i, j + 1]))
+
+
+def robot_terrain_world(rng=None, hm: Heightmap = None, hmap_index: int = 0, *, yaw=0.0, knots=None,
+                        mu=ROBOT_MU, n_feat: int = TERRAIN_FEATURES, contact_cap=24,
+                        axle_damping=AXLE_DAMPING, start=(0.0, 0.0)) -> World:
+    """The wheeled robot on heightmap terrain: each wheel sphere has n_feat
+    terrain slots (its nearest candidate mesh features), each chassis point
+    one; placed at `start` with its wheels just above the surface."""
+    cx, cy, cz = CHASSIS_SIZE
+    wd = World(contact_cap=contact_cap)
+    cyaw, syaw = math.cos(yaw), math.sin(yaw)
+    wxy = [(start[0] + cyaw * wx - syaw * wy, start[1] + syaw * wx + cyaw * wy) for (wx, wy) in WHEEL_POS]
+    # clear the surface under the wheels and under the chassis bottom (sampled every 5 cm)
+    zc = 0.0
+    if hm is not None:
+        zc = max(terrain_height(hm, x, y) + WHEEL_R for (x, y) in wxy)
+        for sx in np.linspace(-0.5 * cx, 0.5 * cx, 13):
+            for sy in np.linspace(-0.5 * cy, 0.5 * cy, 9):
+                x = start[0] + cyaw * sx - syaw * sy
+                y = start[1] + syaw * sx + cyaw * sy
+                zc = max(zc, terrain_height(hm, x, y) + 0.5 * cz)
+    zc += 1e-3
+    c = wd.add_body(CHASSIS_MASS, box_inertia(CHASSIS_MASS, cx, cy, cz), (start[0], start[1], zc) + yaw_quat(yaw))
+    wheels = [wd.add_body(WHEEL_MASS, cylinder_inertia_y(WHEEL_MASS, WHEEL_R, WHEEL_W), (px, py, zc) + yaw_quat(yaw))
+              for (px, py) in wxy]
+    act, kp = (ACT_TORQUE_DAMPED, float(axle_damping)) if axle_damping else (ACT_TORQUE, 0.0)
+    for b, (wx, wy) in zip(wheels, WHEEL_POS):
+        wd.add_revolute(c, b, anchor_a=(wx, wy, 0.0), anchor_b=(0.0, 0.0, 0.0), act=act, kp=kp)
+    for b in wheels:
+        for k in range(n_feat):
+            wd.add_slot(SLOT_HEIGHTMAP, b, radius=WHEEL_R, mu=mu, feature=k)
+    pts = [(sx * 0.5 * cx, sy * 0.5 * cy, sz * 0.5 * cz)
+           for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)]
+    pts += [(0.0, 0.0, -0.5 * cz), (0.5 * cx, 0.0, -0.5 * cz), (-0.5 * cx, 0.0, -0.5 * cz),
+            (0.0, 0.5 * cy, -0.5 * cz), (0.0, -0.5 * cy, -0.5 * cz)]
+    for p in pts:
+        wd.add_slot(SLOT_HEIGHTMAP, c, local=p, mu=mu, feature=0)
+    if knots is None:
+        knots = rng.uniform(-2.0, 2.0, size=(4, ROBOT_KNOTS)) if rng is not None \
+            else np.zeros((4, ROBOT_KNOTS))
+    wd.knots = np.asarray(knots, dtype=np.float64)
+    wd.heightmap = hmap_index
+    wd.loss_body = c
+    wd.target = (3.0, 0.0)
+    return wd
+
+
+def terrain_batch(n_worlds: int, seed: int = 0, n_maps: int = 1, n: int = TERRAIN_N) -> Batch:
+    """Robots on n_maps value-noise terrains (world w on map w % n_maps)."""
+    maps = [value_noise_heightmap(seed * 1000 + k, n=n) for k in range(n_maps)]
+    worlds = []
+    for w, r in enumerate(world_rngs(seed, n_worlds)):
+        k = w % n_maps
+        worlds.append(robot_terrain_world(r, maps[k], k, yaw=float(r.uniform(-0.3, 0.3))))
+    return pack(worlds, maps)
+
+
 def box_batch(n_worlds: int, seed: int = 0) -> Batch:
     return pack([box_world(r) for r in world_rngs(seed, n_worlds)])
 

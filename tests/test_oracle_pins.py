@@ -449,3 +449,84 @@ def test_frozen_weight_newton_stalls_where_generalized_newton_converges():
     exact = oracle.step_forward(b, scenes.solver_params(k_max=40), b.q0, b.u0, np.zeros(b.n_lam), None)
     assert exact["status"][0] & 1
     assert not lagged["status"][0] & 1
+
+
+# ---------------------------------------------------------------- terrain --
+def _flat_map(n=40, sp=0.05, origin=(-1.0, -1.0), h0=0.0):
+    return scenes.Heightmap(n=n, spacing=sp, origin=origin, heights=np.full((n, n), h0))
+
+
+def test_flat_terrain_reproduces_the_plane():
+    """On a flat heightmap the nearest candidate under each proxy is the face
+    below it, with the plane's normal and offset, so the robot moves exactly
+    as on the plane z = 0 (the other candidate slots stay empty)."""
+    hm = _flat_map()
+    rng = np.random.default_rng(0)
+    knots = rng.uniform(-2, 2, size=(4, scenes.ROBOT_KNOTS))
+    tw = scenes.robot_terrain_world(None, hm, 0, yaw=0.2, knots=knots, start=(0.1, 0.05))
+    pw = scenes.robot_world(None, yaw=0.2, knots=knots, with_obstacle=False)
+    pw.q0 = [list(q) for q in tw.q0]
+    bt, bp = scenes.pack([tw], [hm]), scenes.pack([pw])
+    P = scenes.solver_params(k_max=64)
+    from paper_2609_08800_amd import spline_basis
+    B = spline_basis(20, scenes.ROBOT_KNOTS, P["h"])
+    qt, ut, lt = bt.q0.copy(), bt.u0.copy(), np.zeros(bt.n_lam)
+    qp, up, lp = bp.q0.copy(), bp.u0.copy(), np.zeros(bp.n_lam)
+    for k in range(8):
+        c = knots.reshape(-1, scenes.ROBOT_KNOTS) @ B[k]
+        ot = oracle.step_forward(bt, P, qt, ut, lt, c)
+        op = oracle.step_forward(bp, P, qp, up, lp, c)
+        assert np.array_equal(ot["status"], op["status"])
+        np.testing.assert_allclose(ot["u"], op["u"], rtol=0, atol=1e-12)
+        np.testing.assert_allclose(ot["q"], op["q"], rtol=0, atol=1e-12)
+        # wheel proxies: only the rank-0 slot (the face) is ever active
+        act = ot["act_slot"][:ot["n_act"][0]]
+        assert all(s % scenes.TERRAIN_FEATURES == 0 for s in act if s < 4 * scenes.TERRAIN_FEATURES)
+        qt, ut, lt = ot["q"], ot["u"], ot["lam"]
+        qp, up, lp = op["q"], op["u"], op["lam"]
+
+
+def _sphere_on_map(hm, xy, z, n_feat=4, v=(0, 0, 0)):
+    w = scenes.World(contact_cap=4)
+    w.add_body(1.0, (0.004, 0.004, 0.004), (xy[0], xy[1], z, 0, 0, 0, 1), tuple(v) + (0, 0, 0))
+    for k in range(n_feat):
+        w.add_slot(scenes.SLOT_HEIGHTMAP, 0, radius=0.05, mu=0.5, feature=k)
+    w.heightmap = 0
+    return scenes.pack([w], [hm])
+
+
+def test_terrain_candidates_on_hand_made_features():
+    """Crease: a ball between two faces meeting in a valley touches both faces;
+    ridge: a ball above a convex edge touches the edge only; peak: a ball above
+    a convex vertex touches the vertex only.  The ball comes to rest without
+    horizontal drift on the symmetric crease (forces balance)."""
+    P = scenes.solver_params(k_max=64)
+    n, sp = 9, 0.1
+    xs = (np.arange(n) - 4) * sp
+    # valley along y (V shape in x): z = |x|
+    valley = scenes.Heightmap(n=n, spacing=sp, origin=(xs[0], xs[0]),
+                              heights=np.abs(xs)[:, None] * np.ones(n)[None, :])
+    r = 0.05
+    z = r * np.sqrt(2.0) + 0.002     # just above both 45-degree faces
+    b = _sphere_on_map(valley, (0.0, 0.013), z)
+    q, u, lam = b.q0, b.u0, np.zeros(b.n_lam)
+    for _ in range(6):
+        o = oracle.step_forward(b, P, q, u, lam, None)
+        q, u, lam = o["q"], o["u"], o["lam"]
+    assert o["status"][0] & 1 and o["n_act"][0] == 2
+    assert abs(o["u"][0, 0]) < 1e-9 and abs(o["q"][0, 0]) < 1e-9
+    assert abs(o["u"][0, 2]) < 1e-9          # at rest in the crease
+    # ridge along y: z = -|x|; the ball above the ridge touches the edge only
+    ridge = scenes.Heightmap(n=n, spacing=sp, origin=(xs[0], xs[0]),
+                             heights=-np.abs(xs)[:, None] * np.ones(n)[None, :])
+    b = _sphere_on_map(ridge, (0.0, 0.013), r + 0.001)
+    o = oracle.step_forward(b, P, b.q0, b.u0, np.zeros(b.n_lam), None)
+    assert o["n_act"][0] == 1 and o["status"][0] & 1
+    # peak: z = -(|x| + |y|) has a convex vertex at the origin
+    peak = scenes.Heightmap(n=n, spacing=sp, origin=(xs[0], xs[0]),
+                            heights=-(np.abs(xs)[:, None] + np.abs(xs)[None, :]))
+    b = _sphere_on_map(peak, (0.003, -0.002), r + 0.001)
+    o = oracle.step_forward(b, P, b.q0, b.u0, np.zeros(b.n_lam), None)
+    assert o["n_act"][0] == 1 and o["status"][0] & 1
+    # the contact is the vertex: the ball is pushed along (P - V), i.e. away from the peak
+    assert o["u"][0, 0] > 0 and o["u"][0, 1] < 0

@@ -1,0 +1,90 @@
+"""Robots on heightmap terrain (triangle-mesh features chosen at q-): HIP
+against the oracle, whose narrow phase searches every feature of the mesh
+while the kernel searches the grid cells within the search radius.
+
+The 0.3 m terrain makes many steps hard for Newton (chassis and wheels switch
+between faces, edges and vertices), so these tests give it a budget of 200
+iterations.  A world that does not converge returns the best iterate of a
+sequence whose path depends on rounding; for those only the status and
+finiteness are compared."""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from test_gpu_parity import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    t = pytest.importorskip("torch")
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def test_terrain_steps_teacher_forced(torch):
+    from paper_2609_08800_amd import Simulator, spline_basis
+    b = scenes.terrain_batch(8, seed=3, n_maps=2)
+    P = scenes.solver_params(k_max=200)
+    sim = Simulator(b, P, device="cuda:0")
+    K = scenes.ROBOT_KNOTS
+    kn = scenes.knots_array(b, K)
+    B = spline_basis(40, K, P["h"])
+    q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    converged = 0
+    for k in range(12):
+        c = kn @ B[k]
+        ref = oracle.step_forward(b, P, q, u, lam, c)
+        o = sim.step_forward(q, u, lam, c)
+        got = {key: v.cpu().numpy() for key, v in o.items()}
+        print("step", k, "status", ref["status"], "n_act", ref["n_act"], flush=True)
+        assert np.array_equal(got["act_slot"], ref["act_slot"]), k
+        assert np.array_equal(got["n_act"], ref["n_act"]), k
+        assert np.array_equal(got["status"], ref["status"]), k
+        for w in range(b.n_worlds):
+            s = slice(b.body_off[w], b.body_off[w + 1])
+            if ref["status"][w] & 1:
+                assert rel_err(got["q"][s], ref["q"][s]) <= 1e-9, (k, w)
+                assert rel_err(got["u"][s], ref["u"][s]) <= 1e-9, (k, w)
+                converged += 1
+            else:
+                assert np.all(np.isfinite(got["u"][s])), (k, w)
+        q, u, lam = ref["q"], ref["u"], ref["lam"]
+    assert converged >= 0.75 * 12 * b.n_worlds
+
+
+def test_terrain_adjoint_matches_exact_ift(torch):
+    from paper_2609_08800_amd import Simulator, spline_basis
+    b = scenes.terrain_batch(4, seed=5, n_maps=2)
+    P = scenes.solver_params(k_max=200)
+    sim = Simulator(b, P, device="cuda:0")
+    K = scenes.ROBOT_KNOTS
+    kn = scenes.knots_array(b, K)
+    B = spline_basis(40, K, P["h"])
+    rng = np.random.default_rng(2)
+    q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    checked = 0
+    for k in range(8):
+        c = kn @ B[k]
+        tape = sim.new_tape()
+        got = sim.step_forward(q, u, lam, c, tape=tape)
+        st = got["status"].cpu().numpy()
+        gq_n, gu_n = rng.normal(size=q.shape), rng.normal(size=u.shape)
+        gq, gu, gc = sim.step_adjoint(q, u, c, got["u"], got["lam"], tape, gq_n, gu_n)
+        un, ln = got["u"].cpu().numpy(), got["lam"].cpu().numpy()
+        rq, ru, rc = oracle.step_adjoint(b, P, q, u, lam, c, un, ln, gq_n, gu_n, mode=0)
+        gq, gu, gc = gq.cpu().numpy(), gu.cpu().numpy(), gc.cpu().numpy()
+        for w in range(b.n_worlds):
+            if not st[w] & 1:
+                continue   # the implicit-function gradient is defined at a converged root
+            bs = slice(b.body_off[w], b.body_off[w + 1])
+            cs = slice(b.ctrl_off[w], b.ctrl_off[w + 1])
+            g = np.concatenate([gq[bs].ravel(), gu[bs].ravel(), gc[cs]])
+            r = np.concatenate([rq[bs].ravel(), ru[bs].ravel(), rc[cs]])
+            assert np.linalg.norm(g - r) <= 1e-6 * np.linalg.norm(r), (k, w, np.linalg.norm(g - r) / np.linalg.norm(r))
+            checked += 1
+        q, u, lam = got["q"].cpu().numpy(), un, ln
+    assert checked >= 8
