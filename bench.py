@@ -69,6 +69,32 @@ def cpu_baseline(T=100, worlds_per_core=24):
                       f"one process per core, {wall:.1f} s wall"}
 
 
+def serving_measurement(rate, duration, drain, seed=0, capacity=4096, budget_gb=96.0, hmap_slots=64):
+    """Poisson arrivals of trajectory-optimisation requests (robots on their
+    own value-noise terrain, 1..256 worlds, T in 20..100, 10 iterations of
+    forward + adjoint + Adam) served with continuous batching; per-iteration
+    latency percentiles and served world-steps/s."""
+    import scenes
+    from paper_2609_08800_amd.serving import GpuBackend, Request, ServingEngine, poisson_arrivals
+    P = scenes.solver_params()
+    base = scenes.value_noise_heightmap(10_000)
+    tmpl = scenes.robot_terrain_world(None, base, 0)
+    be = GpuBackend(tmpl, capacity, P, scenes.ROBOT_KNOTS, heightmaps=[base], heightmap_slots=hmap_slots)
+    rng = np.random.default_rng(seed)
+    arrivals = poisson_arrivals(rate, duration, seed)
+    reqs = [Request(i, scenes.terrain_request_batch(1000 * seed + i, int(rng.integers(1, 257))),
+                    T=int(rng.integers(20, 101)), iters=10, lr=0.1, arrival=t) for i, t in enumerate(arrivals)]
+    eng = ServingEngine(be, budget_gb * 1e9)
+    out = eng.run(reqs, deadline=duration + drain)
+    lat = [x for r in out["requests"] + [r for r in out["unfinished"] if r.slot0 >= 0] for x in r.iter_latency]
+    return {"rate_req_per_s": rate, "arrival_window_s": duration, "requests": len(reqs),
+            "completed": len(out["requests"]), "iterations": len(lat),
+            "iter_latency_p50_ms": round(1e3 * float(np.percentile(lat, 50)), 1) if lat else None,
+            "iter_latency_p99_ms": round(1e3 * float(np.percentile(lat, 99)), 1) if lat else None,
+            "served_world_steps_per_s": round(out["world_steps_per_s"], 1), "ticks": out["ticks"],
+            "wall_s": round(out["wall_s"], 1), "pool_worlds": capacity}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +105,9 @@ def main():
     ap.add_argument("--ckpt", type=int, default=10)
     ap.add_argument("--team", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=1.0, help="request arrivals per second (0: skip serving)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="arrival window of the serving run")
+    ap.add_argument("--serve-drain", type=float, default=40.0, help="extra time to finish admitted requests")
     ap.add_argument("--roofline-only", action="store_true",
                     help="skip the timed rollouts; run only the per-launch forward measurement "
                          "(for hardware-counter runs)")
@@ -166,12 +195,15 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
                 "kernel": "k_forward", "avg_launch_ms": round(avg_ms, 4),
                 "flop_per_launch": flops / T}
+    serving = None
+    if args.serve_rate > 0 and not args.roofline_only:
+        serving = serving_measurement(args.serve_rate, args.serve_seconds, args.serve_drain)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline()
     iters_all = np.array(iters_all)
     line = {
-        "metric": "fwd+adjoint world-steps/s at 8192 worlds (FP64)",
+        "metric": "fwd+adjoint world-steps/s at 8192 worlds (FP64); p50/p99 served iter latency",
         "value": round(value, 2) if not args.roofline_only else None,
         "unit": "world-steps/s",
         "n_gpus": 1,
@@ -192,7 +224,8 @@ def main():
                   "forward_only_world_steps_per_s": round(W / (avg_ms * 1e-3), 1),
                   "mean_newton_iters": round(float(iters_all.mean()), 3),
                   "frac_converged": round(float(np.mean(status & 1)), 4),
-                  "mean_rows": round(float(np.mean(m_all)), 2)},
+                  "mean_rows": round(float(np.mean(m_all)), 2),
+                  "serving": serving},
     }
     print(json.dumps(line))
 

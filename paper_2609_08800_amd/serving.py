@@ -131,7 +131,10 @@ class ServingEngine:
         self.ticks = []          # per tick: (time, n_forward_worlds, n_backward_worlds, request ids)
         self.world_steps = 0     # forward world-steps (each with its adjoint step)
 
-    def run(self, requests: List[Request]) -> Dict:
+    def run(self, requests: List[Request], deadline: float = math.inf) -> Dict:
+        """Serve the requests (arrival times relative to now).  With a deadline
+        (seconds), stop when it passes: requests still pending or active are
+        reported as unfinished and their device memory is released."""
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         active: List[Request] = []
         done: List[Request] = []
@@ -139,6 +142,8 @@ class ServingEngine:
         tick = 0
         while (pending or active) and tick < self.max_ticks:
             now = self.clock() - t0
+            if now > deadline:
+                break
             if not active and pending and pending[0].arrival > now:
                 self.be.idle(pending[0].arrival - now)
                 now = self.clock() - t0
@@ -148,7 +153,7 @@ class ServingEngine:
                 need = self.be.request_bytes(r)
                 if need > self.budget:
                     raise ValueError(f"request {r.rid} needs {need:.3g} B, more than the HBM budget")
-                if self.used + need > self.budget:
+                if self.used + need > self.budget or not self.be.can_admit(r):
                     break
                 s = self.slots.alloc(r.n_worlds)
                 if s < 0:
@@ -195,8 +200,13 @@ class ServingEngine:
                             r.phase, r.k = 0, 0
                             r.iter_started = now
         wall = self.clock() - t0
-        lat = [x for r in done for x in r.iter_latency]
-        return {"requests": done, "wall_s": wall, "ticks": len(self.ticks),
+        for r in active:
+            self.be.release(r)
+            self.used -= self.be.request_bytes(r)
+            self.slots.release(r.slot0, r.n_worlds)
+        lat = [x for r in done + active for x in r.iter_latency]
+        return {"requests": done, "unfinished": active + pending, "wall_s": wall, "ticks": len(self.ticks),
+                "iterations": len(lat),
                 "iter_latency_p50_s": percentile(lat, 50), "iter_latency_p99_s": percentile(lat, 99),
                 "world_steps_per_s": self.world_steps / wall if wall > 0 else math.nan}
 
@@ -272,6 +282,11 @@ class GpuBackend:
 
     def idle(self, seconds: float):
         time.sleep(max(0.0, min(seconds, 0.05)))
+
+    def can_admit(self, r: Request) -> bool:
+        b = r.batch
+        needs_map = b.hmap_heights.size and np.any(b.world_hmap >= 0)
+        return bool(self.hmap_free) or not needs_map
 
     def _w(self, r):
         return slice(r.slot0, r.slot0 + r.n_worlds)
@@ -461,6 +476,9 @@ class FakeBackend:
 
     def request_bytes(self, r):
         return self.bpws * r.n_worlds * (r.T + 1)
+
+    def can_admit(self, r):
+        return True
 
     def idle(self, seconds):
         self.vtime += max(seconds, 0.0)

@@ -508,6 +508,15 @@ def terrain_batch(n_worlds: int, seed: int = 0, n_maps: int = 1, n: int = TERRAI
     return pack(worlds, maps)
 
 
+def terrain_request_batch(seed: int, n_worlds: int) -> Batch:
+    """One trajectory-optimisation request: n_worlds robots (seeded yaw and
+    knots) on the request's own value-noise terrain (heightmap index 0)."""
+    hm = value_noise_heightmap(10_000 + seed)
+    worlds = [robot_terrain_world(r, hm, 0, yaw=float(r.uniform(-0.3, 0.3)))
+              for r in world_rngs(seed, n_worlds)]
+    return pack(worlds, [hm])
+
+
 def box_batch(n_worlds: int, seed: int = 0) -> Batch:
     return pack([box_world(r) for r in world_rngs(seed, n_worlds)])
 

@@ -92,3 +92,13 @@ def test_percentiles_and_arrivals():
     assert 120 < len(a) < 280
     _, _, out = run([Request(i, B(1), T=2, iters=2, arrival=t) for i, t in enumerate(a[:20])])
     assert out["iter_latency_p50_s"] <= out["iter_latency_p99_s"]
+
+
+def test_deadline_reports_unfinished_and_frees_memory():
+    reqs = [Request(i, B(4), T=50, iters=10, arrival=0.0) for i in range(3)]
+    be = FakeBackend(8, tick_seconds=0.01)
+    eng = ServingEngine(be, 1e12, clock=be.clock)
+    out = eng.run(reqs, deadline=2.0)
+    assert len(out["unfinished"]) == 3 - len(out["requests"])
+    assert out["unfinished"] and eng.used == 0.0 and eng.slots.n_free == 8
+    assert out["iterations"] >= 1

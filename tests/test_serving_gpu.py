@@ -85,3 +85,29 @@ def test_hbm_budget_serialises_requests(torch):
     spans = sorted((r.admitted_at, r.finished_at) for r in out["requests"])
     for (a0, f0), (a1, f1) in zip(spans, spans[1:]):
         assert a1 >= f0
+
+
+def test_terrain_requests_each_on_its_own_map(torch):
+    """Requests on different terrains share the pool and the launches; each
+    request's result equals serving it alone."""
+    from paper_2609_08800_amd.serving import GpuBackend, Request, ServingEngine
+    P = scenes.solver_params()
+    base = scenes.value_noise_heightmap(10_000)
+    tmpl = scenes.robot_terrain_world(None, base, 0)
+
+    def make(rid, n, T, arrival):
+        return Request(rid, scenes.terrain_request_batch(500 + rid, n), T=T, iters=2, arrival=arrival)
+
+    be = GpuBackend(tmpl, 24, P, K, heightmaps=[base], heightmap_slots=4)
+    alone = make(0, 3, 8, 0.0)
+    ServingEngine(be, 8e9).run([alone])
+    be2 = GpuBackend(tmpl, 24, P, K, heightmaps=[base], heightmap_slots=4)
+    mix = [make(0, 3, 8, 0.03), make(1, 5, 6, 0.0), make(2, 2, 10, 0.01), make(3, 4, 7, 0.05)]
+    eng = ServingEngine(be2, 8e9)
+    out = eng.run(mix)
+    assert len(out["requests"]) == 4
+    assert any(len(rids) >= 3 for _, _, _, rids in eng.ticks)
+    assert np.array_equal(alone.knots, mix[0].knots)
+    for a, c in zip(alone.losses, mix[0].losses):
+        assert np.array_equal(a, c)
+    assert sorted(be2.hmap_free) == [0, 1, 2, 3]
