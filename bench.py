@@ -69,6 +69,37 @@ def cpu_baseline(T=100, worlds_per_core=24):
                       f"one process per core, {wall:.1f} s wall"}
 
 
+def plain_path_measurement(n_worlds=64, T=5):
+    """World-steps/s (forward + adjoint) of the plain path: one launch per world
+    per Newton iteration, on a sample of the benchmark's robot worlds.  The
+    plain path runs its worlds one after another, so its rate does not depend
+    on how many worlds are sampled."""
+    import torch
+    import scenes
+    from paper_2609_08800_amd import Simulator, spline_basis
+    dev = torch.device("cuda:0")
+    P = scenes.solver_params()
+    b = scenes.robot_batch(n_worlds, seed=0)
+    sim = Simulator(b, P, device=dev)
+    K = scenes.ROBOT_KNOTS
+    ctrl_all = torch.as_tensor(scenes.knots_array(b, K) @ spline_basis(T, K, P["h"]).T, device=dev).T.contiguous()
+    q, u = torch.as_tensor(b.q0, device=dev), torch.as_tensor(b.u0, device=dev)
+    lam = torch.zeros(max(sim.NL, 1), dtype=torch.float64, device=dev)
+    gq = torch.zeros_like(q)
+    gu = torch.zeros_like(u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(T):
+        tape = sim.new_tape()
+        o = sim.step_forward(q, u, lam, ctrl_all[k], tape=tape, plain=True)
+        sim.step_adjoint(q, u, ctrl_all[k], o["u"], o["lam"], tape, gq, gu, plain=True)
+        q, u, lam = o["q"], o["u"], o["lam"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"world_steps_per_s": round(n_worlds * T / dt, 1), "sample": f"{n_worlds} robot worlds x {T} steps",
+            "launches_per_world_step": P["k_max"] + 3}
+
+
 def serving_measurement(rate, duration, drain, seed=0, capacity=4096, budget_gb=96.0, hmap_slots=64):
     """Poisson arrivals of trajectory-optimisation requests (robots on their
     own value-noise terrain, 1..256 worlds, T in 20..100, 10 iterations of
@@ -195,6 +226,10 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
                 "kernel": "k_forward", "avg_launch_ms": round(avg_ms, 4),
                 "flop_per_launch": flops / T}
+    plain = None
+    if not args.roofline_only:
+        plain = plain_path_measurement()
+        plain["batched_over_plain"] = round(value / plain["world_steps_per_s"], 1)
     serving = None
     if args.serve_rate > 0 and not args.roofline_only:
         serving = serving_measurement(args.serve_rate, args.serve_seconds, args.serve_drain)
@@ -225,6 +260,7 @@ def main():
                   "mean_newton_iters": round(float(iters_all.mean()), 3),
                   "frac_converged": round(float(np.mean(status & 1)), 4),
                   "mean_rows": round(float(np.mean(m_all)), 2),
+                  "plain_path": plain,
                   "serving": serving},
     }
     print(json.dumps(line))

@@ -184,6 +184,21 @@ int ostrich_step_adjoint_list(ostrich_ctx* ctx, const int32_t* worlds, int32_t n
                               const void* tape, const double* gq_next, const double* gu_next, double* gq_prev,
                               double* gu_prev, double* g_ctrl, int32_t refine, void* stream);
 
+/* The plain path, a comparison baseline with the same arguments and the same
+ * results (the same arithmetic, bit for bit): ostrich_step_forward_plain makes
+ * one launch per world per Newton iteration (plus one set-up and one
+ * finalisation launch per world, k_max + 2 in all), with the world's state in
+ * device memory between launches; ostrich_step_adjoint_plain makes one launch
+ * per world. */
+int ostrich_step_forward_plain(ostrich_ctx* ctx, const double* q_prev, const double* u_prev, const double* lam_prev,
+                               const double* ctrl, double* q_next, double* u_next, double* lam_next,
+                               int32_t* act_slot, int32_t* n_act, int32_t* status, int32_t* iters, double* resnorm,
+                               void* tape, void* stream);
+int ostrich_step_adjoint_plain(ostrich_ctx* ctx, const double* q_prev, const double* u_prev, const double* ctrl,
+                               const double* u_next, const double* lam_next, const void* tape, const double* gq_next,
+                               const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl,
+                               int32_t refine, void* stream);
+
 #define OSTRICH_FORWARD 1
 #define OSTRICH_BACKWARD 2
 

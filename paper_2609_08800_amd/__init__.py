@@ -163,8 +163,9 @@ class Simulator:
         return self._f64(ctrl, (self.NCTRL,))
 
     # ------------------------------------------------------------------- calls
-    def step_forward(self, q, u, lam, ctrl=None, tape=None, out=None, stream=None):
-        """One backward-Euler step of every world; returns a dict of device tensors."""
+    def step_forward(self, q, u, lam, ctrl=None, tape=None, out=None, stream=None, plain=False):
+        """One backward-Euler step of every world; returns a dict of device tensors.
+        plain=True runs the comparison baseline (one launch per world per Newton iteration)."""
         torch = self.torch
         q, u, lam = self._f64(q, (self.NB, 7)), self._f64(u, (self.NB, 6)), self._f64(lam)
         ctrl = self._ctrl(ctrl)
@@ -176,7 +177,8 @@ class Simulator:
                        status=torch.empty(self.W, dtype=torch.int32, device=self.device),
                        iters=torch.empty(self.W, dtype=torch.int32, device=self.device),
                        resnorm=torch.empty(self.W, dtype=torch.float64, device=self.device))
-        rc = self.lib.ostrich_step_forward(
+        fn = self.lib.ostrich_step_forward_plain if plain else self.lib.ostrich_step_forward
+        rc = fn(
             self.ctx, q.data_ptr(), u.data_ptr(), lam.data_ptr(), ctrl.data_ptr(), out["q"].data_ptr(),
             out["u"].data_ptr(), out["lam"].data_ptr(), out["act_slot"].data_ptr(), out["n_act"].data_ptr(),
             out["status"].data_ptr(), out["iters"].data_ptr(), out["resnorm"].data_ptr(), self._p(tape),
@@ -184,8 +186,9 @@ class Simulator:
         _capi.check(rc, "ostrich_step_forward")
         return out
 
-    def step_adjoint(self, q, u, ctrl, u_next, lam_next, tape, gq_next, gu_next, refine=-1, stream=None):
-        """Cotangents of (q-, u-, ctrl) from those of (q+, u+)."""
+    def step_adjoint(self, q, u, ctrl, u_next, lam_next, tape, gq_next, gu_next, refine=-1, stream=None,
+                     plain=False):
+        """Cotangents of (q-, u-, ctrl) from those of (q+, u+); plain=True: one launch per world."""
         torch = self.torch
         q, u = self._f64(q, (self.NB, 7)), self._f64(u, (self.NB, 6))
         ctrl = self._ctrl(ctrl)
@@ -194,7 +197,8 @@ class Simulator:
         gq = torch.empty_like(q)
         gu = torch.empty_like(u)
         gc = torch.zeros(max(self.NCTRL, 1), dtype=torch.float64, device=self.device)
-        rc = self.lib.ostrich_step_adjoint(
+        fn = self.lib.ostrich_step_adjoint_plain if plain else self.lib.ostrich_step_adjoint
+        rc = fn(
             self.ctx, q.data_ptr(), u.data_ptr(), ctrl.data_ptr(), u_next.data_ptr(), lam_next.data_ptr(),
             tape.data_ptr(), gq_next.data_ptr(), gu_next.data_ptr(), gq.data_ptr(), gu.data_ptr(), gc.data_ptr(),
             int(refine), self._stream(stream))

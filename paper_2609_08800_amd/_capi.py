@@ -83,6 +83,10 @@ def load() -> ctypes.CDLL:
     L.ostrich_step_forward_list.restype = c_int
     L.ostrich_step_adjoint_list.argtypes = [c_vp, c_vp, c_int] + [c_vp] * 11 + [c_int, c_vp]
     L.ostrich_step_adjoint_list.restype = c_int
+    L.ostrich_step_forward_plain.argtypes = [c_vp] + [c_vp] * 13 + [c_vp]
+    L.ostrich_step_forward_plain.restype = c_int
+    L.ostrich_step_adjoint_plain.argtypes = [c_vp] + [c_vp] * 11 + [c_int, c_vp]
+    L.ostrich_step_adjoint_plain.restype = c_int
     L.ostrich_spline_controls.argtypes = [c_vp, c_vp, c_int, c_int, c_int, c_vp, c_vp]
     L.ostrich_spline_controls.restype = c_int
     L.ostrich_final_loss.argtypes = [c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]

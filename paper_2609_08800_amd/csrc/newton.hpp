@@ -52,89 +52,128 @@ OST_HD void fb_scales(Team& t, const Batch& B, const Params& P, const WorldRef& 
   t.sync();
 }
 
-// One backward-Euler step of world w (Sec. III-A..C).
+// Progress of one world's Newton loop (identical in every thread of the team).
+struct FwState {
+  double nrm, bn;   // residual norm of the current and of the best iterate
+  int have, conv, iters, st, done;
+};
+
+// Step set-up of world w: contact refresh, warm start, FB scales and the
+// residual at the warm start (Sec. III-A, III-B).
 template <class Team>
-OST_HD void forward_world(Team& t, const Batch& B, const Params& P, const Caps& caps, int w, const double* q_prev,
-                          const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
-                          double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
-                          int32_t* iters_out, double* resnorm, double* tape, const int64_t* tape_off,
-                          WorldMem& M) {
-  WorldRef R = world_ref(B, w);
+OST_HD void fw_begin(Team& t, const Batch& B, const Params& P, WorldRef& R, const double* q_prev,
+                     const double* u_prev, const double* lam_prev, const double* ctrl, WorldMem& M, FwState& S) {
   prologue(t, B, P, R, q_prev, u_prev, ctrl, lam_prev, M);
   clamp_all(t, P, R, M, M.lam);
   fb_scales(t, B, P, R, M, ctrl);
-  const int nb = R.nb, m = R.m;
-  int st = M.iscal[1] ? ST_OVERFLOW : 0;
-  double nrm = evaluate(t, B, P, R, M, ctrl, M.u, M.lam, true);
-  for (int i = t.rank(); i < 6 * nb; i += t.size()) M.ubest[i] = M.u[i];
-  for (int i = t.rank(); i < m; i += t.size()) M.lambest[i] = M.lam[i];
-  double bn = nrm;
-  bool have = P.kmin == 0, conv = false;
-  int iters = 0;
-  if (!isfinite(nrm)) {
-    st |= ST_NONFINITE | ST_BUDGET;
-  } else if (nrm <= P.tol) {
-    conv = true;
-  } else {
-    for (int k = 1; k <= P.kmax; ++k) {
-      double dreg;
-      if (!factor(t, P, R, M, true, &dreg, &st)) { st |= ST_NONFINITE; break; }
-      for (int i = t.rank(); i < m; i += t.size()) M.dlam[i] = M.rhs[i];
-      t.sync();
-      lu_solve(t, R, M, M.dlam, false);
-      // Eq. (13): du = M~^-1 (h J^T dlambda - r_dyn), force per (body, component)
-      for (int e = t.rank(); e < 6 * nb; e += t.size()) {
-        int b = e / 6, q = e - 6 * b;
-        double v = -M.rdyn[e];
-        for (int i = 0; i < m; ++i) {
-          if (M.r_a[i] == b) v += P.h * M.J[12 * i + q] * M.dlam[i];
-          if (M.r_b[i] == b) v += P.h * M.J[12 * i + 6 + q] * M.dlam[i];
-        }
-        M.kg[e] = v;
-      }
-      t.sync();
-      for (int b = t.rank(); b < nb; b += t.size()) minv6(M, b, M.kg + 6 * b, M.du + 6 * b);
-      t.sync();
-      // step length: halve until the residual decreases by (1 - 1e-4 alpha), else the best trial
-      // (the full step is evaluated with the Newton rows, which are reused when it is accepted)
-      double alpha = 1.0, best_a = 1.0, best_n = INFINITY;
-      bool first_ok = false;
-      for (int ls = 0; ls <= P.ls_max; ++ls) {
-        for (int i = t.rank(); i < 6 * nb; i += t.size()) M.ut[i] = M.u[i] + alpha * M.du[i];
-        for (int i = t.rank(); i < m; i += t.size()) M.lamt[i] = M.lam[i] + alpha * M.dlam[i];
-        t.sync();
-        clamp_all(t, P, R, M, M.lamt);
-        double tn = evaluate(t, B, P, R, M, ctrl, M.ut, M.lamt, ls == 0);
-        bool ok = tn <= (1.0 - 1e-4 * alpha) * nrm;
-        if (tn < best_n || ok) { best_n = tn; best_a = alpha; }
-        if (ok) { first_ok = ls == 0; break; }
-        alpha *= 0.5;
-      }
-      if (first_ok) {
-        for (int i = t.rank(); i < 6 * nb; i += t.size()) M.u[i] = M.ut[i];
-        for (int i = t.rank(); i < m; i += t.size()) M.lam[i] = M.lamt[i];
-        t.sync();
-        nrm = best_n;
-      } else {
-        for (int i = t.rank(); i < 6 * nb; i += t.size()) M.u[i] = M.u[i] + best_a * M.du[i];
-        for (int i = t.rank(); i < m; i += t.size()) M.lam[i] = M.lam[i] + best_a * M.dlam[i];
-        t.sync();
-        clamp_all(t, P, R, M, M.lam);
-        nrm = evaluate(t, B, P, R, M, ctrl, M.u, M.lam, true);
-      }
-      iters = k;
-      if (!isfinite(nrm)) { st |= ST_NONFINITE; break; }
-      bool take = nrm <= P.tol || (k >= P.kmin && (!have || nrm < bn));
-      if (take) {
-        for (int i = t.rank(); i < 6 * nb; i += t.size()) M.ubest[i] = M.u[i];
-        for (int i = t.rank(); i < m; i += t.size()) M.lambest[i] = M.lam[i];
-        bn = nrm;
-        have = true;
-        t.sync();
-      }
-      if (nrm <= P.tol) { conv = true; break; }
-    }
+  S.st = M.iscal[1] ? ST_OVERFLOW : 0;
+  S.nrm = evaluate(t, B, P, R, M, ctrl, M.u, M.lam, true);
+  for (int i = t.rank(); i < 6 * R.nb; i += t.size()) M.ubest[i] = M.u[i];
+  for (int i = t.rank(); i < R.m; i += t.size()) M.lambest[i] = M.lam[i];
+  S.bn = S.nrm;
+  S.have = P.kmin == 0;
+  S.conv = 0;
+  S.iters = 0;
+  S.done = 0;
+  if (!isfinite(S.nrm)) {
+    S.st |= ST_NONFINITE | ST_BUDGET;
+    S.done = 1;
+  } else if (S.nrm <= P.tol) {
+    S.conv = 1;
+    S.done = 1;
   }
+  t.sync();
+}
+
+// Newton iteration k (Eqs. (12)-(13)): factor, solve, step length, friction
+// clamp, best-iterate bookkeeping (Sec. III-C).  Nothing happens once done.
+template <class Team>
+OST_HD void fw_iteration(Team& t, const Batch& B, const Params& P, const WorldRef& R, const double* ctrl,
+                         WorldMem& M, FwState& S, int k) {
+  if (S.done) return;
+  const int nb = R.nb, m = R.m;
+  double dreg;
+  if (!factor(t, P, R, M, true, &dreg, &S.st)) {
+    S.st |= ST_NONFINITE;
+    S.done = 1;
+    return;
+  }
+  for (int i = t.rank(); i < m; i += t.size()) M.dlam[i] = M.rhs[i];
+  t.sync();
+  lu_solve(t, R, M, M.dlam, false);
+  // Eq. (13): du = M~^-1 (h J^T dlambda - r_dyn), force per (body, component)
+  for (int e = t.rank(); e < 6 * nb; e += t.size()) {
+    int b = e / 6, q = e - 6 * b;
+    double v = -M.rdyn[e];
+    for (int i = 0; i < m; ++i) {
+      if (M.r_a[i] == b) v += P.h * M.J[12 * i + q] * M.dlam[i];
+      if (M.r_b[i] == b) v += P.h * M.J[12 * i + 6 + q] * M.dlam[i];
+    }
+    M.kg[e] = v;
+  }
+  t.sync();
+  for (int b = t.rank(); b < nb; b += t.size()) minv6(M, b, M.kg + 6 * b, M.du + 6 * b);
+  t.sync();
+  // step length: halve until the residual decreases by (1 - 1e-4 alpha), else the best trial
+  // (the full step is evaluated with the Newton rows, which are reused when it is accepted)
+  double alpha = 1.0, best_a = 1.0, best_n = INFINITY;
+  bool first_ok = false;
+  for (int ls = 0; ls <= P.ls_max; ++ls) {
+    for (int i = t.rank(); i < 6 * nb; i += t.size()) M.ut[i] = M.u[i] + alpha * M.du[i];
+    for (int i = t.rank(); i < m; i += t.size()) M.lamt[i] = M.lam[i] + alpha * M.dlam[i];
+    t.sync();
+    clamp_all(t, P, R, M, M.lamt);
+    double tn = evaluate(t, B, P, R, M, ctrl, M.ut, M.lamt, ls == 0);
+    bool ok = tn <= (1.0 - 1e-4 * alpha) * S.nrm;
+    if (tn < best_n || ok) { best_n = tn; best_a = alpha; }
+    if (ok) { first_ok = ls == 0; break; }
+    alpha *= 0.5;
+  }
+  if (first_ok) {
+    for (int i = t.rank(); i < 6 * nb; i += t.size()) M.u[i] = M.ut[i];
+    for (int i = t.rank(); i < m; i += t.size()) M.lam[i] = M.lamt[i];
+    t.sync();
+    S.nrm = best_n;
+  } else {
+    for (int i = t.rank(); i < 6 * nb; i += t.size()) M.u[i] = M.u[i] + best_a * M.du[i];
+    for (int i = t.rank(); i < m; i += t.size()) M.lam[i] = M.lam[i] + best_a * M.dlam[i];
+    t.sync();
+    clamp_all(t, P, R, M, M.lam);
+    S.nrm = evaluate(t, B, P, R, M, ctrl, M.u, M.lam, true);
+  }
+  S.iters = k;
+  if (!isfinite(S.nrm)) {
+    S.st |= ST_NONFINITE;
+    S.done = 1;
+    return;
+  }
+  bool take = S.nrm <= P.tol || (k >= P.kmin && (!S.have || S.nrm < S.bn));
+  if (take) {
+    for (int i = t.rank(); i < 6 * nb; i += t.size()) M.ubest[i] = M.u[i];
+    for (int i = t.rank(); i < m; i += t.size()) M.lambest[i] = M.lam[i];
+    S.bn = S.nrm;
+    S.have = 1;
+    t.sync();
+  }
+  if (S.nrm <= P.tol) {
+    S.conv = 1;
+    S.done = 1;
+  }
+}
+
+// Finalisation of world w (Sec. III-C, III-D): the Schur factor at the
+// returned iterate to the tape, q+ by Eq. (1) with the quaternion
+// renormalised, lambda+ in slot order, status.
+template <class Team>
+OST_HD void fw_end(Team& t, const Batch& B, const Params& P, const WorldRef& R, int w, const double* ctrl,
+                   double* q_next, double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act,
+                   int32_t* status, int32_t* iters_out, double* resnorm, double* tape, const int64_t* tape_off,
+                   WorldMem& M, const FwState& S0) {
+  const int nb = R.nb, m = R.m;
+  int st = S0.st;
+  const int iters = S0.iters;
+  const double bn = S0.bn;
+  const bool conv = S0.conv;
   st |= conv ? ST_CONVERGED : ST_BUDGET;
   // the tape holds the factor of the Schur matrix at the returned iterate
   if (tape) {
@@ -192,6 +231,53 @@ OST_HD void forward_world(Team& t, const Batch& B, const Params& P, const Caps& 
     if (resnorm) resnorm[w] = bn;
   }
   t.sync();
+}
+
+// One backward-Euler step of world w (Sec. III-A..C), fused: set-up, the
+// Newton loop and finalisation in one pass of the team.
+template <class Team>
+OST_HD void forward_world(Team& t, const Batch& B, const Params& P, const Caps& caps, int w, const double* q_prev,
+                          const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
+                          double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
+                          int32_t* iters_out, double* resnorm, double* tape, const int64_t* tape_off,
+                          WorldMem& M) {
+  WorldRef R = world_ref(B, w);
+  FwState S;
+  fw_begin(t, B, P, R, q_prev, u_prev, lam_prev, ctrl, M, S);
+  for (int k = 1; k <= P.kmax && !S.done; ++k) fw_iteration(t, B, P, R, ctrl, M, S, k);
+  fw_end(t, B, P, R, w, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters_out, resnorm, tape, tape_off,
+         M, S);
+}
+
+// Loop state kept in the world's workspace between the launches of the plain
+// path (one launch per world per Newton iteration).
+OST_HD void fw_store(const WorldMem& M, const FwState& S) {
+  M.dscal[0] = S.nrm;
+  M.dscal[1] = S.bn;
+  M.iscal[4] = S.have;
+  M.iscal[5] = S.conv;
+  M.iscal[6] = S.iters;
+  M.iscal[7] = S.st;
+  M.iscal[8] = S.done;
+}
+OST_HD FwState fw_load(const WorldMem& M) {
+  FwState S;
+  S.nrm = M.dscal[0];
+  S.bn = M.dscal[1];
+  S.have = M.iscal[4];
+  S.conv = M.iscal[5];
+  S.iters = M.iscal[6];
+  S.st = M.iscal[7];
+  S.done = M.iscal[8];
+  return S;
+}
+// The world view after its prologue, rebuilt from the workspace.
+OST_HD WorldRef world_ref_after(const Batch& B, const WorldMem& M, int w) {
+  WorldRef R = world_ref(B, w);
+  R.nc = M.iscal[0];
+  R.m = 5 * R.nj + R.nsv + 3 * R.nc;
+  R.bw = M.iscal[3];
+  return R;
 }
 
 // --------------------------------------------------------------------------

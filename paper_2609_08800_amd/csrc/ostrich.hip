@@ -76,6 +76,40 @@ struct GpuTeam {
   }
 };
 
+// Team whose workspace is (partly) in device memory.  A workgroup barrier
+// orders LDS only: each wave also waits for its own vector-memory operations
+// before the barrier, so that device-memory stores of one wave are complete
+// before other waves of the team read or overwrite them.
+struct GpuTeamG : GpuTeam {
+  __device__ void sync() const {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  __device__ double sum64(double v, double* scratch) const {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (blockDim.x == 64) return v;
+    if (threadIdx.x == 0) scratch[0] = v;
+    sync();
+    double r = scratch[0];
+    sync();
+    return r;
+  }
+  __device__ int imax(int v, double* scratch) const {
+    for (int off = 32; off > 0; off >>= 1) {
+      int o = __shfl_xor(v, off, 64);
+      v = o > v ? o : v;
+    }
+    int nw = (blockDim.x + 63) >> 6;
+    if (nw == 1) return v;
+    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = (double)v;
+    sync();
+    int r = v;
+    for (int i = 0; i < nw; ++i) r = (int)scratch[i] > r ? (int)scratch[i] : r;
+    sync();
+    return r;
+  }
+};
+
 // Launch shape of one bucket of worlds: the worlds of the list are taken by
 // workgroups in turn (persistent when the grid is smaller than the list).
 struct Launch {
@@ -86,6 +120,7 @@ struct Launch {
   size_t gstride;
 };
 
+template <class TeamT>
 __global__ void __launch_bounds__(256) k_forward(ost::Batch B, ost::Params P, ost::Caps caps, Launch L,
                                                  const double* q_prev, const double* u_prev, const double* lam_prev,
                                                  const double* ctrl, double* q_next, double* u_next,
@@ -93,7 +128,7 @@ __global__ void __launch_bounds__(256) k_forward(ost::Batch B, ost::Params P, os
                                                  int32_t* status, int32_t* iters, double* resnorm, double* tape,
                                                  const int64_t* tape_off) {
   extern __shared__ __align__(16) char smem[];
-  GpuTeam t;
+  TeamT t;
   ost::WorldMem M = ost::carve(smem, caps, blockDim.x, L.split, L.gscr ? L.gscr + blockIdx.x * L.gstride : nullptr);
   for (int i = blockIdx.x; i < L.nlist; i += gridDim.x) {
     ost::forward_world(t, B, P, caps, L.wlist[i], q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
@@ -102,6 +137,7 @@ __global__ void __launch_bounds__(256) k_forward(ost::Batch B, ost::Params P, os
   }
 }
 
+template <class TeamT>
 __global__ void __launch_bounds__(256) k_adjoint(ost::Batch B, ost::Params P, ost::Caps caps, Launch L,
                                                  const double* q_prev, const double* u_prev, const double* ctrl,
                                                  const double* u_next, const double* lam_next, const double* tape,
@@ -109,13 +145,55 @@ __global__ void __launch_bounds__(256) k_adjoint(ost::Batch B, ost::Params P, os
                                                  const double* gu_next, double* gq_prev, double* gu_prev,
                                                  double* g_ctrl, int refine) {
   extern __shared__ __align__(16) char smem[];
-  GpuTeam t;
+  TeamT t;
   ost::WorldMem M = ost::carve(smem, caps, blockDim.x, L.split, L.gscr ? L.gscr + blockIdx.x * L.gstride : nullptr);
   for (int i = blockIdx.x; i < L.nlist; i += gridDim.x) {
     ost::adjoint_world(t, B, P, caps, L.wlist[i], q_prev, u_prev, ctrl, u_next, lam_next, tape, tape_off,
                        gq_next, gu_next, gq_prev, gu_prev, g_ctrl, refine, M);
     __syncthreads();
   }
+}
+
+// Plain path (the comparison baseline): one launch for a world's set-up, one
+// per Newton iteration and one for its finalisation, with the world's
+// workspace in device memory between launches.  The arithmetic is that of the
+// fused kernel, so the results are the same bits.
+__global__ void __launch_bounds__(256) k_plain_begin(ost::Batch B, ost::Params P, ost::Caps caps, int w,
+                                                     const double* q_prev, const double* u_prev,
+                                                     const double* lam_prev, const double* ctrl, char* ws) {
+  GpuTeamG t;
+  ost::WorldMem M = ost::carve(ws, caps, blockDim.x);
+  ost::WorldRef R = ost::world_ref(B, w);
+  ost::FwState S;
+  ost::fw_begin(t, B, P, R, q_prev, u_prev, lam_prev, ctrl, M, S);
+  t.sync();
+  if (threadIdx.x == 0) ost::fw_store(M, S);
+}
+
+__global__ void __launch_bounds__(256) k_plain_iteration(ost::Batch B, ost::Params P, ost::Caps caps, int w,
+                                                         const double* ctrl, char* ws, int k) {
+  GpuTeamG t;
+  ost::WorldMem M = ost::carve(ws, caps, blockDim.x);
+  ost::WorldRef R = ost::world_ref_after(B, M, w);
+  ost::FwState S = ost::fw_load(M);
+  t.sync();
+  ost::fw_iteration(t, B, P, R, ctrl, M, S, k);
+  t.sync();
+  if (threadIdx.x == 0) ost::fw_store(M, S);
+}
+
+__global__ void __launch_bounds__(256) k_plain_end(ost::Batch B, ost::Params P, ost::Caps caps, int w,
+                                                   const double* ctrl, double* q_next, double* u_next,
+                                                   double* lam_next, int32_t* act_slot, int32_t* n_act,
+                                                   int32_t* status, int32_t* iters, double* resnorm, double* tape,
+                                                   const int64_t* tape_off, char* ws) {
+  GpuTeamG t;
+  ost::WorldMem M = ost::carve(ws, caps, blockDim.x);
+  ost::WorldRef R = ost::world_ref_after(B, M, w);
+  ost::FwState S = ost::fw_load(M);
+  t.sync();
+  ost::fw_end(t, B, P, R, w, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters, resnorm, tape, tape_off,
+              M, S);
 }
 
 // controls of every step: ctrl[k, c] = sum_j basis[k, j] knots[c, j]
@@ -187,6 +265,7 @@ struct Bucket {
 // Row capacity edges of the buckets: a world with row cap mr goes to the first
 // bucket whose edge is >= mr.
 const int kEdges[] = {16, 32, 64, 96, 128, 192, 256, 384, 1 << 30};
+const int kPlainTeam = 128;
 }  // namespace
 
 struct ostrich_ctx {
@@ -203,6 +282,7 @@ struct ostrich_ctx {
   std::vector<ost::Caps> wcaps;  // per world
   std::vector<Bucket> buckets;
   Bucket all;  // every world, shaped for the largest: launches over caller-given world lists
+  char* plain_ws = nullptr;  // one world's workspace for the plain path
   int64_t* d_tape_off = nullptr;
   size_t tape_total = 0;  // doubles
   ~ostrich_ctx() {
@@ -211,6 +291,8 @@ struct ostrich_ctx {
       if (b.gscr) (void)hipFree(b.gscr);
     }
     if (all.gscr) (void)hipFree(all.gscr);
+    if (all.d_worlds) (void)hipFree(all.d_worlds);
+    if (plain_ws) (void)hipFree(plain_ws);
     if (d_tape_off) (void)hipFree(d_tape_off);
   }
 };
@@ -313,7 +395,8 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   HIP_OK(hipGetDeviceProperties(&prop, dev));
   ctx->lds_limit = prop.sharedMemPerBlock;
   ctx->n_cu = std::max(1, prop.multiProcessorCount);
-  for (auto f : {(const void*)k_forward, (const void*)k_adjoint})
+  for (auto f : {(const void*)k_forward<GpuTeam>, (const void*)k_adjoint<GpuTeam>, (const void*)k_forward<GpuTeamG>,
+                 (const void*)k_adjoint<GpuTeamG>})
     HIP_OK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctx->lds_limit));
   std::memcpy(&ctx->B, b, sizeof(ost::Batch));
   static_assert(sizeof(ost::Batch) == sizeof(ostrich_batch), "batch layouts differ");
@@ -365,8 +448,11 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   }
   for (int w = 0; w < W; ++w) ctx->all.worlds.push_back(w);
   ctx->all.caps = c;
+  HIP_OK(hipMalloc(&ctx->all.d_worlds, W * sizeof(int32_t)));
+  HIP_OK(hipMemcpy(ctx->all.d_worlds, ctx->all.worlds.data(), W * sizeof(int32_t), hipMemcpyHostToDevice));
   if (default_config(ctx.get(), ctx->all))
     return fail(OSTRICH_E_UNSUPPORTED, "the batch does not fit a workgroup");
+  HIP_OK(hipMalloc(&ctx->plain_ws, ost::world_lds_bytes(c, kPlainTeam) + 256));
   HIP_OK(hipMalloc(&ctx->d_tape_off, (W + 1) * sizeof(int64_t)));
   HIP_OK(hipMemcpy(ctx->d_tape_off, toff.data(), (W + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
   *out = ctx.release();
@@ -414,7 +500,8 @@ static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, c
                            const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
                            double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
                            int32_t* iters, double* resnorm, double* tape) {
-  hipLaunchKernelGGL(k_forward, dim3(grid_of(bk)), dim3(bk.team), bk.lds, st, ctx->B, ctx->P, bk.caps,
+  auto kf = bk.split == ost::SPLIT_GLOBAL ? k_forward<GpuTeamG> : k_forward<GpuTeam>;
+  hipLaunchKernelGGL(kf, dim3(grid_of(bk)), dim3(bk.team), bk.lds, st, ctx->B, ctx->P, bk.caps,
                      launch_of(bk), q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act,
                      status, iters, resnorm, tape, (const int64_t*)ctx->d_tape_off);
 }
@@ -442,7 +529,8 @@ extern "C" int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, cons
   if (ctx->NCTRL > 0 && (!ctrl || !g_ctrl)) return fail(OSTRICH_E_ARG, "controls required");
   int rf = refine < 0 ? ctx->refine : refine;
   for (const Bucket& bk : ctx->buckets)
-    hipLaunchKernelGGL(k_adjoint, dim3(grid_of(bk)), dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
+    hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>, dim3(grid_of(bk)),
+                       dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
                        bk.caps, launch_of(bk), q_prev, u_prev, ctrl, u_next, lam_next, (const double*)tape,
                        (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf);
   HIP_OK(hipGetLastError());
@@ -468,7 +556,8 @@ extern "C" int ostrich_step_forward_list(ostrich_ctx* ctx, const int32_t* worlds
   if (ctx->NCTRL > 0 && !ctrl) return fail(OSTRICH_E_ARG, "controls required");
   if (n == 0) return 0;
   const Bucket& bk = ctx->all;
-  hipLaunchKernelGGL(k_forward, dim3(list_grid(ctx, n)), dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
+  hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_forward<GpuTeamG> : k_forward<GpuTeam>, dim3(list_grid(ctx, n)),
+                     dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
                      bk.caps, list_launch(ctx, worlds, n), q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
                      act_slot, n_act, status, iters, resnorm, (double*)tape, (const int64_t*)ctx->d_tape_off);
   HIP_OK(hipGetLastError());
@@ -487,10 +576,56 @@ extern "C" int ostrich_step_adjoint_list(ostrich_ctx* ctx, const int32_t* worlds
   if (n == 0) return 0;
   const Bucket& bk = ctx->all;
   int rf = refine < 0 ? ctx->refine : refine;
-  hipLaunchKernelGGL(k_adjoint, dim3(list_grid(ctx, n)), dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
+  hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>,
+                     dim3(list_grid(ctx, n)), dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
                      bk.caps, list_launch(ctx, worlds, n), q_prev, u_prev, ctrl, u_next, lam_next,
                      (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev,
                      g_ctrl, rf);
+  HIP_OK(hipGetLastError());
+  return 0;
+}
+
+extern "C" int ostrich_step_forward_plain(ostrich_ctx* ctx, const double* q_prev, const double* u_prev,
+                                          const double* lam_prev, const double* ctrl, double* q_next,
+                                          double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act,
+                                          int32_t* status, int32_t* iters, double* resnorm, void* tape,
+                                          void* stream) {
+  if (!ctx || !q_prev || !u_prev || !lam_prev || !q_next || !u_next || !lam_next)
+    return fail(OSTRICH_E_ARG, "null state pointer");
+  if (ctx->NCTRL > 0 && !ctrl) return fail(OSTRICH_E_ARG, "controls required");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t lds = 0;
+  for (int w = 0; w < ctx->W; ++w) {
+    hipLaunchKernelGGL(k_plain_begin, dim3(1), dim3(kPlainTeam), lds, st, ctx->B, ctx->P, ctx->caps, w, q_prev,
+                       u_prev, lam_prev, ctrl, ctx->plain_ws);
+    for (int k = 1; k <= ctx->P.kmax; ++k)
+      hipLaunchKernelGGL(k_plain_iteration, dim3(1), dim3(kPlainTeam), lds, st, ctx->B, ctx->P, ctx->caps, w, ctrl,
+                         ctx->plain_ws, k);
+    hipLaunchKernelGGL(k_plain_end, dim3(1), dim3(kPlainTeam), lds, st, ctx->B, ctx->P, ctx->caps, w, ctrl, q_next,
+                       u_next, lam_next, act_slot, n_act, status, iters, resnorm, (double*)tape,
+                       (const int64_t*)ctx->d_tape_off, ctx->plain_ws);
+  }
+  HIP_OK(hipGetLastError());
+  return 0;
+}
+
+extern "C" int ostrich_step_adjoint_plain(ostrich_ctx* ctx, const double* q_prev, const double* u_prev,
+                                          const double* ctrl, const double* u_next, const double* lam_next,
+                                          const void* tape, const double* gq_next, const double* gu_next,
+                                          double* gq_prev, double* gu_prev, double* g_ctrl, int32_t refine,
+                                          void* stream) {
+  if (!ctx || !q_prev || !u_prev || !u_next || !lam_next || !tape || !gq_next || !gu_next || !gq_prev || !gu_prev)
+    return fail(OSTRICH_E_ARG, "null pointer");
+  if (ctx->NCTRL > 0 && (!ctrl || !g_ctrl)) return fail(OSTRICH_E_ARG, "controls required");
+  int rf = refine < 0 ? ctx->refine : refine;
+  const Bucket& bk = ctx->all;
+  if (!bk.d_worlds || (int)bk.worlds.size() != ctx->W) return fail(OSTRICH_E_ARG, "context world list missing");
+  for (int w = 0; w < ctx->W; ++w)  // one launch per world, over the one-world list {w}
+    hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>, dim3(1),
+                       dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P, bk.caps,
+                       list_launch(ctx, bk.d_worlds + w, 1), q_prev, u_prev, ctrl, u_next, lam_next,
+                       (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev,
+                       g_ctrl, rf);
   HIP_OK(hipGetLastError());
   return 0;
 }

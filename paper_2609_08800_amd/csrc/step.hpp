@@ -268,6 +268,8 @@ OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
     if (i - f > bw) bw = i - f;
   }
   R.bw = t.imax(bw, M.red);
+  if (t.rank() == 0) M.iscal[3] = R.bw;
+  t.sync();
 }
 
 // Clamp of the friction multipliers to the Coulomb disk of radius
