@@ -33,9 +33,32 @@ int fail(int code, const std::string& msg) {
   } while (0)
 
 struct GpuTeam {
+  static constexpr bool kGlobal = false;  // workspace entirely in LDS
   __device__ int rank() const { return threadIdx.x; }
   __device__ int size() const { return blockDim.x; }
   __device__ void sync() const { __syncthreads(); }
+  // The first wavefront alone: its width, a sync among its lanes (LDS
+  // operations of a wavefront complete in order; the fences keep the compiler
+  // from moving accesses across), and a max over its lanes.
+  __device__ int wsize() const { return 64; }
+  __device__ void wsync() const {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __device__ double wmax(double v) const {
+    for (int off = 32; off > 0; off >>= 1) {
+      double o = __shfl_xor(v, off, 64);
+      v = o > v ? o : v;
+    }
+    return v;
+  }
+  // v of lane src (uniform) in every lane
+  __device__ double bcast(double v, int src) const {
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+  }
   // Sum over the team: a butterfly within each 64-lane wavefront, then the
   // wavefront sums in wavefront order; every thread returns the same value.
   __device__ double sum(double v, double* scratch) const {
@@ -81,9 +104,15 @@ struct GpuTeam {
 // before the barrier, so that device-memory stores of one wave are complete
 // before other waves of the team read or overwrite them.
 struct GpuTeamG : GpuTeam {
+  static constexpr bool kGlobal = true;
   __device__ void sync() const {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+  }
+  __device__ void wsync() const {
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   __device__ double sum64(double v, double* scratch) const {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -129,7 +158,11 @@ __global__ void __launch_bounds__(256) k_forward(ost::Batch B, ost::Params P, os
                                                  const int64_t* tape_off) {
   extern __shared__ __align__(16) char smem[];
   TeamT t;
-  ost::WorldMem M = ost::carve(smem, caps, blockDim.x, L.split, L.gscr ? L.gscr + blockIdx.x * L.gstride : nullptr);
+  // the on-chip instantiation carves with a constant split, so that every
+  // workspace pointer is known to address LDS
+  ost::WorldMem M = TeamT::kGlobal
+                        ? ost::carve(smem, caps, blockDim.x, L.split, L.gscr ? L.gscr + blockIdx.x * L.gstride : nullptr)
+                        : ost::carve(smem, caps, blockDim.x, ost::SPLIT_LDS, nullptr);
   for (int i = blockIdx.x; i < L.nlist; i += gridDim.x) {
     ost::forward_world(t, B, P, caps, L.wlist[i], q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
                        act_slot, n_act, status, iters, resnorm, tape, tape_off, M);
@@ -146,7 +179,11 @@ __global__ void __launch_bounds__(256) k_adjoint(ost::Batch B, ost::Params P, os
                                                  double* g_ctrl, int refine) {
   extern __shared__ __align__(16) char smem[];
   TeamT t;
-  ost::WorldMem M = ost::carve(smem, caps, blockDim.x, L.split, L.gscr ? L.gscr + blockIdx.x * L.gstride : nullptr);
+  // the on-chip instantiation carves with a constant split, so that every
+  // workspace pointer is known to address LDS
+  ost::WorldMem M = TeamT::kGlobal
+                        ? ost::carve(smem, caps, blockDim.x, L.split, L.gscr ? L.gscr + blockIdx.x * L.gstride : nullptr)
+                        : ost::carve(smem, caps, blockDim.x, ost::SPLIT_LDS, nullptr);
   for (int i = blockIdx.x; i < L.nlist; i += gridDim.x) {
     ost::adjoint_world(t, B, P, caps, L.wlist[i], q_prev, u_prev, ctrl, u_next, lam_next, tape, tape_off,
                        gq_next, gu_next, gq_prev, gu_prev, g_ctrl, refine, M);
@@ -385,6 +422,9 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
     for (int j = jo[w]; j < jo[w + 1]; ++j) nsv += (act[j] == 2 || act[j] == 3);
     int nc = std::min(cap[w], ns);
     ost::Caps wc{nb, nj, std::max(ns, 1), std::max(nc, 1), std::max(5 * nj + nsv + 3 * nc, 1), nsv};
+    if (wc.mr > ost::kMaxRows)
+      return fail(OSTRICH_E_UNSUPPORTED, "world " + std::to_string(w) + " has " + std::to_string(wc.mr) +
+                                             " constraint rows, more than " + std::to_string(ost::kMaxRows));
     ctx->wcaps[w] = wc;
     c = caps_max(c, wc);
     toff[w + 1] = toff[w] + (int64_t)ost::tape_doubles_world(wc.mr);

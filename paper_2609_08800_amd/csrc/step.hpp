@@ -417,70 +417,207 @@ OST_HD void assemble(Team& t, const Params& P, const WorldRef& R, const WorldMem
   t.sync();
 }
 
+constexpr int kMaxRows = 384;  // largest row count of a world (six rows per lane of a wavefront)
+
 // In-place LU without pivoting, restricted to the band |i - j| <= bw (no
-// fill-in leaves the band without pivoting); false on a non-finite or tiny
-// pivot.
+// fill-in leaves the band without pivoting); false on a non-finite pivot or
+// one below 1e-14 of its row's largest entry.  One wavefront factors, each
+// lane updating its own rows in rounds of eight entries (all loads of a round
+// first), so the per-pivot work costs no workgroup barrier; the row maxima
+// needed by the pivot test are kept as the rows are updated.
 template <class Team> OST_HD bool lu_factor(Team& t, const WorldRef& R, const WorldMem& M) {
-  const int m = R.m, bw = R.bw;
+  const int m = R.m, bw = R.bw, W = t.wsize();
   double* A = M.A;
-  for (int k = 0; k < m; ++k) {
-    const int hi = k + bw + 1 < m ? k + bw + 1 : m;
-    if (t.rank() == 0) {
-      double piv = A[k * m + k], rmax = 0.0;
-      for (int j = k; j < hi; ++j) {
-        double v = fabs(A[k * m + j]);
-        rmax = v > rmax ? v : rmax;
+  double* rmax = M.rmax;
+  if (t.rank() < W) {
+    const int lane = t.rank();
+    for (int i = lane; i < m; i += W) {  // row maxima of the assembled band
+      const int lo = i - bw > 0 ? i - bw : 0, hi = i + bw + 1 < m ? i + bw + 1 : m;
+      double v = 0.0;
+      for (int j = lo; j < hi; ++j) v = fmax(v, fabs(A[i * m + j]));
+      rmax[i] = v;
+    }
+    t.wsync();
+    int ok = 1;
+    for (int k = 0; k < m; ++k) {
+      const int hi = k + bw + 1 < m ? k + bw + 1 : m;
+      const double piv = A[k * m + k], rk = rmax[k];
+      if (!(isfinite(piv) && fabs(piv) > 1e-14 * rk && rk > 0.0)) {
+        ok = 0;
+        break;
       }
-      M.iscal[2] = (isfinite(piv) && fabs(piv) > 1e-14 * rmax && rmax > 0.0) ? 1 : 0;
+      const double ip = 1.0 / piv;
+      const double* Ak = A + k * m;
+      for (int i = k + 1 + (lane + W - (k + 1) % W) % W; i < hi; i += W) {
+        double* Ai = A + i * m;
+        const double l = Ai[k] * ip;
+        Ai[k] = l;
+        double v = 0.0;
+        int j = k + 1;
+        for (; j + 7 < hi; j += 8) {  // rounds of eight: all loads first
+          double a[8], b[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) { a[q] = Ai[j + q]; b[q] = Ak[j + q]; }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            a[q] = a[q] - l * b[q];
+            Ai[j + q] = a[q];
+            v = fmax(v, fabs(a[q]));
+          }
+        }
+        if (j + 3 < hi) {  // a round of four
+          double a[4], b[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) { a[q] = Ai[j + q]; b[q] = Ak[j + q]; }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            a[q] = a[q] - l * b[q];
+            Ai[j + q] = a[q];
+            v = fmax(v, fabs(a[q]));
+          }
+          j += 4;
+        }
+        for (; j < hi; ++j) {
+          const double a = Ai[j] - l * Ak[j];
+          Ai[j] = a;
+          v = fmax(v, fabs(a));
+        }
+        const int hi_i = i + bw + 1 < m ? i + bw + 1 : m;  // entries of the row this pivot leaves alone
+        for (; j < hi_i; ++j) v = fmax(v, fabs(Ai[j]));
+        rmax[i] = v;
+      }
+      t.wsync();
     }
-    t.sync();
-    if (!M.iscal[2]) return false;
-    double ip = 1.0 / A[k * m + k];
-    for (int i = k + 1 + t.rank(); i < hi; i += t.size()) A[i * m + k] *= ip;
-    t.sync();
-    int w = hi - k - 1;
-    for (int e = t.rank(); e < w * w; e += t.size()) {
-      int i = k + 1 + e / w, j = k + 1 + e % w;
-      A[i * m + j] -= A[i * m + k] * A[k * m + j];
-    }
-    t.sync();
+    if (lane == 0) M.iscal[2] = ok;
   }
-  return true;
+  t.sync();
+  return M.iscal[2] != 0;
 }
 
-// Solve A x = b (trans = false) or A^T x = b (trans = true) with the banded LU in M.A.
+// Solve A x = b (trans = false) or A^T x = b (trans = true) with the banded LU
+// in M.A, by one wavefront.  Up to 128 rows, lane l keeps x_l and x_{l+64} in
+// registers and takes x_k from its owner lane at step k, with the matrix
+// entries of four steps loaded ahead; beyond, x stays in LDS and each segment
+// between wavefront syncs writes an entry from one lane and reads it from none.
 template <class Team> OST_HD void lu_solve(Team& t, const WorldRef& R, const WorldMem& M, double* x, bool trans) {
-  const int m = R.m, bw = R.bw;
+  const int m = R.m, bw = R.bw, W = t.wsize();
   const double* A = M.A;
-  if (!trans) {
-    for (int k = 0; k < m; ++k) {  // L y = b (unit lower)
-      double yk = x[k];
-      const int hi = k + bw + 1 < m ? k + bw + 1 : m;
-      for (int i = k + 1 + t.rank(); i < hi; i += t.size()) x[i] -= A[i * m + k] * yk;
-      t.sync();
-    }
-    for (int k = m - 1; k >= 0; --k) {  // U x = y
-      double xk = x[k] / A[k * m + k];
-      t.sync();
-      if (t.rank() == 0) x[k] = xk;
-      for (int i = (k - bw > 0 ? k - bw : 0) + t.rank(); i < k; i += t.size()) x[i] -= A[i * m + k] * xk;
-      t.sync();
-    }
-  } else {
-    for (int k = 0; k < m; ++k) {  // U^T z = b
-      double zk = x[k] / A[k * m + k];
-      const int hi = k + bw + 1 < m ? k + bw + 1 : m;
-      t.sync();
-      if (t.rank() == 0) x[k] = zk;
-      for (int i = k + 1 + t.rank(); i < hi; i += t.size()) x[i] -= A[k * m + i] * zk;
-      t.sync();
-    }
-    for (int k = m - 1; k >= 0; --k) {  // L^T x = z (unit)
-      double xk = x[k];
-      for (int i = (k - bw > 0 ? k - bw : 0) + t.rank(); i < k; i += t.size()) x[i] -= A[k * m + i] * xk;
-      t.sync();
+  if (t.rank() < W) {
+    const int lane = t.rank();
+    if (W == 64 && m <= 128) {
+      const int i0 = lane, i1 = lane + 64;
+      double x0 = i0 < m ? x[i0] : 0.0, x1 = i1 < m ? x[i1] : 0.0;
+      auto get = [&](int k) { return k < 64 ? t.bcast(x0, k) : t.bcast(x1, k - 64); };
+      // entry (row i, step k) of the operator: L or U by rows (plain) or by columns (transposed)
+      auto ent = [&](int i, int k) { return trans ? A[k * m + i] : A[i * m + k]; };
+      if (!trans) {
+        for (int k0 = 0; k0 < m; k0 += 4) {  // L y = b (unit lower)
+          double e0[4], e1[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int k = k0 + q, hi = k + bw + 1 < m ? k + bw + 1 : m;
+            e0[q] = (k < m && i0 > k && i0 < hi) ? ent(i0, k) : 0.0;
+            e1[q] = (k < m && i1 > k && i1 < hi) ? ent(i1, k) : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (k0 + q < m) {
+              const double yk = get(k0 + q);
+              x0 -= e0[q] * yk;
+              x1 -= e1[q] * yk;
+            }
+        }
+        for (int k0 = m - 1; k0 >= 0; k0 -= 4) {  // U x = y
+          double e0[4], e1[4], d[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int k = k0 - q, lo = k - bw > 0 ? k - bw : 0;
+            d[q] = k >= 0 ? A[k * m + k] : 1.0;
+            e0[q] = (k >= 0 && i0 >= lo && i0 < k) ? ent(i0, k) : 0.0;
+            e1[q] = (k >= 0 && i1 >= lo && i1 < k) ? ent(i1, k) : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (k0 - q >= 0) {
+              const int k = k0 - q;
+              const double xk = get(k) / d[q];
+              if (i0 == k) x0 = xk;
+              if (i1 == k) x1 = xk;
+              x0 -= e0[q] * xk;
+              x1 -= e1[q] * xk;
+            }
+        }
+      } else {
+        for (int k0 = 0; k0 < m; k0 += 4) {  // U^T z = b
+          double e0[4], e1[4], d[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int k = k0 + q, hi = k + bw + 1 < m ? k + bw + 1 : m;
+            d[q] = k < m ? A[k * m + k] : 1.0;
+            e0[q] = (k < m && i0 > k && i0 < hi) ? ent(i0, k) : 0.0;
+            e1[q] = (k < m && i1 > k && i1 < hi) ? ent(i1, k) : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (k0 + q < m) {
+              const int k = k0 + q;
+              const double zk = get(k) / d[q];
+              if (i0 == k) x0 = zk;
+              if (i1 == k) x1 = zk;
+              x0 -= e0[q] * zk;
+              x1 -= e1[q] * zk;
+            }
+        }
+        for (int k0 = m - 1; k0 >= 0; k0 -= 4) {  // L^T x = z (unit)
+          double e0[4], e1[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int k = k0 - q, lo = k - bw > 0 ? k - bw : 0;
+            e0[q] = (k >= 0 && i0 >= lo && i0 < k) ? ent(i0, k) : 0.0;
+            e1[q] = (k >= 0 && i1 >= lo && i1 < k) ? ent(i1, k) : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (k0 - q >= 0) {
+              const double xk = get(k0 - q);
+              x0 -= e0[q] * xk;
+              x1 -= e1[q] * xk;
+            }
+        }
+      }
+      if (i0 < m) x[i0] = x0;
+      if (i1 < m) x[i1] = x1;
+    } else if (!trans) {
+      for (int k = 0; k < m; ++k) {  // L y = b (unit lower)
+        const double yk = x[k];
+        const int hi = k + bw + 1 < m ? k + bw + 1 : m;
+        for (int i = k + 1 + lane; i < hi; i += W) x[i] -= A[i * m + k] * yk;
+        t.wsync();
+      }
+      for (int k = m - 1; k >= 0; --k) {  // U x = y
+        const double xk = x[k] / A[k * m + k];
+        t.wsync();
+        if (lane == k % W) x[k] = xk;
+        for (int i = (k - bw > 0 ? k - bw : 0) + lane; i < k; i += W) x[i] -= A[i * m + k] * xk;
+        t.wsync();
+      }
+    } else {
+      for (int k = 0; k < m; ++k) {  // U^T z = b
+        const double zk = x[k] / A[k * m + k];
+        const int hi = k + bw + 1 < m ? k + bw + 1 : m;
+        t.wsync();
+        if (lane == k % W) x[k] = zk;
+        for (int i = k + 1 + lane; i < hi; i += W) x[i] -= A[k * m + i] * zk;
+        t.wsync();
+      }
+      for (int k = m - 1; k >= 0; --k) {  // L^T x = z (unit)
+        const double xk = x[k];
+        for (int i = (k - bw > 0 ? k - bw : 0) + lane; i < k; i += W) x[i] -= A[k * m + i] * xk;
+        t.wsync();
+      }
     }
   }
+  t.sync();
 }
 
 // Assemble and factor with the regularisation raised tenfold on failure.

@@ -24,7 +24,7 @@ struct WorldMem {
   double *c_n, *c_t1, *c_t2, *c_noff, *c_la, *c_lb, *c_r, *c_mu, *c_sn, *c_sf;
   // rows
   int *r_kind, *r_a, *r_b, *r_idx, *r_sub, *r_g;
-  double *J, *Y, *Gl, *D, *res, *lam, *dlam, *lamt, *lambest, *Abar;
+  double *J, *Y, *Gl, *D, *res, *lam, *dlam, *lamt, *lambest, *Abar, *rmax;
   // Schur matrix and right-hand side
   double *A, *rhs;
   // slot scratch; first row touching each body (band of the Schur matrix)
@@ -45,8 +45,12 @@ OST_HD size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
 // for worlds whose rows do not fit on chip.
 enum { SPLIT_LDS = 0, SPLIT_GLOBAL = 1 };
 
+// The Schur matrix is followed by kPadA spare doubles, so that the factor may
+// read whole rounds of eight entries past the end of a row.
+constexpr int kPadA = 8;
+
 OST_HD size_t world_glob_doubles(const Caps& c, int split) {
-  return split == SPLIT_GLOBAL ? (size_t)c.mr * c.mr + (size_t)27 * c.mr : 0;
+  return split == SPLIT_GLOBAL ? (size_t)c.mr * c.mr + kPadA + (size_t)27 * c.mr : 0;
 }
 
 // Bytes of LDS one world needs for the given capacities, team size and split.
@@ -54,8 +58,8 @@ OST_HD size_t world_lds_bytes(const Caps& c, int team, int split = SPLIT_LDS) {
   size_t d = 0, i = 0;
   d += (size_t)c.nb * (3 + 7 + 9 + 9 + 9 + 1 + 3 + 6 * 7 + 7 + 6);
   d += (size_t)c.nc * 20;
-  d += (size_t)c.mr * 7;
-  if (split == SPLIT_LDS) d += (size_t)c.mr * 27 + (size_t)c.mr * c.mr;
+  d += (size_t)c.mr * 8;
+  if (split == SPLIT_LDS) d += (size_t)c.mr * 27 + (size_t)c.mr * c.mr + kPadA;
   d += c.mr;
   d += (size_t)team + 8;
   i += (size_t)c.nc * 4 + (size_t)c.mr * 6 + c.ns + c.nb + 16;
@@ -83,7 +87,8 @@ OST_HD WorldMem carve(char* base, const Caps& c, int team, int split = SPLIT_LDS
   M.J = gtake(12 * c.mr); M.Y = gtake(12 * c.mr); M.Gl = gtake(3 * c.mr);
   M.D = take(c.mr); M.res = take(c.mr);
   M.lam = take(c.mr); M.dlam = take(c.mr); M.lamt = take(c.mr); M.lambest = take(c.mr); M.Abar = take(c.mr);
-  M.A = gtake((size_t)c.mr * c.mr); M.rhs = take(c.mr);
+  M.rmax = take(c.mr);
+  M.A = gtake((size_t)c.mr * c.mr + kPadA); M.rhs = take(c.mr);
   M.red = take(team); M.dscal = take(8);
   int* q = (int*)p;
   auto itake = [&](size_t n) { int* r = q; q += n; return r; };
