@@ -140,6 +140,17 @@ int ostrich_ctx_caps(const ostrich_ctx* ctx, int64_t* out);
  * tuned flag). */
 int ostrich_ctx_schedule(const ostrich_ctx* ctx, int32_t* out, int32_t max_buckets);
 
+/* Measurement of the forward steps (a set-up facility, not for the hot
+ * path).  mode 1: reset and start: every later ostrich_step_forward call with
+ * n_act and iters (including those inside ostrich_rollout) is bracketed by a
+ * pair of HIP events on its stream, and a one-workgroup kernel adds the
+ * step's algorithmic FP64 flops (from each world's rows m and Newton iteration
+ * count k: k (26 m^2 + 2 m^3 / 3 + 800 m) + 400 m, plus 24 m^2 + 2 m^3 / 3 when
+ * a tape is written) to a device counter; mode 0: stop; mode 2: synchronise
+ * the device and write out[3] = (timed calls, their total duration in ms,
+ * their algorithmic flops). */
+int ostrich_ctx_timing(ostrich_ctx* ctx, int32_t mode, double* out);
+
 /* Autotuner of the batching system: times `reps` forward steps of every bucket
  * from the given state (device pointers, as for ostrich_step_forward) under
  * each candidate launch (64, 128 or 256 threads per world; Schur matrix on

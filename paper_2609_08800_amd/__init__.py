@@ -116,6 +116,12 @@ class Simulator:
         keys = ("rows", "worlds", "team", "split", "lds", "tuned")
         return [dict(zip(keys, map(int, buf[6 * i:6 * i + 6]))) for i in range(n)]
 
+    def timing(self, mode: int):
+        """Forward-launch measurement: 1 start, 0 stop, 2 read (launches, total ms, algorithmic flops)."""
+        out = np.zeros(3)
+        _capi.check(self.lib.ostrich_ctx_timing(self.ctx, int(mode), out.ctypes.data), "ostrich_ctx_timing")
+        return {"launches": int(out[0]), "ms": float(out[1]), "flops": float(out[2])} if mode == 2 else None
+
     def autotune(self, q, u, lam=None, ctrl=None, reps: int = 2, stream=None):
         """Pick each bucket's launch by timing forward steps from (q, u, lam, ctrl)."""
         q, u = self._f64(q, (self.NB, 7)), self._f64(u, (self.NB, 6))

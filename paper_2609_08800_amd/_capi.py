@@ -77,6 +77,8 @@ def load() -> ctypes.CDLL:
     L.ostrich_rollout.restype = c_int
     L.ostrich_ctx_schedule.argtypes = [c_vp, c_vp, c_int]
     L.ostrich_ctx_schedule.restype = c_int
+    L.ostrich_ctx_timing.argtypes = [c_vp, c_int, c_vp]
+    L.ostrich_ctx_timing.restype = c_int
     L.ostrich_autotune.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp, c_int, c_vp]
     L.ostrich_autotune.restype = c_int
     L.ostrich_step_forward_list.argtypes = [c_vp, c_vp, c_int] + [c_vp] * 13 + [c_vp]

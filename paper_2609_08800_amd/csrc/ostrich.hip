@@ -233,6 +233,30 @@ __global__ void __launch_bounds__(256) k_plain_end(ost::Batch B, ost::Params P, 
               M, S);
 }
 
+// Measurement: algorithmic FP64 flops of the forward steps just taken, from
+// each world's rows m = 5 joints + servo rows + 3 contacts and its Newton
+// iteration count k: k (24 m^2 + 2 m^3 / 3 + 2 m^2 + 800 m) per step, plus the
+// factor at the returned iterate when a tape is written (24 m^2 + 2 m^3 / 3)
+// and 400 m for the set-up.  One workgroup sums in a fixed order.
+__global__ void k_flops(ost::Batch B, const int32_t* n_act, const int32_t* iters, int with_tape, double* acc) {
+  __shared__ double part[256];
+  double s = 0.0;
+  for (int w = threadIdx.x; w < B.n_worlds; w += blockDim.x) {
+    int nsv = 0;
+    for (int j = B.joint_off[w]; j < B.joint_off[w + 1]; ++j) nsv += (B.joint_act[j] == 2 || B.joint_act[j] == 3);
+    const double m = 5.0 * (B.joint_off[w + 1] - B.joint_off[w]) + nsv + 3.0 * n_act[w];
+    const double per_it = 24.0 * m * m + 2.0 * m * m * m / 3.0 + 2.0 * m * m + 800.0 * m;
+    s += iters[w] * per_it + 400.0 * m + (with_tape ? 24.0 * m * m + 2.0 * m * m * m / 3.0 : 0.0);
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < (int)blockDim.x; ++i) t += part[i];
+    acc[0] += t;
+  }
+}
+
 // controls of every step: ctrl[k, c] = sum_j basis[k, j] knots[c, j]
 __global__ void k_ctrl(const double* basis, const double* knots, int T, int K, int nctrl, double* ctrl) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -320,6 +344,11 @@ struct ostrich_ctx {
   std::vector<Bucket> buckets;
   Bucket all;  // every world, shaped for the largest: launches over caller-given world lists
   char* plain_ws = nullptr;  // one world's workspace for the plain path
+  // measurement of the forward launches (ostrich_ctx_timing)
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // start / stop pairs
+  size_t n_ev = 0;
+  double* d_flops = nullptr;
   int64_t* d_tape_off = nullptr;
   size_t tape_total = 0;  // doubles
   ~ostrich_ctx() {
@@ -330,6 +359,8 @@ struct ostrich_ctx {
     if (all.gscr) (void)hipFree(all.gscr);
     if (all.d_worlds) (void)hipFree(all.d_worlds);
     if (plain_ws) (void)hipFree(plain_ws);
+    if (d_flops) (void)hipFree(d_flops);
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (d_tape_off) (void)hipFree(d_tape_off);
   }
 };
@@ -553,10 +584,56 @@ extern "C" int ostrich_step_forward(ostrich_ctx* ctx, const double* q_prev, cons
   if (!ctx || !q_prev || !u_prev || !lam_prev || !q_next || !u_next || !lam_next)
     return fail(OSTRICH_E_ARG, "null state pointer");
   if (ctx->NCTRL > 0 && !ctrl) return fail(OSTRICH_E_ARG, "controls required");
+  const bool timed = ctx->timing && n_act && iters;
+  if (timed) {
+    if (ctx->n_ev + 2 > ctx->ev.size()) {
+      for (int k = 0; k < 2; ++k) {
+        hipEvent_t e;
+        HIP_OK(hipEventCreate(&e));
+        ctx->ev.push_back(e);
+      }
+    }
+    HIP_OK(hipEventRecord(ctx->ev[ctx->n_ev], (hipStream_t)stream));
+  }
   for (const Bucket& bk : ctx->buckets)
     launch_forward(ctx, bk, (hipStream_t)stream, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
                    act_slot, n_act, status, iters, resnorm, (double*)tape);
+  if (timed) {
+    HIP_OK(hipEventRecord(ctx->ev[ctx->n_ev + 1], (hipStream_t)stream));
+    ctx->n_ev += 2;
+    hipLaunchKernelGGL(k_flops, dim3(1), dim3(256), 0, (hipStream_t)stream, ctx->B, n_act, iters, tape ? 1 : 0,
+                       ctx->d_flops);
+  }
   HIP_OK(hipGetLastError());
+  return 0;
+}
+
+extern "C" int ostrich_ctx_timing(ostrich_ctx* ctx, int32_t mode, double* out) {
+  if (!ctx) return fail(OSTRICH_E_ARG, "null context");
+  if (mode == 1 || mode == 0) {  // start (reset) or stop
+    if (!ctx->d_flops) HIP_OK(hipMalloc(&ctx->d_flops, sizeof(double)));
+    if (mode == 1) {
+      HIP_OK(hipDeviceSynchronize());
+      const double z = 0.0;
+      HIP_OK(hipMemcpy(ctx->d_flops, &z, sizeof(double), hipMemcpyHostToDevice));
+      ctx->n_ev = 0;
+    }
+    ctx->timing = mode == 1;
+    return 0;
+  }
+  if (mode != 2 || !out) return fail(OSTRICH_E_ARG, "timing mode");
+  HIP_OK(hipDeviceSynchronize());
+  double total = 0.0;
+  for (size_t i = 0; i + 1 < ctx->n_ev; i += 2) {
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
+    total += ms;
+  }
+  double fl = 0.0;
+  HIP_OK(hipMemcpy(&fl, ctx->d_flops, sizeof(double), hipMemcpyDeviceToHost));
+  out[0] = (double)(ctx->n_ev / 2);
+  out[1] = total;
+  out[2] = fl;
   return 0;
 }
 
