@@ -120,6 +120,47 @@ def plain_path_measurement(n_worlds=64, T=5):
             "launches_per_world_step": P["k_max"] + 3}
 
 
+def uneven_measurement(n_stacks=2048, n_robots=2048, T=50, ckpt=10, seed=0):
+    """The uneven batch (box stacks of 1..32 boxes with robots; Schur sizes 12..384): forward +
+    adjoint world-steps/s of a checkpointed rollout under one fixed schedule and under the bucketed
+    schedule after autotuning (the results are the same bits under both)."""
+    import torch
+    import scenes
+    from paper_2609_08800_amd import Simulator, spline_basis
+    dev = torch.device("cuda:0")
+    P = scenes.solver_params()
+    b = scenes.mixed_batch(n_stacks, n_robots, seed=seed, max_boxes=32)
+    K = scenes.ROBOT_KNOTS
+    knots = torch.as_tensor(scenes.knots_array(b, K), device=dev)
+    basis = torch.as_tensor(spline_basis(T, K, P["h"]), device=dev)
+    q0, u0 = torch.as_tensor(b.q0, device=dev), torch.as_tensor(b.u0, device=dev)
+    tg = torch.as_tensor(b.target, device=dev)
+    res = {"worlds": b.n_worlds, "T": T, "ckpt_every": ckpt,
+           "rows_max": int(max(w.row_cap for w in b.worlds)), "rows_min": int(min(w.row_cap for w in b.worlds))}
+    outs = {}
+    for name in ("fixed", "autotuned"):
+        sim = Simulator(b, P, device=dev, schedule="fixed" if name == "fixed" else "bucketed")
+        if name == "autotuned":
+            sim.autotune(q0, u0, None, basis[0] @ knots.t() if sim.NCTRL else None, reps=1)
+        ws = sim.new_workspace(T, ckpt)
+        run = lambda: sim.rollout(q0, u0, knots, basis, T, ckpt_every=ckpt, loss_body=b.loss_body, target=tg,
+                                  workspace=ws)
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        outs[name] = torch.cat([o[k].reshape(-1) for k in ("loss", "g_knots", "g_q0", "g_u0")])
+        res[name] = {"world_steps_per_s": round(b.n_worlds * T / dt, 1), "seconds": round(dt, 3),
+                     "buckets": [(x["rows"], x["worlds"], x["team"], x["split"]) for x in sim.schedule()]}
+    # bit patterns, so that worlds whose trajectory runs away to non-finite values compare too
+    res["same_bits"] = bool(torch.equal(outs["fixed"].view(torch.int64), outs["autotuned"].view(torch.int64)))
+    res["frac_worlds_nonfinite"] = round(float(((o["status"] & 4) > 0).double().mean()), 4)
+    res["autotuned_over_fixed"] = round(res["autotuned"]["world_steps_per_s"] / res["fixed"]["world_steps_per_s"], 2)
+    return res
+
+
 def serving_measurement(rate, duration, drain, seed=0, capacity=4096, budget_gb=96.0, hmap_slots=64):
     """Poisson arrivals of trajectory-optimisation requests (robots on their
     own value-noise terrain, 1..256 worlds, T in 20..100, 10 iterations of
@@ -159,6 +200,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=1.0, help="request arrivals per second (0: skip serving)")
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="arrival window of the serving run")
     ap.add_argument("--serve-drain", type=float, default=40.0, help="extra time to finish admitted requests")
+    ap.add_argument("--uneven", type=int, default=1, help="also measure the uneven stacks + robots batch")
     ap.add_argument("--roofline-only", action="store_true",
                     help="skip the timed rollouts; run only the per-launch forward measurement "
                          "(for hardware-counter runs)")
@@ -253,6 +295,9 @@ def main():
     if not args.roofline_only:
         plain = plain_path_measurement()
         plain["batched_over_plain"] = round(value / plain["world_steps_per_s"], 1)
+    uneven = None
+    if args.uneven and not args.roofline_only:
+        uneven = uneven_measurement()
     serving = None
     if args.serve_rate > 0 and not args.roofline_only:
         serving = serving_measurement(args.serve_rate, args.serve_seconds, args.serve_drain)
@@ -283,8 +328,11 @@ def main():
                   "forward_only_world_steps_per_s": round(W * fo["launches"] / (fo["ms"] * 1e-3), 1),
                   "mean_newton_iters": round(float(iters_all.mean()), 3),
                   "frac_converged": round(float(np.mean(status & 1)), 4),
+                  "frac_budget": round(float(np.mean((status & 2) > 0)), 4),
+                  "frac_worlds_nonfinite_at_T": round(float(np.mean((status[-1] & 4) > 0)), 4),
                   "mean_rows": round(float(np.mean(m_all)), 2),
                   "plain_path": plain,
+                  "uneven_batch": uneven,
                   "serving": serving},
     }
     print(json.dumps(line))

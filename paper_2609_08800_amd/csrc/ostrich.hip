@@ -100,19 +100,21 @@ struct GpuTeam {
 };
 
 // Team whose workspace is (partly) in device memory.  A workgroup barrier
-// orders LDS only: each wave also waits for its own vector-memory operations
-// before the barrier, so that device-memory stores of one wave are complete
-// before other waves of the team read or overwrite them.
+// orders LDS only, so at each sync a wave first waits for its own
+// vector-memory operations (its stores are then in L2) and afterwards
+// invalidates its CU's vector L1 (agent-scope acquire), so that no lane reads
+// a line cached before another lane's store.
 struct GpuTeamG : GpuTeam {
   static constexpr bool kGlobal = true;
   __device__ void sync() const {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __device__ void wsync() const {
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __device__ double sum64(double v, double* scratch) const {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -344,6 +346,10 @@ struct ostrich_ctx {
   std::vector<Bucket> buckets;
   Bucket all;  // every world, shaped for the largest: launches over caller-given world lists
   char* plain_ws = nullptr;  // one world's workspace for the plain path
+  // concurrent buckets: one stream per bucket, forked from and joined to the caller's stream
+  std::vector<hipStream_t> bstreams;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
   // measurement of the forward launches (ostrich_ctx_timing)
   bool timing = false;
   std::vector<hipEvent_t> ev;  // start / stop pairs
@@ -360,6 +366,9 @@ struct ostrich_ctx {
     if (all.d_worlds) (void)hipFree(all.d_worlds);
     if (plain_ws) (void)hipFree(plain_ws);
     if (d_flops) (void)hipFree(d_flops);
+    for (hipStream_t x : bstreams) (void)hipStreamDestroy(x);
+    for (hipEvent_t e : ev_join) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (d_tape_off) (void)hipFree(d_tape_off);
   }
@@ -524,6 +533,17 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   if (default_config(ctx.get(), ctx->all))
     return fail(OSTRICH_E_UNSUPPORTED, "the batch does not fit a workgroup");
   HIP_OK(hipMalloc(&ctx->plain_ws, ost::world_lds_bytes(c, kPlainTeam) + 256));
+  if (ctx->buckets.size() > 1) {  // streams of default priority, events without timing
+    HIP_OK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    for (size_t i = 0; i < ctx->buckets.size(); ++i) {
+      hipStream_t x;
+      hipEvent_t e;
+      HIP_OK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+      ctx->bstreams.push_back(x);
+      HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      ctx->ev_join.push_back(e);
+    }
+  }
   HIP_OK(hipMalloc(&ctx->d_tape_off, (W + 1) * sizeof(int64_t)));
   HIP_OK(hipMemcpy(ctx->d_tape_off, toff.data(), (W + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
   *out = ctx.release();
@@ -567,6 +587,24 @@ extern "C" int ostrich_ctx_schedule(const ostrich_ctx* ctx, int32_t* out, int32_
 
 extern "C" size_t ostrich_tape_bytes(const ostrich_ctx* ctx) { return ctx ? ctx->tape_total * sizeof(double) : 0; }
 
+// Run f(bucket, stream) for every bucket: on the caller's stream when there is
+// one bucket, else each on its own stream between a fork and a join event, so
+// that the buckets' launches overlap on the device.
+template <class F> static int for_buckets(ostrich_ctx* ctx, hipStream_t st, F f) {
+  if (ctx->buckets.size() == 1) {
+    f(ctx->buckets[0], st);
+    return 0;
+  }
+  HIP_OK(hipEventRecord(ctx->ev_fork, st));
+  for (size_t i = 0; i < ctx->buckets.size(); ++i) {
+    HIP_OK(hipStreamWaitEvent(ctx->bstreams[i], ctx->ev_fork, 0));
+    f(ctx->buckets[i], ctx->bstreams[i]);
+    HIP_OK(hipEventRecord(ctx->ev_join[i], ctx->bstreams[i]));
+  }
+  for (size_t i = 0; i < ctx->buckets.size(); ++i) HIP_OK(hipStreamWaitEvent(st, ctx->ev_join[i], 0));
+  return 0;
+}
+
 static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, const double* q_prev,
                            const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
                            double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
@@ -595,9 +633,11 @@ extern "C" int ostrich_step_forward(ostrich_ctx* ctx, const double* q_prev, cons
     }
     HIP_OK(hipEventRecord(ctx->ev[ctx->n_ev], (hipStream_t)stream));
   }
-  for (const Bucket& bk : ctx->buckets)
-    launch_forward(ctx, bk, (hipStream_t)stream, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
-                   act_slot, n_act, status, iters, resnorm, (double*)tape);
+  int rc = for_buckets(ctx, (hipStream_t)stream, [&](const Bucket& bk, hipStream_t s) {
+    launch_forward(ctx, bk, s, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status,
+                   iters, resnorm, (double*)tape);
+  });
+  if (rc) return rc;
   if (timed) {
     HIP_OK(hipEventRecord(ctx->ev[ctx->n_ev + 1], (hipStream_t)stream));
     ctx->n_ev += 2;
@@ -645,11 +685,13 @@ extern "C" int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, cons
     return fail(OSTRICH_E_ARG, "null pointer");
   if (ctx->NCTRL > 0 && (!ctrl || !g_ctrl)) return fail(OSTRICH_E_ARG, "controls required");
   int rf = refine < 0 ? ctx->refine : refine;
-  for (const Bucket& bk : ctx->buckets)
+  int rc = for_buckets(ctx, (hipStream_t)stream, [&](const Bucket& bk, hipStream_t s) {
     hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>, dim3(grid_of(bk)),
-                       dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
+                       dim3(bk.team), bk.lds, s, ctx->B, ctx->P,
                        bk.caps, launch_of(bk), q_prev, u_prev, ctrl, u_next, lam_next, (const double*)tape,
                        (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf);
+  });
+  if (rc) return rc;
   HIP_OK(hipGetLastError());
   return 0;
 }

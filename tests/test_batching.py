@@ -105,6 +105,34 @@ def test_schedules_are_bitwise_identical(torch):
             assert torch.equal(o[key], outs[0][key]), key
 
 
+def test_device_memory_split_is_bitwise_identical_to_on_chip(torch):
+    """Stacks up to 32 boxes (some buckets keep the Schur matrix in device
+    memory) with robots: the fixed schedule (everything in device memory) and
+    the bucketed one give the same bits, steps and adjoint."""
+    rng = scenes.world_rngs(33, 6)
+    worlds = [scenes.stack_world(r, n) for r, n in zip(rng, (32, 24, 17, 9, 3, 1))]
+    worlds += list(scenes.robot_batch(4, seed=34).worlds)
+    b = scenes.pack(worlds)
+    P = scenes.solver_params()
+    from paper_2609_08800_amd import spline_basis
+    ctrl = scenes.knots_array(b, scenes.ROBOT_KNOTS) @ spline_basis(10, scenes.ROBOT_KNOTS, P["h"])[1]
+    lam = np.zeros(b.n_lam)
+    rng2 = np.random.default_rng(3)
+    gq_n, gu_n = rng2.normal(size=b.q0.shape), rng2.normal(size=b.u0.shape)
+    res = []
+    for sched in ("fixed", "bucketed"):
+        sim = sim_for(b, P, schedule=sched)
+        tape = sim.new_tape()
+        o = sim.step_forward(b.q0, b.u0, lam, ctrl, tape=tape)
+        g = sim.step_adjoint(b.q0, b.u0, ctrl, o["u"], o["lam"], tape, gq_n, gu_n)
+        res.append((o, g, sim.schedule()))
+    assert any(x["split"] == 1 for x in res[1][2]) and any(x["split"] == 0 for x in res[1][2])
+    for key in ("q", "u", "lam", "status", "iters", "resnorm"):
+        assert torch.equal(res[0][0][key], res[1][0][key]), key
+    for x, y in zip(res[0][1], res[1][1]):
+        assert torch.equal(x, y)
+
+
 def test_largest_stack_uses_device_memory_split(torch):
     """A 32-box stack (384 rows) runs with its Schur matrix in device memory."""
     rng = scenes.world_rngs(21, 2)
@@ -152,12 +180,14 @@ def test_mixed_adjoint_matches_exact_ift(torch):
         q, u, lam = got["q"].cpu().numpy(), un, ln
 
 
-def test_graph_captured_rollout_replays_match_eager(torch):
-    """One hipGraph launch per rollout (forward + adjoint).  Replays with new
-    knots, interleaved with eager work, equal the eager rollout bit for bit."""
+@pytest.mark.parametrize("kind", ["robots", "mixed"])
+def test_graph_captured_rollout_replays_match_eager(torch, kind):
+    """One hipGraph launch per rollout (forward + adjoint; for a mixed batch the
+    buckets run on forked streams inside the graph).  Replays with new knots,
+    interleaved with eager work, equal the eager rollout bit for bit."""
     from paper_2609_08800_amd import GraphRollout, spline_basis
     T, ck = 12, 4
-    b = scenes.robot_batch(16, seed=30)
+    b = scenes.robot_batch(16, seed=30) if kind == "robots" else scenes.mixed_batch(6, 4, seed=31, max_boxes=20)
     P = scenes.solver_params()
     sim = sim_for(b, P)
     K = scenes.ROBOT_KNOTS
@@ -174,3 +204,29 @@ def test_graph_captured_rollout_replays_match_eager(torch):
         torch.cuda.synchronize()
         for key, v in snap.items():
             assert torch.equal(v, ref[key]), (it, key)
+
+
+def test_checkpointed_rollout_bits_agree_across_schedules(torch):
+    """A checkpointed rollout of stacks up to 32 boxes with robots: the fixed
+    schedule and the autotuned bucketed one give the same bit patterns for the
+    loss, the final state and every gradient (bit patterns, so that a world
+    whose trajectory runs away to non-finite values compares too)."""
+    from paper_2609_08800_amd import spline_basis
+    b = scenes.mixed_batch(24, 24, seed=7, max_boxes=32)
+    P = scenes.solver_params()
+    T, ck, K = 12, 4, scenes.ROBOT_KNOTS
+    knots = scenes.knots_array(b, K)
+    basis = spline_basis(T, K, P["h"])
+    outs = []
+    for sched in ("fixed", "bucketed"):
+        sim = sim_for(b, P, schedule=sched)
+        if sched == "bucketed":
+            sim.autotune(b.q0, b.u0, None, knots @ basis[0], reps=1)
+            assert len(sim.schedule()) >= 3
+        r = sim.rollout(b.q0, b.u0, knots, basis, T, ckpt_every=ck, loss_body=b.loss_body, target=b.target)
+        outs.append(r)
+    for key in ("loss", "qT", "uT", "g_knots", "g_q0", "g_u0", "status"):
+        x, y = outs[0][key], outs[1][key]
+        if x.dtype == torch.float64:
+            x, y = x.view(torch.int64), y.view(torch.int64)
+        assert torch.equal(x, y), key
