@@ -31,6 +31,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CU x 4 SIMD x 16 lane
 HBM_PEAK_GBS = 8000.0
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash():
     """Hash of the HIP sources, to tell whether recorded counters still describe the kernel."""
     import hashlib
@@ -264,6 +268,7 @@ def main():
     world_steps = W * T * args.steps
     value = world_steps / dt if not args.roofline_only else float("nan")
     peak_gb = (torch.cuda.max_memory_allocated(dev)) / 1e9
+    progress(f"timed region done: {args.steps} steps in {dt:.2f} s")
 
     # Forward-only pass of the same trajectory (outside the timed region): solver statistics.
     q, u = q0.clone(), u0.clone()
@@ -281,6 +286,7 @@ def main():
         q, u, lam = o["q"], o["u"], o["lam"]
     sim.timing(0)
     fo = sim.timing(2)
+    progress("solver statistics pass done")
     if args.roofline_only:
         fwd = fo
     avg_ms = fwd["ms"] / max(fwd["launches"], 1)
@@ -295,15 +301,19 @@ def main():
     if not args.roofline_only:
         plain = plain_path_measurement()
         plain["batched_over_plain"] = round(value / plain["world_steps_per_s"], 1)
+        progress("plain path done")
     uneven = None
     if args.uneven and not args.roofline_only:
         uneven = uneven_measurement()
+        progress("uneven batch done")
     serving = None
     if args.serve_rate > 0 and not args.roofline_only:
         serving = serving_measurement(args.serve_rate, args.serve_seconds, args.serve_drain)
+        progress("serving done")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline()
+        progress("cpu baseline done")
     iters_all = np.array(iters_all)
     status = np.array(st_all)
     line = {

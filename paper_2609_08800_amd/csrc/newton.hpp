@@ -105,9 +105,23 @@ OST_HD void fw_iteration(Team& t, const Batch& B, const Params& P, const WorldRe
   for (int e = t.rank(); e < 6 * nb; e += t.size()) {
     int b = e / 6, q = e - 6 * b;
     double v = -M.rdyn[e];
-    for (int i = 0; i < m; ++i) {
-      if (M.r_a[i] == b) v += P.h * M.J[12 * i + q] * M.dlam[i];
-      if (M.r_b[i] == b) v += P.h * M.J[12 * i + 6 + q] * M.dlam[i];
+    for (int i0 = 0; i0 < m; i0 += 4) {  // rows in fours: the loads first, then the sum in row order
+      int ra[4], rb[4];
+      double ja[4], jb[4], dl[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + r < m ? i0 + r : m - 1;
+        ra[r] = i0 + r < m ? M.r_a[i] : -2;
+        rb[r] = i0 + r < m ? M.r_b[i] : -2;
+        ja[r] = M.J[12 * i + q];
+        jb[r] = M.J[12 * i + 6 + q];
+        dl[r] = M.dlam[i];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (ra[r] == b) v += P.h * ja[r] * dl[r];
+        if (rb[r] == b) v += P.h * jb[r] * dl[r];
+      }
     }
     M.kg[e] = v;
   }
