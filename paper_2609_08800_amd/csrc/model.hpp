@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
 
 #define OST_HD __host__ __device__ __forceinline__
 
@@ -266,14 +267,29 @@ OST_HD bool hm_feature(const HmapRef& H, int key, const v3<T>& P, v3<T>& n, T& n
   return true;
 }
 
-// The rank-th nearest candidate feature within radius rc of P, ordered by
-// distance quantised to 1e-9 m and then by key; -1 if there are fewer.
-OST_HD int hm_select(const HmapRef& H, const v3<double>& P, double rc, int rank) {
+// Order of terrain candidates: distance quantised to 1e-9 m, then key.
+OST_HD bool hm_before(long long d, int key, long long d2, int key2) { return d < d2 || (d == d2 && key < key2); }
+
+// Insert (d, key) into the sorted best list (bd, bk) of at most 4 entries.
+OST_HD void hm_insert(long long* bd, int* bk, int& nb, long long d, int key) {
   const int K = 4;
-  long long bd[K];
-  int bk[K];
+  int pos = nb;
+  while (pos > 0 && hm_before(d, key, bd[pos - 1], bk[pos - 1])) --pos;
+  if (pos >= K) return;
+  int last = nb < K ? nb : K - 1;
+  for (int q = last; q > pos; --q) { bd[q] = bd[q - 1]; bk[q] = bk[q - 1]; }
+  bd[pos] = d;
+  bk[pos] = key;
+  if (nb < K) ++nb;
+}
+
+// The four nearest candidate features within radius rc of P among the cells
+// part, part + nparts, ... (row-major) of P's search range, sorted; returns
+// how many.  The best four of the union of the parts' lists are the best
+// four of the whole range, whatever the split.
+OST_HD int hm_best4(const HmapRef& H, const v3<double>& P, double rc, int part, int nparts, long long* bd, int* bk) {
   int nb = 0;
-  if (rank < 0 || rank >= K || H.n < 2) return -1;
+  if (H.n < 2) return 0;
   // vertex range covering the search disc (clamped in floating point, so that
   // non-finite or far-away points give an empty or bounded range)
   const double reach = rc + 2.0 * H.sp, top = H.n - 1;
@@ -283,28 +299,31 @@ OST_HD int hm_select(const HmapRef& H, const v3<double>& P, double rc, int rank)
   if (!(fj0 >= 0.0)) fj0 = 0.0;
   if (!(fi1 <= top)) fi1 = top;
   if (!(fj1 <= top)) fj1 = top;
-  if (!(fi0 <= top) || !(fj0 <= top) || !(fi1 >= 0.0) || !(fj1 >= 0.0) || !(rc >= 0.0)) return -1;
+  if (!(fi0 <= top) || !(fj0 <= top) || !(fi1 >= 0.0) || !(fj1 >= 0.0) || !(rc >= 0.0)) return 0;
   const int i0 = (int)fi0, i1 = (int)fi1, j0 = (int)fj0, j1 = (int)fj1;
-  for (int i = i0; i <= i1; ++i)
-    for (int j = j0; j <= j1; ++j)
-      for (int kind = 0; kind < 6; ++kind) {
-        if ((kind == 1 || kind == 3 || kind >= 4) && i + 1 >= H.n) continue;
-        if ((kind == 2 || kind == 3 || kind >= 4) && j + 1 >= H.n) continue;
-        int key = 6 * (i * H.n + j) + kind;
-        v3<double> nn;
-        double no, dd;
-        if (!hm_feature<double>(H, key, P, nn, no, &dd) || !(dd <= rc)) continue;
-        long long d = (long long)floor(dd / 1e-9);
-        // insert into the sorted best list (distance, then key)
-        int pos = nb;
-        while (pos > 0 && (d < bd[pos - 1] || (d == bd[pos - 1] && key < bk[pos - 1]))) --pos;
-        if (pos >= K) continue;
-        int last = nb < K ? nb : K - 1;
-        for (int q = last; q > pos; --q) { bd[q] = bd[q - 1]; bk[q] = bk[q - 1]; }
-        bd[pos] = d;
-        bk[pos] = key;
-        if (nb < K) ++nb;
-      }
+  const int nj = j1 - j0 + 1, ncell = (i1 - i0 + 1) * nj;
+  for (int c = part; c < ncell; c += nparts) {
+    const int i = i0 + c / nj, j = j0 + c % nj;
+    for (int kind = 0; kind < 6; ++kind) {
+      if ((kind == 1 || kind == 3 || kind >= 4) && i + 1 >= H.n) continue;
+      if ((kind == 2 || kind == 3 || kind >= 4) && j + 1 >= H.n) continue;
+      int key = 6 * (i * H.n + j) + kind;
+      v3<double> nn;
+      double no, dd;
+      if (!hm_feature<double>(H, key, P, nn, no, &dd) || !(dd <= rc)) continue;
+      hm_insert(bd, bk, nb, (long long)floor(dd / 1e-9), key);
+    }
+  }
+  return nb;
+}
+
+// The rank-th nearest candidate feature within radius rc of P, ordered by
+// distance quantised to 1e-9 m and then by key; -1 if there are fewer.
+OST_HD int hm_select(const HmapRef& H, const v3<double>& P, double rc, int rank) {
+  long long bd[4];
+  int bk[4];
+  if (rank < 0 || rank >= 4) return -1;
+  const int nb = hm_best4(H, P, rc, 0, 1, bd, bk);
   return rank < nb ? bk[rank] : -1;
 }
 
@@ -319,11 +338,12 @@ template <class T> struct Frame {
 // Frame of a slot at q-.  With `decide`, the feature choice is made (value
 // arithmetic) and written to F; otherwise F is used as given.
 // Heightmap slots (kind 3) take the rank-th nearest mesh feature within the
-// search radius rc (decided at q-; rc is only used when deciding).
+// search radius rc (decided at q-; rc is only used when deciding), or, keyed,
+// the feature already in F.hkey.
 template <class T>
 OST_HD Frame<T> slot_frame(int kind, const double* sreal, const double* obs, const v3<T>& xa, const m3<T>& Ra,
                            const v3<T>& xb, const m3<T>& Rb, Feature& F, bool decide, double* gap_out,
-                           const HmapRef* hm = nullptr, int rank = 0, double rc = 0.0) {
+                           const HmapRef* hm = nullptr, int rank = 0, double rc = 0.0, bool keyed = false) {
   Frame<T> C;
   C.la = mul(Ra, ld3<T>(sreal));
   v3<T> P = xa + C.la;
@@ -332,7 +352,7 @@ OST_HD Frame<T> slot_frame(int kind, const double* sreal, const double* obs, con
   C.lb = mk(T(0.0), T(0.0), T(0.0));
   T gap;
   if (kind == 3) {  // heightmap feature
-    if (decide) F.hkey = hm ? hm_select(*hm, v3<double>{val(P.x), val(P.y), val(P.z)}, rc, rank) : -1;
+    if (decide && !keyed) F.hkey = hm ? hm_select(*hm, v3<double>{val(P.x), val(P.y), val(P.z)}, rc, rank) : -1;
     bool ok = F.hkey >= 0 && hm_feature<T>(*hm, F.hkey, P, C.n, C.noff, nullptr);
     if (!ok) {  // no candidate: an inactive frame
       C.n = mk(T(0.0), T(0.0), T(1.0));

@@ -77,6 +77,101 @@ OST_HD void eval_row_group(const Batch& B, const Params& P, const WorldRef& R, c
 // --------------------------------------------------------------------------
 // Prologue: bodies at q-, contact refresh (A1), rows, warm start, FB scales.
 // --------------------------------------------------------------------------
+// The slot whose heightmap search a terrain slot s shares: the slot r places
+// before it when s takes rank r > 0 of the same body point and radius as that
+// rank-0 slot, else s itself.
+OST_HD int hm_leader(const Batch& B, const WorldRef& R, int s) {
+  const int* si = B.slot_int + 4 * (R.s0 + s);
+  const int r = si[3];
+  if (r <= 0 || r >= 4 || s - r < 0) return s;
+  const int l = s - r;
+  const int* li = B.slot_int + 4 * (R.s0 + l);
+  const double* sr = B.slot_real + 6 * (R.s0 + s);
+  const double* lr = B.slot_real + 6 * (R.s0 + l);
+  if (li[0] != 3 || li[3] != 0 || li[1] != si[1]) return s;
+  for (int k = 0; k < 4; ++k)
+    if (!(lr[k] == sr[k])) return s;
+  return l;
+}
+
+OST_HD double ll_bits(long long v) {
+  double d;
+  memcpy(&d, &v, sizeof d);
+  return d;
+}
+OST_HD long long bits_ll(double d) {
+  long long v;
+  memcpy(&v, &d, sizeof v);
+  return v;
+}
+
+// Heightmap candidates of the world's terrain slots at q- (the choice of
+// hm_select, computed together): one search per searching slot (hm_leader),
+// its cells spread over the team, each thread keeping the best four of its
+// cells; the lists are merged in the candidates' order, so the chosen keys do
+// not depend on the split.  The best four keys of searching slot l are left
+// in A[4 l .. 4 l + 3] (the Schur matrix's storage is free until assembly; a
+// world row capacity's square of it is always there), the searching slots in
+// s_act.  Returns false, with nothing done, when the world has no heightmap
+// or too little room, and each slot then searches for itself.
+template <class Team>
+OST_HD bool terrain_candidates(Team& t, const Batch& B, const Params& P, const WorldRef& R, const WorldMem& M) {
+  if (R.hm.n < 2) return false;
+  const int mrw = 5 * R.nj + R.nsv + 3 * R.cap;
+  const size_t room = (size_t)mrw * mrw + kPadA;
+  if (t.rank() == 0) {
+    int n = 0;
+    for (int s = 0; s < R.ns; ++s)
+      if (B.slot_int[4 * (R.s0 + s)] == 3 && hm_leader(B, R, s) == s) M.s_act[n++] = s;
+    M.iscal[9] = n;
+  }
+  t.sync();
+  const int ntask = M.iscal[9];
+  if (ntask == 0 || room < (size_t)4 * R.ns + (size_t)8 * ntask) {
+    t.sync();
+    return false;
+  }
+  double* fin = M.A;
+  double* lists = M.A + 4 * R.ns;
+  int G = t.size() / ntask;
+  const int gmax = (int)((room - (size_t)4 * R.ns) / ((size_t)8 * ntask));
+  if (G > gmax) G = gmax;
+  if (G < 1) G = 1;
+  for (int u = t.rank(); u < ntask * G; u += t.size()) {
+    const int task = u / G, part = u - task * G, s = M.s_act[task];
+    const int* si = B.slot_int + 4 * (R.s0 + s);
+    const double* sr = B.slot_real + 6 * (R.s0 + s);
+    const int a = si[1];
+    // the proxy centre and search radius of the slot loop below
+    const v3<double> la = mul(ldm(M.Rm + 9 * a), ldv(sr));
+    const double* ua = M.um + 6 * a;
+    const v3<double> vp = ldv(ua) + cross(ldv(ua + 3), la);
+    const double rc = sr[3] + P.d0 + P.h * ::sqrt(dot(vp, vp));
+    const v3<double> Pc = ldv(M.xm + 3 * a) + la;
+    long long bd[4];
+    int bk[4];
+    const int nb = hm_best4(R.hm, Pc, rc, part, G, bd, bk);
+    double* o = lists + 8 * u;
+    for (int q = 0; q < 4; ++q) {
+      o[q] = q < nb ? ll_bits(bd[q]) : 0.0;
+      o[4 + q] = q < nb ? (double)bk[q] : -1.0;
+    }
+  }
+  t.sync();
+  for (int task = t.rank(); task < ntask; task += t.size()) {
+    long long bd[4];
+    int bk[4], nb = 0;
+    for (int part = 0; part < G; ++part) {
+      const double* o = lists + 8 * (task * G + part);
+      for (int q = 0; q < 4 && o[4 + q] >= 0.0; ++q) hm_insert(bd, bk, nb, bits_ll(o[q]), (int)o[4 + q]);
+    }
+    double* f = fin + 4 * M.s_act[task];
+    for (int q = 0; q < 4; ++q) f[q] = q < nb ? (double)bk[q] : -1.0;
+  }
+  t.sync();
+  return true;
+}
+
 template <class Team>
 OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, const double* q_prev,
                      const double* u_prev, const double* ctrl, const double* lam_prev, WorldMem& M) {
@@ -123,12 +218,14 @@ OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
     }
   }
   // contact refresh: frame and activation of every slot at q-
+  const bool keyed = terrain_candidates(t, B, P, R, M);
   for (int s = t.rank(); s < R.ns; s += t.size()) {
     const int* si = B.slot_int + 4 * (R.s0 + s);
     const double* sr = B.slot_real + 6 * (R.s0 + s);
     int kind = si[0], a = si[1], b = si[2];
     Feature F{};
     double gap;
+    if (kind == 3 && keyed) F.hkey = si[3] >= 0 && si[3] < 4 ? (int)M.A[4 * hm_leader(B, R, s) + si[3]] : -1;
     v3<double> xb{0, 0, 0};
     m3<double> Rb = ldm(M.Rm + 9 * a);
     if (kind == 2) { xb = ldv(M.xm + 3 * b); Rb = ldm(M.Rm + 9 * b); }
@@ -141,7 +238,7 @@ OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
       rc = sr[3] + P.d0 + P.h * ::sqrt(dot(vp, vp));
     }
     Frame<double> C = slot_frame<double>(kind, sr, obs, ldv(M.xm + 3 * a), ldm(M.Rm + 9 * a), xb, Rb, F, true, &gap,
-                                         &R.hm, si[3], rc);
+                                         &R.hm, si[3], rc, kind == 3 && keyed);
     // relative velocity of the contact point at q-, approach along n
     v3<double> pc = ldv(M.xm + 3 * a) + C.la - C.n * sr[3];
     const double* ua = M.um + 6 * a;

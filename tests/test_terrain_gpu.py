@@ -88,3 +88,33 @@ def test_terrain_adjoint_matches_exact_ift(torch):
             checked += 1
         q, u, lam = got["q"].cpu().numpy(), un, ln
     assert checked >= 8
+
+
+def test_terrain_candidates_do_not_depend_on_the_team(torch):
+    """The heightmap search of a step is shared by the rank slots of one wheel
+    and split over the team's threads; the merged best lists, and so every
+    output of the step and of its adjoint, are the same bits for teams of 128
+    and 256 threads (different splits of each search)."""
+    from paper_2609_08800_amd import Simulator, spline_basis
+    b = scenes.terrain_batch(16, seed=5, n_maps=2)
+    P = scenes.solver_params()
+    K = scenes.ROBOT_KNOTS
+    ctrl = scenes.knots_array(b, K) @ spline_basis(20, K, P["h"])[4]
+    res = []
+    for team in (128, 256):
+        sim = Simulator(b, P, device="cuda:0", team=team)
+        q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+        outs = []
+        for k in range(4):
+            tape = sim.new_tape()
+            o = sim.step_forward(q, u, lam, ctrl, tape=tape)
+            g = sim.step_adjoint(q, u, ctrl, o["u"], o["lam"], tape, np.ones_like(q), np.ones_like(u))
+            outs.append([o[key].clone() for key in ("q", "u", "lam", "act_slot", "n_act", "iters", "status")] +
+                        [x.clone() for x in g])
+            q, u, lam = o["q"].cpu().numpy(), o["u"].cpu().numpy(), o["lam"].cpu().numpy()
+        res.append(outs)
+    for s0, s1 in zip(*res):
+        for x, y in zip(s0, s1):
+            if x.dtype == torch.float64:
+                x, y = x.view(torch.int64), y.view(torch.int64)
+            assert torch.equal(x, y)
