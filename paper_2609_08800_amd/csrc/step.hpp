@@ -454,9 +454,24 @@ OST_HD double evaluate(Team& t, const Batch& B, const Params& P, const WorldRef&
     v3<double> tq{M.fext[6 * b + 3], M.fext[6 * b + 4], M.fext[6 * b + 5]};
     body_terms<double>(P, M.mass[b], M.inert + 3 * b, ldm(M.Rm + 9 * b), M.um + 6 * b, u + 6 * b, tq, out);
     double v = out[comp];
-    for (int i = 0; i < R.m; ++i) {
-      if (M.r_a[i] == b) v -= P.h * (M.J[12 * i + comp] * lam[i]);
-      if (M.r_b[i] == b) v -= P.h * (M.J[12 * i + 6 + comp] * lam[i]);
+    const int m = R.m;
+    for (int i0 = 0; i0 < m; i0 += 4) {  // rows in fours: the loads first, then the sum in row order
+      int ra[4], rb[4];
+      double ja[4], jb[4], lm[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + r < m ? i0 + r : m - 1;
+        ra[r] = i0 + r < m ? M.r_a[i] : -2;
+        rb[r] = i0 + r < m ? M.r_b[i] : -2;
+        ja[r] = M.J[12 * i + comp];
+        jb[r] = M.J[12 * i + 6 + comp];
+        lm[r] = lam[i];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (ra[r] == b) v -= P.h * (ja[r] * lm[r]);
+        if (rb[r] == b) v -= P.h * (jb[r] * lm[r]);
+      }
     }
     M.rdyn[e] = v;
   }
@@ -489,8 +504,10 @@ OST_HD void assemble(Team& t, const Params& P, const WorldRef& R, const WorldMem
       j = i - bw + (e - i * wd);
       if (j < 0 || j >= m) continue;
     }
-    const double* Y = M.Y + 12 * i;
-    const double* Jj = M.J + 12 * j;
+    // all loads of the entry at once, then the sums of the shared bodies' blocks in order
+    double Y[12], Jj[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) { Y[k] = M.Y[12 * i + k]; Jj[k] = M.J[12 * j + k]; }
     int ai = M.r_a[i], bi = M.r_b[i], aj = M.r_a[j], bj = M.r_b[j];
     double s = 0.0;
     if (ai == aj) for (int k = 0; k < 6; ++k) s += Y[k] * Jj[k];
@@ -538,16 +555,18 @@ template <class Team> OST_HD bool lu_factor(Team& t, const WorldRef& R, const Wo
     int ok = 1;
     for (int k = 0; k < m; ++k) {
       const int hi = k + bw + 1 < m ? k + bw + 1 : m;
-      const double piv = A[k * m + k], rk = rmax[k];
+      // the lane's first row below the pivot: its column-k entry is read with the pivot
+      const int i1 = k + 1 + (lane + W - (k + 1) % W) % W;
+      const double piv = A[k * m + k], rk = rmax[k], a1 = i1 < hi ? A[i1 * m + k] : 0.0;
       if (!(isfinite(piv) && fabs(piv) > 1e-14 * rk && rk > 0.0)) {
         ok = 0;
         break;
       }
       const double ip = 1.0 / piv;
       const double* Ak = A + k * m;
-      for (int i = k + 1 + (lane + W - (k + 1) % W) % W; i < hi; i += W) {
+      for (int i = i1; i < hi; i += W) {
         double* Ai = A + i * m;
-        const double l = Ai[k] * ip;
+        const double l = (i == i1 ? a1 : Ai[k]) * ip;
         Ai[k] = l;
         double v = 0.0;
         int j = k + 1;
