@@ -46,10 +46,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per k_forward launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None when the
-    kernel sources changed since the counters were taken."""
+def recorded_traffic(key="hbm_bytes_per_launch"):
+    """HBM bytes per k_forward launch (or, with key="adjoint_hbm_bytes_per_launch", per
+    k_adjoint launch) from the committed rocprofv3 counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by the copy calibration), or None when the kernel sources
+    changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "k_forward_robot8192_counters.txt")
     if not os.path.exists(path):
         return None
@@ -62,7 +63,7 @@ def recorded_traffic():
     if vals.get("kernel_source_hash") != kernel_source_hash():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
@@ -122,6 +123,27 @@ def plain_path_measurement(n_worlds=64, T=5):
     dt = time.perf_counter() - t0
     return {"world_steps_per_s": round(n_worlds * T / dt, 1), "sample": f"{n_worlds} robot worlds x {T} steps",
             "launches_per_world_step": P["k_max"] + 3}
+
+
+def checkpoint_measurement(sim, q0, u0, knots, basis, T, loss_body, target, W):
+    """One rollout with its adjoint at checkpoint interval 1 (every state kept, every
+    step recomputed once) and with every step's factor kept (no recomputation):
+    world-steps/s and peak HBM of each."""
+    import torch
+    dev = q0.device
+    res = []
+    for ck, what in ((1, "every state kept, each step recomputed"), (0, "every step's factor kept, no recomputation")):
+        wsk = sim.new_workspace(T, ck)
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats(dev)
+        t0 = time.perf_counter()
+        sim.rollout(q0, u0, knots, basis, T, ckpt_every=ck, loss_body=loss_body, target=target, workspace=wsk)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res.append({"ckpt_every": ck, "what": what, "world_steps_per_s": round(W * T / dt, 1),
+                    "peak_hbm_gb": round(torch.cuda.max_memory_allocated(dev) / 1e9, 3)})
+        del wsk
+    return res
 
 
 def uneven_measurement(n_stacks=2048, n_robots=2048, T=50, ckpt=10, seed=0):
@@ -205,6 +227,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="arrival window of the serving run")
     ap.add_argument("--serve-drain", type=float, default=40.0, help="extra time to finish admitted requests")
     ap.add_argument("--uneven", type=int, default=1, help="also measure the uneven stacks + robots batch")
+    ap.add_argument("--serve-sweep", type=str, default="",
+                    help="comma-separated arrival rates (req/s) of an additional serving sweep")
     ap.add_argument("--roofline-only", action="store_true",
                     help="skip the timed rollouts; run only the per-launch forward measurement "
                          "(for hardware-counter runs)")
@@ -264,6 +288,7 @@ def main():
     dt = time.perf_counter() - t0
     sim.timing(0)
     fwd = sim.timing(2)
+    adj = sim.timing(3)
     ms = dt / args.steps * 1e3
     world_steps = W * T * args.steps
     value = world_steps / dt if not args.roofline_only else float("nan")
@@ -297,6 +322,20 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5),
                 "traffic": traffic, "kernel": "k_forward", "launches_timed": fwd["launches"],
                 "avg_launch_ms": round(avg_ms, 4), "flop_per_launch": flop_per_launch}
+    adjoint_roofline = None
+    if adj["launches"]:
+        a_ms = adj["ms"] / adj["launches"]
+        a_bytes = adj["bytes"] / adj["launches"]
+        a_gbs = a_bytes / (a_ms * 1e-3) / 1e9
+        adjoint_roofline = {"bound": "hbm", "achieved": round(a_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(a_gbs / HBM_PEAK_GBS, 5),
+                            "traffic": recorded_traffic("adjoint_hbm_bytes_per_launch"), "kernel": "k_adjoint",
+                            "launches_timed": adj["launches"], "avg_launch_ms": round(a_ms, 4),
+                            "bytes_per_launch": a_bytes}
+    ckpt_modes = None
+    if not args.roofline_only:
+        ckpt_modes = checkpoint_measurement(sim, q0, u0, knots, basis, T, lb, tg, W)
+        progress("checkpoint modes done")
     plain = None
     if not args.roofline_only:
         plain = plain_path_measurement()
@@ -310,6 +349,12 @@ def main():
     if args.serve_rate > 0 and not args.roofline_only:
         serving = serving_measurement(args.serve_rate, args.serve_seconds, args.serve_drain)
         progress("serving done")
+    sweep = None
+    if args.serve_sweep and not args.roofline_only:
+        sweep = []
+        for r in args.serve_sweep.split(","):
+            sweep.append(serving_measurement(float(r), args.serve_seconds, args.serve_drain))
+            progress(f"serving at {r} req/s done")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline()
@@ -341,9 +386,12 @@ def main():
                   "frac_budget": round(float(np.mean((status & 2) > 0)), 4),
                   "frac_worlds_nonfinite_at_T": round(float(np.mean((status[-1] & 4) > 0)), 4),
                   "mean_rows": round(float(np.mean(m_all)), 2),
+                  "adjoint_roofline": adjoint_roofline,
+                  "checkpointing": ckpt_modes,
                   "plain_path": plain,
                   "uneven_batch": uneven,
-                  "serving": serving},
+                  "serving": serving,
+                  "serving_sweep": sweep},
     }
     print(json.dumps(line))
 

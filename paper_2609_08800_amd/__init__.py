@@ -117,10 +117,15 @@ class Simulator:
         return [dict(zip(keys, map(int, buf[6 * i:6 * i + 6]))) for i in range(n)]
 
     def timing(self, mode: int):
-        """Forward-launch measurement: 1 start, 0 stop, 2 read (launches, total ms, algorithmic flops)."""
+        """Launch measurement: 1 start, 0 stop; 2 reads the forward steps (launches, total ms, algorithmic
+        flops), 3 the adjoint steps (launches, total ms, algorithmic bytes)."""
         out = np.zeros(3)
         _capi.check(self.lib.ostrich_ctx_timing(self.ctx, int(mode), out.ctypes.data), "ostrich_ctx_timing")
-        return {"launches": int(out[0]), "ms": float(out[1]), "flops": float(out[2])} if mode == 2 else None
+        if mode == 2:
+            return {"launches": int(out[0]), "ms": float(out[1]), "flops": float(out[2])}
+        if mode == 3:
+            return {"launches": int(out[0]), "ms": float(out[1]), "bytes": float(out[2])}
+        return None
 
     def autotune(self, q, u, lam=None, ctrl=None, reps: int = 2, stream=None):
         """Pick each bucket's launch by timing forward steps from (q, u, lam, ctrl)."""

@@ -319,9 +319,23 @@ OST_HD void adjoint_solve(Team& t, const WorldRef& R, const WorldMem& M, const d
   for (int e = t.rank(); e < 6 * nb; e += t.size()) {
     int q = e / 6, k = e - 6 * q;
     double s = M.kg[e];
-    for (int i = 0; i < m; ++i) {
-      if (M.r_a[i] == q) s += M.Y[12 * i + k] * wl[i];
-      if (M.r_b[i] == q) s += M.Y[12 * i + 6 + k] * wl[i];
+    for (int i0 = 0; i0 < m; i0 += 4) {  // rows in fours: the loads first, then the sum in row order
+      int ra[4], rb[4];
+      double ya[4], yb[4], w[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + r < m ? i0 + r : m - 1;
+        ra[r] = i0 + r < m ? M.r_a[i] : -2;
+        rb[r] = i0 + r < m ? M.r_b[i] : -2;
+        ya[r] = M.Y[12 * i + k];
+        yb[r] = M.Y[12 * i + 6 + k];
+        w[r] = wl[i];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (ra[r] == q) s += ya[r] * w[r];
+        if (rb[r] == q) s += yb[r] * w[r];
+      }
     }
     wu[e] = -s;
   }

@@ -259,6 +259,30 @@ __global__ void k_flops(ost::Batch B, const int32_t* n_act, const int32_t* iters
   }
 }
 
+// Algorithmic bytes of one adjoint step of every world: the factor's band read
+// from the tape (rows m and half band bw from the tape's trailer), the states
+// and multipliers read, the cotangents read and written, and the control
+// cotangents written.
+__global__ void k_abytes(ost::Batch B, const double* tape, const int64_t* tape_off, double* acc) {
+  __shared__ double part[256];
+  double s = 0.0;
+  for (int w = threadIdx.x; w < B.n_worlds; w += blockDim.x) {
+    const double* tr = tape + tape_off[w + 1] - 4;
+    const double m = tr[1], bw = tr[3] < tr[1] - 1 ? tr[3] : tr[1] - 1;
+    const double band = m > 0 ? m * (2.0 * bw + 1.0) - bw * (bw + 1.0) : 0.0;
+    const double nb = B.body_off[w + 1] - B.body_off[w];
+    const double nl = B.lam_off[w + 1] - B.lam_off[w], nc = B.ctrl_off[w + 1] - B.ctrl_off[w];
+    s += 8.0 * (band + 4 + 13.0 * nb + 6.0 * nb + nl + 2.0 * 13.0 * nb + nc);
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < (int)blockDim.x; ++i) t += part[i];
+    acc[0] += t;
+  }
+}
+
 // controls of every step: ctrl[k, c] = sum_j basis[k, j] knots[c, j]
 __global__ void k_ctrl(const double* basis, const double* knots, int T, int K, int nctrl, double* ctrl) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -350,11 +374,13 @@ struct ostrich_ctx {
   std::vector<hipStream_t> bstreams;
   hipEvent_t ev_fork = nullptr;
   std::vector<hipEvent_t> ev_join;
-  // measurement of the forward launches (ostrich_ctx_timing)
+  // measurement of the forward and adjoint launches (ostrich_ctx_timing)
   bool timing = false;
-  std::vector<hipEvent_t> ev;  // start / stop pairs
+  std::vector<hipEvent_t> ev;  // forward start / stop pairs
   size_t n_ev = 0;
-  double* d_flops = nullptr;
+  double* d_flops = nullptr;   // [0] forward algorithmic flops, [1] adjoint algorithmic bytes
+  std::vector<hipEvent_t> eva;  // adjoint start / stop pairs
+  size_t n_eva = 0;
   int64_t* d_tape_off = nullptr;
   size_t tape_total = 0;  // doubles
   ~ostrich_ctx() {
@@ -370,6 +396,7 @@ struct ostrich_ctx {
     for (hipEvent_t e : ev_join) (void)hipEventDestroy(e);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : eva) (void)hipEventDestroy(e);
     if (d_tape_off) (void)hipFree(d_tape_off);
   }
 };
@@ -651,29 +678,36 @@ extern "C" int ostrich_step_forward(ostrich_ctx* ctx, const double* q_prev, cons
 extern "C" int ostrich_ctx_timing(ostrich_ctx* ctx, int32_t mode, double* out) {
   if (!ctx) return fail(OSTRICH_E_ARG, "null context");
   if (mode == 1 || mode == 0) {  // start (reset) or stop
-    if (!ctx->d_flops) HIP_OK(hipMalloc(&ctx->d_flops, sizeof(double)));
+    if (!ctx->d_flops) HIP_OK(hipMalloc(&ctx->d_flops, 2 * sizeof(double)));
     if (mode == 1) {
       HIP_OK(hipDeviceSynchronize());
-      const double z = 0.0;
-      HIP_OK(hipMemcpy(ctx->d_flops, &z, sizeof(double), hipMemcpyHostToDevice));
+      const double z[2] = {0.0, 0.0};
+      HIP_OK(hipMemcpy(ctx->d_flops, z, sizeof(z), hipMemcpyHostToDevice));
       ctx->n_ev = 0;
+      ctx->n_eva = 0;
     }
     ctx->timing = mode == 1;
     return 0;
   }
-  if (mode != 2 || !out) return fail(OSTRICH_E_ARG, "timing mode");
+  if ((mode != 2 && mode != 3) || !out) return fail(OSTRICH_E_ARG, "timing mode");
+  if (!ctx->d_flops) {
+    out[0] = out[1] = out[2] = 0.0;
+    return 0;
+  }
   HIP_OK(hipDeviceSynchronize());
+  const std::vector<hipEvent_t>& ev = mode == 2 ? ctx->ev : ctx->eva;
+  const size_t n_ev = mode == 2 ? ctx->n_ev : ctx->n_eva;
   double total = 0.0;
-  for (size_t i = 0; i + 1 < ctx->n_ev; i += 2) {
+  for (size_t i = 0; i + 1 < n_ev; i += 2) {
     float ms = 0.f;
-    HIP_OK(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
+    HIP_OK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
     total += ms;
   }
-  double fl = 0.0;
-  HIP_OK(hipMemcpy(&fl, ctx->d_flops, sizeof(double), hipMemcpyDeviceToHost));
-  out[0] = (double)(ctx->n_ev / 2);
+  double acc[2] = {0.0, 0.0};
+  HIP_OK(hipMemcpy(acc, ctx->d_flops, sizeof(acc), hipMemcpyDeviceToHost));
+  out[0] = (double)(n_ev / 2);
   out[1] = total;
-  out[2] = fl;
+  out[2] = acc[mode - 2];
   return 0;
 }
 
@@ -685,6 +719,17 @@ extern "C" int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, cons
     return fail(OSTRICH_E_ARG, "null pointer");
   if (ctx->NCTRL > 0 && (!ctrl || !g_ctrl)) return fail(OSTRICH_E_ARG, "controls required");
   int rf = refine < 0 ? ctx->refine : refine;
+  const bool timed = ctx->timing && ctx->d_flops;
+  if (timed) {
+    if (ctx->n_eva + 2 > ctx->eva.size()) {
+      for (int k = 0; k < 2; ++k) {
+        hipEvent_t e;
+        HIP_OK(hipEventCreate(&e));
+        ctx->eva.push_back(e);
+      }
+    }
+    HIP_OK(hipEventRecord(ctx->eva[ctx->n_eva], (hipStream_t)stream));
+  }
   int rc = for_buckets(ctx, (hipStream_t)stream, [&](const Bucket& bk, hipStream_t s) {
     hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>, dim3(grid_of(bk)),
                        dim3(bk.team), bk.lds, s, ctx->B, ctx->P,
@@ -692,6 +737,12 @@ extern "C" int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, cons
                        (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf);
   });
   if (rc) return rc;
+  if (timed) {
+    HIP_OK(hipEventRecord(ctx->eva[ctx->n_eva + 1], (hipStream_t)stream));
+    ctx->n_eva += 2;
+    hipLaunchKernelGGL(k_abytes, dim3(1), dim3(256), 0, (hipStream_t)stream, ctx->B, (const double*)tape,
+                       (const int64_t*)ctx->d_tape_off, ctx->d_flops + 1);
+  }
   HIP_OK(hipGetLastError());
   return 0;
 }
