@@ -233,3 +233,42 @@ def test_status_edge_cases(torch):
     for w in ok:
         s = slice(b.body_off[w], b.body_off[w + 1])
         assert rel_err(got["u"][s], ref["u"][s]) <= 1e-6
+
+
+def test_step_timing_counts_launches_and_algorithmic_work(torch):
+    """The measurement facility: one forward step with a tape and its adjoint
+    are counted once each; the forward's flops and the adjoint's bytes follow
+    the documented formulas from each world's rows m, half band and Newton
+    iterations."""
+    b = scenes.robot_batch(6, seed=12)
+    P = scenes.solver_params()
+    sim = sim_for(b, P)
+    ctrl = robot_ctrl(b)(3)
+    tape = sim.new_tape()
+    sim.timing(1)
+    o = sim.step_forward(b.q0, b.u0, np.zeros(b.n_lam), ctrl, tape=tape)
+    sim.step_adjoint(b.q0, b.u0, ctrl, o["u"], o["lam"], tape, np.ones_like(b.q0), np.ones_like(b.u0))
+    sim.timing(0)
+    fwd, adj = sim.timing(2), sim.timing(3)
+    assert fwd["launches"] == 1 and adj["launches"] == 1
+    assert fwd["ms"] > 0 and adj["ms"] > 0
+    n_act, iters = o["n_act"].cpu().numpy(), o["iters"].cpu().numpy()
+    # world w's tape: row capacity squared plus a trailer (dreg, m, valid, half band)
+    toff = np.cumsum([0] + [max(min(x.contact_cap, len(x.slots)) * 3 + 5 * len(x.joints) + x.n_servo, 1) ** 2 + 4
+                            for x in b.worlds])
+    tp = tape.cpu().numpy()
+    flops, nbytes = 0.0, 0.0
+    for w in range(b.n_worlds):
+        nj = b.joint_off[w + 1] - b.joint_off[w]
+        nsv = b.worlds[w].n_servo
+        m = 5.0 * nj + nsv + 3.0 * n_act[w]
+        flops += iters[w] * (26 * m * m + 2 * m ** 3 / 3 + 800 * m) + 400 * m + 24 * m * m + 2 * m ** 3 / 3
+        nb = b.body_off[w + 1] - b.body_off[w]
+        nl = b.lam_off[w + 1] - b.lam_off[w]
+        nc = b.ctrl_off[w + 1] - b.ctrl_off[w]
+        tm, bw = tp[toff[w + 1] - 3], min(tp[toff[w + 1] - 1], m - 1)
+        assert tm == m
+        band = m * (2 * bw + 1) - bw * (bw + 1)
+        nbytes += 8.0 * (band + 4 + 13 * nb + 6 * nb + nl + 26 * nb + nc)
+    assert abs(fwd["flops"] - flops) <= 1e-9 * flops
+    assert abs(adj["bytes"] - nbytes) <= 1e-9 * nbytes
