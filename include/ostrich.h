@@ -186,6 +186,20 @@ int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, const double* u
                          const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl, int32_t refine,
                          void* stream);
 
+/* The adjoint of ostrich_step_adjoint together with the cotangents of the
+ * model parameters (Eq. (17) with xi a parameter, the paper's system
+ * identification use): g_mass [NB] of every body's mass, g_mu [NS] of every
+ * slot's friction coefficient (zero for slots without an active contact at
+ * q-), g_kp [NJ] of every joint's servo gain (zero for joints without a servo
+ * row).  Device pointers, all required (OSTRICH_E_ARG otherwise); every entry
+ * is written.  The FB scales and the Schur regularisation are held as in the
+ * solve, so these are the derivatives of the solved, regularised step. */
+int ostrich_step_adjoint_params(ostrich_ctx* ctx, const double* q_prev, const double* u_prev, const double* ctrl,
+                                const double* u_next, const double* lam_next, const void* tape,
+                                const double* gq_next, const double* gu_next, double* gq_prev, double* gu_prev,
+                                double* g_ctrl, double* g_mass, double* g_mu, double* g_kp, int32_t refine,
+                                void* stream);
+
 /* The same two steps restricted to the worlds listed in `worlds` (device
  * int32 [n], distinct ids): only those worlds' entries of the state, status
  * and tape arrays are read or written.  The serving loop uses them to advance

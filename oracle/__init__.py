@@ -55,7 +55,8 @@ def lib():
     if _lib is None:
         build()
         _lib = ctypes.CDLL(_SO)
-        for name in ("ostrich_ref_step_forward", "ostrich_ref_step_adjoint", "ostrich_ref_spline_basis",
+        for name in ("ostrich_ref_step_forward", "ostrich_ref_step_adjoint", "ostrich_ref_step_adjoint_params",
+                     "ostrich_ref_spline_basis",
                      "ostrich_ref_rollout", "ostrich_ref_inspect"):
             getattr(_lib, name).restype = c_int
     return _lib
@@ -141,6 +142,30 @@ def step_adjoint(batch, params, q, u, lam, ctrl, u_next, lam_next, gq_next, gu_n
     if rc != 0:
         raise RuntimeError("oracle step_adjoint failed: %d" % rc)
     return gq, gu, gc[:batch.n_ctrl]
+
+
+def step_adjoint_params(batch, params, q, u, ctrl, u_next, lam_next, gq_next, gu_next, mode=0):
+    """The adjoint of step_adjoint and the cotangents of the body masses, the
+    slots' friction coefficients and the joints' servo gains (Eq. (17) with a
+    model parameter as xi)."""
+    H = _Handle(batch, params)
+    q, u = _d(q), _d(u)
+    ctrl = _d(ctrl if ctrl is not None else np.zeros(max(batch.n_ctrl, 1)))
+    u_next, lam_next, gq_next, gu_next = _d(u_next), _d(lam_next), _d(gq_next), _d(gu_next)
+    gq, gu = np.zeros_like(q), np.zeros_like(u)
+    gc = np.zeros(max(batch.n_ctrl, 1))
+    gm = np.zeros(int(batch.body_off[-1]))
+    gmu = np.zeros(max(int(batch.slot_off[-1]), 1))
+    gkp = np.zeros(max(int(batch.joint_off[-1]), 1))
+    rc = lib().ostrich_ref_step_adjoint_params(
+        ctypes.byref(H.cb), ctypes.byref(H.cp), _p(q, c_dbl_p), _p(u, c_dbl_p), _p(ctrl, c_dbl_p),
+        _p(u_next, c_dbl_p), _p(lam_next, c_dbl_p), _p(gq_next, c_dbl_p), _p(gu_next, c_dbl_p),
+        _p(gq, c_dbl_p), _p(gu, c_dbl_p), _p(gc, c_dbl_p), _p(gm, c_dbl_p), _p(gmu, c_dbl_p), _p(gkp, c_dbl_p),
+        c_int(mode))
+    if rc != 0:
+        raise RuntimeError("oracle step_adjoint_params failed: %d" % rc)
+    return dict(gq=gq, gu=gu, gc=gc[:batch.n_ctrl], g_mass=gm, g_mu=gmu[:int(batch.slot_off[-1])],
+                g_kp=gkp[:int(batch.joint_off[-1])])
 
 
 def spline_basis(T, K, h):

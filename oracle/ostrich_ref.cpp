@@ -125,6 +125,23 @@ struct HmapD {
   double sp = 0, ox = 0, oy = 0;
   V3<double> vert(int i, int j) const { return {ox + sp * i, oy + sp * j, z[i * n + j]}; }
 };
+// Model parameters as the evaluation's number type.  With dual numbers, the
+// parameter named by the current seed (a body's mass, a slot's friction
+// coefficient or a joint's servo gain) carries derivative 1, so that one
+// evaluation gives the residual's derivative with respect to it (Eq. (17)
+// with xi a parameter).  No seed is set outside the parameter pull-back.
+enum { PS_NONE = 0, PS_MASS = 1, PS_MU = 2, PS_KP = 3 };
+thread_local int g_seed_kind = PS_NONE, g_seed_idx = -1;
+template <class T> T param(double v, int kind, int idx) {
+  if constexpr (std::is_same<T, double>::value) {
+    (void)kind;
+    (void)idx;
+    return v;
+  } else {
+    return T(v, kind == g_seed_kind && idx == g_seed_idx ? 1.0 : 0.0);
+  }
+}
+
 struct WorldD {
   int nb = 0, nctrl = 0, nservo = 0, lam_len = 0, cap = 0;
   HmapD hm;
@@ -669,7 +686,8 @@ void group_residual(const WorldD& W, const Prm& P, const Layout& L, int g, const
     V3<S> ax = qrot(prev_rot(qa_m), cst3<S>(J.axis_a));
     S vel = ax.x * (ub[3] - ua[3]) + ax.y * (ub[4] - ua[4]) + ax.z * (ub[5] - ua[5]);
     // act 2: commanded joint speed; act 3: target 0 (axle damping beside a torque)
-    r[0] = J.act == 2 ? vel + lg[0] / J.kp - ctrl[J.ctrl] : vel + lg[0] / J.kp;
+    const S kp = param<S>(J.kp, PS_KP, L.idx[g]);
+    r[0] = J.act == 2 ? vel + lg[0] / kp - ctrl[J.ctrl] : vel + lg[0] / kp;
     return;
   }
   // normal row: eps-smoothed FB of (gap, sigma_n lambda_n), Eq. (4)
@@ -686,9 +704,10 @@ void group_residual(const WorldD& W, const Prm& P, const Layout& L, int g, const
   const S& ln = lg[0];
   S s2 = vt[0] * vt[0] + vt[1] * vt[1] + P.eps * P.eps;
   S lf = sqrt(lg[1] * lg[1] + lg[2] * lg[2] + P.eps * P.eps);
-  S beta = sf * (C->mu * ln - lf);
+  const S mu = param<S>(C->mu, PS_MU, C->slot);
+  S beta = sf * (mu * ln - lf);
   S Q = sqrt(s2 + beta * beta);
-  S den = vmax(C->mu * ln, S(P.dg));
+  S den = vmax(mu * ln, S(P.dg));
   // (Q - beta) written as s^2 / (Q + beta) when beta > 0: same value, no cancellation
   S Wt = val(beta) > 0 ? s2 / ((Q + beta) * den) : (Q - beta) / den;
   r[1] = vt[0] + Wt * lg[1];
@@ -779,7 +798,7 @@ void evaluate(const WorldD& W, const Prm& P, const Layout& L, const std::vector<
       tq[J.a] = tq[J.a] - ax * ctrl[J.ctrl];
     }
   for (int b = 0; b < nb; ++b) {
-    double mb = W.mass[b];
+    const T mb = param<T>(W.mass[b], PS_MASS, b);
     for (int k = 0; k < 3; ++k) E.F[6 * b + k] = mb * (u[6 * b + k] - um[6 * b + k]) - h * (mb * P.g[k]);
     V3<T> wm{um[6 * b + 3], um[6 * b + 4], um[6 * b + 5]};
     V3<T> wk{u[6 * b + 3], u[6 * b + 4], u[6 * b + 5]};
@@ -1267,7 +1286,8 @@ void exact_jacobian(const StepCtx& X, const Eval<double>& E, const Schur& S, con
 // ------------------------------------------------------- adjoint ---------
 // Gradients of L(s+) w.r.t. (q-, u-, a) through one step (Sec. III-D).
 void adjoint_world(StepCtx& X, const double* u_star, const double* lam_slots, const double* gq_next,
-                   const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl, int mode) {
+                   const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl, int mode,
+                   double* g_mass = nullptr, double* g_mu = nullptr, double* g_kp = nullptr) {
   const Prm& P = X.P;
   const WorldD& W = X.W;
   const int nb = W.nb, nu = X.L.nu, m = X.L.m, n = nu + m;
@@ -1377,6 +1397,21 @@ void adjoint_world(StepCtx& X, const double* u_star, const double* lam_slots, co
   for (int t = 0; t < 7 * nb; ++t) gq_prev[t] = dq_prev[t] + pull(0, t);
   for (int t = 0; t < 6 * nb; ++t) gu_prev[t] = pull(1, t);
   for (int t = 0; t < W.nctrl; ++t) g_ctrl[t] = pull(2, t);
+  // model parameters: the same pull-back with the parameter seeded instead
+  auto pull_param = [&](int kind, int idx) -> double {
+    g_seed_kind = kind;
+    g_seed_idx = idx;
+    const double s = pull(3, 0);
+    g_seed_kind = PS_NONE;
+    g_seed_idx = -1;
+    return s;
+  };
+  if (g_mass)
+    for (int t = 0; t < nb; ++t) g_mass[t] = pull_param(PS_MASS, t);
+  if (g_mu)
+    for (int t = 0; t < (int)W.slots.size(); ++t) g_mu[t] = pull_param(PS_MU, t);
+  if (g_kp)
+    for (int t = 0; t < (int)W.joints.size(); ++t) g_kp[t] = pull_param(PS_KP, t);
 }
 
 }  // namespace
@@ -1432,6 +1467,31 @@ extern "C" int ostrich_ref_step_adjoint(const ostrich_ref_batch* b, const ostric
     std::vector<double> gc(X.W.nctrl + 1, 0.0);
     adjoint_world(X, u_next + 6 * b0, lam_next + l0, gq_next + 7 * b0, gu_next + 6 * b0, gq_prev + 7 * b0,
                   gu_prev + 6 * b0, gc.data(), mode);
+    if (g_ctrl)
+      for (int t = 0; t < X.W.nctrl; ++t) g_ctrl[c0 + t] = gc[t];
+  }
+  return 0;
+}
+
+extern "C" int ostrich_ref_step_adjoint_params(const ostrich_ref_batch* b, const ostrich_ref_params* p,
+                                               const double* q_prev, const double* u_prev, const double* ctrl,
+                                               const double* u_next, const double* lam_next, const double* gq_next,
+                                               const double* gu_next, double* gq_prev, double* gu_prev,
+                                               double* g_ctrl, double* g_mass, double* g_mu, double* g_kp,
+                                               int32_t mode) {
+  if (!b || !p || !q_prev || !u_prev || !u_next || !lam_next || !gq_next || !gu_next || !gq_prev || !gu_prev ||
+      !g_mass || !g_mu || !g_kp)
+    return -1;
+  Prm P = load_params(p);
+  for (int w = 0; w < b->n_worlds; ++w) {
+    StepCtx X;
+    X.W = load_world(b, w);
+    X.P = P;
+    int b0 = b->body_off[w], c0 = b->ctrl_off[w], l0 = b->lam_off[w], s0 = b->slot_off[w], j0 = b->joint_off[w];
+    prepare(X, q_prev + 7 * b0, u_prev + 6 * b0, ctrl ? ctrl + c0 : nullptr);
+    std::vector<double> gc(X.W.nctrl + 1, 0.0);
+    adjoint_world(X, u_next + 6 * b0, lam_next + l0, gq_next + 7 * b0, gu_next + 6 * b0, gq_prev + 7 * b0,
+                  gu_prev + 6 * b0, gc.data(), mode, g_mass + b0, g_mu + s0, g_kp + j0);
     if (g_ctrl)
       for (int t = 0; t < X.W.nctrl; ++t) g_ctrl[c0 + t] = gc[t];
   }

@@ -79,6 +79,17 @@ int ostrich_ref_step_adjoint(const ostrich_ref_batch* b, const ostrich_ref_param
                              const double* gq_next, const double* gu_next,
                              double* gq_prev, double* gu_prev, double* g_ctrl, int32_t mode);
 
+/* The adjoint above and, by the same pull-back (Eq. (17)) with a model
+ * parameter as xi, the cotangents of every body's mass (g_mass, per body),
+ * every slot's friction coefficient (g_mu, per slot; zero for slots without an
+ * active contact) and every joint's servo gain (g_kp, per joint; zero for
+ * joints without a servo row).  All outputs are required. */
+int ostrich_ref_step_adjoint_params(const ostrich_ref_batch* b, const ostrich_ref_params* p,
+                                    const double* q_prev, const double* u_prev, const double* ctrl,
+                                    const double* u_next, const double* lam_next, const double* gq_next,
+                                    const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl,
+                                    double* g_mass, double* g_mu, double* g_kp, int32_t mode);
+
 /* Natural cubic spline basis B[T*K]: control at step k is sum_j B[k,j] knot_j,
  * knots at t_j = j*T*h/(K-1), step k samples t = k*h. */
 int ostrich_ref_spline_basis(int32_t T, int32_t K, double h, double* B);

@@ -73,6 +73,7 @@ class Simulator:
         self.NB = int(batch.body_off[-1])
         self.NL = int(batch.lam_off[-1])
         self.NS = int(batch.slot_off[-1])
+        self.NJ = int(batch.joint_off[-1])
         self.NCTRL = int(batch.ctrl_off[-1])
         self._dev = {}
         ptrs = {}
@@ -215,6 +216,27 @@ class Simulator:
             int(refine), self._stream(stream))
         _capi.check(rc, "ostrich_step_adjoint")
         return gq, gu, gc[:self.NCTRL]
+
+    def step_adjoint_params(self, q, u, ctrl, u_next, lam_next, tape, gq_next, gu_next, refine=-1, stream=None):
+        """step_adjoint and the cotangents of every body's mass, every slot's friction
+        coefficient and every joint's servo gain: (gq, gu, g_ctrl, g_mass, g_mu, g_kp)."""
+        torch = self.torch
+        q, u = self._f64(q, (self.NB, 7)), self._f64(u, (self.NB, 6))
+        ctrl = self._ctrl(ctrl)
+        u_next, lam_next = self._f64(u_next, (self.NB, 6)), self._f64(lam_next)
+        gq_next, gu_next = self._f64(gq_next, (self.NB, 7)), self._f64(gu_next, (self.NB, 6))
+        f64 = dict(dtype=torch.float64, device=self.device)
+        gq, gu = torch.empty_like(q), torch.empty_like(u)
+        gc = torch.zeros(max(self.NCTRL, 1), **f64)
+        gm = torch.empty(self.NB, **f64)
+        gmu = torch.empty(max(self.NS, 1), **f64)
+        gkp = torch.empty(max(self.NJ, 1), **f64)
+        rc = self.lib.ostrich_step_adjoint_params(
+            self.ctx, q.data_ptr(), u.data_ptr(), ctrl.data_ptr(), u_next.data_ptr(), lam_next.data_ptr(),
+            tape.data_ptr(), gq_next.data_ptr(), gu_next.data_ptr(), gq.data_ptr(), gu.data_ptr(), gc.data_ptr(),
+            gm.data_ptr(), gmu.data_ptr(), gkp.data_ptr(), int(refine), self._stream(stream))
+        _capi.check(rc, "ostrich_step_adjoint_params")
+        return gq, gu, gc[:self.NCTRL], gm, gmu[:self.NS], gkp[:self.NJ]
 
     def workspace_bytes(self, T: int, ckpt_every: int) -> int:
         return int(self.lib.ostrich_rollout_workspace_bytes(self.ctx, int(T), int(ckpt_every)))

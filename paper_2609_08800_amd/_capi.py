@@ -72,6 +72,8 @@ def load() -> ctypes.CDLL:
     L.ostrich_step_forward.restype = c_int
     L.ostrich_step_adjoint.argtypes = [c_vp] + [c_vp] * 11 + [c_int, c_vp]
     L.ostrich_step_adjoint.restype = c_int
+    L.ostrich_step_adjoint_params.argtypes = [c_vp] + [c_vp] * 14 + [c_int, c_vp]
+    L.ostrich_step_adjoint_params.restype = c_int
     L.ostrich_rollout.argtypes = ([c_vp, c_int, c_vp, c_vp, c_vp, c_int, c_vp, c_int, c_int, c_vp, c_vp, c_vp,
                                    c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp, c_vp])
     L.ostrich_rollout.restype = c_int

@@ -359,7 +359,7 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
                           const double* u_prev, const double* ctrl, const double* u_next, const double* lam_next,
                           const double* tape, const int64_t* tape_off, const double* gq_next,
                           const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl, int refine,
-                          WorldMem& M) {
+                          WorldMem& M, double* g_mass = nullptr, double* g_mu = nullptr, double* g_kp = nullptr) {
   WorldRef R = world_ref(B, w);
   const double h = P.h;
   prologue(t, B, P, R, q_prev, u_prev, ctrl, lam_next, M);
@@ -592,6 +592,64 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
     }
     gq_prev[7 * R.b0 + p] = direct + s;
   }
+  // model parameters, Eq. (17) with xi a parameter (the FB scales and the
+  // Schur regularisation held as in the solve): a body's mass enters its
+  // dynamics rows, m (u - u-) - h m g; a servo gain its servo row through
+  // lambda / k_p; a friction coefficient the friction rows of its slot's active
+  // contact.  Every entry is written once: zero where the parameter does not
+  // enter this step.
+  if (g_mass)
+    for (int b = t.rank(); b < nb; b += t.size()) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += wu[6 * b + k] * ((M.u[6 * b + k] - M.um[6 * b + k]) - h * P.g[k]);
+      g_mass[R.b0 + b] = s;
+    }
+  if (g_kp)
+    for (int j = t.rank(); j < R.nj; j += t.size()) {
+      double g = 0.0;
+      for (int i = 5 * R.nj; i < 5 * R.nj + R.nsv; ++i)
+        if (M.r_idx[i] == j) {
+          const double kp = B.joint_kp[R.j0 + j];
+          g = wl[i] * M.D[i] * (-M.lam[i] / (kp * kp));
+        }
+      g_kp[R.j0 + j] = g;
+    }
+  if (g_mu)
+    for (int s = t.rank(); s < R.ns; s += t.size()) {
+      const int c = M.s_act[s];
+      double g = 0.0;
+      if (c >= 0) {  // d r / d mu of the contact's rows, one dual evaluation with mu seeded
+        const int row = 5 * R.nj + R.nsv + 3 * c;
+        const int a = M.r_a[row], b = M.r_b[row];
+        GroupIn<double> in = group_in_lds(M, row, M.u, M.lam, 0.0);
+        dual ua[6], ub[6], lg[3];
+        for (int k = 0; k < 6; ++k) {
+          ua[k] = dual(M.u[6 * a + k]);
+          ub[k] = b >= 0 ? dual(M.u[6 * b + k]) : dual(0.0);
+        }
+        for (int k = 0; k < 3; ++k) lg[k] = dual(M.lam[row + k]);
+        GroupIn<dual> ind;
+        ind.xa = v3<dual>{in.xa.x, in.xa.y, in.xa.z};
+        ind.xb = v3<dual>{in.xb.x, in.xb.y, in.xb.z};
+        for (int k = 0; k < 9; ++k) { ind.Ra.a[k] = in.Ra.a[k]; ind.Rb.a[k] = in.Rb.a[k]; }
+        ind.ua = ua;
+        ind.ub = b >= 0 ? ub : nullptr;
+        ind.lg = lg;
+        ind.target = dual(0.0);
+        ind.fr.n = v3<dual>{in.fr.n.x, in.fr.n.y, in.fr.n.z};
+        ind.fr.t1 = v3<dual>{in.fr.t1.x, in.fr.t1.y, in.fr.t1.z};
+        ind.fr.t2 = v3<dual>{in.fr.t2.x, in.fr.t2.y, in.fr.t2.z};
+        ind.fr.noff = dual(in.fr.noff);
+        ind.fr.la = v3<dual>{in.fr.la.x, in.fr.la.y, in.fr.la.z};
+        ind.fr.lb = v3<dual>{in.fr.lb.x, in.fr.lb.y, in.fr.lb.z};
+        dual rd[3], Jd[36];
+        double Dd[3];
+        eval_group<dual>(B, P, R, RK_CONTACT, M.r_idx[row], M.r_sub[row], b >= 0, M.c_r[c], dual(M.c_mu[c], 1.0),
+                         M.c_sn[c], M.c_sf[c], M.c_kind[c], ind, rd, Jd, Dd);
+        for (int k = 1; k < 3; ++k) g += wl[row + k] * M.D[row + k] * rd[k].d;
+      }
+      g_mu[R.s0 + s] = g;
+    }
   t.sync();
 }
 

@@ -178,7 +178,8 @@ __global__ void __launch_bounds__(256) k_adjoint(ost::Batch B, ost::Params P, os
                                                  const double* u_next, const double* lam_next, const double* tape,
                                                  const int64_t* tape_off, const double* gq_next,
                                                  const double* gu_next, double* gq_prev, double* gu_prev,
-                                                 double* g_ctrl, int refine) {
+                                                 double* g_ctrl, int refine, double* g_mass, double* g_mu,
+                                                 double* g_kp) {
   extern __shared__ __align__(16) char smem[];
   TeamT t;
   // the on-chip instantiation carves with a constant split, so that every
@@ -188,7 +189,7 @@ __global__ void __launch_bounds__(256) k_adjoint(ost::Batch B, ost::Params P, os
                         : ost::carve(smem, caps, blockDim.x, ost::SPLIT_LDS, nullptr);
   for (int i = blockIdx.x; i < L.nlist; i += gridDim.x) {
     ost::adjoint_world(t, B, P, caps, L.wlist[i], q_prev, u_prev, ctrl, u_next, lam_next, tape, tape_off,
-                       gq_next, gu_next, gq_prev, gu_prev, g_ctrl, refine, M);
+                       gq_next, gu_next, gq_prev, gu_prev, g_ctrl, refine, M, g_mass, g_mu, g_kp);
     __syncthreads();
   }
 }
@@ -711,10 +712,10 @@ extern "C" int ostrich_ctx_timing(ostrich_ctx* ctx, int32_t mode, double* out) {
   return 0;
 }
 
-extern "C" int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, const double* u_prev,
-                                    const double* ctrl, const double* u_next, const double* lam_next,
-                                    const void* tape, const double* gq_next, const double* gu_next, double* gq_prev,
-                                    double* gu_prev, double* g_ctrl, int32_t refine, void* stream) {
+static int adjoint_step(ostrich_ctx* ctx, const double* q_prev, const double* u_prev, const double* ctrl,
+                        const double* u_next, const double* lam_next, const void* tape, const double* gq_next,
+                        const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl, double* g_mass,
+                        double* g_mu, double* g_kp, int32_t refine, void* stream) {
   if (!ctx || !q_prev || !u_prev || !u_next || !lam_next || !tape || !gq_next || !gu_next || !gq_prev || !gu_prev)
     return fail(OSTRICH_E_ARG, "null pointer");
   if (ctx->NCTRL > 0 && (!ctrl || !g_ctrl)) return fail(OSTRICH_E_ARG, "controls required");
@@ -734,7 +735,8 @@ extern "C" int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, cons
     hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>, dim3(grid_of(bk)),
                        dim3(bk.team), bk.lds, s, ctx->B, ctx->P,
                        bk.caps, launch_of(bk), q_prev, u_prev, ctrl, u_next, lam_next, (const double*)tape,
-                       (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf);
+                       (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass,
+                       g_mu, g_kp);
   });
   if (rc) return rc;
   if (timed) {
@@ -745,6 +747,24 @@ extern "C" int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, cons
   }
   HIP_OK(hipGetLastError());
   return 0;
+}
+
+extern "C" int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, const double* u_prev,
+                                    const double* ctrl, const double* u_next, const double* lam_next,
+                                    const void* tape, const double* gq_next, const double* gu_next, double* gq_prev,
+                                    double* gu_prev, double* g_ctrl, int32_t refine, void* stream) {
+  return adjoint_step(ctx, q_prev, u_prev, ctrl, u_next, lam_next, tape, gq_next, gu_next, gq_prev, gu_prev, g_ctrl,
+                      nullptr, nullptr, nullptr, refine, stream);
+}
+
+extern "C" int ostrich_step_adjoint_params(ostrich_ctx* ctx, const double* q_prev, const double* u_prev,
+                                           const double* ctrl, const double* u_next, const double* lam_next,
+                                           const void* tape, const double* gq_next, const double* gu_next,
+                                           double* gq_prev, double* gu_prev, double* g_ctrl, double* g_mass,
+                                           double* g_mu, double* g_kp, int32_t refine, void* stream) {
+  if (!g_mass || !g_mu || !g_kp) return fail(OSTRICH_E_ARG, "parameter cotangent outputs required");
+  return adjoint_step(ctx, q_prev, u_prev, ctrl, u_next, lam_next, tape, gq_next, gu_next, gq_prev, gu_prev, g_ctrl,
+                      g_mass, g_mu, g_kp, refine, stream);
 }
 
 static Launch list_launch(const ostrich_ctx* ctx, const int32_t* worlds, int n) {
@@ -790,7 +810,7 @@ extern "C" int ostrich_step_adjoint_list(ostrich_ctx* ctx, const int32_t* worlds
                      dim3(list_grid(ctx, n)), dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
                      bk.caps, list_launch(ctx, worlds, n), q_prev, u_prev, ctrl, u_next, lam_next,
                      (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev,
-                     g_ctrl, rf);
+                     g_ctrl, rf, (double*)nullptr, (double*)nullptr, (double*)nullptr);
   HIP_OK(hipGetLastError());
   return 0;
 }
@@ -835,7 +855,7 @@ extern "C" int ostrich_step_adjoint_plain(ostrich_ctx* ctx, const double* q_prev
                        dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P, bk.caps,
                        list_launch(ctx, bk.d_worlds + w, 1), q_prev, u_prev, ctrl, u_next, lam_next,
                        (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev,
-                       g_ctrl, rf);
+                       g_ctrl, rf, (double*)nullptr, (double*)nullptr, (double*)nullptr);
   HIP_OK(hipGetLastError());
   return 0;
 }

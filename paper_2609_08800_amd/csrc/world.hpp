@@ -163,7 +163,7 @@ template <class T> struct GroupIn {
 // scale D of one group: a joint row, a servo row, or a contact (n, t1, t2).
 template <class T>
 OST_HD void eval_group(const Batch& B, const Params& P, const WorldRef& R, int kind, int idx, int sub,
-                       int has_b, double r_prox, double mu, double sn, double sf, int ckind,
+                       int has_b, double r_prox, T mu, double sn, double sf, int ckind,
                        const GroupIn<T>& in, T* r, T* J, double* D) {
   const double h = P.h;
   const v3<T> zero = mk(T(0.0), T(0.0), T(0.0));

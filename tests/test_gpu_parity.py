@@ -272,3 +272,44 @@ def test_step_timing_counts_launches_and_algorithmic_work(torch):
         nbytes += 8.0 * (band + 4 + 13 * nb + 6 * nb + nl + 26 * nb + nc)
     assert abs(fwd["flops"] - flops) <= 1e-9 * flops
     assert abs(adj["bytes"] - nbytes) <= 1e-9 * nbytes
+
+
+@pytest.mark.parametrize("scene", ["robots", "boxes", "tripods", "terrain"])
+def test_parameter_gradients_match_oracle(torch, scene):
+    """Cotangents of every body's mass, every slot's friction coefficient and every
+    joint's servo gain (Eq. (17) with a model parameter as xi), GPU against the
+    oracle's dual-number pull-back at the same converged step, over two steps."""
+    from paper_2609_08800_amd import spline_basis
+    from test_oracle_pins import tripod_world
+    P = scenes.solver_params(k_max=64)
+    ctrl_at = lambda k: None
+    if scene == "robots":
+        b = scenes.robot_batch(4, seed=21)
+        ctrl_at = robot_ctrl(b)
+    elif scene == "boxes":
+        b = scenes.box_batch(4, 8)
+    elif scene == "tripods":
+        rng = np.random.default_rng(3)
+        b = scenes.pack([tripod_world(tuple(rng.uniform(-1, 1, 2)) + (0.0,), tuple(rng.normal(0, 0.5, 3)),
+                                      float(rng.uniform(-3, 3)), (0.0, 0.0)) for _ in range(3)])
+    else:
+        b = scenes.terrain_batch(3, seed=4, n_maps=2)
+        K = scenes.ROBOT_KNOTS
+        kn = scenes.knots_array(b, K)
+        B = spline_basis(20, K, P["h"])
+        ctrl_at = lambda k: kn @ B[k]
+    sim = sim_for(b, P)
+    q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    rng = np.random.default_rng(5)
+    for k in range(2):
+        c = ctrl_at(k)
+        tape = sim.new_tape()
+        o = sim.step_forward(q, u, lam, c, tape=tape)
+        un, ln = o["u"].cpu().numpy(), o["lam"].cpu().numpy()
+        gqn, gun = rng.normal(size=q.shape), rng.normal(size=u.shape)
+        _, _, _, gm, gmu, gkp = sim.step_adjoint_params(q, u, c, un, ln, tape, gqn, gun)
+        R = oracle.step_adjoint_params(b, P, q, u, c, un, ln, gqn, gun, mode=0)
+        for g, r in ((gm, R["g_mass"]), (gmu, R["g_mu"]), (gkp, R["g_kp"])):
+            g = g.cpu().numpy()
+            assert np.linalg.norm(g - r) <= GRAD_TOL * max(np.linalg.norm(r), 1e-12), (k, np.linalg.norm(g - r))
+        q, u, lam = o["q"].cpu().numpy(), un, ln

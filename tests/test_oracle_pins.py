@@ -530,3 +530,58 @@ def test_terrain_candidates_on_hand_made_features():
     assert o["n_act"][0] == 1 and o["status"][0] & 1
     # the contact is the vertex: the ball is pushed along (P - V), i.e. away from the peak
     assert o["u"][0, 0] > 0 and o["u"][0, 1] < 0
+
+
+def _param_fd(b, P, ctrl, eps=1e-6):
+    """Oracle parameter cotangents (masses, friction coefficients, servo gains) against
+    central differences of a random linear loss of the converged step."""
+    import copy
+    q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    ref = oracle.step_forward(b, P, q, u, lam, ctrl)
+    assert np.all(ref["status"] & 1)
+    rng = np.random.default_rng(0)
+    gq, gu = rng.normal(size=q.shape), rng.normal(size=u.shape)
+    A = oracle.step_adjoint_params(b, P, q, u, ctrl, ref["u"], ref["lam"], gq, gu, mode=0)
+
+    def loss(arr_name, i, col, d):
+        bb = copy.copy(b)
+        arr = getattr(b, arr_name).copy()
+        if col is None:
+            arr[i] += d
+        else:
+            arr[i, col] += d
+        setattr(bb, arr_name, arr)
+        o = oracle.step_forward(bb, P, q, u, lam, ctrl)
+        return float(np.sum(gq * o["q"]) + np.sum(gu * o["u"]))
+
+    checked = 0
+    for arr_name, col, g in (("body_mass", None, A["g_mass"]), ("slot_real", 4, A["g_mu"]),
+                             ("joint_kp", None, A["g_kp"])):
+        for i in range(len(g)):
+            base = getattr(b, arr_name)[i] if col is None else getattr(b, arr_name)[i, col]
+            e = eps * max(1.0, abs(base))
+            fd = (loss(arr_name, i, col, e) - loss(arr_name, i, col, -e)) / (2 * e)
+            assert abs(fd - g[i]) <= 1e-5 * max(abs(fd), abs(g[i])) + 1e-9, (arr_name, i, g[i], fd)
+            checked += abs(g[i]) > 1e-9
+    return checked
+
+
+def test_parameter_gradients_match_finite_differences():
+    """Eq. (17) with a model parameter as xi: the cotangents of the body masses, the slots'
+    friction coefficients and the servo gains, against central differences, on determinate
+    contact sets (sliding, spinning tripods) and a robot in flight (joints and axle servos
+    only).  The Schur regularisation is switched off here: the adjoint solves with the
+    forward's regularised matrix, whose bias (of order delta_reg) would show on small
+    cotangents."""
+    P = scenes.solver_params(k_max=200, tol=1e-14, delta_reg=0.0)
+    tb = scenes.pack([tripod_world((0.9, 0.4, 0), (0.05, -0.05, 1.2), 0.2, (0.3, -0.2)),
+                      tripod_world((-0.5, 0.7, 0), (0.0, 0.02, -0.6), 1.1, (0.0, 0.0))])
+    assert _param_fd(tb, P, None) >= 8  # 2 masses, 6 friction coefficients
+    from paper_2609_08800_amd import spline_basis
+    rb = scenes.robot_batch(1, seed=7)
+    q0 = rb.q0.copy()
+    q0[:, 2] += 0.5
+    rb.q0 = q0
+    K = scenes.ROBOT_KNOTS
+    ctrl = scenes.knots_array(rb, K) @ spline_basis(20, K, P["h"])[3]
+    assert _param_fd(rb, P, ctrl) >= 8  # of 5 masses and 4 axle servo gains
