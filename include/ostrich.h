@@ -94,7 +94,7 @@ typedef struct {
   double delta_reg;    /* relative Schur diagonal regularisation */
   double delta0;       /* contact activation margin (m) */
   int32_t ls_max;      /* step-length halvings of the residual-decrease test */
-  int32_t refine;      /* adjoint refinement sweeps toward the exact Jacobian (0: factor only) */
+  int32_t refine;      /* most Krylov operator applications of the adjoint (0: factor only) */
   int32_t team;        /* threads per world (64, 128 or 256; 0 = 128) before autotuning */
   int32_t schedule;    /* OSTRICH_SCHED_FIXED or OSTRICH_SCHED_BUCKETED */
 } ostrich_params;
@@ -179,8 +179,14 @@ int ostrich_step_forward(ostrich_ctx* ctx, const double* q_prev, const double* u
 /* Adjoint of one step (Sec. III-D, Eqs. (16)-(19)): given s-, the controls,
  * s+ (u_next, lam_next) and the tape written by the forward call, map the
  * loss cotangents (gq_next [NB*7], gu_next [NB*6]) to gq_prev, gu_prev and
- * g_ctrl [NCTRL].  The stored factor is back-solved, then `refine` sweeps add
- * the geometric-stiffness term of the exact Jacobian (params.refine if < 0). */
+ * g_ctrl [NCTRL].  The stored factor is back-solved; with refine > 0 the
+ * exact implicit-function Jacobian, whose velocity block adds the geometric
+ * stiffness h K = h d(J(u)^T lambda)/du that the factor leaves out, is solved
+ * by restarted GMRES on the 6 NB velocity unknowns, preconditioned by the
+ * factor, with at most `refine` operator applications (params.refine if < 0)
+ * and a stop at 1e-12 of the relative residual; refine = 0 keeps the factor's
+ * solve alone.  The adjoint kernel's LDS adds the Krylov workspace,
+ * 60 NB_cap + 106 doubles per world (NB_cap: most bodies of a world). */
 int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, const double* u_prev, const double* ctrl,
                          const double* u_next, const double* lam_next, const void* tape, const double* gq_next,
                          const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl, int32_t refine,

@@ -342,6 +342,172 @@ OST_HD void adjoint_solve(Team& t, const WorldRef& R, const WorldMem& M, const d
   t.sync();
 }
 
+// Product with the transposed geometric stiffness, out = K^T v, where K =
+// d(J(u)^T lambda)/du at the converged step: the stored factor leaves K out of
+// the Jacobian.  Each thread seeds one velocity component with a dual number.
+template <class Team>
+OST_HD void stiffness_t(Team& t, const Batch& B, const Params& P, const WorldRef& R, WorldMem& M,
+                        const double* ctrl, const double* v, double* out) {
+  for (int p = t.rank(); p < 6 * R.nb; p += t.size()) {
+    int beta = p / 6, comp = p % 6;
+    double s = 0.0;
+    const int ng = n_groups(R);
+    for (int g = 0; g < ng; ++g) {
+      int row = group_row(R, g);
+      int a = M.r_a[row], c = M.r_b[row];
+      if (a != beta && c != beta) continue;
+      int kind = M.r_kind[row];
+      int n = kind == RK_CONTACT ? 3 : 1;
+      double target = kind == RK_SERVO ? servo_target(B, R, ctrl, M.r_idx[row]) : 0.0;
+      GroupIn<double> in = group_in_lds(M, row, M.u, M.lam, target);
+      dual ua[6], ub[6], lg[3];
+      for (int k = 0; k < 6; ++k) {
+        ua[k] = dual(M.u[6 * a + k], (a == beta && k == comp) ? 1.0 : 0.0);
+        ub[k] = c >= 0 ? dual(M.u[6 * c + k], (c == beta && k == comp) ? 1.0 : 0.0) : dual(0.0);
+      }
+      #pragma unroll
+      for (int k = 0; k < 3; ++k) if (k < n) lg[k] = dual(M.lam[row + k]);
+      GroupIn<dual> ind;
+      ind.xa = v3<dual>{in.xa.x, in.xa.y, in.xa.z};
+      ind.xb = v3<dual>{in.xb.x, in.xb.y, in.xb.z};
+      for (int k = 0; k < 9; ++k) { ind.Ra.a[k] = in.Ra.a[k]; ind.Rb.a[k] = in.Rb.a[k]; }
+      ind.ua = ua;
+      ind.ub = c >= 0 ? ub : nullptr;
+      ind.lg = lg;
+      ind.target = dual(target);
+      ind.fr.n = v3<dual>{in.fr.n.x, in.fr.n.y, in.fr.n.z};
+      ind.fr.t1 = v3<dual>{in.fr.t1.x, in.fr.t1.y, in.fr.t1.z};
+      ind.fr.t2 = v3<dual>{in.fr.t2.x, in.fr.t2.y, in.fr.t2.z};
+      ind.fr.noff = dual(in.fr.noff);
+      ind.fr.la = v3<dual>{in.fr.la.x, in.fr.la.y, in.fr.la.z};
+      ind.fr.lb = v3<dual>{in.fr.lb.x, in.fr.lb.y, in.fr.lb.z};
+      dual rd[3], Jd[36];
+      double Dd[3];
+      eval_row_group<dual>(B, P, R, M, row, ind, rd, Jd, Dd);
+      #pragma unroll
+      for (int k = 0; k < 3; ++k) if (k < n) {
+        double jw = 0.0;
+        for (int q = 0; q < 6; ++q) jw += Jd[12 * k + q].d * v[6 * a + q];
+        if (c >= 0) for (int q = 0; q < 6; ++q) jw += Jd[12 * k + 6 + q].d * v[6 * c + q];
+        s += M.lam[row + k] * jw;
+      }
+    }
+    out[p] = s;
+  }
+  t.sync();
+}
+
+// Dot product over a fixed partition into 64 lanes (independent of the team size).
+template <class Team>
+OST_HD double dot64(Team& t, const WorldMem& M, const double* x, const double* y, int n) {
+  double s = 0.0;
+  for (int l = t.rank(); l < 64; l += t.size())
+    for (int i = l; i < n; i += 64) s += x[i] * y[i];
+  return t.sum64(s, M.red);
+}
+
+// out = v + S(h K^T v): the velocity block of the exact adjoint system after
+// the stored factor's solve S (the velocity part of adjoint_solve) is applied.
+template <class Team>
+OST_HD void kry_apply(Team& t, const Batch& B, const Params& P, const WorldRef& R, WorldMem& M,
+                      const double* ctrl, const double* v, double* out) {
+  const int n = 6 * R.nb;
+  stiffness_t(t, B, P, R, M, ctrl, v, M.ubest);
+  for (int p = t.rank(); p < n; p += t.size()) M.ubest[p] = P.h * M.ubest[p];
+  t.sync();
+  adjoint_solve(t, R, M, M.ubest, out, M.lamt);
+  for (int p = t.rank(); p < n; p += t.size()) out[p] += v[p];
+  t.sync();
+}
+
+// Relative residual at which the adjoint's Krylov solve stops.
+constexpr double kKryTol = 1e-12;
+
+// Velocity part x of the exact adjoint, (I + S h K^T) x = c with c = S b the
+// stored factor's solution: restarted GMRES (restart kKry, modified
+// Gram-Schmidt, Givens rotations) from x = 0, at most `max_apply` operator
+// applications, stopping at a residual of kKryTol |c|.  The residual never
+// grows, whatever the spectral radius of S h K^T (a fixed-point iteration
+// on the same operator diverges once that radius reaches one).  Returns the
+// number of applications.
+template <class Team>
+OST_HD int adjoint_krylov(Team& t, const Batch& B, const Params& P, const WorldRef& R, WorldMem& M,
+                          const double* ctrl, const double* c, int max_apply) {
+  const int n = 6 * R.nb;
+  double *V = M.kv, *x = M.kx, *H = M.kh, *cs = M.kcs, *sn = M.ksn, *gv = M.kgv, *y = M.ky;
+  const double cn = ::sqrt(dot64(t, M, c, c, n));
+  const double stop = kKryTol * cn;
+  for (int e = t.rank(); e < n; e += t.size()) { x[e] = 0.0; V[e] = c[e]; }
+  t.sync();
+  double beta = cn;  // |c - A x| at x = 0
+  int used = 0;
+  while (used < max_apply && beta > stop) {
+    for (int e = t.rank(); e < n; e += t.size()) V[e] = V[e] / beta;
+    if (t.rank() == 0) {
+      gv[0] = beta;
+      for (int i = 1; i <= kKry; ++i) gv[i] = 0.0;
+    }
+    t.sync();
+    int k = 0;
+    double res = beta;
+    bool more = true;
+    while (more && k < kKry && used < max_apply && res > stop) {
+      double* w = V + (size_t)(k + 1) * n;
+      kry_apply(t, B, P, R, M, ctrl, V + (size_t)k * n, w);
+      ++used;
+      for (int i = 0; i <= k; ++i) {
+        const double hik = dot64(t, M, w, V + (size_t)i * n, n);
+        for (int e = t.rank(); e < n; e += t.size()) w[e] -= hik * V[(size_t)i * n + e];
+        if (t.rank() == 0) H[i * kKry + k] = hik;
+        t.sync();
+      }
+      const double hn = ::sqrt(dot64(t, M, w, w, n));
+      more = hn > 0.0;  // zero: the Krylov space holds the solution; not finite: give up
+      if (more)
+        for (int e = t.rank(); e < n; e += t.size()) w[e] = w[e] / hn;
+      if (t.rank() == 0) {
+        H[(k + 1) * kKry + k] = hn;
+        for (int i = 0; i < k; ++i) {
+          const double a = H[i * kKry + k], b = H[(i + 1) * kKry + k];
+          H[i * kKry + k] = cs[i] * a + sn[i] * b;
+          H[(i + 1) * kKry + k] = -sn[i] * a + cs[i] * b;
+        }
+        const double a = H[k * kKry + k], b = H[(k + 1) * kKry + k];
+        const double r = ::sqrt(a * a + b * b);
+        cs[k] = r > 0.0 ? a / r : 1.0;
+        sn[k] = r > 0.0 ? b / r : 0.0;
+        H[k * kKry + k] = r;
+        H[(k + 1) * kKry + k] = 0.0;
+        gv[k + 1] = -sn[k] * gv[k];
+        gv[k] = cs[k] * gv[k];
+      }
+      t.sync();
+      res = ::fabs(gv[k + 1]);
+      ++k;
+    }
+    if (t.rank() == 0)  // the k x k triangle: H y = g
+      for (int i = k - 1; i >= 0; --i) {
+        double s = gv[i];
+        for (int j = i + 1; j < k; ++j) s -= H[i * kKry + j] * y[j];
+        y[i] = H[i * kKry + i] != 0.0 ? s / H[i * kKry + i] : 0.0;
+      }
+    t.sync();
+    for (int e = t.rank(); e < n; e += t.size()) {
+      double s = x[e];
+      for (int i = 0; i < k; ++i) s += y[i] * V[(size_t)i * n + e];
+      x[e] = s;
+    }
+    t.sync();
+    if (!more || !(res > stop) || used >= max_apply) break;
+    kry_apply(t, B, P, R, M, ctrl, x, V);  // restart from the true residual c - A x
+    ++used;
+    for (int e = t.rank(); e < n; e += t.size()) V[e] = c[e] - V[e];
+    t.sync();
+    beta = ::sqrt(dot64(t, M, V, V, n));
+  }
+  return used;
+}
+
 // Dual input of a group with body data recomputed from q- (seeded), used by
 // the pose pull-back.  seed_body / seed_comp select the seeded q- component.
 OST_HD void dual_pose(const double* q, int seeded, int comp, v3<dual>& x, m3<dual>& Rm) {
@@ -408,56 +574,12 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
   double* wu = M.ut;
   double* wl = M.dlam;
   adjoint_solve(t, R, M, M.du, wu, wl);
-  // refinement towards the exact Jacobian: the factor omits the geometric
-  // stiffness K = d(J(u)^T lambda)/du; w <- Hhat^-T (-[b; 0] + [h K^T w_u; 0])
-  for (int sweep = 0; sweep < refine; ++sweep) {
-    for (int p = t.rank(); p < 6 * nb; p += t.size()) {
-      int beta = p / 6, comp = p % 6;
-      double s = 0.0;
-      const int ng = n_groups(R);
-      for (int g = 0; g < ng; ++g) {
-        int row = group_row(R, g);
-        int a = M.r_a[row], c = M.r_b[row];
-        if (a != beta && c != beta) continue;
-        int kind = M.r_kind[row];
-        int n = kind == RK_CONTACT ? 3 : 1;
-        double target = kind == RK_SERVO ? servo_target(B, R, ctrl, M.r_idx[row]) : 0.0;
-        GroupIn<double> in = group_in_lds(M, row, M.u, M.lam, target);
-        dual ua[6], ub[6], lg[3];
-        for (int k = 0; k < 6; ++k) {
-          ua[k] = dual(M.u[6 * a + k], (a == beta && k == comp) ? 1.0 : 0.0);
-          ub[k] = c >= 0 ? dual(M.u[6 * c + k], (c == beta && k == comp) ? 1.0 : 0.0) : dual(0.0);
-        }
-        #pragma unroll
-        for (int k = 0; k < 3; ++k) if (k < n) lg[k] = dual(M.lam[row + k]);
-        GroupIn<dual> ind;
-        ind.xa = v3<dual>{in.xa.x, in.xa.y, in.xa.z};
-        ind.xb = v3<dual>{in.xb.x, in.xb.y, in.xb.z};
-        for (int k = 0; k < 9; ++k) { ind.Ra.a[k] = in.Ra.a[k]; ind.Rb.a[k] = in.Rb.a[k]; }
-        ind.ua = ua;
-        ind.ub = c >= 0 ? ub : nullptr;
-        ind.lg = lg;
-        ind.target = dual(target);
-        ind.fr.n = v3<dual>{in.fr.n.x, in.fr.n.y, in.fr.n.z};
-        ind.fr.t1 = v3<dual>{in.fr.t1.x, in.fr.t1.y, in.fr.t1.z};
-        ind.fr.t2 = v3<dual>{in.fr.t2.x, in.fr.t2.y, in.fr.t2.z};
-        ind.fr.noff = dual(in.fr.noff);
-        ind.fr.la = v3<dual>{in.fr.la.x, in.fr.la.y, in.fr.la.z};
-        ind.fr.lb = v3<dual>{in.fr.lb.x, in.fr.lb.y, in.fr.lb.z};
-        dual rd[3], Jd[36];
-        double Dd[3];
-        eval_row_group<dual>(B, P, R, M, row, ind, rd, Jd, Dd);
-        #pragma unroll
-        for (int k = 0; k < 3; ++k) if (k < n) {
-          double jw = 0.0;
-          for (int q = 0; q < 6; ++q) jw += Jd[12 * k + q].d * wu[6 * a + q];
-          if (c >= 0) for (int q = 0; q < 6; ++q) jw += Jd[12 * k + 6 + q].d * wu[6 * c + q];
-          s += M.lam[row + k] * jw;
-        }
-      }
-      M.kg[p] = s;
-    }
-    t.sync();
+  // refinement towards the exact Jacobian, whose velocity block adds the
+  // geometric stiffness h K that the factor leaves out: the Krylov solve gives
+  // the velocity part x, then one solve with [b - h K^T x; 0] gives w_u, w_l
+  if (refine > 0 && M.kv) {
+    adjoint_krylov(t, B, P, R, M, ctrl, wu, refine);
+    stiffness_t(t, B, P, R, M, ctrl, M.kx, M.kg);
     for (int p = t.rank(); p < 6 * nb; p += t.size()) M.ubest[p] = M.rdyn[p] - h * M.kg[p];
     t.sync();
     adjoint_solve(t, R, M, M.ubest, wu, wl);

@@ -185,8 +185,9 @@ __global__ void __launch_bounds__(256) k_adjoint(ost::Batch B, ost::Params P, os
   // the on-chip instantiation carves with a constant split, so that every
   // workspace pointer is known to address LDS
   ost::WorldMem M = TeamT::kGlobal
-                        ? ost::carve(smem, caps, blockDim.x, L.split, L.gscr ? L.gscr + blockIdx.x * L.gstride : nullptr)
-                        : ost::carve(smem, caps, blockDim.x, ost::SPLIT_LDS, nullptr);
+                        ? ost::carve(smem, caps, blockDim.x, L.split, L.gscr ? L.gscr + blockIdx.x * L.gstride : nullptr,
+                                      true)
+                        : ost::carve(smem, caps, blockDim.x, ost::SPLIT_LDS, nullptr, true);
   for (int i = blockIdx.x; i < L.nlist; i += gridDim.x) {
     ost::adjoint_world(t, B, P, caps, L.wlist[i], q_prev, u_prev, ctrl, u_next, lam_next, tape, tape_off,
                        gq_next, gu_next, gq_prev, gu_prev, g_ctrl, refine, M, g_mass, g_mu, g_kp);
@@ -343,7 +344,8 @@ struct Bucket {
   int32_t* d_worlds = nullptr;
   int team = 128;
   int split = ost::SPLIT_LDS;
-  size_t lds = 0;
+  size_t lds = 0;                // forward kernel's LDS per workgroup
+  size_t lds_adj = 0;            // adjoint kernel's (adds the Krylov workspace)
   int slots = 0;                // SPLIT_GLOBAL: workgroups of the persistent grid
   double* gscr = nullptr;
   size_t gstride = 0;
@@ -417,10 +419,12 @@ static bool team_ok(int t) { return t == 64 || t == 128 || t == 256; }
 // device scratch; fails if the world does not fit either way.
 static int configure_bucket(ostrich_ctx* ctx, Bucket& bk, int team, int split) {
   size_t lds = ost::world_lds_bytes(bk.caps, team, split);
-  if (lds > ctx->lds_limit) return fail(OSTRICH_E_UNSUPPORTED, "bucket does not fit in LDS");
+  size_t lds_adj = ost::world_lds_bytes(bk.caps, team, split, true);
+  if (lds_adj > ctx->lds_limit) return fail(OSTRICH_E_UNSUPPORTED, "bucket does not fit in LDS");
   bk.team = team;
   bk.split = split;
   bk.lds = lds;
+  bk.lds_adj = lds_adj;
   if (split == ost::SPLIT_GLOBAL) {
     size_t per_cu = std::max<size_t>(1, ctx->lds_limit / std::max<size_t>(lds, 1));
     per_cu = std::min<size_t>(per_cu, 2048 / team);
@@ -440,7 +444,7 @@ static int configure_bucket(ostrich_ctx* ctx, Bucket& bk, int team, int split) {
 // Default launch choice: the requested team (or 128), on chip when it fits.
 static int default_config(ostrich_ctx* ctx, Bucket& bk) {
   int team = ctx->team;
-  if (ost::world_lds_bytes(bk.caps, team, ost::SPLIT_LDS) <= ctx->lds_limit)
+  if (ost::world_lds_bytes(bk.caps, team, ost::SPLIT_LDS, true) <= ctx->lds_limit)
     return configure_bucket(ctx, bk, team, ost::SPLIT_LDS);
   return configure_bucket(ctx, bk, team, ost::SPLIT_GLOBAL);
 }
@@ -733,7 +737,7 @@ static int adjoint_step(ostrich_ctx* ctx, const double* q_prev, const double* u_
   }
   int rc = for_buckets(ctx, (hipStream_t)stream, [&](const Bucket& bk, hipStream_t s) {
     hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>, dim3(grid_of(bk)),
-                       dim3(bk.team), bk.lds, s, ctx->B, ctx->P,
+                       dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P,
                        bk.caps, launch_of(bk), q_prev, u_prev, ctrl, u_next, lam_next, (const double*)tape,
                        (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass,
                        g_mu, g_kp);
@@ -807,7 +811,7 @@ extern "C" int ostrich_step_adjoint_list(ostrich_ctx* ctx, const int32_t* worlds
   const Bucket& bk = ctx->all;
   int rf = refine < 0 ? ctx->refine : refine;
   hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>,
-                     dim3(list_grid(ctx, n)), dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
+                     dim3(list_grid(ctx, n)), dim3(bk.team), bk.lds_adj, (hipStream_t)stream, ctx->B, ctx->P,
                      bk.caps, list_launch(ctx, worlds, n), q_prev, u_prev, ctrl, u_next, lam_next,
                      (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev,
                      g_ctrl, rf, (double*)nullptr, (double*)nullptr, (double*)nullptr);
@@ -852,7 +856,7 @@ extern "C" int ostrich_step_adjoint_plain(ostrich_ctx* ctx, const double* q_prev
   if (!bk.d_worlds || (int)bk.worlds.size() != ctx->W) return fail(OSTRICH_E_ARG, "context world list missing");
   for (int w = 0; w < ctx->W; ++w)  // one launch per world, over the one-world list {w}
     hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>, dim3(1),
-                       dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P, bk.caps,
+                       dim3(bk.team), bk.lds_adj, (hipStream_t)stream, ctx->B, ctx->P, bk.caps,
                        list_launch(ctx, bk.d_worlds + w, 1), q_prev, u_prev, ctrl, u_next, lam_next,
                        (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev,
                        g_ctrl, rf, (double*)nullptr, (double*)nullptr, (double*)nullptr);
@@ -895,7 +899,7 @@ extern "C" int ostrich_autotune(ostrich_ctx* ctx, const double* q, const double*
     int bt = bk.team, bs = bk.split;
     for (int split : {ost::SPLIT_LDS, ost::SPLIT_GLOBAL})
       for (int team : {64, 128, 256}) {
-        if (ost::world_lds_bytes(bk.caps, team, split) > ctx->lds_limit) continue;
+        if (ost::world_lds_bytes(bk.caps, team, split, true) > ctx->lds_limit) continue;
         if ((rc = configure_bucket(ctx, bk, team, split))) break;
         launch_forward(ctx, bk, st, q, u, lam, ctrl, qn, un, ln, as, na, ss, it, rn, nullptr);  // warm
         (void)hipEventRecord(e0, st);

@@ -31,6 +31,9 @@ struct WorldMem {
   int* s_act;
   int* b_first;
   Feature* s_feat;
+  // adjoint only: Krylov basis, iterate, Hessenberg matrix, rotations and
+  // reduced right-hand side of the refinement solve (null in the forward)
+  double *kv, *kx, *kh, *kcs, *ksn, *kgv, *ky;
   // reduction scratch and scalars
   double* red;
   int* iscal;
@@ -49,13 +52,22 @@ enum { SPLIT_LDS = 0, SPLIT_GLOBAL = 1 };
 // read whole rounds of eight entries past the end of a row.
 constexpr int kPadA = 8;
 
+// Restart length of the adjoint's Krylov solve and the doubles its workspace
+// takes: kKry + 1 basis vectors and the iterate over the 6 nb velocities, the
+// (kKry + 1) x kKry Hessenberg matrix, and four short vectors.
+constexpr int kKry = 8;
+OST_HD size_t kry_doubles(const Caps& c) {
+  return (size_t)(kKry + 2) * 6 * c.nb + (size_t)(kKry + 1) * kKry + 4 * kKry + 2;
+}
+
 OST_HD size_t world_glob_doubles(const Caps& c, int split) {
   return split == SPLIT_GLOBAL ? (size_t)c.mr * c.mr + kPadA + (size_t)27 * c.mr : 0;
 }
 
-// Bytes of LDS one world needs for the given capacities, team size and split.
-OST_HD size_t world_lds_bytes(const Caps& c, int team, int split = SPLIT_LDS) {
-  size_t d = 0, i = 0;
+// Bytes of LDS one world needs for the given capacities, team size and split;
+// `adjoint` adds the Krylov workspace of the adjoint kernel.
+OST_HD size_t world_lds_bytes(const Caps& c, int team, int split = SPLIT_LDS, bool adjoint = false) {
+  size_t d = adjoint ? kry_doubles(c) : 0, i = 0;
   d += (size_t)c.nb * (3 + 7 + 9 + 9 + 9 + 1 + 3 + 6 * 7 + 7 + 6);
   d += (size_t)c.nc * 20;
   d += (size_t)c.mr * 8;
@@ -68,7 +80,8 @@ OST_HD size_t world_lds_bytes(const Caps& c, int team, int split = SPLIT_LDS) {
 }
 
 // Carve one world's workspace from LDS (and, with SPLIT_GLOBAL, from `glob`).
-OST_HD WorldMem carve(char* base, const Caps& c, int team, int split = SPLIT_LDS, double* glob = nullptr) {
+OST_HD WorldMem carve(char* base, const Caps& c, int team, int split = SPLIT_LDS, double* glob = nullptr,
+                      bool adjoint = false) {
   WorldMem M;
   double* p = (double*)base;
   auto take = [&](size_t n) { double* r = p; p += n; return r; };
@@ -90,6 +103,12 @@ OST_HD WorldMem carve(char* base, const Caps& c, int team, int split = SPLIT_LDS
   M.rmax = take(c.mr);
   M.A = gtake((size_t)c.mr * c.mr + kPadA); M.rhs = take(c.mr);
   M.red = take(team); M.dscal = take(8);
+  M.kv = M.kx = M.kh = M.kcs = M.ksn = M.kgv = M.ky = nullptr;
+  if (adjoint) {
+    const size_t n = 6 * (size_t)c.nb;
+    M.kv = take((kKry + 1) * n); M.kx = take(n); M.kh = take((size_t)(kKry + 1) * kKry);
+    M.kcs = take(kKry); M.ksn = take(kKry); M.kgv = take(kKry + 1); M.ky = take(kKry + 1);
+  }
   int* q = (int*)p;
   auto itake = [&](size_t n) { int* r = q; q += n; return r; };
   M.c_slot = itake(c.nc); M.c_kind = itake(c.nc); M.c_a = itake(c.nc); M.c_b = itake(c.nc);
