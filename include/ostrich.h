@@ -97,6 +97,10 @@ typedef struct {
   int32_t refine;      /* most Krylov operator applications of the adjoint (0: factor only) */
   int32_t team;        /* threads per world (64, 128 or 256; 0 = 128) before autotuning */
   int32_t schedule;    /* OSTRICH_SCHED_FIXED or OSTRICH_SCHED_BUCKETED */
+  int32_t truncate;    /* 1: the adjoint holds the contact geometry fixed within the step, so no
+                          derivative with respect to q- passes through a contact row or its force
+                          (the truncated position pull-back of the terrain task, Sec. V); 0: the
+                          complete pull-back of Eq. (17) */
 } ostrich_params;
 
 /* Launch schedules.  FIXED: every world in one launch shaped for the largest
@@ -253,6 +257,38 @@ int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0, const dou
                     const double* target, const double* loss_grad, double* loss, double* qT, double* uT,
                     double* g_q0, double* g_u0, double* g_knots, void* workspace, size_t workspace_bytes,
                     int32_t* status_or, void* stream);
+
+/* Shaped loss of the optimisation workloads (Sec. IV-B: final position and
+ * heading, a terminal-velocity penalty, control regularisers and a per-step
+ * straight-line tracking term; Sec. V: position tracking, yaw alignment and
+ * control regularisation against a reference trajectory).  The paper names the
+ * terms but not their forms; per world w, with p_k the xy, psi_k the yaw (the
+ * heading of the body x axis in the ground plane) and v_k the linear velocity
+ * of the loss body in state k, a_k the controls of step k, and (r_k, rho_k) the
+ * reference of step k:
+ *   L_w = w_pos |p_T - p*|^2 + w_head (1 - cos(psi_T - psi*)) + w_vel |v_T|^2
+ *       + (w_ctrl / T) sum_{k=0}^{T-1} |a_k|^2
+ *       + (w_track / T) sum_{k=1}^{T} |p_k - r_k|^2
+ *       + (w_yaw / T) sum_{k=1}^{T} (1 - cos(psi_k - rho_k)).
+ * goal [W*3] device: (x*, y*, psi*) per world.  ref [T*W*3] device: entry
+ * (k - 1) W + w holds (r_k, rho_k); it is read only when w_track or w_yaw is
+ * not zero (then it must not be NULL).  Weights must be finite. */
+typedef struct {
+  double w_pos, w_head, w_vel, w_ctrl, w_track, w_yaw;
+  const double* goal;
+  const double* ref;
+} ostrich_loss;
+
+/* ostrich_rollout with the shaped loss `spec` (host struct, device arrays;
+ * read during the call) in place of the final-xy loss: the same phases,
+ * workspace, checkpointing and outputs; loss [W] holds L_w, and the gradients
+ * are those of sum_w loss_grad[w] L_w.  With P.truncate set every adjoint step
+ * holds the contact geometry fixed (the terrain task of Sec. V). */
+int ostrich_rollout_shaped(ostrich_ctx* ctx, int32_t phase, const double* q0, const double* u0, const double* knots,
+                           int32_t K, const double* basis, int32_t T, int32_t ckpt_every, const int32_t* loss_body,
+                           const ostrich_loss* spec, const double* loss_grad, double* loss, double* qT, double* uT,
+                           double* g_q0, double* g_u0, double* g_knots, void* workspace, size_t workspace_bytes,
+                           int32_t* status_or, void* stream);
 
 /* Device helpers of the trajectory-optimisation loop (Sec. IV: spline
  * controls, the final-position loss, Adam on the knots), all asynchronous on

@@ -47,7 +47,7 @@ class Params(ctypes.Structure):
                 ("k_max", c_int), ("k_min", c_int), ("eps", ctypes.c_double),
                 ("delta_g", ctypes.c_double), ("delta_reg", ctypes.c_double),
                 ("delta0", ctypes.c_double), ("sigma_mode", c_int), ("n_feat", c_int),
-                ("newton_mode", c_int), ("ls_max", c_int)]
+                ("newton_mode", c_int), ("ls_max", c_int), ("truncate", c_int)]
 
 
 def lib():
@@ -57,7 +57,7 @@ def lib():
         _lib = ctypes.CDLL(_SO)
         for name in ("ostrich_ref_step_forward", "ostrich_ref_step_adjoint", "ostrich_ref_step_adjoint_params",
                      "ostrich_ref_spline_basis",
-                     "ostrich_ref_rollout", "ostrich_ref_inspect"):
+                     "ostrich_ref_rollout", "ostrich_ref_rollout_shaped", "ostrich_ref_inspect"):
             getattr(_lib, name).restype = c_int
     return _lib
 
@@ -106,6 +106,7 @@ class _Handle:
             setattr(self.cp, k, int(params[k]))
         self.cp.newton_mode = int(params.get("newton_mode", 0))
         self.cp.ls_max = int(params.get("ls_max", 0))
+        self.cp.truncate = int(params.get("truncate", 0))
 
 
 def step_forward(batch, params, q, u, lam, ctrl):
@@ -195,6 +196,42 @@ def rollout(batch, params, q0, u0, knots, T, mode=0, grad=True):
         _p(gk, c_dbl_p), c_int(mode), _p(st, c_int_p))
     if rc != 0:
         raise RuntimeError("oracle rollout failed: %d" % rc)
+    return dict(loss=loss, qT=qT, uT=uT, g_q0=gq0, g_u0=gu0, g_knots=gk, status=st)
+
+
+LOSS_WEIGHTS = ("w_pos", "w_head", "w_vel", "w_ctrl", "w_track", "w_yaw")
+
+
+class Loss(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in LOSS_WEIGHTS] + [("goal", c_dbl_p), ("ref", c_dbl_p)]
+
+
+def rollout_shaped(batch, params, q0, u0, knots, T, weights, goal, ref=None, mode=0, grad=True):
+    """T-step rollout with the shaped loss (final position, heading and velocity,
+    control regulariser, per-step tracking and yaw alignment; weights by name,
+    goal [W, 3], ref [T, W, 3]) and its gradient (per world)."""
+    H = _Handle(batch, params)
+    W = batch.n_worlds
+    q0, u0 = _d(q0), _d(u0)
+    knots = _d(knots) if knots is not None and knots.size else np.zeros((max(batch.n_ctrl, 1), 2))
+    K = knots.shape[1] if knots.ndim == 2 else 0
+    goal = _d(np.reshape(goal, (W, 3)))
+    ref = _d(np.reshape(ref, (T, W, 3))) if ref is not None else None
+    spec = Loss(*[float(weights.get(k, 0.0)) for k in LOSS_WEIGHTS])
+    spec.goal = _p(goal, c_dbl_p)
+    spec.ref = _p(ref, c_dbl_p)
+    loss = np.zeros(W)
+    qT, uT = np.zeros_like(q0), np.zeros_like(u0)
+    gq0, gu0 = (np.zeros_like(q0), np.zeros_like(u0)) if grad else (None, None)
+    gk = np.zeros_like(knots) if grad else None
+    st = np.zeros(W, np.int32)
+    rc = lib().ostrich_ref_rollout_shaped(
+        ctypes.byref(H.cb), ctypes.byref(H.cp), _p(q0, c_dbl_p), _p(u0, c_dbl_p), _p(knots, c_dbl_p),
+        c_int(K), c_int(T), _p(_i(batch.loss_body), c_int_p), ctypes.byref(spec),
+        _p(loss, c_dbl_p), _p(qT, c_dbl_p), _p(uT, c_dbl_p), _p(gq0, c_dbl_p), _p(gu0, c_dbl_p),
+        _p(gk, c_dbl_p), c_int(mode), _p(st, c_int_p))
+    if rc != 0:
+        raise RuntimeError("oracle rollout_shaped failed: %d" % rc)
     return dict(loss=loss, qT=qT, uT=uT, g_q0=gq0, g_u0=gu0, g_knots=gk, status=st)
 
 

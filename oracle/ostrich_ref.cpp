@@ -62,6 +62,18 @@ template <class T> Dual<T> sqrt(const Dual<T>& a) {
   return Dual<T>(s, a.d / (2.0 * s));
 }
 using std::sqrt;
+template <class T> Dual<T> cos(const Dual<T>& a) {
+  using std::cos;
+  using std::sin;
+  return Dual<T>(cos(a.v), -(sin(a.v) * a.d));
+}
+template <class T> Dual<T> atan2(const Dual<T>& y, const Dual<T>& x) {
+  using std::atan2;
+  T r2 = x.v * x.v + y.v * y.v;
+  return Dual<T>(atan2(y.v, x.v), (x.v * y.d - y.v * x.d) / r2);
+}
+using std::atan2;
+using std::cos;
 
 template <class T> Dual<T> lift(const T& a) { return Dual<T>(a, T(0.0)); }
 template <class T> Dual<T> seed(const T& a) { return Dual<T>(a, T(1.0)); }
@@ -81,6 +93,8 @@ template <class T> T norm(const V3<T>& a) { return sqrt(dot(a, a)); }
 template <class T> V3<T> cst3(const double* p) { return {T(p[0]), T(p[1]), T(p[2])}; }
 template <class T> V3<T> cst3(double a, double b, double c) { return {T(a), T(b), T(c)}; }
 template <class T> V3<Dual<T>> lift3(const V3<T>& a) { return {lift(a.x), lift(a.y), lift(a.z)}; }
+// the value of a vector with every derivative part dropped
+template <class T> V3<T> const3(const V3<T>& a) { return {T(val(a.x)), T(val(a.y)), T(val(a.z))}; }
 
 template <class T> struct Q4 { T x, y, z, w; };
 // Hamilton product, (x, y, z, w) storage.
@@ -210,7 +224,7 @@ WorldD load_world(const ostrich_ref_batch* B, int w) {
 
 struct Prm {
   double h, g[3], tol, eps, dg, dreg, d0;
-  int kmax, kmin, sigma_mode, newton_mode, ls_max;
+  int kmax, kmin, sigma_mode, newton_mode, ls_max, truncate;
 };
 Prm load_params(const ostrich_ref_params* p) {
   Prm P;
@@ -226,6 +240,7 @@ Prm load_params(const ostrich_ref_params* p) {
   P.sigma_mode = p->sigma_mode;
   P.newton_mode = p->newton_mode;
   P.ls_max = p->ls_max;
+  P.truncate = p->truncate;
   return P;
 }
 
@@ -817,6 +832,21 @@ void evaluate(const WorldD& W, const Prm& P, const Layout& L, const std::vector<
     double sn = k == R_NORMAL ? sig_n[L.idx[g]] : 1.0, sf = k == R_NORMAL ? sig_f[L.idx[g]] : 1.0;
     const T* qa_m = qm + 7 * a;
     const T* qb_m = b >= 0 ? qm + 7 * b : zero7;
+    // truncated pull-back (Sec. V, terrain): a contact group sees its frame
+    // and the bodies' poses at q- as constants, so no derivative with respect
+    // to q- passes through it; values, and derivatives in u and lambda, are
+    // those of the complete residual
+    T qa_c[7], qb_c[7];
+    Contact<T> Cc;
+    if (P.truncate && k == R_NORMAL) {
+      for (int t = 0; t < 7; ++t) { qa_c[t] = T(val(qa_m[t])); qb_c[t] = T(val(qb_m[t])); }
+      Cc = *Cg;
+      Cc.n = const3(Cg->n); Cc.t1 = const3(Cg->t1); Cc.t2 = const3(Cg->t2); Cc.lb = const3(Cg->lb);
+      Cc.noff = T(val(Cg->noff));
+      Cg = &Cc;
+      qa_m = qa_c;
+      qb_m = qb_c;
+    }
     const T* ua = u + 6 * a;
     const T* ub = b >= 0 ? u + 6 * b : zero6;
     group_jacobian(W, P, L, g, Cg, qa_m, qb_m, ua, ub, &E.J[12 * g]);
@@ -1529,16 +1559,58 @@ extern "C" int ostrich_ref_spline_basis(int32_t T, int32_t K, double h, double* 
   return 0;
 }
 
-extern "C" int ostrich_ref_rollout(const ostrich_ref_batch* b, const ostrich_ref_params* p, const double* q0,
-                                   const double* u0, const double* knots, int32_t K, int32_t T,
-                                   const int32_t* loss_body, const double* target, double* loss, double* qT,
-                                   double* uT, double* g_q0, double* g_u0, double* g_knots, int32_t mode,
-                                   int32_t* status_or) {
-  if (!b || !p || !q0 || !u0 || T < 1) return -1;
+// Terms of the shaped loss contributed by state k (1 <= k <= T): tracking and
+// yaw alignment against the reference of step k and, at k = T, the final
+// position, heading and velocity, for the loss body's pose q (7) and velocity
+// u (6).  The yaw is the angle of the body x axis in the ground plane.
+template <class S>
+S state_loss(const ostrich_ref_loss& L, int W, int w, int k, int T, const S* q, const S* u) {
+  V3<S> ex = qrot(prev_rot(q), cst3<S>(1.0, 0.0, 0.0));
+  S psi = atan2(ex.y, ex.x);
+  S s(0.0);
+  if (L.w_track != 0.0 || L.w_yaw != 0.0) {
+    const double* r = L.ref + 3 * ((size_t)(k - 1) * W + w);
+    S dx = q[0] - r[0], dy = q[1] - r[1];
+    s = s + (L.w_track / T) * (dx * dx + dy * dy);
+    s = s + (L.w_yaw / T) * (1.0 - cos(psi - r[2]));
+  }
+  if (k == T) {
+    const double* g = L.goal + 3 * w;
+    S dx = q[0] - g[0], dy = q[1] - g[1];
+    s = s + L.w_pos * (dx * dx + dy * dy);
+    s = s + L.w_head * (1.0 - cos(psi - g[2]));
+    s = s + L.w_vel * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  }
+  return s;
+}
+
+// Cotangents of state_loss on the loss body's q (7) and u (6), by duals,
+// added to gq and gu.
+static void state_loss_grad(const ostrich_ref_loss& L, int W, int w, int k, int T, const double* q, const double* u,
+                            double* gq, double* gu) {
+  typedef Dual<double> Dd;
+  for (int c = 0; c < 13; ++c) {
+    Dd qd[7], ud[6];
+    for (int t = 0; t < 7; ++t) qd[t] = Dd(q[t], c == t ? 1.0 : 0.0);
+    for (int t = 0; t < 6; ++t) ud[t] = Dd(u[t], c == 7 + t ? 1.0 : 0.0);
+    const double d = state_loss<Dd>(L, W, w, k, T, qd, ud).d;
+    if (c < 7) gq[c] += d;
+    else gu[c - 7] += d;
+  }
+}
+
+// Rollout of every world with the final-xy loss (spec null) or the shaped loss.
+static int rollout_impl(const ostrich_ref_batch* b, const ostrich_ref_params* p, const double* q0, const double* u0,
+                        const double* knots, int32_t K, int32_t T, const int32_t* loss_body, const double* target,
+                        const ostrich_ref_loss* spec, double* loss, double* qT, double* uT, double* g_q0,
+                        double* g_u0, double* g_knots, int32_t mode, int32_t* status_or) {
+  if (!b || !p || !q0 || !u0 || T < 1 || (!target && !spec)) return -1;
   Prm P = load_params(p);
   std::vector<double> B(T * std::max(K, 2), 0.0);
   if (K >= 2) ostrich_ref_spline_basis(T, K, P.h, B.data());
-  for (int w = 0; w < b->n_worlds; ++w) {
+  const int NW = b->n_worlds;
+  const bool per_step = spec && (spec->w_track != 0.0 || spec->w_yaw != 0.0);
+  for (int w = 0; w < NW; ++w) {
     WorldD W = load_world(b, w);
     int b0 = b->body_off[w], c0 = b->ctrl_off[w];
     int nb = W.nb, nc = W.nctrl, nl = W.lam_len;
@@ -1563,16 +1635,34 @@ extern "C" int ostrich_ref_rollout(const ostrich_ref_batch* b, const ostrich_ref
       st_or |= R.status;
     }
     if (status_or) status_or[w] = st_or;
-    int lb = loss_body[w];
+    const int lb = loss_body[w];
     const double* qf = &qs[T * 7 * nb];
-    double dx = qf[7 * lb] - target[2 * w], dy = qf[7 * lb + 1] - target[2 * w + 1];
-    if (loss) loss[w] = dx * dx + dy * dy;
+    auto q_at = [&](int k) { return &qs[k * 7 * nb + 7 * lb]; };
+    auto u_at = [&](int k) { return &us[k * 6 * nb + 6 * lb]; };
+    double dx = 0, dy = 0;
+    if (!spec) {
+      dx = qf[7 * lb] - target[2 * w];
+      dy = qf[7 * lb + 1] - target[2 * w + 1];
+      if (loss) loss[w] = dx * dx + dy * dy;
+    } else if (loss) {
+      double s = 0;
+      for (int k = 1; k <= T; ++k)
+        if (k == T || per_step) s += state_loss<double>(*spec, NW, w, k, T, q_at(k), u_at(k));
+      double r = 0;
+      for (int k = 0; k < T; ++k)
+        for (int c = 0; c < nc; ++c) r += cs[k * (nc + 1) + c] * cs[k * (nc + 1) + c];
+      loss[w] = s + spec->w_ctrl / T * r;
+    }
     if (qT) std::copy(qf, qf + 7 * nb, qT + 7 * b0);
     if (uT) std::copy(&us[T * 6 * nb], &us[T * 6 * nb] + 6 * nb, uT + 6 * b0);
     if (!g_q0 && !g_u0 && !g_knots) continue;
     std::vector<double> gq(7 * nb, 0.0), gu(6 * nb, 0.0), gq2(7 * nb), gu2(6 * nb), gc(nc + 1);
-    gq[7 * lb] = 2 * dx;
-    gq[7 * lb + 1] = 2 * dy;
+    if (!spec) {
+      gq[7 * lb] = 2 * dx;
+      gq[7 * lb + 1] = 2 * dy;
+    } else {
+      state_loss_grad(*spec, NW, w, T, T, q_at(T), u_at(T), &gq[7 * lb], &gu[6 * lb]);
+    }
     std::vector<double> gk(nc * std::max(K, 1), 0.0);
     for (int k = T - 1; k >= 0; --k) {
       StepCtx X;
@@ -1583,14 +1673,37 @@ extern "C" int ostrich_ref_rollout(const ostrich_ref_batch* b, const ostrich_ref
                     gc.data(), mode);
       gq = gq2;
       gu = gu2;
+      if (spec)  // control regulariser
+        for (int c = 0; c < nc; ++c) gc[c] += 2.0 * spec->w_ctrl / T * cs[k * (nc + 1) + c];
       for (int c = 0; c < nc; ++c)
         for (int j = 0; j < K; ++j) gk[c * K + j] += B[k * K + j] * gc[c];
+      if (per_step && k >= 1) state_loss_grad(*spec, NW, w, k, T, q_at(k), u_at(k), &gq[7 * lb], &gu[6 * lb]);
     }
     if (g_q0) std::copy(gq.begin(), gq.end(), g_q0 + 7 * b0);
     if (g_u0) std::copy(gu.begin(), gu.end(), g_u0 + 6 * b0);
     if (g_knots) std::copy(gk.begin(), gk.begin() + nc * K, g_knots + c0 * K);
   }
   return 0;
+}
+
+extern "C" int ostrich_ref_rollout(const ostrich_ref_batch* b, const ostrich_ref_params* p, const double* q0,
+                                   const double* u0, const double* knots, int32_t K, int32_t T,
+                                   const int32_t* loss_body, const double* target, double* loss, double* qT,
+                                   double* uT, double* g_q0, double* g_u0, double* g_knots, int32_t mode,
+                                   int32_t* status_or) {
+  if (!target) return -1;
+  return rollout_impl(b, p, q0, u0, knots, K, T, loss_body, target, nullptr, loss, qT, uT, g_q0, g_u0, g_knots, mode,
+                      status_or);
+}
+
+extern "C" int ostrich_ref_rollout_shaped(const ostrich_ref_batch* b, const ostrich_ref_params* p, const double* q0,
+                                          const double* u0, const double* knots, int32_t K, int32_t T,
+                                          const int32_t* loss_body, const ostrich_ref_loss* spec, double* loss,
+                                          double* qT, double* uT, double* g_q0, double* g_u0, double* g_knots,
+                                          int32_t mode, int32_t* status_or) {
+  if (!spec || !spec->goal || ((spec->w_track != 0.0 || spec->w_yaw != 0.0) && !spec->ref)) return -1;
+  return rollout_impl(b, p, q0, u0, knots, K, T, loss_body, nullptr, spec, loss, qT, uT, g_q0, g_u0, g_knots, mode,
+                      status_or);
 }
 
 extern "C" int ostrich_ref_inspect(const ostrich_ref_batch* b, const ostrich_ref_params* p, int32_t world,

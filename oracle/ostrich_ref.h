@@ -56,6 +56,7 @@ typedef struct {
   int32_t n_feat;    /* heightmap features per proxy */
   int32_t newton_mode;/* 0: generalized Jacobian of the constraint rows, 1: W frozen (symmetric) */
   int32_t ls_max;    /* step halvings of the residual-decrease step length (0: full steps) */
+  int32_t truncate;  /* 1: contact geometry held fixed within the step in the q- pull-back */
 } ostrich_ref_params;
 
 /* status bits */
@@ -96,11 +97,34 @@ int ostrich_ref_spline_basis(int32_t T, int32_t K, double h, double* B);
 
 /* T-step rollout with loss |xy(loss_body) - target|^2 at step T, and its
  * gradient by the per-step adjoint (mode as above).  knots [n_ctrl*K]. */
+/* Shaped loss of the optimisation workloads; per world w, with p_k the xy,
+ * psi_k the yaw (angle of the body x axis in the ground plane) and v_k the
+ * linear velocity of the loss body in state k, a_k the controls of step k and
+ * (r_k, rho_k) the reference of step k:
+ *   L_w = w_pos |p_T - p*|^2 + w_head (1 - cos(psi_T - psi*)) + w_vel |v_T|^2
+ *       + (w_ctrl / T) sum_{k<T} |a_k|^2 + (w_track / T) sum_{k=1..T} |p_k - r_k|^2
+ *       + (w_yaw / T) sum_{k=1..T} (1 - cos(psi_k - rho_k)).
+ * goal [W*3] (x*, y*, psi*); ref [T*W*3], entry (k - 1) W + w = (r_k, rho_k),
+ * read only when w_track or w_yaw is not zero.  Host arrays. */
+typedef struct {
+  double w_pos, w_head, w_vel, w_ctrl, w_track, w_yaw;
+  const double* goal;
+  const double* ref;
+} ostrich_ref_loss;
+
 int ostrich_ref_rollout(const ostrich_ref_batch* b, const ostrich_ref_params* p,
                         const double* q0, const double* u0, const double* knots, int32_t K,
                         int32_t T, const int32_t* loss_body, const double* target,
                         double* loss, double* qT, double* uT, double* g_q0, double* g_u0,
                         double* g_knots, int32_t mode, int32_t* status_or);
+
+/* The rollout above with the shaped loss in place of the final-xy loss. */
+int ostrich_ref_rollout_shaped(const ostrich_ref_batch* b, const ostrich_ref_params* p, const double* q0,
+                               const double* u0, const double* knots, int32_t K, int32_t T,
+                               const int32_t* loss_body, const ostrich_ref_loss* spec, double* loss, double* qT,
+                               double* uT, double* g_q0, double* g_u0, double* g_knots, int32_t mode,
+                               int32_t* status_or);
+
 
 /* Inspection of one world at a given iterate (u, lam in active-row order):
  * sizes, raw residual F [n_u+m], row scale D [n_u+m], constraint Jacobian

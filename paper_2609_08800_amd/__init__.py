@@ -7,6 +7,7 @@ There is no CPU fallback: without the built library every entry point raises.
 """
 from __future__ import annotations
 
+import ctypes
 import os
 import subprocess
 
@@ -277,6 +278,51 @@ class Simulator:
             ws.data_ptr(), ws.numel() * 8, st.data_ptr(), self._stream(stream))
         _capi.check(rc, "ostrich_rollout")
         return dict(loss=loss, qT=qT, uT=uT, g_q0=g_q0, g_u0=g_u0, g_knots=g_knots, status=st, workspace=ws)
+
+    def rollout_shaped(self, q0, u0, knots, basis, T, weights, goal, ref=None, ckpt_every=10, loss_body=None,
+                       phase=3, workspace=None, grads=True, loss_grad=None, stream=None):
+        """T-step rollout with the shaped loss of ``ostrich_rollout_shaped``: ``weights``
+        maps the names in LOSS_WEIGHTS to their values (missing: 0), ``goal`` is [W, 3]
+        (x*, y*, psi*), ``ref`` [T, W, 3] the per-step reference (needed when w_track
+        or w_yaw is not zero)."""
+        torch = self.torch
+        q0, u0 = self._f64(q0, (self.NB, 7)), self._f64(u0, (self.NB, 6))
+        K = 0
+        if self.NCTRL > 0:
+            knots = self._f64(knots)
+            K = knots.numel() // self.NCTRL
+            knots = knots.reshape(self.NCTRL, K)
+            basis = self._f64(basis, (T, K))
+        if torch.is_tensor(loss_body):
+            lb = loss_body.to(self.device, torch.int32).contiguous()
+        else:
+            lb = torch.as_tensor(np.asarray(loss_body, dtype=np.int32), device=self.device).contiguous()
+        unknown = set(weights) - set(LOSS_WEIGHTS)
+        if unknown:
+            raise ValueError("unknown loss weights: %s" % sorted(unknown))
+        gl = self._f64(goal, (self.W, 3))
+        rf = self._f64(ref, (T, self.W, 3)) if ref is not None else None
+        spec = _capi.OstrichLoss(*[float(weights.get(k, 0.0)) for k in LOSS_WEIGHTS])
+        spec.goal = gl.data_ptr()
+        spec.ref = rf.data_ptr() if rf is not None else None
+        lg = self._f64(loss_grad, (self.W,)) if loss_grad is not None else None
+        ws = workspace if workspace is not None else self.new_workspace(T, ckpt_every)
+        loss = torch.empty(self.W, dtype=torch.float64, device=self.device)
+        qT, uT, _ = self.empty_state()
+        st = torch.zeros(self.W, dtype=torch.int32, device=self.device)
+        g_q0 = torch.empty_like(q0) if grads else None
+        g_u0 = torch.empty_like(u0) if grads else None
+        g_knots = torch.empty(self.NCTRL, max(K, 1), dtype=torch.float64, device=self.device) if grads else None
+        rc = self.lib.ostrich_rollout_shaped(
+            self.ctx, int(phase), q0.data_ptr(), u0.data_ptr(), self._p(knots) if self.NCTRL else None, int(K),
+            self._p(basis) if self.NCTRL else None, int(T), int(ckpt_every), lb.data_ptr(), ctypes.byref(spec),
+            self._p(lg), loss.data_ptr(), qT.data_ptr(), uT.data_ptr(), self._p(g_q0), self._p(g_u0), self._p(g_knots),
+            ws.data_ptr(), ws.numel() * 8, st.data_ptr(), self._stream(stream))
+        _capi.check(rc, "ostrich_rollout_shaped")
+        return dict(loss=loss, qT=qT, uT=uT, g_q0=g_q0, g_u0=g_u0, g_knots=g_knots, status=st, workspace=ws)
+
+
+LOSS_WEIGHTS = ("w_pos", "w_head", "w_vel", "w_ctrl", "w_track", "w_yaw")
 
 
 class GraphRollout:

@@ -34,7 +34,13 @@ class OstrichBatch(ctypes.Structure):
 class OstrichParams(ctypes.Structure):
     _fields_ = [("h", c_dbl), ("gravity", c_dbl * 3), ("tol", c_dbl), ("k_max", c_int), ("k_min", c_int),
                 ("eps", c_dbl), ("delta_g", c_dbl), ("delta_reg", c_dbl), ("delta0", c_dbl),
-                ("ls_max", c_int), ("refine", c_int), ("team", c_int), ("schedule", c_int)]
+                ("ls_max", c_int), ("refine", c_int), ("team", c_int), ("schedule", c_int),
+                ("truncate", c_int)]
+
+
+class OstrichLoss(ctypes.Structure):
+    _fields_ = [("w_pos", c_dbl), ("w_head", c_dbl), ("w_vel", c_dbl), ("w_ctrl", c_dbl), ("w_track", c_dbl),
+                ("w_yaw", c_dbl), ("goal", c_vp), ("ref", c_vp)]
 
 
 BATCH_ARRAYS = ("body_off", "body_mass", "body_inertia", "joint_off", "joint_body", "joint_frame", "joint_act",
@@ -77,6 +83,10 @@ def load() -> ctypes.CDLL:
     L.ostrich_rollout.argtypes = ([c_vp, c_int, c_vp, c_vp, c_vp, c_int, c_vp, c_int, c_int, c_vp, c_vp, c_vp,
                                    c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp, c_vp])
     L.ostrich_rollout.restype = c_int
+    L.ostrich_rollout_shaped.argtypes = ([c_vp, c_int, c_vp, c_vp, c_vp, c_int, c_vp, c_int, c_int, c_vp,
+                                          ctypes.POINTER(OstrichLoss), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                          c_vp, c_size, c_vp, c_vp])
+    L.ostrich_rollout_shaped.restype = c_int
     L.ostrich_ctx_schedule.argtypes = [c_vp, c_vp, c_int]
     L.ostrich_ctx_schedule.restype = c_int
     L.ostrich_ctx_timing.argtypes = [c_vp, c_int, c_vp]
@@ -127,6 +137,7 @@ def make_params(p: dict, team: int = 0, schedule: int = SCHED_BUCKETED) -> Ostri
     cp.refine = int(p.get("refine", 8))
     cp.team = int(team)
     cp.schedule = int(schedule)
+    cp.truncate = int(p.get("truncate", 0))
     return cp
 
 

@@ -157,6 +157,7 @@ struct Batch {
 struct Params {
   double h, g[3], tol, eps, dg, dreg, d0;
   int32_t kmax, kmin, ls_max, refine;
+  int32_t truncate;  // adjoint: contact geometry held fixed in the q- pull-back
 };
 
 enum { RK_ANCHOR = 0, RK_AXIS = 1, RK_SERVO = 2, RK_CONTACT = 3 };

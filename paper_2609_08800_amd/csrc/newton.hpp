@@ -617,7 +617,9 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
       if (act) g_ctrl[R.c0 + c++] = g;
     }
   }
-  // q-: forward duals over the 7 components of every body's pose
+  // q-: forward duals over the 7 components of every body's pose; with
+  // P.truncate the contact groups, whose geometry is then held fixed within
+  // the step, contribute nothing
   for (int p = t.rank(); p < 7 * nb; p += t.size()) {
     int beta = p / 7, comp = p % 7;
     double s = 0.0;
@@ -655,6 +657,7 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
       int a = M.r_a[row], c = M.r_b[row];
       if (a != beta && c != beta) continue;
       int kind = M.r_kind[row];
+      if (kind == RK_CONTACT && P.truncate) continue;
       int n = kind == RK_CONTACT ? 3 : 1;
       double target = kind == RK_SERVO ? servo_target(B, R, ctrl, M.r_idx[row]) : 0.0;
       GroupIn<dual> ind;

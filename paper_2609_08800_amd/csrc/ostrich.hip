@@ -315,6 +315,98 @@ __global__ void k_loss(const int32_t* body_off, int W, const double* qT, const i
   }
 }
 
+// Shaped loss of the optimisation workload (device copy of ostrich_loss).
+struct LossDev {
+  double w_pos, w_head, w_vel, w_ctrl, w_track, w_yaw;
+  const double* goal;
+  const double* ref;
+};
+
+// wt (1 - cos(psi - rho)) of a body's yaw psi (the heading of its x axis in the
+// ground plane) from its unit quaternion (x, y, z, w), with the cotangent on
+// the quaternion added to dq[3..6]: with R00 = 1 - 2 (y^2 + z^2), R10 =
+// 2 (x y + w z) and n = |(R00, R10)|, cos(psi - rho) = (R00 cos rho + R10 sin rho) / n.
+__device__ double yaw_term(const double* qb, double rho, double wt, double* dq) {
+  const double x = qb[3], y = qb[4], z = qb[5], w = qb[6];
+  const double r00 = 1.0 - 2.0 * (y * y + z * z), r10 = 2.0 * (x * y + w * z);
+  const double n2 = r00 * r00 + r10 * r10, n = ::sqrt(n2);
+  const double ca = ::cos(rho), sa = ::sin(rho);
+  const double c = (r00 * ca + r10 * sa) / n;
+  const double sg = (ca * r10 - sa * r00) / (n2 * n);
+  const double f00 = -wt * r10 * sg, f10 = wt * r00 * sg;  // d/dR00, d/dR10 of wt (1 - c)
+  dq[3] += f10 * 2.0 * y;
+  dq[4] += f00 * (-4.0 * y) + f10 * 2.0 * x;
+  dq[5] += f00 * (-4.0 * z) + f10 * 2.0 * w;
+  dq[6] += f10 * 2.0 * z;
+  return wt * (1.0 - c);
+}
+
+// Terms of state k (1 <= k <= T) of each world's shaped loss: tracking and yaw
+// alignment against the reference of step k and, at k = T, the final position,
+// heading and velocity.  Adds them to loss[w] (if loss) and their cotangents,
+// times loss_grad[w], to the state's gq, gu (if gq).
+__global__ void k_state_loss(const int32_t* body_off, int W, const double* q, const double* u,
+                             const int32_t* loss_body, LossDev L, int k, int T, const double* loss_grad,
+                             double* loss, double* gq, double* gu) {
+  int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  const int b = body_off[w] + loss_body[w];
+  const double* qb = q + 7 * b;
+  const double* ub = u + 6 * b;
+  double dq[7] = {0, 0, 0, 0, 0, 0, 0}, du[3] = {0, 0, 0};
+  double s = 0.0;
+  const double iT = 1.0 / T;
+  if (L.w_track != 0.0 || L.w_yaw != 0.0) {
+    const double* r = L.ref + 3 * ((size_t)(k - 1) * W + w);
+    const double ex = qb[0] - r[0], ey = qb[1] - r[1];
+    const double wt = L.w_track * iT;
+    s += wt * (ex * ex + ey * ey);
+    dq[0] += 2.0 * wt * ex;
+    dq[1] += 2.0 * wt * ey;
+    if (L.w_yaw != 0.0) s += yaw_term(qb, r[2], L.w_yaw * iT, dq);
+  }
+  if (k == T) {
+    const double* gl = L.goal + 3 * w;
+    const double ex = qb[0] - gl[0], ey = qb[1] - gl[1];
+    s += L.w_pos * (ex * ex + ey * ey);
+    dq[0] += 2.0 * L.w_pos * ex;
+    dq[1] += 2.0 * L.w_pos * ey;
+    if (L.w_head != 0.0) s += yaw_term(qb, gl[2], L.w_head, dq);
+    s += L.w_vel * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
+    for (int i = 0; i < 3; ++i) du[i] = 2.0 * L.w_vel * ub[i];
+  }
+  if (loss) loss[w] += s;
+  if (gq) {
+    const double g = loss_grad ? loss_grad[w] : 1.0;
+    for (int i = 0; i < 7; ++i) gq[7 * b + i] += g * dq[i];
+    for (int i = 0; i < 3; ++i) gu[6 * b + i] += g * du[i];
+  }
+}
+
+// Control regulariser of the shaped loss, wt sum_{k<T} |a_k|^2 over each
+// world's controls, added to loss[w].
+__global__ void k_ctrl_loss(const int32_t* ctrl_off, int W, const double* ctrl, int T, int nctrl, double wt,
+                            double* loss) {
+  int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  double s = 0.0;
+  for (int k = 0; k < T; ++k)
+    for (int c = ctrl_off[w]; c < ctrl_off[w + 1]; ++c) {
+      const double a = ctrl[(size_t)k * nctrl + c];
+      s += a * a;
+    }
+  loss[w] += wt * s;
+}
+
+// Its cotangent on the controls of one step: g_ctrl[c] += 2 wt a[c] loss_grad[w].
+__global__ void k_ctrl_reg_grad(const int32_t* ctrl_off, int W, const double* ctrl_k, double wt,
+                                const double* loss_grad, double* gctrl) {
+  int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  const double g = loss_grad ? loss_grad[w] : 1.0;
+  for (int c = ctrl_off[w]; c < ctrl_off[w + 1]; ++c) gctrl[c] += 2.0 * wt * ctrl_k[c] * g;
+}
+
 __global__ void k_gknots(const double* basis, const double* gctrl, int k, int K, int nctrl, double* g_knots) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nctrl * K) return;
@@ -523,6 +615,7 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   ctx->P.kmin = std::min(p->k_min, p->k_max);
   ctx->P.ls_max = p->ls_max;
   ctx->P.refine = p->refine;
+  ctx->P.truncate = p->truncate ? 1 : 0;
   ctx->refine = p->refine;
   ctx->caps = c;
   ctx->team = team;
@@ -961,14 +1054,27 @@ extern "C" size_t ostrich_rollout_workspace_bytes(const ostrich_ctx* ctx, int32_
   return roll_layout(ctx, T, ckpt_every).total;
 }
 
-extern "C" int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0, const double* u0,
-                               const double* knots, int32_t K, const double* basis, int32_t T, int32_t ckpt_every,
-                               const int32_t* loss_body, const double* target, const double* loss_grad,
-                               double* loss, double* qT,
-                               double* uT, double* g_q0, double* g_u0, double* g_knots, void* workspace,
-                               size_t workspace_bytes, int32_t* status_or, void* stream_) {
-  if (!ctx || !q0 || !u0 || T < 1 || !workspace || !loss_body || !target)
+// Rollout with the final-xy loss (spec == nullptr, target [W*2]) or the shaped
+// loss of `spec` (target unused).
+static int rollout_run(ostrich_ctx* ctx, int32_t phase, const double* q0, const double* u0, const double* knots,
+                       int32_t K, const double* basis, int32_t T, int32_t ckpt_every, const int32_t* loss_body,
+                       const double* target, const ostrich_loss* spec, const double* loss_grad, double* loss,
+                       double* qT, double* uT, double* g_q0, double* g_u0, double* g_knots, void* workspace,
+                       size_t workspace_bytes, int32_t* status_or, void* stream_) {
+  if (!ctx || !q0 || !u0 || T < 1 || !workspace || !loss_body || (!target && !spec))
     return fail(OSTRICH_E_ARG, "null argument or T < 1");
+  LossDev LD{};
+  if (spec) {
+    LD = LossDev{spec->w_pos, spec->w_head, spec->w_vel, spec->w_ctrl, spec->w_track, spec->w_yaw, spec->goal,
+                 spec->ref};
+    const double wts[6] = {LD.w_pos, LD.w_head, LD.w_vel, LD.w_ctrl, LD.w_track, LD.w_yaw};
+    for (double v : wts)
+      if (!std::isfinite(v)) return fail(OSTRICH_E_ARG, "loss weights must be finite");
+    if (!LD.goal) return fail(OSTRICH_E_ARG, "loss goal required");
+    if ((LD.w_track != 0.0 || LD.w_yaw != 0.0) && !LD.ref) return fail(OSTRICH_E_ARG, "loss reference required");
+  }
+  const bool per_step = spec && (LD.w_track != 0.0 || LD.w_yaw != 0.0);
+  const bool ctrl_reg = spec && LD.w_ctrl != 0.0 && ctx->NCTRL > 0;
   if (ctx->NCTRL > 0 && (!knots || !basis || K < 1)) return fail(OSTRICH_E_ARG, "knots and basis required");
   if (!(phase & (OSTRICH_FORWARD | OSTRICH_BACKWARD))) return fail(OSTRICH_E_ARG, "phase");
   RollLayout L = roll_layout(ctx, T, ckpt_every);
@@ -1009,6 +1115,7 @@ extern "C" int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0
     HIP_OK(hipMemcpyAsync(st_u(s0), u0, sizeof(double) * 6 * NB, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_fill, dim3(nblk(NL, 256)), dim3(256), 0, st, st_l(s0), (long)NL, 0.0);
     double* cur = s0;
+    if (spec && loss) hipLaunchKernelGGL(k_fill, dim3(nblk(W, 256)), dim3(256), 0, st, loss, (long)W, 0.0);
     for (int k = 0; k < T; ++k) {
       double* nxt;
       double* tp = nullptr;
@@ -1022,6 +1129,10 @@ extern "C" int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0
                                 act, nact, sts, its, resn, tp, st);
       if (rc) return rc;
       if (status_or) hipLaunchKernelGGL(k_or, dim3(nblk(W, 256)), dim3(256), 0, st, status_or, sts, W);
+      if (loss && (per_step || (spec && k + 1 == T)))
+        hipLaunchKernelGGL(k_state_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.body_off, W, st_q(nxt),
+                           st_u(nxt), loss_body, LD, k + 1, (int)T, (const double*)nullptr, loss, (double*)nullptr,
+                           (double*)nullptr);
       cur = nxt;
       if (ckpt_every > 0 && (k + 1) % ckpt_every == 0 && k + 1 < T) {
         double* dst = ck + (size_t)((k + 1) / ckpt_every) * L.S;
@@ -1035,8 +1146,12 @@ extern "C" int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0
       double* fin = ck + (size_t)L.n_seg * L.S;
       if (cur != fin) HIP_OK(hipMemcpyAsync(fin, cur, sizeof(double) * L.S, hipMemcpyDeviceToDevice, st));
     }
-    hipLaunchKernelGGL(k_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.body_off, W, st_q(cur), loss_body,
-                       target, (const double*)nullptr, loss, (double*)nullptr);
+    if (!spec)
+      hipLaunchKernelGGL(k_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.body_off, W, st_q(cur), loss_body,
+                         target, (const double*)nullptr, loss, (double*)nullptr);
+    else if (ctrl_reg && loss)
+      hipLaunchKernelGGL(k_ctrl_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.ctrl_off, W, ctrl, (int)T,
+                         ctx->NCTRL, LD.w_ctrl / T, loss);
   }
   if (phase & OSTRICH_BACKWARD) {
     if (!g_q0 || !g_u0 || (ctx->NCTRL > 0 && !g_knots)) return fail(OSTRICH_E_ARG, "gradient outputs required");
@@ -1046,18 +1161,30 @@ extern "C" int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0
     if (ctx->NCTRL > 0)
       hipLaunchKernelGGL(k_fill, dim3(nblk((long)ctx->NCTRL * K, 256)), dim3(256), 0, st, g_knots,
                          (long)ctx->NCTRL * K, 0.0);
-    hipLaunchKernelGGL(k_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.body_off, W, st_q(fin), loss_body,
-                       target, loss_grad, (double*)nullptr, gqa);
+    if (!spec)
+      hipLaunchKernelGGL(k_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.body_off, W, st_q(fin), loss_body,
+                         target, loss_grad, (double*)nullptr, gqa);
+    else
+      hipLaunchKernelGGL(k_state_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.body_off, W, st_q(fin),
+                         st_u(fin), loss_body, LD, (int)T, (int)T, loss_grad, (double*)nullptr, gqa, gua);
     double *gq = gqa, *gq2 = gqb, *gu = gua, *gu2 = gub;
+    // adjoint of step k: cotangents of state k + 1 (its own loss terms included)
+    // to those of state k, to which state k's loss terms are then added
     auto adj = [&](double* sm, double* sp, double* tp, int k) -> int {
       int r = ostrich_step_adjoint(ctx, st_q(sm), st_u(sm), ctrl_at(k), st_u(sp), st_l(sp), tp, gq, gu, gq2, gu2,
                                    gc, -1, st);
       if (r) return r;
+      if (ctrl_reg)
+        hipLaunchKernelGGL(k_ctrl_reg_grad, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.ctrl_off, W, ctrl_at(k),
+                           LD.w_ctrl / T, loss_grad, gc);
       if (ctx->NCTRL > 0)
         hipLaunchKernelGGL(k_gknots, dim3(nblk((long)ctx->NCTRL * K, 256)), dim3(256), 0, st, basis, gc, k, K,
                            ctx->NCTRL, g_knots);
       std::swap(gq, gq2);
       std::swap(gu, gu2);
+      if (per_step && k >= 1)
+        hipLaunchKernelGGL(k_state_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.body_off, W, st_q(sm),
+                           st_u(sm), loss_body, LD, k, (int)T, loss_grad, (double*)nullptr, gq, gu);
       return 0;
     };
     if (ckpt_every <= 0) {
@@ -1086,6 +1213,27 @@ extern "C" int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0
     HIP_OK(hipMemcpyAsync(g_u0, gu, sizeof(double) * 6 * NB, hipMemcpyDeviceToDevice, st));
   }
   return 0;
+}
+
+extern "C" int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0, const double* u0,
+                               const double* knots, int32_t K, const double* basis, int32_t T, int32_t ckpt_every,
+                               const int32_t* loss_body, const double* target, const double* loss_grad,
+                               double* loss, double* qT, double* uT, double* g_q0, double* g_u0, double* g_knots,
+                               void* workspace, size_t workspace_bytes, int32_t* status_or, void* stream) {
+  if (!target) return fail(OSTRICH_E_ARG, "target required");
+  return rollout_run(ctx, phase, q0, u0, knots, K, basis, T, ckpt_every, loss_body, target, nullptr, loss_grad, loss,
+                     qT, uT, g_q0, g_u0, g_knots, workspace, workspace_bytes, status_or, stream);
+}
+
+extern "C" int ostrich_rollout_shaped(ostrich_ctx* ctx, int32_t phase, const double* q0, const double* u0,
+                                      const double* knots, int32_t K, const double* basis, int32_t T,
+                                      int32_t ckpt_every, const int32_t* loss_body, const ostrich_loss* spec,
+                                      const double* loss_grad, double* loss, double* qT, double* uT, double* g_q0,
+                                      double* g_u0, double* g_knots, void* workspace, size_t workspace_bytes,
+                                      int32_t* status_or, void* stream) {
+  if (!spec) return fail(OSTRICH_E_ARG, "loss spec required");
+  return rollout_run(ctx, phase, q0, u0, knots, K, basis, T, ckpt_every, loss_body, nullptr, spec, loss_grad, loss,
+                     qT, uT, g_q0, g_u0, g_knots, workspace, workspace_bytes, status_or, stream);
 }
 
 __global__ void k_adam(double* x, const double* g, double* m, double* v, long n, double lr, double b1, double b2,

@@ -317,3 +317,69 @@ def test_parameter_gradients_match_oracle(torch, scene):
             g = g.cpu().numpy()
             assert np.linalg.norm(g - r) <= GRAD_TOL * max(np.linalg.norm(r), 1e-12), (k, np.linalg.norm(g - r))
         q, u, lam = o["q"].cpu().numpy(), un, ln
+
+
+@pytest.mark.parametrize("ck", [0, 4])
+def test_shaped_rollout_matches_oracle(torch, ck):
+    """The control-synthesis workload (Sec. IV-B) with every term of the shaped loss: final
+    position and heading, terminal velocity, control regulariser and per-step straight-line
+    tracking with heading; loss and gradients of the GPU rollout against the oracle's."""
+    from paper_2609_08800_amd import spline_basis
+    from test_oracle_pins import SHAPED_W, straight_line_reference
+    T = 10
+    b = scenes.robot_batch(4, seed=2)
+    P = scenes.solver_params(k_max=64)
+    sim = sim_for(b, P)
+    K = scenes.ROBOT_KNOTS
+    knots = scenes.knots_array(b, K)
+    B = spline_basis(T, K, P["h"])
+    goal = np.concatenate([b.target, np.full((b.n_worlds, 1), 0.3)], axis=1)
+    p0 = b.q0[b.body_off[:-1] + b.loss_body, :2]
+    ref = straight_line_reference(p0, goal, T)
+    r = sim.rollout_shaped(b.q0, b.u0, knots, B, T, SHAPED_W, goal, ref, ckpt_every=ck, loss_body=b.loss_body)
+    o = oracle.rollout_shaped(b, P, b.q0, b.u0, knots, T, SHAPED_W, goal, ref)
+    assert not np.any(o["status"] & 6)  # every step of every world converged
+    np.testing.assert_allclose(r["loss"].cpu().numpy(), o["loss"], rtol=1e-9, atol=1e-12)
+    for key in ("g_knots", "g_u0", "g_q0"):
+        g = r[key].cpu().numpy().reshape(-1)
+        w = o[key].reshape(-1)
+        assert np.linalg.norm(g - w) <= GRAD_TOL * np.linalg.norm(w), (key, np.linalg.norm(g - w) / np.linalg.norm(w))
+
+
+def test_shaped_terrain_rollout_with_truncated_pull_back(torch):
+    """The terrain workload (Sec. V): position tracking, yaw alignment and control
+    regularisation against the trajectory of a target spline (simulated by the oracle), with
+    the truncated position pull-back; GPU rollout against the oracle's."""
+    from paper_2609_08800_amd import spline_basis
+    T = 8
+    b = scenes.terrain_batch(3, seed=6, n_maps=2)
+    P = scenes.solver_params(k_max=200, truncate=1)
+    K = scenes.ROBOT_KNOTS
+    target_knots = scenes.knots_array(b, K)
+    B = spline_basis(T, K, P["h"])
+    q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    lb = b.body_off[:-1] + b.loss_body
+    ref = np.zeros((T, b.n_worlds, 3))
+    for k in range(T):
+        s = oracle.step_forward(b, P, q, u, lam, target_knots @ B[k])
+        q, u, lam = s["q"], s["u"], s["lam"]
+        x, y, z, w = q[lb, 3], q[lb, 4], q[lb, 5], q[lb, 6]
+        ref[k] = np.stack([q[lb, 0], q[lb, 1], np.arctan2(2 * (x * y + w * z), 1 - 2 * (y * y + z * z))], axis=1)
+    knots = target_knots + np.random.default_rng(3).normal(0, 1.5, target_knots.shape)
+    wts = dict(w_track=1.0, w_yaw=0.5, w_ctrl=0.01)
+    goal = np.zeros((b.n_worlds, 3))
+    sim = sim_for(b, P)
+    r = sim.rollout_shaped(b.q0, b.u0, knots, B, T, wts, goal, ref, ckpt_every=4, loss_body=b.loss_body)
+    o = oracle.rollout_shaped(b, P, b.q0, b.u0, knots, T, wts, goal, ref)
+    st, gst = o["status"], r["status"].cpu().numpy()
+    checked = 0
+    for w in range(b.n_worlds):
+        if st[w] & 6:
+            continue  # the gradient is defined where every step converged (no budget or non-finite bit)
+        assert not gst[w] & 6, w
+        checked += 1
+        assert abs(r["loss"][w].item() - o["loss"][w]) <= 1e-9 * max(1.0, abs(o["loss"][w]))
+        cs = slice(b.ctrl_off[w], b.ctrl_off[w + 1])
+        g, gw = r["g_knots"].cpu().numpy()[cs].ravel(), o["g_knots"][cs].ravel()
+        assert np.linalg.norm(g - gw) <= GRAD_TOL * np.linalg.norm(gw), (w, np.linalg.norm(g - gw) / np.linalg.norm(gw))
+    assert checked >= 2

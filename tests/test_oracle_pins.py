@@ -585,3 +585,159 @@ def test_parameter_gradients_match_finite_differences():
     K = scenes.ROBOT_KNOTS
     ctrl = scenes.knots_array(rb, K) @ spline_basis(20, K, P["h"])[3]
     assert _param_fd(rb, P, ctrl) >= 8  # of 5 masses and 4 axle servo gains
+
+
+def test_truncated_pull_back_closed_form():
+    """The truncated position pull-back (contact geometry held fixed within the step, the
+    terrain task of Sec. V) on a tripod at rest.  With the complete pull-back the three
+    contacts pin the height, z+ = sz/2 whatever z- is, so dz+/dz- = 0; with the contact
+    geometry held fixed no derivative with respect to q- passes through a contact, and the
+    height passes straight through the kinematic update, dz+/dz- = 1.  Sideways, static
+    friction keeps u+ = 0, so dx+/dx- = 1 either way.  Truncation changes only the q-
+    cotangent: those of u- and of the controls keep their bits."""
+    b = scenes.pack([tripod_world((0, 0, 0), (0, 0, 0), 0.3, (0.0, 0.0))])
+    P = scenes.solver_params(k_max=200, tol=1e-14, delta_reg=0.0)
+    q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    for _ in range(3):  # settle the contact forces
+        o = oracle.step_forward(b, P, q, u, lam, None)
+        q, u, lam = o["q"], o["u"], o["lam"]
+    o = oracle.step_forward(b, P, q, u, lam, None)
+    assert o["status"][0] & 1
+    out = {}
+    for tr in (0, 1):
+        Pt = dict(P, truncate=tr)
+        for comp in (0, 2):
+            gq_next = np.zeros_like(q)
+            gq_next[0, comp] = 1.0
+            out[tr, comp] = oracle.step_adjoint(b, Pt, q, u, lam, None, o["u"], o["lam"], gq_next,
+                                                np.zeros_like(u), mode=0)
+    assert abs(out[0, 2][0][0, 2]) < 1e-9
+    assert abs(out[1, 2][0][0, 2] - 1.0) < 1e-9
+    assert abs(out[0, 0][0][0, 0] - 1.0) < 1e-9
+    assert abs(out[1, 0][0][0, 0] - 1.0) < 1e-9
+    for comp in (0, 2):
+        assert np.array_equal(out[0, comp][1], out[1, comp][1])
+    # in flight there is no contact to truncate: every cotangent keeps its bits
+    fb = scenes.pack([tripod_world((0.4, 0, 0), (0, 0, 0.5), 0.0, (0.0, 0.0))])
+    qf = fb.q0.copy()
+    qf[:, 2] += 1.0
+    of = oracle.step_forward(fb, P, qf, fb.u0, np.zeros(fb.n_lam), None)
+    rng = np.random.default_rng(2)
+    gqn, gun = rng.normal(size=qf.shape), rng.normal(size=fb.u0.shape)
+    ga = oracle.step_adjoint(fb, P, qf, fb.u0, np.zeros(fb.n_lam), None, of["u"], of["lam"], gqn, gun, mode=0)
+    gb = oracle.step_adjoint(fb, dict(P, truncate=1), qf, fb.u0, np.zeros(fb.n_lam), None, of["u"], of["lam"],
+                             gqn, gun, mode=0)
+    for x, y in zip(ga, gb):
+        assert np.array_equal(x, y)
+
+
+# ------------------------------------------------------------- shaped loss
+
+SHAPED_W = dict(w_pos=1.3, w_head=0.7, w_vel=0.4, w_ctrl=0.05, w_track=2.0, w_yaw=0.9)
+
+
+def straight_line_reference(p0, goal, T):
+    """Reference of the control-synthesis task: the straight line from the start to the goal
+    at constant speed, heading along it; [T, W, 3] for steps k = 1..T."""
+    p0, goal = np.asarray(p0, float).reshape(-1, 2), np.asarray(goal, float).reshape(-1, 3)
+    k = np.arange(1, T + 1)[:, None, None] / T
+    xy = p0[None] + k * (goal[None, :, :2] - p0[None])
+    d = goal[:, :2] - p0
+    rho = np.broadcast_to(np.arctan2(d[:, 1], d[:, 0])[None, :, None], (T, len(p0), 1))
+    return np.concatenate([xy, rho], axis=2)
+
+
+def test_shaped_loss_closed_form_in_free_flight():
+    """The shaped loss and its gradient on a torque-free body in flight, where every state is
+    known in closed form: p_n = p0 + n h v_xy, v_T = v0 + T h g, and a spin about the
+    principal z axis turns the heading by 2 atan(h w / 2) per step (Cayley rotation).
+    dL/dv and dL/dw_z follow from the chain rule through those closed forms."""
+    h, T = 0.1, 7
+    v0, wz, p0 = np.array([0.3, -0.2, 1.0]), 1.7, np.array([0.2, -0.4])
+    wd = scenes.World(contact_cap=0)
+    wd.add_body(2.0, (0.1, 0.2, 0.3), (p0[0], p0[1], 5.0, 0, 0, 0, 1), tuple(v0) + (0.0, 0.0, wz))
+    b = scenes.pack([wd])
+    P = scenes.solver_params(tol=1e-12)
+    goal = np.array([[1.0, -0.5, 0.6]])
+    ref = np.stack([[[0.1 * k, -0.3 + 0.02 * k, 0.15 * k]] for k in range(1, T + 1)])
+    r = oracle.rollout_shaped(b, P, b.q0, b.u0, None, T, SHAPED_W, goal, ref)
+    g = np.array(P["gravity"])
+    n = np.arange(1, T + 1)
+    pn = p0[None] + (n * h)[:, None] * v0[None, :2]
+    psi = n * 2 * math.atan(h * wz / 2)
+    dpsi = n * h / (1 + (h * wz / 2) ** 2)
+    vT = v0 + T * h * g
+    W = SHAPED_W
+    e = pn - ref[:, 0, :2]
+    eT = pn[-1] - goal[0, :2]
+    L = (W["w_pos"] * eT @ eT + W["w_head"] * (1 - math.cos(psi[-1] - goal[0, 2])) + W["w_vel"] * vT @ vT
+         + W["w_track"] / T * np.sum(e * e) + W["w_yaw"] / T * np.sum(1 - np.cos(psi - ref[:, 0, 2])))
+    assert abs(r["loss"][0] - L) <= 1e-12 * L
+    gv = np.zeros(3)
+    gv[:2] = 2 * W["w_pos"] * eT * T * h + 2 * W["w_track"] / T * np.sum(e * (n * h)[:, None], axis=0)
+    gv += 2 * W["w_vel"] * vT
+    gw = (W["w_head"] * math.sin(psi[-1] - goal[0, 2]) * dpsi[-1]
+          + W["w_yaw"] / T * np.sum(np.sin(psi - ref[:, 0, 2]) * dpsi))
+    np.testing.assert_allclose(r["g_u0"][0, :3], gv, rtol=1e-10, atol=1e-12)
+    assert abs(r["g_u0"][0, 5] - gw) <= 1e-10 * abs(gw)
+    gx = 2 * W["w_pos"] * eT + 2 * W["w_track"] / T * np.sum(e, axis=0)
+    np.testing.assert_allclose(r["g_q0"][0, :2], gx, rtol=1e-10, atol=1e-12)
+
+
+def test_shaped_loss_reduces_to_the_final_xy_loss():
+    """With only w_pos the shaped loss is the final-xy loss, value and gradient."""
+    b = scenes.robot_batch(2, seed=2)
+    P = scenes.solver_params(k_max=64)
+    kn = scenes.knots_array(b, scenes.ROBOT_KNOTS)
+    a = oracle.rollout(b, P, b.q0, b.u0, kn, 5)
+    goal = np.concatenate([b.target, np.zeros((2, 1))], axis=1)
+    s = oracle.rollout_shaped(b, P, b.q0, b.u0, kn, 5, dict(w_pos=1.0), goal)
+    for key in ("loss", "g_q0", "g_u0", "g_knots"):
+        np.testing.assert_allclose(s[key], a[key], rtol=1e-14, atol=1e-14)
+
+
+def test_shaped_loss_gradient_matches_finite_differences():
+    """The robot of the control-synthesis task with every term of the shaped loss (including
+    the control regulariser and per-step straight-line tracking and heading), against central
+    differences in the knots."""
+    b = scenes.robot_batch(1, seed=1)
+    P = scenes.solver_params(k_max=64, tol=1e-12)
+    T = 3
+    kn = scenes.knots_array(b, scenes.ROBOT_KNOTS)
+    goal = np.concatenate([b.target, [[0.4]]], axis=1)
+    p0 = b.q0[b.body_off[0] + b.loss_body[0], :2][None]
+    ref = straight_line_reference(p0, goal, T)
+    base = oracle.rollout_shaped(b, P, b.q0, b.u0, kn, T, SHAPED_W, goal, ref)
+    assert np.all(base["status"] & 1)
+    flat = kn.reshape(-1)
+    idx = [0, 1, 9, 17, 26, 31]
+    fd = []
+    for i in idx:
+        d = 1e-6 * max(1.0, abs(flat[i]))
+        xp, xm = flat.copy(), flat.copy()
+        xp[i] += d
+        xm[i] -= d
+        lp = oracle.rollout_shaped(b, P, b.q0, b.u0, xp.reshape(kn.shape), T, SHAPED_W, goal, ref, grad=False)
+        lm = oracle.rollout_shaped(b, P, b.q0, b.u0, xm.reshape(kn.shape), T, SHAPED_W, goal, ref, grad=False)
+        fd.append((lp["loss"].sum() - lm["loss"].sum()) / (2 * d))
+    g = base["g_knots"].reshape(-1)[idx]
+    assert np.linalg.norm(np.array(fd) - g) <= 1e-5 * np.linalg.norm(g), (fd, g)
+
+
+def test_control_regulariser_closed_form():
+    """With only w_ctrl the shaped loss is (w_ctrl / T) sum_k |a_k|^2 of the spline controls
+    (computed here with scipy's natural cubic spline, knots at j T h / (K - 1)), its knot
+    gradient (2 w_ctrl / T) sum_k a_k dA_k/dknots, and no state enters it."""
+    from scipy.interpolate import CubicSpline
+    b = scenes.robot_batch(1, seed=4)
+    P = scenes.solver_params(k_max=64)
+    T, K, h, wc = 4, scenes.ROBOT_KNOTS, P["h"], 0.3
+    kn = scenes.knots_array(b, K)
+    r = oracle.rollout_shaped(b, P, b.q0, b.u0, kn, T, dict(w_ctrl=wc), np.zeros((1, 3)))
+    tk = np.arange(K) * T * h / (K - 1)
+    ts = np.arange(T) * h
+    a = np.stack([CubicSpline(tk, kn[c], bc_type="natural")(ts) for c in range(kn.shape[0])])  # [nctrl, T]
+    assert abs(r["loss"][0] - wc / T * np.sum(a * a)) <= 1e-12 * np.sum(a * a)
+    basis = np.stack([CubicSpline(tk, np.eye(K)[j], bc_type="natural")(ts) for j in range(K)], axis=1)  # [T, K]
+    np.testing.assert_allclose(r["g_knots"], 2 * wc / T * a @ basis, rtol=1e-10, atol=1e-13)
+    assert not np.any(r["g_q0"]) and not np.any(r["g_u0"])

@@ -56,10 +56,14 @@ def test_terrain_steps_teacher_forced(torch):
     assert converged >= 0.75 * 12 * b.n_worlds
 
 
-def test_terrain_adjoint_matches_exact_ift(torch):
+@pytest.mark.parametrize("truncate", [0, 1])
+def test_terrain_adjoint_matches_exact_ift(torch, truncate):
+    """The step adjoint on terrain against the oracle's exact one, with the complete
+    position pull-back and with the truncated one (contact geometry held fixed within the
+    step, as on the long terrain horizons of Sec. V)."""
     from paper_2609_08800_amd import Simulator, spline_basis
     b = scenes.terrain_batch(4, seed=5, n_maps=2)
-    P = scenes.solver_params(k_max=200)
+    P = scenes.solver_params(k_max=200, truncate=truncate)
     sim = Simulator(b, P, device="cuda:0")
     K = scenes.ROBOT_KNOTS
     kn = scenes.knots_array(b, K)
