@@ -187,6 +187,104 @@ def uneven_measurement(n_stacks=2048, n_robots=2048, T=50, ckpt=10, seed=0):
     return res
 
 
+# Weights of the shaped loss, and the learning rate and servo gain of the control-synthesis
+# task, chosen by a small sweep (lr 0.3 / 1 / 3, gain 0.5 / 2, five weight sets).  The knots
+# are wheel speeds of 0.1 m wheels; the paper's lr 0.3 for 0.35 m wheels scales to about 1.
+SHAPED_WEIGHTS = dict(w_pos=4.0, w_head=0.2, w_vel=4.0, w_ctrl=1e-3, w_track=0.05, w_yaw=0.0)
+SYNTHESIS_LR = 1.0
+SYNTHESIS_SERVO_KP = 2.0
+
+
+# The pallet of the control-synthesis task: 1.2 x 0.8 m like the paper's, and low enough
+# (0.02 m) for the synthetic robot's 0.1 m wheels to climb and its 0.025 m chassis
+# clearance to pass (the paper's 0.35 m wheels climb a 0.144 m pallet).
+SYNTHESIS_PALLET = (1.2, 0.8, 0.02)
+
+
+def straight_line_ref(p0, goal, T):
+    """Per-step reference of the control-synthesis task: the point moving from the start to
+    the goal at constant speed, heading along the line; [T, W, 3]."""
+    k = np.arange(1, T + 1)[:, None, None] / T
+    xy = p0[None] + k * (goal[None, :, :2] - p0[None])
+    d = goal[:, :2] - p0
+    rho = np.broadcast_to(np.arctan2(d[:, 1], d[:, 0])[None, :, None], (T, len(p0), 1))
+    return np.concatenate([xy, rho], axis=2)
+
+
+def shaped_measurement(sim, q0, u0, knots, basis, T, batch, ckpt):
+    """World-steps/s of the timed workload's rollout + adjoint with the shaped loss (final
+    pose, heading and velocity, control regulariser, per-step straight-line tracking)."""
+    import torch
+    W = batch.n_worlds
+    goal = np.concatenate([batch.target, np.zeros((W, 1))], axis=1)
+    p0 = batch.q0[batch.body_off[:-1] + batch.loss_body, :2]
+    ref = straight_line_ref(p0, goal, T)
+    ws = sim.new_workspace(T, ckpt)
+    run = lambda: sim.rollout_shaped(q0, u0, knots, basis, T, SHAPED_WEIGHTS, goal, ref, ckpt_every=ckpt,
+                                     loss_body=batch.loss_body, workspace=ws)
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"world_steps_per_s": round(W * T / dt, 1), "weights": SHAPED_WEIGHTS}
+
+
+def control_synthesis_measurement(trials=25, iters=50, lr=SYNTHESIS_LR, T=60, K=10, seed=0,
+                                  servo_kp=SYNTHESIS_SERVO_KP, weights=None):
+    """The control-synthesis task of Sec. IV-B on the robot over a pallet: open-loop
+    wheel-velocity splines (K knots per wheel, velocity servos) from zero, the shaped loss
+    towards a random goal at x = 3 m, 50 Adam iterations; per trial the iterate of least loss,
+    success when its final position error is below 0.2 m and its terminal speed below
+    0.3 m/s.  All trials run as one batch."""
+    import torch
+    import scenes
+    from paper_2609_08800_amd import Simulator, spline_basis
+    rng = np.random.default_rng(seed)
+    wts = SHAPED_WEIGHTS if weights is None else weights
+    worlds = [scenes.robot_world(rng, yaw=float(rng.normal(0, 0.1)), servo_kp=servo_kp, knots=np.zeros((4, K)),
+                                 obstacle_size=SYNTHESIS_PALLET) for _ in range(trials)]
+    b = scenes.pack(worlds)
+    q0 = b.q0.copy()
+    for w in range(trials):  # perturbed start
+        q0[b.body_off[w]:b.body_off[w + 1], :2] += rng.normal(0, 0.05, 2)
+    goal = np.stack([np.full(trials, 3.0), rng.uniform(-0.5, 0.5, trials), rng.uniform(-0.3, 0.3, trials)], axis=1)
+    P = scenes.solver_params()
+    dev = torch.device("cuda:0")
+    sim = Simulator(b, P, device=dev)
+    lb = b.body_off[:-1] + b.loss_body
+    ref = straight_line_ref(q0[lb, :2], goal, T)
+    basis = torch.as_tensor(spline_basis(T, K, P["h"]), device=dev)
+    x = torch.zeros(sim.NCTRL, K, dtype=torch.float64, device=dev)
+    m, v = torch.zeros_like(x), torch.zeros_like(x)
+    ws = sim.new_workspace(T, 10)
+    best = np.full(trials, np.inf)
+    best_err, best_speed = np.zeros(trials), np.zeros(trials)
+    t0 = time.perf_counter()
+    for it in range(1, iters + 1):
+        r = sim.rollout_shaped(q0, b.u0, x, basis, T, wts, goal, ref, ckpt_every=10,
+                               loss_body=b.loss_body, workspace=ws)
+        rc = sim.lib.ostrich_adam(x.data_ptr(), r["g_knots"].data_ptr(), m.data_ptr(), v.data_ptr(), x.numel(),
+                                  lr, 0.9, 0.999, 1e-8, it, None)
+        if rc != 0:
+            raise RuntimeError("ostrich_adam failed: %d" % rc)
+        loss = r["loss"].cpu().numpy()
+        qT, uT = r["qT"].cpu().numpy(), r["uT"].cpu().numpy()
+        err = np.hypot(qT[lb, 0] - goal[:, 0], qT[lb, 1] - goal[:, 1])
+        speed = np.linalg.norm(uT[lb, :3], axis=1)
+        better = np.isfinite(loss) & (loss < best)
+        best[better], best_err[better], best_speed[better] = loss[better], err[better], speed[better]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ok = (best_err < 0.2) & (best_speed < 0.3)
+    return {"trials": trials, "adam_iterations": iters, "lr": lr, "T": T, "knots_per_wheel": K,
+            "success_rate": round(float(ok.mean()), 3), "median_final_position_error_m": round(float(np.median(best_err)), 4),
+            "median_terminal_speed_m_s": round(float(np.median(best_speed)), 4),
+            "median_best_loss": round(float(np.median(best)), 5), "seconds": round(dt, 2),
+            "servo_kp": servo_kp, "weights": wts}
+
+
 def serving_measurement(rate, duration, drain, seed=0, capacity=4096, budget_gb=96.0, hmap_slots=64):
     """Poisson arrivals of trajectory-optimisation requests (robots on their
     own value-noise terrain, 1..256 worlds, T in 20..100, 10 iterations of
@@ -227,6 +325,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="arrival window of the serving run")
     ap.add_argument("--serve-drain", type=float, default=40.0, help="extra time to finish admitted requests")
     ap.add_argument("--uneven", type=int, default=1, help="also measure the uneven stacks + robots batch")
+    ap.add_argument("--synthesis-trials", type=int, default=25,
+                    help="trials of the control-synthesis task (0: skip)")
     ap.add_argument("--serve-sweep", type=str, default="",
                     help="comma-separated arrival rates (req/s) of an additional serving sweep")
     ap.add_argument("--roofline-only", action="store_true",
@@ -341,6 +441,13 @@ def main():
         plain = plain_path_measurement()
         plain["batched_over_plain"] = round(value / plain["world_steps_per_s"], 1)
         progress("plain path done")
+    shaped = synthesis = None
+    if not args.roofline_only:
+        shaped = shaped_measurement(sim, q0, u0, knots, basis, T, batch, args.ckpt)
+        progress("shaped-loss rollout done")
+        if args.synthesis_trials > 0:
+            synthesis = control_synthesis_measurement(trials=args.synthesis_trials)
+            progress("control synthesis done")
     uneven = None
     if args.uneven and not args.roofline_only:
         uneven = uneven_measurement()
@@ -389,6 +496,8 @@ def main():
                   "adjoint_roofline": adjoint_roofline,
                   "checkpointing": ckpt_modes,
                   "plain_path": plain,
+                  "shaped_loss_rollout": shaped,
+                  "control_synthesis": synthesis,
                   "uneven_batch": uneven,
                   "serving": serving,
                   "serving_sweep": sweep},

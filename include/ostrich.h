@@ -301,7 +301,9 @@ int ostrich_rollout_shaped(ostrich_ctx* ctx, int32_t phase, const double* q0, co
  *     the x, y entries of gq (other entries untouched).
  *   ostrich_knot_grad_accumulate: g_knots[c*K + j] += basis[k*K + j] g_ctrl[c].
  *   ostrich_adam: x -= lr mhat / (sqrt(vhat) + eps) with the moments m, v
- *     updated in place from g, bias corrections of step t >= 1. */
+ *     updated in place from g, bias corrections of step t >= 1; a non-finite
+ *     entry of g (a rollout that diverged) counts as zero, so its moments
+ *     decay instead of turning the knot into NaN. */
 int ostrich_spline_controls(const double* basis, const double* knots, int32_t T, int32_t K, int32_t nctrl,
                             double* ctrl, void* stream);
 int ostrich_final_loss(const int32_t* body_off, int32_t n_worlds, const double* qT, const int32_t* loss_body,

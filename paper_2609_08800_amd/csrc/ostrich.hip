@@ -1241,6 +1241,7 @@ __global__ void k_adam(double* x, const double* g, double* m, double* v, long n,
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double gi = g[i];
+  if (!isfinite(gi)) gi = 0.0;  // a diverged rollout leaves the moments to decay
   double mi = b1 * m[i] + (1.0 - b1) * gi;
   double vi = b2 * v[i] + (1.0 - b2) * gi * gi;
   m[i] = mi;

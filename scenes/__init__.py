@@ -311,7 +311,7 @@ AXLE_DAMPING = 0.05    # N m s / rad: gain of the axle's zero-speed servo row
 
 def robot_world(rng=None, *, yaw=0.0, obstacle_x=1.0, knots=None, mu=ROBOT_MU,
                 servo_kp=None, with_obstacle=True, contact_cap=16,
-                axle_damping=AXLE_DAMPING) -> World:
+                axle_damping=AXLE_DAMPING, obstacle_size=OBSTACLE_SIZE) -> World:
     """Wheeled robot: 10 kg chassis box and four 0.5 kg wheels on revolute joints.
 
     The wheels are driven by torques (8 spline knots per wheel) with viscous
@@ -320,8 +320,8 @@ def robot_world(rng=None, *, yaw=0.0, obstacle_x=1.0, knots=None, mu=ROBOT_MU,
     ``servo_kp``, by velocity servos.  Wheel contact uses a sphere proxy of the
     wheel radius at the wheel centre (rotation invariant about the axle); the
     chassis uses its 8 corners and 5 bottom-face points.  ``obstacle_x`` is the
-    x of the obstacle's near face; the obstacle is 1.2 x 0.8 x 0.15 m centred
-    at y = 0.
+    x of the obstacle's near face; the obstacle (``obstacle_size``, 1.2 x 0.8 x
+    0.15 m by default) is centred at y = 0.
     """
     cx, cy, cz = CHASSIS_SIZE
     wd = World(contact_cap=contact_cap)
@@ -354,7 +354,7 @@ def robot_world(rng=None, *, yaw=0.0, obstacle_x=1.0, knots=None, mu=ROBOT_MU,
         for k in kinds:
             wd.add_slot(k, c, local=p, mu=mu, feature=0 if k == SLOT_BOX else -1)
     if with_obstacle:
-        ox, oy, oz = OBSTACLE_SIZE
+        ox, oy, oz = obstacle_size
         wd.add_obstacle((obstacle_x + 0.5 * ox, 0.0, 0.5 * oz), (0.5 * ox, 0.5 * oy, 0.5 * oz))
     if knots is None:
         knots = rng.uniform(-2.0, 2.0, size=(4, ROBOT_KNOTS)) if rng is not None \

@@ -383,3 +383,28 @@ def test_shaped_terrain_rollout_with_truncated_pull_back(torch):
         g, gw = r["g_knots"].cpu().numpy()[cs].ravel(), o["g_knots"][cs].ravel()
         assert np.linalg.norm(g - gw) <= GRAD_TOL * np.linalg.norm(gw), (w, np.linalg.norm(g - gw) / np.linalg.norm(gw))
     assert checked >= 2
+
+
+def test_adam_matches_its_formula_and_skips_non_finite_gradients(torch):
+    """ostrich_adam against Adam written out in numpy (bias-corrected moments), over three
+    steps; a NaN gradient entry counts as zero, so that knot moves by its momentum alone."""
+    from paper_2609_08800_amd import _capi
+    L = _capi.load()
+    rng = np.random.default_rng(0)
+    n = 37
+    x0, g = rng.normal(size=n), rng.normal(size=(3, n))
+    g[1, 5] = np.nan
+    x = torch.tensor(x0, dtype=torch.float64, device="cuda:0")
+    m, v = torch.zeros_like(x), torch.zeros_like(x)
+    xr, mr, vr = x0.copy(), np.zeros(n), np.zeros(n)
+    lr, b1, b2, eps = 0.3, 0.9, 0.999, 1e-8
+    for t in range(1, 4):
+        gt = torch.tensor(g[t - 1], dtype=torch.float64, device="cuda:0")
+        assert L.ostrich_adam(x.data_ptr(), gt.data_ptr(), m.data_ptr(), v.data_ptr(), n, lr, b1, b2, eps, t, None) == 0
+        gi = np.where(np.isfinite(g[t - 1]), g[t - 1], 0.0)
+        mr = b1 * mr + (1 - b1) * gi
+        vr = b2 * vr + (1 - b2) * gi * gi
+        xr = xr - lr * (mr / (1 - b1 ** t)) / (np.sqrt(vr / (1 - b2 ** t)) + eps)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(x.cpu().numpy(), xr, rtol=1e-14, atol=1e-14)
+    assert np.all(np.isfinite(x.cpu().numpy()))
