@@ -65,8 +65,9 @@ typedef struct {
   const int32_t* joint_off;
   const int32_t* joint_body;   /* [NJ*2] world-local body indices (parent a, child b) */
   const double* joint_frame;   /* [NJ*18] anchor_a, anchor_b, axis_b, perp1_a, perp2_a, axis_a (body frames) */
-  const int32_t* joint_act;    /* [NJ] 0 none, 1 torque, 2 velocity servo, 3 torque + zero-speed servo */
-  const double* joint_kp;      /* [NJ] servo gain k_p (compliance 1/k_p, Eq. (8)) */
+  const int32_t* joint_act;    /* [NJ] 0 none, 1 torque, 2 velocity servo, 3 torque + zero-speed servo,
+                                  4 position servo (the control is the target angle) */
+  const double* joint_kp;      /* [NJ] servo gain k_p (compliance 1/k_p of a velocity servo, Eq. (8)) */
   const int32_t* ctrl_off;     /* controls: one per actuated joint, in joint order */
   const int32_t* slot_off;     /* contact candidate slots */
   const int32_t* slot_int;     /* [NS*4] kind (0 plane, 1 static box, 2 face of body b), body a, body b, obstacle */
@@ -80,6 +81,10 @@ typedef struct {
   double hmap_spacing;
   const double* hmap_origin;
   const double* hmap_heights;
+  const double* joint_kd;      /* [NJ] derivative gain k_d of position servos: compliance
+                                  1 / (k_d + h k_p) and b_c = k_p (theta(q-) - theta*) / (k_d + h k_p),
+                                  theta the angle of R_b perp1_a from R_a perp1_a about R_a axis_a
+                                  (Eq. (8)); unused by other joints */
 } ostrich_batch;
 
 /* Solver parameters (host struct, copied at context creation). */

@@ -39,7 +39,7 @@ class Batch(ctypes.Structure):
                 ("slot_real", c_dbl_p), ("obs_off", c_int_p), ("obs_box", c_dbl_p),
                 ("lam_off", c_int_p), ("contact_cap", c_int_p), ("world_hmap", c_int_p),
                 ("hmap_n", c_int), ("hmap_spacing", ctypes.c_double), ("hmap_origin", c_dbl_p),
-                ("hmap_heights", c_dbl_p)]
+                ("hmap_heights", c_dbl_p), ("joint_kd", c_dbl_p)]
 
 
 class Params(ctypes.Structure):
@@ -88,7 +88,7 @@ class _Handle:
             slot_off=_i(b.slot_off), slot_int=_i(b.slot_int), slot_real=_d(b.slot_real),
             obs_off=_i(b.obs_off), obs_box=_d(b.obs_box), lam_off=_i(b.lam_off),
             contact_cap=_i(b.contact_cap), world_hmap=_i(b.world_hmap),
-            hmap_origin=_d(b.hmap_origin), hmap_heights=_d(b.hmap_heights))
+            hmap_origin=_d(b.hmap_origin), hmap_heights=_d(b.hmap_heights), joint_kd=_d(b.joint_kd))
         a = self.arrays
         self.cb = Batch()
         self.cb.n_worlds = b.n_worlds

@@ -124,7 +124,7 @@ constexpr double kFaceEps = 1e-12;
 
 struct JointD {
   int a, b, act, ctrl;
-  double anc_a[3], anc_b[3], axis_b[3], p1[3], p2[3], axis_a[3], kp;
+  double anc_a[3], anc_b[3], axis_b[3], p1[3], p2[3], axis_a[3], kp, kd;
 };
 struct SlotD {
   int kind, a, b, feat;
@@ -189,8 +189,9 @@ WorldD load_world(const ostrich_ref_batch* B, int w) {
     }
     J.act = B->joint_act[j];
     J.kp = B->joint_kp[j];
+    J.kd = B->joint_kd ? B->joint_kd[j] : 0.0;
     J.ctrl = J.act ? c++ : -1;
-    if (J.act == 2 || J.act == 3) W.nservo++;
+    if (J.act == 2 || J.act == 3 || J.act == 4) W.nservo++;
     W.joints.push_back(J);
   }
   W.nctrl = c;
@@ -569,7 +570,7 @@ Layout make_layout(const WorldD& W, const std::vector<Feature>& act) {
     }
   int sv = 0;
   for (int j = 0; j < nj; ++j)
-    if (W.joints[j].act == 2 || W.joints[j].act == 3) {
+    if (W.joints[j].act == 2 || W.joints[j].act == 3 || W.joints[j].act == 4) {
       L.kind.push_back(R_SERVO);
       L.ra.push_back(W.joints[j].a);
       L.rb.push_back(W.joints[j].b);
@@ -700,9 +701,22 @@ void group_residual(const WorldD& W, const Prm& P, const Layout& L, int g, const
     const JointD& J = W.joints[L.idx[g]];
     V3<S> ax = qrot(prev_rot(qa_m), cst3<S>(J.axis_a));
     S vel = ax.x * (ub[3] - ua[3]) + ax.y * (ub[4] - ua[4]) + ax.z * (ub[5] - ua[5]);
-    // act 2: commanded joint speed; act 3: target 0 (axle damping beside a torque)
+    // act 2: commanded joint speed; act 3: target 0 (axle damping beside a torque);
+    // act 4: commanded joint angle, the implicit PD force k_p (theta* - theta+) -
+    // k_d theta_dot+ with theta+ = theta(q-) + h theta_dot+, i.e. compliance
+    // 1 / (k_d + h k_p) and b = k_p (theta(q-) - theta*) / (k_d + h k_p)
     const S kp = param<S>(J.kp, PS_KP, L.idx[g]);
-    r[0] = J.act == 2 ? vel + lg[0] / kp - ctrl[J.ctrl] : vel + lg[0] / kp;
+    if (J.act == 4) {
+      // joint angle at q-: of R_b p1 from R_a p1 about R_a axis_a
+      Q4<S> ra = prev_rot(qa_m), rb = prev_rot(qb_m);
+      V3<S> pa = qrot(ra, cst3<S>(J.p1)), pb = qrot(rb, cst3<S>(J.p1));
+      V3<S> c = cross(pa, pb);
+      S th = atan2(c.x * ax.x + c.y * ax.y + c.z * ax.z, pa.x * pb.x + pa.y * pb.y + pa.z * pb.z);
+      S den = J.kd + h * kp;
+      r[0] = vel + lg[0] / den + kp * (th - ctrl[J.ctrl]) / den;
+    } else {
+      r[0] = J.act == 2 ? vel + lg[0] / kp - ctrl[J.ctrl] : vel + lg[0] / kp;
+    }
     return;
   }
   // normal row: eps-smoothed FB of (gap, sigma_n lambda_n), Eq. (4)

@@ -25,7 +25,8 @@ typedef struct {
   const int32_t* joint_off;    /* [W+1] */
   const int32_t* joint_body;   /* [NJ*2] world-local (a, b) */
   const double*  joint_frame;  /* [NJ*18] anchor_a, anchor_b, axis_b, perp1_a, perp2_a, axis_a */
-  const int32_t* joint_act;    /* [NJ] 0 none, 1 torque, 2 velocity servo, 3 torque + damping servo */
+  const int32_t* joint_act;    /* [NJ] 0 none, 1 torque, 2 velocity servo, 3 torque + damping servo,
+                                  4 position servo */
   const double*  joint_kp;     /* [NJ] servo gain */
   const int32_t* ctrl_off;     /* [W+1] */
   const int32_t* slot_off;     /* [W+1] */
@@ -40,6 +41,7 @@ typedef struct {
   double hmap_spacing;
   const double* hmap_origin;   /* [NH*2] */
   const double* hmap_heights;  /* [NH*n*n], index i*n + j, i along x */
+  const double* joint_kd;      /* [NJ] derivative gain of position servos */
 } ostrich_ref_batch;
 
 typedef struct {

@@ -28,7 +28,7 @@ class OstrichBatch(ctypes.Structure):
                 ("joint_kp", c_vp), ("ctrl_off", c_vp), ("slot_off", c_vp), ("slot_int", c_vp),
                 ("slot_real", c_vp), ("obs_off", c_vp), ("obs_box", c_vp), ("lam_off", c_vp),
                 ("contact_cap", c_vp), ("world_hmap", c_vp), ("hmap_n", c_int), ("hmap_spacing", c_dbl),
-                ("hmap_origin", c_vp), ("hmap_heights", c_vp)]
+                ("hmap_origin", c_vp), ("hmap_heights", c_vp), ("joint_kd", c_vp)]
 
 
 class OstrichParams(ctypes.Structure):
@@ -45,7 +45,7 @@ class OstrichLoss(ctypes.Structure):
 
 BATCH_ARRAYS = ("body_off", "body_mass", "body_inertia", "joint_off", "joint_body", "joint_frame", "joint_act",
                 "joint_kp", "ctrl_off", "slot_off", "slot_int", "slot_real", "obs_off", "obs_box", "lam_off",
-                "contact_cap", "world_hmap", "hmap_origin", "hmap_heights")
+                "contact_cap", "world_hmap", "hmap_origin", "hmap_heights", "joint_kd")
 
 _lib = None
 

@@ -613,7 +613,11 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
         for (int k = 0; k < 3; ++k) g += -h * at(ax, k) * (wu[6 * b + 3 + k] - wu[6 * a + 3 + k]);
       }
       if (act == 2) g = -wl[5 * R.nj + sv];
-      if (act == 2 || act == 3) ++sv;
+      if (act == 4) {  // the servo row holds -alpha k_p theta*
+        const double kp = B.joint_kp[R.j0 + j];
+        g = -(kp / (B.joint_kd[R.j0 + j] + h * kp)) * wl[5 * R.nj + sv];
+      }
+      if (act == 2 || act == 3 || act == 4) ++sv;
       if (act) g_ctrl[R.c0 + c++] = g;
     }
   }
@@ -735,7 +739,15 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
       for (int i = 5 * R.nj; i < 5 * R.nj + R.nsv; ++i)
         if (M.r_idx[i] == j) {
           const double kp = B.joint_kp[R.j0 + j];
-          g = wl[i] * M.D[i] * (-M.lam[i] / (kp * kp));
+          if (B.joint_act[R.j0 + j] == 4) {  // d/dk_p of alpha lambda + alpha k_p e = alpha^2 (k_d e - h lambda)
+            const double kd = B.joint_kd[R.j0 + j], al = 1.0 / (kd + h * kp);
+            const int a = B.joint_body[2 * (R.j0 + j)], b = B.joint_body[2 * (R.j0 + j) + 1];
+            const double e = joint_angle(ldm(M.Rm + 9 * a), ldm(M.Rm + 9 * b), B.joint_frame + 18 * (R.j0 + j)) -
+                             servo_target(B, R, ctrl, j);
+            g = wl[i] * M.D[i] * (al * al * (kd * e - h * M.lam[i]));
+          } else {
+            g = wl[i] * M.D[i] * (-M.lam[i] / (kp * kp));
+          }
         }
       g_kp[R.j0 + j] = g;
     }

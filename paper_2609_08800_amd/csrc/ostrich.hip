@@ -247,7 +247,7 @@ __global__ void k_flops(ost::Batch B, const int32_t* n_act, const int32_t* iters
   double s = 0.0;
   for (int w = threadIdx.x; w < B.n_worlds; w += blockDim.x) {
     int nsv = 0;
-    for (int j = B.joint_off[w]; j < B.joint_off[w + 1]; ++j) nsv += (B.joint_act[j] == 2 || B.joint_act[j] == 3);
+    for (int j = B.joint_off[w]; j < B.joint_off[w + 1]; ++j) nsv += (B.joint_act[j] == 2 || B.joint_act[j] == 3 || B.joint_act[j] == 4);
     const double m = 5.0 * (B.joint_off[w + 1] - B.joint_off[w]) + nsv + 3.0 * n_act[w];
     const double per_it = 24.0 * m * m + 2.0 * m * m * m / 3.0 + 2.0 * m * m + 800.0 * m;
     s += iters[w] * per_it + 400.0 * m + (with_tape ? 24.0 * m * m + 2.0 * m * m * m / 3.0 : 0.0);
@@ -583,7 +583,7 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
     if (nb < 1 || nj < 0 || ns < 0 || cap[w] < 0 || co[w + 1] < co[w] || lo[w + 1] < lo[w])
       return fail(OSTRICH_E_ARG, "malformed offsets");
     int nsv = 0;
-    for (int j = jo[w]; j < jo[w + 1]; ++j) nsv += (act[j] == 2 || act[j] == 3);
+    for (int j = jo[w]; j < jo[w + 1]; ++j) nsv += (act[j] == 2 || act[j] == 3 || act[j] == 4);
     int nc = std::min(cap[w], ns);
     ost::Caps wc{nb, nj, std::max(ns, 1), std::max(nc, 1), std::max(5 * nj + nsv + 3 * nc, 1), nsv};
     if (wc.mr > ost::kMaxRows)

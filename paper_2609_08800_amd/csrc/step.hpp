@@ -55,9 +55,16 @@ OST_HD GroupIn<double> group_in_lds(const WorldMem& M, int row, const double* u,
   return in;
 }
 
+// Compliance alpha of a servo row (Eq. (8)): 1/k_p for a speed target,
+// 1/(k_d + h k_p) for an angle target.
+OST_HD double servo_compliance(const Batch& B, const WorldRef& R, int joint, double h) {
+  const double kp = B.joint_kp[R.j0 + joint];
+  return B.joint_act[R.j0 + joint] == 4 ? 1.0 / (B.joint_kd[R.j0 + joint] + h * kp) : 1.0 / kp;
+}
+
 OST_HD double servo_target(const Batch& B, const WorldRef& R, const double* ctrl, int joint) {
   int act = B.joint_act[R.j0 + joint];
-  if (act != 2) return 0.0;
+  if (act != 2 && act != 4) return 0.0;  // speed (2) or angle (4) from the control; 3: speed 0
   int c = 0;
   for (int j = 0; j < joint; ++j)
     if (B.joint_act[R.j0 + j]) ++c;
@@ -317,7 +324,7 @@ OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
       idx = 0;
       for (int j = 0; j < R.nj; ++j) {
         int act = B.joint_act[R.j0 + j];
-        if (act == 2 || act == 3) {
+        if (act == 2 || act == 3 || act == 4) {
           if (++c == sv) { idx = j; break; }
         }
       }
@@ -424,9 +431,9 @@ OST_HD double evaluate(Team& t, const Batch& B, const Params& P, const WorldRef&
     if (kind == RK_CONTACT) {
       int c = M.r_idx[row];
       contact_G(P, in, b >= 0, M.c_r[c], M.c_mu[c], M.c_sn[c], M.c_sf[c], M.c_kind[c], Jg, D, Gu, Gl);
-    } else {  // joint rows: D r = c(q(u)) / h, so D dr/du = J; servo rows: dr/du = J, dr/dlambda = 1/k_p
+    } else {  // joint rows: D r = c(q(u)) / h, so D dr/du = J; servo rows: dr/du = J, dr/dlambda = alpha
       for (int q = 0; q < 12; ++q) Gu[q] = Jg[q];
-      Gl[0] = kind == RK_SERVO ? 1.0 / B.joint_kp[R.j0 + M.r_idx[row]] : 0.0;
+      Gl[0] = kind == RK_SERVO ? servo_compliance(B, R, M.r_idx[row], P.h) : 0.0;
     }
     #pragma unroll
     for (int k = 0; k < 3; ++k) if (k < n) {

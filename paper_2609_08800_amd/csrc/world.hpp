@@ -146,7 +146,7 @@ OST_HD WorldRef world_ref(const Batch& B, int w) {
   R.nsv = 0;
   for (int j = 0; j < R.nj; ++j) {
     int a = B.joint_act[R.j0 + j];
-    if (a == 2 || a == 3) R.nsv++;
+    if (a == 2 || a == 3 || a == 4) R.nsv++;
   }
   R.m = 0;
   R.nc = 0;
@@ -180,6 +180,14 @@ template <class T> struct GroupIn {
 
 // Residual rows r (raw), Jacobian rows J (12 each) and the value of the row
 // scale D of one group: a joint row, a servo row, or a contact (n, t1, t2).
+// Angle of a revolute joint at the poses Ra, Rb: that of R_b perp1_a from
+// R_a perp1_a about R_a axis_a (zero where the two frames coincide).
+template <class T>
+OST_HD T joint_angle(const m3<T>& Ra, const m3<T>& Rb, const double* fr) {
+  const v3<T> pa = mul(Ra, ld3<T>(fr + 9)), pb = mul(Rb, ld3<T>(fr + 9)), ax = mul(Ra, ld3<T>(fr + 15));
+  return satan2(dot(cross(pa, pb), ax), dot(pa, pb));
+}
+
 template <class T>
 OST_HD void eval_group(const Batch& B, const Params& P, const WorldRef& R, int kind, int idx, int sub,
                        int has_b, double r_prox, T mu, double sn, double sf, int ckind,
@@ -214,13 +222,18 @@ OST_HD void eval_group(const Batch& B, const Params& P, const WorldRef& R, int k
     D[0] = 1.0 / h;
     return;
   }
-  if (kind == RK_SERVO) {  // Eq. (8), velocity target, alpha = 1/k_p
+  if (kind == RK_SERVO) {  // Eq. (8): velocity target (alpha = 1/k_p, b = -u_bar) or position target
     const double* fr = B.joint_frame + 18 * (R.j0 + idx);
     double kp = B.joint_kp[R.j0 + idx];
     v3<T> ax = mul(in.Ra, ld3<T>(fr + 15));
     J[3] = -ax.x; J[4] = -ax.y; J[5] = -ax.z;
     J[9] = ax.x; J[10] = ax.y; J[11] = ax.z;
-    r[0] = dot(ax, Bb.w - Ba.w) + in.lg[0] / kp - in.target;
+    if (B.joint_act[R.j0 + idx] == 4) {  // alpha = 1/(k_d + h k_p), b = alpha k_p (theta(q-) - theta*)
+      const double al = 1.0 / (B.joint_kd[R.j0 + idx] + h * kp);
+      r[0] = dot(ax, Bb.w - Ba.w) + in.lg[0] * al + (joint_angle(in.Ra, in.Rb, fr) - in.target) * (al * kp);
+    } else {
+      r[0] = dot(ax, Bb.w - Ba.w) + in.lg[0] / kp - in.target;
+    }
     D[0] = 1.0;
     return;
   }

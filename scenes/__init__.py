@@ -37,6 +37,7 @@ ACT_NONE = 0
 ACT_TORQUE = 1
 ACT_SERVO_VEL = 2
 ACT_TORQUE_DAMPED = 3   # torque from the control plus a velocity servo row with target 0
+ACT_SERVO_POS = 4       # position servo: the control is the target joint angle (gains k_p, k_d)
 
 JOINT_FRAME_LEN = 18   # anchor_a, anchor_b, axis_b, perp1_a, perp2_a, axis_a
 SLOT_INT_LEN = 4       # kind, body_a, body_b, feature index
@@ -87,11 +88,13 @@ class World:
 
     def add_revolute(self, a, b, anchor_a, anchor_b, axis_b=(0, 1, 0),
                      perp1_a=(1, 0, 0), perp2_a=(0, 0, 1), axis_a=(0, 1, 0),
-                     act=ACT_NONE, kp=0.0) -> int:
-        """Revolute joint: anchors coincide and axis_b stays normal to perp1_a, perp2_a."""
+                     act=ACT_NONE, kp=0.0, kd=0.0) -> int:
+        """Revolute joint: anchors coincide and axis_b stays normal to perp1_a, perp2_a.
+        The joint angle (position servos) is that of R_b perp1_a from R_a perp1_a about
+        R_a axis_a: zero where the two bodies' frames coincide."""
         self.joints.append(dict(a=a, b=b, anchor_a=anchor_a, anchor_b=anchor_b,
                                 axis_b=axis_b, perp1_a=perp1_a, perp2_a=perp2_a,
-                                axis_a=axis_a, act=act, kp=kp))
+                                axis_a=axis_a, act=act, kp=kp, kd=kd))
         return len(self.joints) - 1
 
     def add_slot(self, kind, a, local=(0, 0, 0), radius=0.0, mu=0.5, b=-1,
@@ -110,7 +113,7 @@ class World:
 
     @property
     def n_servo(self) -> int:
-        return sum(1 for j in self.joints if j["act"] in (ACT_SERVO_VEL, ACT_TORQUE_DAMPED))
+        return sum(1 for j in self.joints if j["act"] in (ACT_SERVO_VEL, ACT_TORQUE_DAMPED, ACT_SERVO_POS))
 
     @property
     def lam_len(self) -> int:
@@ -142,6 +145,7 @@ class Batch:
     joint_frame: np.ndarray
     joint_act: np.ndarray
     joint_kp: np.ndarray
+    joint_kd: np.ndarray
     ctrl_off: np.ndarray
     slot_off: np.ndarray
     slot_int: np.ndarray
@@ -209,7 +213,7 @@ def pack(worlds: Sequence[World], heightmaps: Sequence[Heightmap] = ()) -> Batch
 
     mass = np.array([m for w in worlds for m in w.mass], dtype=np.float64)
     inertia = cat([i for w in worlds for i in w.inertia], 3, np.float64)
-    jb, jf, ja, jk = [], [], [], []
+    jb, jf, ja, jk, jd = [], [], [], [], []
     for w in worlds:
         for j in w.joints:
             jb.append((j["a"], j["b"]))
@@ -217,6 +221,7 @@ def pack(worlds: Sequence[World], heightmaps: Sequence[Heightmap] = ()) -> Batch
                       tuple(j["perp1_a"]) + tuple(j["perp2_a"]) + tuple(j["axis_a"]))
             ja.append(j["act"])
             jk.append(j["kp"])
+            jd.append(j.get("kd", 0.0))
     si, sr = [], []
     for w in worlds:
         for s in w.slots:
@@ -240,7 +245,7 @@ def pack(worlds: Sequence[World], heightmaps: Sequence[Heightmap] = ()) -> Batch
         n_worlds=W, body_off=body_off, body_mass=mass, body_inertia=inertia,
         joint_off=joint_off, joint_body=cat(jb, 2, np.int32), joint_frame=cat(jf, JOINT_FRAME_LEN, np.float64),
         joint_act=np.array(ja, dtype=np.int32), joint_kp=np.array(jk, dtype=np.float64),
-        ctrl_off=ctrl_off, slot_off=slot_off, slot_int=cat(si, SLOT_INT_LEN, np.int32),
+        joint_kd=np.array(jd, dtype=np.float64), ctrl_off=ctrl_off, slot_off=slot_off, slot_int=cat(si, SLOT_INT_LEN, np.int32),
         slot_real=cat(sr, SLOT_REAL_LEN, np.float64), obs_off=obs_off, obs_box=obs,
         lam_off=lam_off, row_off=row_off,
         contact_cap=np.array([w.contact_cap for w in worlds], dtype=np.int32),

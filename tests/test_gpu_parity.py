@@ -58,6 +58,33 @@ def gpu_step(sim, q, u, lam, ctrl, tape=None):
     return {k: v.cpu().numpy() for k, v in o.items()}
 
 
+def position_servo_robots(n, seed):
+    """Robots whose wheels are position servos (Eq. (8) with a target angle; k_p = 5,
+    k_d = 0.2): the velocity-servo robot with its servos switched to angle targets, which
+    keeps the row layout."""
+    rng = np.random.default_rng(seed)
+    b = scenes.pack([scenes.robot_world(rng, yaw=float(rng.uniform(-0.3, 0.3)), servo_kp=5.0) for _ in range(n)])
+    b.joint_act = np.full_like(b.joint_act, scenes.ACT_SERVO_POS)
+    b.joint_kd = np.full_like(b.joint_kd, 0.2)
+    return b
+
+
+def test_position_servo_robot_steps_teacher_forced(torch):
+    """Wheel angle targets ramping up (0.2 rad per step): states, contact sets and status
+    against the oracle, every step started from the oracle's state."""
+    b = position_servo_robots(8, seed=2)
+    P = scenes.solver_params(k_max=64)
+    sim = sim_for(b, P)
+    q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    for k in range(10):
+        c = np.full(b.n_ctrl, 0.2 * (k + 1))
+        ref = oracle.step_forward(b, P, q, u, lam, c)
+        got = gpu_step(sim, q, u, lam, c)
+        assert np.array_equal(got["act_slot"], ref["act_slot"]), k
+        check_states(b, got, ref)
+        q, u, lam = ref["q"], ref["u"], ref["lam"]
+
+
 def robot_ctrl(batch, T=100):
     from paper_2609_08800_amd import spline_basis
     K = scenes.ROBOT_KNOTS
@@ -274,7 +301,7 @@ def test_step_timing_counts_launches_and_algorithmic_work(torch):
     assert abs(adj["bytes"] - nbytes) <= 1e-9 * nbytes
 
 
-@pytest.mark.parametrize("scene", ["robots", "boxes", "tripods", "terrain"])
+@pytest.mark.parametrize("scene", ["robots", "boxes", "tripods", "terrain", "position_servos", "hinges"])
 def test_parameter_gradients_match_oracle(torch, scene):
     """Cotangents of every body's mass, every slot's friction coefficient and every
     joint's servo gain (Eq. (17) with a model parameter as xi), and of the state
@@ -295,6 +322,14 @@ def test_parameter_gradients_match_oracle(torch, scene):
         rng = np.random.default_rng(3)
         b = scenes.pack([tripod_world(tuple(rng.uniform(-1, 1, 2)) + (0.0,), tuple(rng.normal(0, 0.5, 3)),
                                       float(rng.uniform(-3, 3)), (0.0, 0.0)) for _ in range(3)])
+    elif scene == "position_servos":
+        b = position_servo_robots(3, seed=1)
+        ctrl_at = lambda k: np.full(b.n_ctrl, 0.5 * (k + 1))
+    elif scene == "hinges":
+        from test_oracle_pins import _hinge_z_world
+        b = scenes.pack([_hinge_z_world(0.4, 1.5, 3.0, 0.05), _hinge_z_world(-0.2, -0.7, 1.0, 0.0)])
+        P = scenes.solver_params(k_max=64, gravity=(0, 0, 0))
+        ctrl_at = lambda k: np.array([-0.3, 0.5])
     else:
         b = scenes.terrain_batch(3, seed=4, n_maps=2)
         K = scenes.ROBOT_KNOTS

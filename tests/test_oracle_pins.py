@@ -741,3 +741,71 @@ def test_control_regulariser_closed_form():
     basis = np.stack([CubicSpline(tk, np.eye(K)[j], bc_type="natural")(ts) for j in range(K)], axis=1)  # [T, K]
     np.testing.assert_allclose(r["g_knots"], 2 * wc / T * a @ basis, rtol=1e-10, atol=1e-13)
     assert not np.any(r["g_q0"]) and not np.any(r["g_u0"])
+
+
+# ------------------------------------------------------------- position servo
+
+def _hinge_z_world(theta0, w_rel, kp, kd):
+    """A 10 kg base and a 0.5 kg rotor on a hinge about z through both centres, the rotor
+    turned by theta0 and spinning at w_rel relative to the base; a position servo."""
+    wd = scenes.World(contact_cap=0)
+    a = wd.add_body(10.0, (0.3, 0.4, 0.5), (0, 0, 3, 0, 0, 0, 1), (0, 0, 0, 0, 0, 0.2))
+    c = wd.add_body(0.5, (0.002, 0.002, 0.0025), (0, 0, 3, 0, 0, math.sin(theta0 / 2), math.cos(theta0 / 2)),
+                    (0, 0, 0, 0, 0, 0.2 + w_rel))
+    wd.add_revolute(a, c, anchor_a=(0, 0, 0), anchor_b=(0, 0, 0), axis_b=(0, 0, 1), perp1_a=(1, 0, 0),
+                    perp2_a=(0, 1, 0), axis_a=(0, 0, 1), act=scenes.ACT_SERVO_POS, kp=kp, kd=kd)
+    wd.loss_body = c
+    return wd
+
+
+def test_position_servo_closed_form():
+    """Position servo (Eq. (8) with a target angle): the servo force is the implicit PD force
+    lambda = k_p (theta* - theta+) - k_d theta_dot+ with theta+ = theta- + h theta_dot+, so the
+    relative rate obeys I_eff (theta_dot+ - theta_dot-) = h lambda, i.e.
+    theta_dot+ = (I_eff theta_dot- + h k_p (theta* - theta-)) / (I_eff + h k_d + h^2 k_p);
+    each body turns about z by its own Cayley angle 2 atan(h w / 2).  Five steps, for
+    k_d = 0 (where b_c is the joint error divided by h) and k_d > 0."""
+    for kp, kd in ((3.0, 0.0), (2.0, 0.05)):
+        th0, target = 0.4, -0.3
+        b = scenes.pack([_hinge_z_world(th0, 1.5, kp, kd)])
+        P = scenes.solver_params(gravity=(0, 0, 0), k_max=64, tol=1e-13)
+        h = P["h"]
+        outs = run(b, P, 5, ctrl=lambda k: np.array([target]))
+        Ia, Ib = 0.5, 0.0025
+        Ieff = 1.0 / (1.0 / Ia + 1.0 / Ib)
+        wa, wb, fa, fb = 0.2, 1.7, 0.0, th0
+        for o in outs:
+            rate = ((wb - wa) * Ieff + h * kp * (target - (fb - fa))) / (Ieff + h * kd + h * h * kp)
+            lam = (rate - (wb - wa)) * Ieff / h
+            wa, wb = wa - h * lam / Ia, wb + h * lam / Ib
+            fa, fb = fa + 2 * math.atan(h * wa / 2), fb + 2 * math.atan(h * wb / 2)
+            assert abs(o["u"][0, 5] - wa) < 1e-10 and abs(o["u"][1, 5] - wb) < 1e-10, (kp, kd)
+            assert abs(o["q"][1, 5] - math.sin(fb / 2)) < 1e-10 and abs(o["q"][0, 5] - math.sin(fa / 2)) < 1e-10
+            assert o["status"][0] & 1
+
+
+def test_position_servo_gradients_match_finite_differences():
+    """Cotangents of the gains (Eq. (17) with k_p as xi, one step) and of the target angles
+    (a rollout whose shaped loss sees the rotor's heading), against central differences."""
+    P = scenes.solver_params(gravity=(0, 0, 0), k_max=200, tol=1e-14, delta_reg=0.0)
+    b = scenes.pack([_hinge_z_world(0.4, 1.5, 3.0, 0.05), _hinge_z_world(-0.2, -0.7, 1.0, 0.0)])
+    # the two gains; the masses do not enter (no gravity, no translation), and all agree
+    assert _param_fd(b, P, np.array([-0.3, 0.5])) == 2
+    # the target angle through a 4-step rollout with heading terms
+    T, K = 4, 3
+    kn = np.array([[-0.3, 0.1, 0.4], [0.5, 0.2, -0.1]])
+    goal = np.array([[0, 0, 0.8], [0, 0, -0.6]])
+    ref = np.tile(np.array([[[0, 0, 0.3], [0, 0, -0.2]]]), (T, 1, 1))
+    wts = dict(w_head=1.0, w_yaw=0.5, w_ctrl=0.01)
+    base = oracle.rollout_shaped(b, P, b.q0, b.u0, kn, T, wts, goal, ref)
+    fd = np.zeros(kn.size)
+    for i in range(kn.size):
+        d = 1e-6
+        xp, xm = kn.reshape(-1).copy(), kn.reshape(-1).copy()
+        xp[i] += d
+        xm[i] -= d
+        lp = oracle.rollout_shaped(b, P, b.q0, b.u0, xp.reshape(kn.shape), T, wts, goal, ref, grad=False)
+        lm = oracle.rollout_shaped(b, P, b.q0, b.u0, xm.reshape(kn.shape), T, wts, goal, ref, grad=False)
+        fd[i] = (lp["loss"].sum() - lm["loss"].sum()) / (2 * d)
+    g = base["g_knots"].reshape(-1)
+    assert np.linalg.norm(fd - g) <= 1e-6 * np.linalg.norm(g), (fd, g)
