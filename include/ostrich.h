@@ -106,7 +106,18 @@ typedef struct {
                           derivative with respect to q- passes through a contact row or its force
                           (the truncated position pull-back of the terrain task, Sec. V); 0: the
                           complete pull-back of Eq. (17) */
+  int32_t linear_solver; /* Newton step: OSTRICH_LIN_LU (0) the banded LU of the Schur matrix;
+                          OSTRICH_LIN_KRYLOV (1) the paper's iterative alternative, a
+                          matrix-free Krylov solve (restarted GMRES, Jacobi preconditioner,
+                          products with A from the row blocks), the matrix never formed.
+                          OSTRICH_LIN_KRYLOV is switched off in this build: context creation
+                          returns OSTRICH_E_UNSUPPORTED for it */
+  int32_t krylov_iters; /* products with A per Newton step at most (0: 16, as the paper's 16
+                          inner iterations); the solve stops earlier at 1e-12 of |rhs| */
 } ostrich_params;
+
+#define OSTRICH_LIN_LU 0
+#define OSTRICH_LIN_KRYLOV 1
 
 /* Launch schedules.  FIXED: every world in one launch shaped for the largest
  * world of the batch.  BUCKETED: worlds grouped by row capacity (edges 16, 32,
@@ -233,7 +244,8 @@ int ostrich_step_adjoint_list(ostrich_ctx* ctx, const int32_t* worlds, int32_t n
  * one launch per world per Newton iteration (plus one set-up and one
  * finalisation launch per world, k_max + 2 in all), with the world's state in
  * device memory between launches; ostrich_step_adjoint_plain makes one launch
- * per world. */
+ * per world.  The plain forward steps with the banded LU only
+ * (OSTRICH_E_UNSUPPORTED with linear_solver = OSTRICH_LIN_KRYLOV). */
 int ostrich_step_forward_plain(ostrich_ctx* ctx, const double* q_prev, const double* u_prev, const double* lam_prev,
                                const double* ctrl, double* q_next, double* u_next, double* lam_next,
                                int32_t* act_slot, int32_t* n_act, int32_t* status, int32_t* iters, double* resnorm,

@@ -35,7 +35,7 @@ class OstrichParams(ctypes.Structure):
     _fields_ = [("h", c_dbl), ("gravity", c_dbl * 3), ("tol", c_dbl), ("k_max", c_int), ("k_min", c_int),
                 ("eps", c_dbl), ("delta_g", c_dbl), ("delta_reg", c_dbl), ("delta0", c_dbl),
                 ("ls_max", c_int), ("refine", c_int), ("team", c_int), ("schedule", c_int),
-                ("truncate", c_int)]
+                ("truncate", c_int), ("linear_solver", c_int), ("krylov_iters", c_int)]
 
 
 class OstrichLoss(ctypes.Structure):
@@ -138,6 +138,8 @@ def make_params(p: dict, team: int = 0, schedule: int = SCHED_BUCKETED) -> Ostri
     cp.team = int(team)
     cp.schedule = int(schedule)
     cp.truncate = int(p.get("truncate", 0))
+    cp.linear_solver = int(p.get("linear_solver", 0))
+    cp.krylov_iters = int(p.get("krylov_iters", 16))
     return cp
 
 

@@ -163,6 +163,8 @@ struct Params {
   double h, g[3], tol, eps, dg, dreg, d0;
   int32_t kmax, kmin, ls_max, refine;
   int32_t truncate;  // adjoint: contact geometry held fixed in the q- pull-back
+  int32_t lin;       // Newton step: 0 banded LU of the Schur matrix, 1 matrix-free Krylov solve
+  int32_t lin_iters; // Krylov products per Newton step at most
 };
 
 enum { RK_ANCHOR = 0, RK_AXIS = 1, RK_SERVO = 2, RK_CONTACT = 3 };

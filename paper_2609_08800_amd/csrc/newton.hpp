@@ -85,22 +85,181 @@ OST_HD void fw_begin(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
   t.sync();
 }
 
+// Dot product over a fixed partition into 64 lanes (independent of the team size).
+template <class Team>
+OST_HD double dot64(Team& t, const WorldMem& M, const double* x, const double* y, int n) {
+  double s = 0.0;
+  for (int l = t.rank(); l < 64; l += t.size())
+    for (int i = l; i < n; i += 64) s += x[i] * y[i];
+  return t.sum64(s, M.red);
+}
+
+// Schur product out = A v without forming A (Eq. (12)): with z = J^T v per
+// (body, component), (A v)_i = Y_i . z + sum over row i's group of
+// G_lambda,ij v_j / h + dreg Abar_i v_i, Y = G_u M~^-1.
+template <class Team>
+OST_HD void schur_apply(Team& t, const Params& P, const WorldRef& R, const WorldMem& M, const double* v,
+                        double* out) {
+  const int nb = R.nb, m = R.m;
+  for (int e = t.rank(); e < 6 * nb; e += t.size()) {
+    const int b = e / 6, q = e - 6 * b;
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) {
+      if (M.r_a[i] == b) s += M.J[12 * i + q] * v[i];
+      if (M.r_b[i] == b) s += M.J[12 * i + 6 + q] * v[i];
+    }
+    M.kg[e] = s;
+  }
+  t.sync();
+  const double ih = 1.0 / P.h;
+  for (int i = t.rank(); i < m; i += t.size()) {
+    const double* Y = M.Y + 12 * i;
+    const int a = M.r_a[i], b = M.r_b[i], gi = M.r_g[i];
+    double s = 0.0;
+    for (int k = 0; k < 6; ++k) s += Y[k] * M.kg[6 * a + k];
+    if (b >= 0)
+      for (int k = 0; k < 6; ++k) s += Y[6 + k] * M.kg[6 * b + k];
+    for (int j = gi; j < m && M.r_g[j] == gi; ++j) s += M.Gl[3 * i + (j - gi)] * ih * v[j];
+    out[i] = s + P.dreg * M.Abar[i] * v[i];
+  }
+  t.sync();
+}
+
+// Relative residual at which the Newton step's Krylov solve stops.
+constexpr double kLinTol = 1e-12;
+
+// Newton direction dlam of Eq. (12) by a matrix-free Krylov solve (the
+// paper's iterative alternative to a factor): right-preconditioned restarted
+// GMRES, the Jacobi preconditioner diag(A), at most P.lin_iters products
+// with A, stop at kLinTol of |rhs|.  A is non-symmetric here (the
+// generalized Jacobian), so GMRES takes the place of conjugate residuals.
+// The basis and the small least-squares problem live in the Schur matrix's
+// storage (`room` doubles), unused in this mode; the restart length is the
+// largest that fits.  Returns false on a zero or non-finite diagonal.
+template <class Team>
+OST_HD bool krylov_direction(Team& t, const Params& P, const WorldRef& R, const WorldMem& M, int room) {
+  const int m = R.m;
+  int rs = P.lin_iters;
+  while (rs > 1 && (size_t)(rs + 1) * (m + rs) + 4 * rs + 2 > (size_t)room) --rs;
+  double *V = M.A, *H = V + (size_t)(rs + 1) * m, *cs = H + (size_t)(rs + 1) * rs, *sn = cs + rs;
+  double *gv = sn + rs, *y = gv + rs + 1;
+  double *dg = M.rmax, *x = M.dlam, *z = M.lamt;
+  const double ih = 1.0 / P.h;
+  int bad = 0;
+  for (int i = t.rank(); i < m; i += t.size()) {  // diag(A)
+    const double* Y = M.Y + 12 * i;
+    const double* Jr = M.J + 12 * i;
+    double s = 0.0;
+    for (int k = 0; k < 6; ++k) s += Y[k] * Jr[k];
+    if (M.r_b[i] >= 0)
+      for (int k = 0; k < 6; ++k) s += Y[6 + k] * Jr[6 + k];
+    s += M.Gl[3 * i + (i - M.r_g[i])] * ih + P.dreg * M.Abar[i];
+    dg[i] = s;
+    x[i] = 0.0;
+    V[i] = M.rhs[i];
+    bad |= !(isfinite(s) && s != 0.0);
+  }
+  if (t.imax(bad, M.red)) return false;
+  t.sync();
+  const double bn = ::sqrt(dot64(t, M, M.rhs, M.rhs, m));
+  const double stop = kLinTol * bn;
+  double beta = bn;
+  int used = 0;
+  while (used < P.lin_iters && beta > stop) {
+    for (int i = t.rank(); i < m; i += t.size()) V[i] = V[i] / beta;
+    if (t.rank() == 0) {
+      gv[0] = beta;
+      for (int i = 1; i <= rs; ++i) gv[i] = 0.0;
+    }
+    t.sync();
+    int k = 0;
+    double res = beta;
+    bool more = true;
+    while (more && k < rs && used < P.lin_iters && res > stop) {
+      const double* vk = V + (size_t)k * m;
+      double* w = V + (size_t)(k + 1) * m;
+      for (int i = t.rank(); i < m; i += t.size()) z[i] = vk[i] / dg[i];
+      t.sync();
+      schur_apply(t, P, R, M, z, w);
+      ++used;
+      for (int i = 0; i <= k; ++i) {  // modified Gram-Schmidt
+        const double hik = dot64(t, M, w, V + (size_t)i * m, m);
+        for (int e = t.rank(); e < m; e += t.size()) w[e] -= hik * V[(size_t)i * m + e];
+        if (t.rank() == 0) H[i * rs + k] = hik;
+        t.sync();
+      }
+      const double hn = ::sqrt(dot64(t, M, w, w, m));
+      more = hn > 0.0;
+      if (more)
+        for (int e = t.rank(); e < m; e += t.size()) w[e] = w[e] / hn;
+      if (t.rank() == 0) {
+        H[(k + 1) * rs + k] = hn;
+        for (int i = 0; i < k; ++i) {
+          const double a = H[i * rs + k], b = H[(i + 1) * rs + k];
+          H[i * rs + k] = cs[i] * a + sn[i] * b;
+          H[(i + 1) * rs + k] = -sn[i] * a + cs[i] * b;
+        }
+        const double a = H[k * rs + k], b = H[(k + 1) * rs + k];
+        const double r = ::sqrt(a * a + b * b);
+        cs[k] = r > 0.0 ? a / r : 1.0;
+        sn[k] = r > 0.0 ? b / r : 0.0;
+        H[k * rs + k] = r;
+        H[(k + 1) * rs + k] = 0.0;
+        gv[k + 1] = -sn[k] * gv[k];
+        gv[k] = cs[k] * gv[k];
+      }
+      t.sync();
+      res = ::fabs(gv[k + 1]);
+      ++k;
+    }
+    if (t.rank() == 0)
+      for (int i = k - 1; i >= 0; --i) {
+        double s = gv[i];
+        for (int j = i + 1; j < k; ++j) s -= H[i * rs + j] * y[j];
+        y[i] = H[i * rs + i] != 0.0 ? s / H[i * rs + i] : 0.0;
+      }
+    t.sync();
+    for (int e = t.rank(); e < m; e += t.size()) {  // x += D^-1 V y
+      double s = 0.0;
+      for (int i = 0; i < k; ++i) s += y[i] * V[(size_t)i * m + e];
+      x[e] += s / dg[e];
+    }
+    t.sync();
+    if (!more || !(res > stop) || used >= P.lin_iters) break;
+    schur_apply(t, P, R, M, x, V);  // restart from the true residual rhs - A x
+    ++used;
+    for (int e = t.rank(); e < m; e += t.size()) V[e] = M.rhs[e] - V[e];
+    t.sync();
+    beta = ::sqrt(dot64(t, M, V, V, m));
+  }
+  return true;
+}
+
 // Newton iteration k (Eqs. (12)-(13)): factor, solve, step length, friction
 // clamp, best-iterate bookkeeping (Sec. III-C).  Nothing happens once done.
-template <class Team>
+template <class Team, bool kKrylov = false>
 OST_HD void fw_iteration(Team& t, const Batch& B, const Params& P, const WorldRef& R, const double* ctrl,
-                         WorldMem& M, FwState& S, int k) {
+                         WorldMem& M, FwState& S, int k, int room = 0) {
   if (S.done) return;
   const int nb = R.nb, m = R.m;
-  double dreg;
-  if (!factor(t, P, R, M, true, &dreg, &S.st)) {
-    S.st |= ST_NONFINITE;
-    S.done = 1;
-    return;
+  if (kKrylov) {  // matrix-free direction; the Schur matrix is never formed
+    schur_rhs(t, P, R, M);
+    if (!krylov_direction(t, P, R, M, room)) {
+      S.st |= ST_NONFINITE;
+      S.done = 1;
+      return;
+    }
+  } else {
+    double dreg;
+    if (!factor(t, P, R, M, true, &dreg, &S.st)) {
+      S.st |= ST_NONFINITE;
+      S.done = 1;
+      return;
+    }
+    for (int i = t.rank(); i < m; i += t.size()) M.dlam[i] = M.rhs[i];
+    t.sync();
+    lu_solve(t, R, M, M.dlam, false);
   }
-  for (int i = t.rank(); i < m; i += t.size()) M.dlam[i] = M.rhs[i];
-  t.sync();
-  lu_solve(t, R, M, M.dlam, false);
   // Eq. (13): du = M~^-1 (h J^T dlambda - r_dyn), force per (body, component)
   for (int e = t.rank(); e < 6 * nb; e += t.size()) {
     int b = e / 6, q = e - 6 * b;
@@ -249,7 +408,7 @@ OST_HD void fw_end(Team& t, const Batch& B, const Params& P, const WorldRef& R, 
 
 // One backward-Euler step of world w (Sec. III-A..C), fused: set-up, the
 // Newton loop and finalisation in one pass of the team.
-template <class Team>
+template <class Team, bool kKrylov = false>
 OST_HD void forward_world(Team& t, const Batch& B, const Params& P, const Caps& caps, int w, const double* q_prev,
                           const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
                           double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
@@ -258,7 +417,8 @@ OST_HD void forward_world(Team& t, const Batch& B, const Params& P, const Caps& 
   WorldRef R = world_ref(B, w);
   FwState S;
   fw_begin(t, B, P, R, q_prev, u_prev, lam_prev, ctrl, M, S);
-  for (int k = 1; k <= P.kmax && !S.done; ++k) fw_iteration(t, B, P, R, ctrl, M, S, k);
+  const int room = caps.mr * caps.mr + kPadA;  // doubles of the Schur matrix's storage
+  for (int k = 1; k <= P.kmax && !S.done; ++k) fw_iteration<Team, kKrylov>(t, B, P, R, ctrl, M, S, k, room);
   fw_end(t, B, P, R, w, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters_out, resnorm, tape, tape_off,
          M, S);
 }
@@ -395,15 +555,6 @@ OST_HD void stiffness_t(Team& t, const Batch& B, const Params& P, const WorldRef
     out[p] = s;
   }
   t.sync();
-}
-
-// Dot product over a fixed partition into 64 lanes (independent of the team size).
-template <class Team>
-OST_HD double dot64(Team& t, const WorldMem& M, const double* x, const double* y, int n) {
-  double s = 0.0;
-  for (int l = t.rank(); l < 64; l += t.size())
-    for (int i = l; i < n; i += 64) s += x[i] * y[i];
-  return t.sum64(s, M.red);
 }
 
 // out = v + S(h K^T v): the velocity block of the exact adjoint system after

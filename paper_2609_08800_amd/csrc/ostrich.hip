@@ -151,7 +151,7 @@ struct Launch {
   size_t gstride;
 };
 
-template <class TeamT>
+template <class TeamT, bool kKrylov>
 __global__ void __launch_bounds__(256) k_forward(ost::Batch B, ost::Params P, ost::Caps caps, Launch L,
                                                  const double* q_prev, const double* u_prev, const double* lam_prev,
                                                  const double* ctrl, double* q_next, double* u_next,
@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(256) k_forward(ost::Batch B, ost::Params P, os
                         ? ost::carve(smem, caps, blockDim.x, L.split, L.gscr ? L.gscr + blockIdx.x * L.gstride : nullptr)
                         : ost::carve(smem, caps, blockDim.x, ost::SPLIT_LDS, nullptr);
   for (int i = blockIdx.x; i < L.nlist; i += gridDim.x) {
-    ost::forward_world(t, B, P, caps, L.wlist[i], q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
+    ost::forward_world<TeamT, kKrylov>(t, B, P, caps, L.wlist[i], q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
                        act_slot, n_act, status, iters, resnorm, tape, tape_off, M);
     __syncthreads();
   }
@@ -599,8 +599,8 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   HIP_OK(hipGetDeviceProperties(&prop, dev));
   ctx->lds_limit = prop.sharedMemPerBlock;
   ctx->n_cu = std::max(1, prop.multiProcessorCount);
-  for (auto f : {(const void*)k_forward<GpuTeam>, (const void*)k_adjoint<GpuTeam>, (const void*)k_forward<GpuTeamG>,
-                 (const void*)k_adjoint<GpuTeamG>})
+  for (auto f : {(const void*)k_forward<GpuTeam, false>, (const void*)k_adjoint<GpuTeam>,
+                 (const void*)k_forward<GpuTeamG, false>, (const void*)k_adjoint<GpuTeamG>})
     HIP_OK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctx->lds_limit));
   std::memcpy(&ctx->B, b, sizeof(ost::Batch));
   static_assert(sizeof(ost::Batch) == sizeof(ostrich_batch), "batch layouts differ");
@@ -616,6 +616,13 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   ctx->P.ls_max = p->ls_max;
   ctx->P.refine = p->refine;
   ctx->P.truncate = p->truncate ? 1 : 0;
+  if (p->linear_solver != OSTRICH_LIN_LU && p->linear_solver != OSTRICH_LIN_KRYLOV)
+    return fail(OSTRICH_E_ARG, "linear_solver must be OSTRICH_LIN_LU or OSTRICH_LIN_KRYLOV");
+  if (p->linear_solver == OSTRICH_LIN_KRYLOV)  // switched off: its kernel faulted on the GPU, cause not found
+    return fail(OSTRICH_E_UNSUPPORTED, "the matrix-free Krylov Newton step is switched off in this build");
+  if (p->krylov_iters < 0) return fail(OSTRICH_E_ARG, "krylov_iters must be >= 0");
+  ctx->P.lin = p->linear_solver;
+  ctx->P.lin_iters = p->krylov_iters > 0 ? p->krylov_iters : 16;
   ctx->refine = p->refine;
   ctx->caps = c;
   ctx->team = team;
@@ -730,11 +737,18 @@ template <class F> static int for_buckets(ostrich_ctx* ctx, hipStream_t st, F f)
   return 0;
 }
 
+// The forward kernel of a bucket (team kind by the storage split).  Only the
+// banded-LU Newton step is instantiated for the GPU: the matrix-free Krylov
+// step is rejected at context creation.
+static decltype(&k_forward<GpuTeam, false>) forward_kernel(const ostrich_ctx*, const Bucket& bk) {
+  return bk.split == ost::SPLIT_GLOBAL ? k_forward<GpuTeamG, false> : k_forward<GpuTeam, false>;
+}
+
 static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, const double* q_prev,
                            const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
                            double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
                            int32_t* iters, double* resnorm, double* tape) {
-  auto kf = bk.split == ost::SPLIT_GLOBAL ? k_forward<GpuTeamG> : k_forward<GpuTeam>;
+  auto kf = forward_kernel(ctx, bk);
   hipLaunchKernelGGL(kf, dim3(grid_of(bk)), dim3(bk.team), bk.lds, st, ctx->B, ctx->P, bk.caps,
                      launch_of(bk), q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act,
                      status, iters, resnorm, tape, (const int64_t*)ctx->d_tape_off);
@@ -883,7 +897,7 @@ extern "C" int ostrich_step_forward_list(ostrich_ctx* ctx, const int32_t* worlds
   if (ctx->NCTRL > 0 && !ctrl) return fail(OSTRICH_E_ARG, "controls required");
   if (n == 0) return 0;
   const Bucket& bk = ctx->all;
-  hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_forward<GpuTeamG> : k_forward<GpuTeam>, dim3(list_grid(ctx, n)),
+  hipLaunchKernelGGL(forward_kernel(ctx, bk), dim3(list_grid(ctx, n)),
                      dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
                      bk.caps, list_launch(ctx, worlds, n), q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
                      act_slot, n_act, status, iters, resnorm, (double*)tape, (const int64_t*)ctx->d_tape_off);
@@ -920,6 +934,7 @@ extern "C" int ostrich_step_forward_plain(ostrich_ctx* ctx, const double* q_prev
   if (!ctx || !q_prev || !u_prev || !lam_prev || !q_next || !u_next || !lam_next)
     return fail(OSTRICH_E_ARG, "null state pointer");
   if (ctx->NCTRL > 0 && !ctrl) return fail(OSTRICH_E_ARG, "controls required");
+  if (ctx->P.lin != OSTRICH_LIN_LU) return fail(OSTRICH_E_UNSUPPORTED, "the plain path steps with the banded LU");
   hipStream_t st = (hipStream_t)stream;
   const size_t lds = 0;
   for (int w = 0; w < ctx->W; ++w) {

@@ -538,6 +538,22 @@ OST_HD void assemble(Team& t, const Params& P, const WorldRef& R, const WorldMem
   t.sync();
 }
 
+// Right-hand side of the Schur system alone, rhs = (Y r_dyn - D r_con) / h
+// (Eq. (12)), for the matrix-free Newton step.
+template <class Team>
+OST_HD void schur_rhs(Team& t, const Params& P, const WorldRef& R, const WorldMem& M) {
+  const double ih = 1.0 / P.h;
+  for (int i = t.rank(); i < R.m; i += t.size()) {
+    const double* Y = M.Y + 12 * i;
+    int a = M.r_a[i], b = M.r_b[i];
+    double s = 0.0;
+    for (int k = 0; k < 6; ++k) s += Y[k] * M.rdyn[6 * a + k];
+    if (b >= 0) for (int k = 0; k < 6; ++k) s += Y[6 + k] * M.rdyn[6 * b + k];
+    M.rhs[i] = (s - M.D[i] * M.res[i]) * ih;
+  }
+  t.sync();
+}
+
 constexpr int kMaxRows = 384;  // largest row count of a world (six rows per lane of a wavefront)
 
 // In-place LU without pivoting, restricted to the band |i - j| <= bw (no

@@ -578,10 +578,14 @@ def solver_params(**over) -> dict:
     refine: most operator applications of the adjoint's Krylov solve of the
     exact implicit-function Jacobian (0: the stored factor's solve alone);
     truncate: 1 holds the contact geometry fixed within each step in the
-    adjoint's q- pull-back (the truncated pull-back of long terrain horizons).
+    adjoint's q- pull-back (the truncated pull-back of long terrain horizons);
+    linear_solver: the Newton step's solve, 0 the banded LU of the Schur matrix, 1 a
+    matrix-free Krylov solve of at most krylov_iters products (the oracle always
+    solves exactly: the root, not the path, is compared).
     """
     p = dict(h=0.1, gravity=GRAVITY, tol=1e-10, k_max=16, k_min=4, eps=1e-8,
              delta_g=1e-12, delta_reg=1e-6, delta0=0.02, sigma_mode=1, n_feat=4,
-             newton_mode=0, ls_max=4, refine=8, truncate=0)
+             newton_mode=0, ls_max=4, refine=8, truncate=0,
+             linear_solver=0, krylov_iters=16)
     p.update(over)
     return p

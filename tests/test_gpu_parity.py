@@ -443,3 +443,61 @@ def test_adam_matches_its_formula_and_skips_non_finite_gradients(torch):
     torch.cuda.synchronize()
     np.testing.assert_allclose(x.cpu().numpy(), xr, rtol=1e-14, atol=1e-14)
     assert np.all(np.isfinite(x.cpu().numpy()))
+
+
+@pytest.mark.skip(reason="the matrix-free Krylov Newton step faulted the GPU on its first run; no cause has "
+                         "been found (a CPU emulation of the kernel with a 128-thread team and every workspace "
+                         "region bounds-checked under AddressSanitizer runs clean), so the path is switched off "
+                         "and context creation rejects it")
+@pytest.mark.parametrize("scene", ["robots", "tripods"])
+def test_krylov_newton_step_reaches_the_oracle_root(torch, scene):
+    """The matrix-free Newton step (linear_solver = 1: restarted GMRES with a Jacobi
+    preconditioner on the Schur system, products from the row blocks) changes the Newton path,
+    not the root: where both it and the oracle converge (tol 1e-12), states agree to the state
+    bar; the step adjoint, from the factor the tape takes at the returned iterate, matches the
+    oracle's exact one."""
+    from test_oracle_pins import tripod_world
+    P = scenes.solver_params(k_max=64, tol=1e-12, linear_solver=1, krylov_iters=16)
+    ctrl_at = lambda k: None
+    if scene == "robots":
+        b = scenes.robot_batch(8, seed=3)
+        ctrl_at = robot_ctrl(b)
+    else:
+        rng = np.random.default_rng(4)
+        b = scenes.pack([tripod_world(tuple(rng.uniform(-1.5, 1.5, 2)) + (0.0,), tuple(rng.normal(0, 0.5, 3)),
+                                      float(rng.uniform(-3, 3)), (0.0, 0.0)) for _ in range(8)])
+    sim = sim_for(b, P)
+    rng = np.random.default_rng(6)
+    q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    both = total = 0
+    for k in range(8):
+        c = ctrl_at(k)
+        ref = oracle.step_forward(b, P, q, u, lam, c)
+        tape = sim.new_tape()
+        o = sim.step_forward(q, u, lam, c, tape=tape)
+        got = {key: v.cpu().numpy() for key, v in o.items()}
+        assert np.array_equal(got["act_slot"], ref["act_slot"]), k
+        gqn, gun = rng.normal(size=q.shape), rng.normal(size=u.shape)
+        gq, gu, gc = (x.cpu().numpy() for x in sim.step_adjoint(q, u, c, o["u"], o["lam"], tape, gqn, gun))
+        rq, ru, rc = oracle.step_adjoint(b, P, q, u, lam, c, got["u"], got["lam"], gqn, gun, mode=0)
+        for w in range(b.n_worlds):
+            total += 1
+            if not (ref["status"][w] & 1 and got["status"][w] & 1):
+                continue
+            both += 1
+            s = slice(b.body_off[w], b.body_off[w + 1])
+            assert rel_err(got["u"][s], ref["u"][s]) <= STATE_TOL, (k, w, rel_err(got["u"][s], ref["u"][s]))
+            assert rel_err(got["q"][s], ref["q"][s]) <= STATE_TOL, (k, w)
+            g = np.concatenate([gq[s].ravel(), gu[s].ravel()])
+            r = np.concatenate([rq[s].ravel(), ru[s].ravel()])
+            assert np.linalg.norm(g - r) <= GRAD_TOL * np.linalg.norm(r), (k, w)
+        q, u, lam = ref["q"], ref["u"], ref["lam"]
+    assert both >= 0.75 * total, (both, total)
+
+
+def test_krylov_newton_step_is_rejected(torch):
+    """The switched-off Krylov Newton step fails loudly at context creation."""
+    from paper_2609_08800_amd import _capi
+    b = scenes.robot_batch(2, seed=3)
+    with pytest.raises(Exception, match="switched off"):
+        sim_for(b, scenes.solver_params(linear_solver=1))
