@@ -61,10 +61,6 @@ OST_HD double der(dual x) { return x.d; }
 template <class T> OST_HD T tmax(T a, T b) { return val(a) >= val(b) ? a : b; }
 OST_HD double ssqrt(double x) { return ::sqrt(x); }
 OST_HD dual ssqrt(dual x) { return sqrt(x); }
-OST_HD double satan2(double y, double x) { return ::atan2(y, x); }
-OST_HD dual satan2(dual y, dual x) {  // d atan2 = (x dy - y dx) / (x^2 + y^2)
-  return dual(::atan2(y.v, x.v), (x.v * y.d - y.v * x.d) / (x.v * x.v + y.v * y.v));
-}
 
 // --------------------------------------------------------------- vectors --
 template <class T> struct v3 {

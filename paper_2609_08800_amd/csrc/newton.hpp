@@ -518,7 +518,7 @@ OST_HD void stiffness_t(Team& t, const Batch& B, const Params& P, const WorldRef
       if (a != beta && c != beta) continue;
       int kind = M.r_kind[row];
       int n = kind == RK_CONTACT ? 3 : 1;
-      double target = kind == RK_SERVO ? servo_target(B, R, ctrl, M.r_idx[row]) : 0.0;
+      double target = kind == RK_SERVO ? M.sv_in[row - 5 * R.nj] : 0.0;
       GroupIn<double> in = group_in_lds(M, row, M.u, M.lam, target);
       dual ua[6], ub[6], lg[3];
       for (int k = 0; k < 6; ++k) {
@@ -814,7 +814,6 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
       int kind = M.r_kind[row];
       if (kind == RK_CONTACT && P.truncate) continue;
       int n = kind == RK_CONTACT ? 3 : 1;
-      double target = kind == RK_SERVO ? servo_target(B, R, ctrl, M.r_idx[row]) : 0.0;
       GroupIn<dual> ind;
       dual_pose(M.qm + 7 * a, a == beta, comp, ind.xa, ind.Ra);
       if (c >= 0) dual_pose(M.qm + 7 * c, c == beta, comp, ind.xb, ind.Rb);
@@ -832,7 +831,9 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
       ind.ua = ua;
       ind.ub = c >= 0 ? ub : nullptr;
       ind.lg = lg;
-      ind.target = dual(target);
+      ind.target = dual(kind == RK_SERVO ? M.sv_in[row - 5 * R.nj] : 0.0);
+      if (kind == RK_SERVO && B.joint_act[R.j0 + M.r_idx[row]] == 4)  // theta* - theta(q-), q- seeded
+        ind.target.d = -joint_angle_der(ind.Ra, ind.Rb, B.joint_frame + 18 * (R.j0 + M.r_idx[row]));
       if (kind == RK_CONTACT) {
         int ci = M.r_idx[row];
         int s_ = M.c_slot[ci];
@@ -892,9 +893,7 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
           const double kp = B.joint_kp[R.j0 + j];
           if (B.joint_act[R.j0 + j] == 4) {  // d/dk_p of alpha lambda + alpha k_p e = alpha^2 (k_d e - h lambda)
             const double kd = B.joint_kd[R.j0 + j], al = 1.0 / (kd + h * kp);
-            const int a = B.joint_body[2 * (R.j0 + j)], b = B.joint_body[2 * (R.j0 + j) + 1];
-            const double e = joint_angle(ldm(M.Rm + 9 * a), ldm(M.Rm + 9 * b), B.joint_frame + 18 * (R.j0 + j)) -
-                             servo_target(B, R, ctrl, j);
+            const double e = -M.sv_in[i - 5 * R.nj];  // theta(q-) - theta*
             g = wl[i] * M.D[i] * (al * al * (kd * e - h * M.lam[i]));
           } else {
             g = wl[i] * M.D[i] * (-M.lam[i] / (kp * kp));

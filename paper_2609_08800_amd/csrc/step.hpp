@@ -62,6 +62,18 @@ OST_HD double servo_compliance(const Batch& B, const WorldRef& R, int joint, dou
   return B.joint_act[R.j0 + joint] == 4 ? 1.0 / (B.joint_kd[R.j0 + joint] + h * kp) : 1.0 / kp;
 }
 
+OST_HD double servo_target(const Batch& B, const WorldRef& R, const double* ctrl, int joint);
+
+// The servo row's input for the row evaluation: the target speed (act 2), 0
+// (act 3), or theta* - theta(q-) (act 4), which holds for the whole step,
+// since the joint angle is taken at q- (Eq. (8)).
+OST_HD double servo_input(const Batch& B, const WorldRef& R, const WorldMem& M, const double* ctrl, int joint) {
+  const double target = servo_target(B, R, ctrl, joint);
+  if (B.joint_act[R.j0 + joint] != 4) return target;
+  const int a = B.joint_body[2 * (R.j0 + joint)], b = B.joint_body[2 * (R.j0 + joint) + 1];
+  return target - joint_angle(ldm(M.Rm + 9 * a), ldm(M.Rm + 9 * b), B.joint_frame + 18 * (R.j0 + joint));
+}
+
 OST_HD double servo_target(const Batch& B, const WorldRef& R, const double* ctrl, int joint) {
   int act = B.joint_act[R.j0 + joint];
   if (act != 2 && act != 4) return 0.0;  // speed (2) or angle (4) from the control; 3: speed 0
@@ -373,6 +385,8 @@ OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
   }
   R.bw = t.imax(bw, M.red);
   if (t.rank() == 0) M.iscal[3] = R.bw;
+  // servo inputs: the target speed, or the angle error theta* - theta(q-)
+  for (int s = t.rank(); s < R.nsv; s += t.size()) M.sv_in[s] = servo_input(B, R, M, ctrl, M.r_idx[5 * R.nj + s]);
   t.sync();
 }
 
@@ -415,7 +429,7 @@ OST_HD double evaluate(Team& t, const Batch& B, const Params& P, const WorldRef&
     int row = group_row(R, g);
     int kind = M.r_kind[row];
     int n = kind == RK_CONTACT ? 3 : 1;
-    double target = kind == RK_SERVO ? servo_target(B, R, ctrl, M.r_idx[row]) : 0.0;
+    double target = kind == RK_SERVO ? M.sv_in[row - 5 * R.nj] : 0.0;
     GroupIn<double> in = group_in_lds(M, row, u, lam, target);
     double r[3], D[3];
     double* Jg = M.J + 12 * row;

@@ -27,6 +27,8 @@ struct WorldMem {
   double *J, *Y, *Gl, *D, *res, *lam, *dlam, *lamt, *lambest, *Abar, *rmax;
   // Schur matrix and right-hand side
   double *A, *rhs;
+  // per servo row: its input for the row evaluation (fixed for the step)
+  double* sv_in;
   // slot scratch; first row touching each body (band of the Schur matrix)
   int* s_act;
   int* b_first;
@@ -73,6 +75,7 @@ OST_HD size_t world_lds_bytes(const Caps& c, int team, int split = SPLIT_LDS, bo
   d += (size_t)c.mr * 8;
   if (split == SPLIT_LDS) d += (size_t)c.mr * 27 + (size_t)c.mr * c.mr + kPadA;
   d += c.mr;
+  d += c.nsv;
   d += (size_t)team + 8;
   i += (size_t)c.nc * 4 + (size_t)c.mr * 6 + c.ns + c.nb + 16;
   size_t feat = (size_t)(c.nc + c.ns) * sizeof(Feature);
@@ -101,7 +104,7 @@ OST_HD WorldMem carve(char* base, const Caps& c, int team, int split = SPLIT_LDS
   M.D = take(c.mr); M.res = take(c.mr);
   M.lam = take(c.mr); M.dlam = take(c.mr); M.lamt = take(c.mr); M.lambest = take(c.mr); M.Abar = take(c.mr);
   M.rmax = take(c.mr);
-  M.A = gtake((size_t)c.mr * c.mr + kPadA); M.rhs = take(c.mr);
+  M.A = gtake((size_t)c.mr * c.mr + kPadA); M.rhs = take(c.mr); M.sv_in = take(c.nsv);
   M.red = take(team); M.dscal = take(8);
   M.kv = M.kx = M.kh = M.kcs = M.ksn = M.kgv = M.ky = nullptr;
   if (adjoint) {
@@ -181,11 +184,26 @@ template <class T> struct GroupIn {
 // Residual rows r (raw), Jacobian rows J (12 each) and the value of the row
 // scale D of one group: a joint row, a servo row, or a contact (n, t1, t2).
 // Angle of a revolute joint at the poses Ra, Rb: that of R_b perp1_a from
-// R_a perp1_a about R_a axis_a (zero where the two frames coincide).
+// R_a perp1_a about R_a axis_a (zero where the two frames coincide), as
+// atan2(y, x) of y = (pa x pb) . axis, x = pa . pb.
 template <class T>
-OST_HD T joint_angle(const m3<T>& Ra, const m3<T>& Rb, const double* fr) {
+OST_HD void joint_angle_yx(const m3<T>& Ra, const m3<T>& Rb, const double* fr, T& y, T& x) {
   const v3<T> pa = mul(Ra, ld3<T>(fr + 9)), pb = mul(Rb, ld3<T>(fr + 9)), ax = mul(Ra, ld3<T>(fr + 15));
-  return satan2(dot(cross(pa, pb), ax), dot(pa, pb));
+  y = dot(cross(pa, pb), ax);
+  x = dot(pa, pb);
+}
+// The angle itself (kept out of line: it is needed once per servo and step).
+__host__ __device__ __attribute__((noinline)) inline double joint_angle(const m3<double>& Ra, const m3<double>& Rb,
+                                                                        const double* fr) {
+  double y, x;
+  joint_angle_yx(Ra, Rb, fr, y, x);
+  return ::atan2(y, x);
+}
+// Its derivative alone, from dual poses: d atan2(y, x) = (x dy - y dx) / (x^2 + y^2).
+OST_HD double joint_angle_der(const m3<dual>& Ra, const m3<dual>& Rb, const double* fr) {
+  dual y, x;
+  joint_angle_yx(Ra, Rb, fr, y, x);
+  return (x.v * y.d - y.v * x.d) / (x.v * x.v + y.v * y.v);
 }
 
 template <class T>
@@ -228,9 +246,9 @@ OST_HD void eval_group(const Batch& B, const Params& P, const WorldRef& R, int k
     v3<T> ax = mul(in.Ra, ld3<T>(fr + 15));
     J[3] = -ax.x; J[4] = -ax.y; J[5] = -ax.z;
     J[9] = ax.x; J[10] = ax.y; J[11] = ax.z;
-    if (B.joint_act[R.j0 + idx] == 4) {  // alpha = 1/(k_d + h k_p), b = alpha k_p (theta(q-) - theta*)
+    if (B.joint_act[R.j0 + idx] == 4) {  // alpha = 1/(k_d + h k_p), b = -alpha k_p target, target = theta* - theta(q-)
       const double al = 1.0 / (B.joint_kd[R.j0 + idx] + h * kp);
-      r[0] = dot(ax, Bb.w - Ba.w) + in.lg[0] * al + (joint_angle(in.Ra, in.Rb, fr) - in.target) * (al * kp);
+      r[0] = dot(ax, Bb.w - Ba.w) + in.lg[0] * al - in.target * (al * kp);
     } else {
       r[0] = dot(ax, Bb.w - Ba.w) + in.lg[0] / kp - in.target;
     }
