@@ -55,6 +55,13 @@ OST_HD GroupIn<double> group_in_lds(const WorldMem& M, int row, const double* u,
   return in;
 }
 
+// Compliance alpha of a servo row (Eq. (8)): 1/k_p for a speed target,
+// 1/(k_d + h k_p) for an angle target.
+OST_HD double servo_compliance(const Batch& B, const WorldRef& R, int joint, double h) {
+  const double kp = B.joint_kp[R.j0 + joint];
+  return B.joint_act[R.j0 + joint] == 4 ? 1.0 / (B.joint_kd[R.j0 + joint] + h * kp) : 1.0 / kp;
+}
+
 OST_HD double servo_target(const Batch& B, const WorldRef& R, const double* ctrl, int joint);
 
 // The servo row's input for the row evaluation: the target speed (act 2), 0
@@ -81,12 +88,9 @@ OST_HD void eval_row_group(const Batch& B, const Params& P, const WorldRef& R, c
                            const GroupIn<T>& in, T* r, T* J, double* D) {
   int kind = M.r_kind[row];
   int c = kind == RK_CONTACT ? M.r_idx[row] : 0;
-  const int s = kind == RK_SERVO ? row - 5 * R.nj : 0;  // servo rows: alpha and beta in the FB scales' places
   eval_group<T>(B, P, R, kind, M.r_idx[row], M.r_sub[row], M.r_b[row] >= 0, kind == RK_CONTACT ? M.c_r[c] : 0.0,
-                kind == RK_CONTACT ? M.c_mu[c] : 0.0,
-                kind == RK_CONTACT ? M.c_sn[c] : (kind == RK_SERVO ? M.sv_al[s] : 1.0),
-                kind == RK_CONTACT ? M.c_sf[c] : (kind == RK_SERVO ? M.sv_be[s] : 1.0),
-                kind == RK_CONTACT ? M.c_kind[c] : 0, in, r, J, D);
+                kind == RK_CONTACT ? M.c_mu[c] : 0.0, kind == RK_CONTACT ? M.c_sn[c] : 1.0,
+                kind == RK_CONTACT ? M.c_sf[c] : 1.0, kind == RK_CONTACT ? M.c_kind[c] : 0, in, r, J, D);
 }
 
 // --------------------------------------------------------------------------
@@ -381,18 +385,8 @@ OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
   }
   R.bw = t.imax(bw, M.red);
   if (t.rank() == 0) M.iscal[3] = R.bw;
-  // servo rows (Eq. (8)): input (the target speed, or the angle error
-  // theta* - theta(q-)), compliance alpha = 1/k_p for a speed target and
-  // 1/(k_d + h k_p) for an angle target, input weight 1 or alpha k_p
-  for (int s = t.rank(); s < R.nsv; s += t.size()) {
-    const int j = M.r_idx[5 * R.nj + s];
-    const double kp = B.joint_kp[R.j0 + j];
-    const bool pos = B.joint_act[R.j0 + j] == 4;
-    const double al = pos ? 1.0 / (B.joint_kd[R.j0 + j] + P.h * kp) : 1.0 / kp;
-    M.sv_in[s] = servo_input(B, R, M, ctrl, j);
-    M.sv_al[s] = al;
-    M.sv_be[s] = pos ? al * kp : 1.0;
-  }
+  // servo inputs: the target speed, or the angle error theta* - theta(q-)
+  for (int s = t.rank(); s < R.nsv; s += t.size()) M.sv_in[s] = servo_input(B, R, M, ctrl, M.r_idx[5 * R.nj + s]);
   t.sync();
 }
 
@@ -453,7 +447,7 @@ OST_HD double evaluate(Team& t, const Batch& B, const Params& P, const WorldRef&
       contact_G(P, in, b >= 0, M.c_r[c], M.c_mu[c], M.c_sn[c], M.c_sf[c], M.c_kind[c], Jg, D, Gu, Gl);
     } else {  // joint rows: D r = c(q(u)) / h, so D dr/du = J; servo rows: dr/du = J, dr/dlambda = alpha
       for (int q = 0; q < 12; ++q) Gu[q] = Jg[q];
-      Gl[0] = kind == RK_SERVO ? M.sv_al[row - 5 * R.nj] : 0.0;
+      Gl[0] = kind == RK_SERVO ? servo_compliance(B, R, M.r_idx[row], P.h) : 0.0;
     }
     #pragma unroll
     for (int k = 0; k < 3; ++k) if (k < n) {

@@ -27,9 +27,8 @@ struct WorldMem {
   double *J, *Y, *Gl, *D, *res, *lam, *dlam, *lamt, *lambest, *Abar, *rmax;
   // Schur matrix and right-hand side
   double *A, *rhs;
-  // per servo row, fixed for the step: its input (target speed or angle
-  // error), compliance alpha and input weight beta: r = J u + alpha lambda - beta input
-  double *sv_in, *sv_al, *sv_be;
+  // per servo row: its input for the row evaluation (fixed for the step)
+  double* sv_in;
   // slot scratch; first row touching each body (band of the Schur matrix)
   int* s_act;
   int* b_first;
@@ -76,7 +75,7 @@ OST_HD size_t world_lds_bytes(const Caps& c, int team, int split = SPLIT_LDS, bo
   d += (size_t)c.mr * 8;
   if (split == SPLIT_LDS) d += (size_t)c.mr * 27 + (size_t)c.mr * c.mr + kPadA;
   d += c.mr;
-  d += 3 * (size_t)c.nsv;
+  d += c.nsv;
   d += (size_t)team + 8;
   i += (size_t)c.nc * 4 + (size_t)c.mr * 6 + c.ns + c.nb + 16;
   size_t feat = (size_t)(c.nc + c.ns) * sizeof(Feature);
@@ -105,8 +104,7 @@ OST_HD WorldMem carve(char* base, const Caps& c, int team, int split = SPLIT_LDS
   M.D = take(c.mr); M.res = take(c.mr);
   M.lam = take(c.mr); M.dlam = take(c.mr); M.lamt = take(c.mr); M.lambest = take(c.mr); M.Abar = take(c.mr);
   M.rmax = take(c.mr);
-  M.A = gtake((size_t)c.mr * c.mr + kPadA); M.rhs = take(c.mr);
-  M.sv_in = take(c.nsv); M.sv_al = take(c.nsv); M.sv_be = take(c.nsv);
+  M.A = gtake((size_t)c.mr * c.mr + kPadA); M.rhs = take(c.mr); M.sv_in = take(c.nsv);
   M.red = take(team); M.dscal = take(8);
   M.kv = M.kx = M.kh = M.kcs = M.ksn = M.kgv = M.ky = nullptr;
   if (adjoint) {
@@ -242,12 +240,18 @@ OST_HD void eval_group(const Batch& B, const Params& P, const WorldRef& R, int k
     D[0] = 1.0 / h;
     return;
   }
-  if (kind == RK_SERVO) {  // Eq. (8): r = J_c u + alpha lambda - beta input, alpha = sn, beta = sf
+  if (kind == RK_SERVO) {  // Eq. (8): velocity target (alpha = 1/k_p, b = -u_bar) or position target
     const double* fr = B.joint_frame + 18 * (R.j0 + idx);
+    double kp = B.joint_kp[R.j0 + idx];
     v3<T> ax = mul(in.Ra, ld3<T>(fr + 15));
     J[3] = -ax.x; J[4] = -ax.y; J[5] = -ax.z;
     J[9] = ax.x; J[10] = ax.y; J[11] = ax.z;
-    r[0] = dot(ax, Bb.w - Ba.w) + in.lg[0] * sn - in.target * sf;
+    if (B.joint_act[R.j0 + idx] == 4) {  // alpha = 1/(k_d + h k_p), b = -alpha k_p target, target = theta* - theta(q-)
+      const double al = 1.0 / (B.joint_kd[R.j0 + idx] + h * kp);
+      r[0] = dot(ax, Bb.w - Ba.w) + in.lg[0] * al - in.target * (al * kp);
+    } else {
+      r[0] = dot(ax, Bb.w - Ba.w) + in.lg[0] / kp - in.target;
+    }
     D[0] = 1.0;
     return;
   }
