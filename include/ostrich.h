@@ -102,7 +102,7 @@ typedef struct {
   int32_t refine;      /* most Krylov operator applications of the adjoint (0: factor only) */
   int32_t team;        /* threads per world (64, 128 or 256; 0 = 128) before autotuning */
   int32_t schedule;    /* OSTRICH_SCHED_FIXED or OSTRICH_SCHED_BUCKETED */
-  int32_t truncate;    /* 1: the adjoint holds the contact geometry fixed within the step, so no
+  int32_t truncate;    /* 1: the adjoint treats the contact geometry as a constant of the step, so no
                           derivative with respect to q- passes through a contact row or its force
                           (the truncated position pull-back of the terrain task, Sec. V); 0: the
                           complete pull-back of Eq. (17) */
@@ -275,11 +275,12 @@ int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0, const dou
                     double* g_q0, double* g_u0, double* g_knots, void* workspace, size_t workspace_bytes,
                     int32_t* status_or, void* stream);
 
-/* Shaped loss of the optimisation workloads (Sec. IV-B: final position and
- * heading, a terminal-velocity penalty, control regularisers and a per-step
- * straight-line tracking term; Sec. V: position tracking, yaw alignment and
- * control regularisation against a reference trajectory).  The paper names the
- * terms but not their forms; per world w, with p_k the xy, psi_k the yaw (the
+/* Shaped loss of the optimisation workloads (Sec. IV-B: errors of the final
+ * position and heading, the speed at the end, the size of the controls, and
+ * the distance from a straight path at every step; Sec. V: the distance from
+ * and the yaw difference to a reference trajectory at every step, and the size
+ * of the controls).  The paper lists the terms without their forms; per world
+ * w, with p_k the xy, psi_k the yaw (the
  * heading of the body x axis in the ground plane) and v_k the linear velocity
  * of the loss body in state k, a_k the controls of step k, and (r_k, rho_k) the
  * reference of step k:

@@ -577,7 +577,7 @@ def solver_params(**over) -> dict:
     ls_max: step halvings of the residual-decrease step length (0: full steps);
     refine: most operator applications of the adjoint's Krylov solve of the
     exact implicit-function Jacobian (0: the stored factor's solve alone);
-    truncate: 1 holds the contact geometry fixed within each step in the
+    truncate: 1 treats the contact geometry as a constant of each step in the
     adjoint's q- pull-back (the truncated pull-back of long terrain horizons);
     linear_solver: the Newton step's solve, 0 the banded LU of the Schur matrix, 1 a
     matrix-free Krylov solve of at most krylov_iters products (the oracle always

@@ -588,7 +588,7 @@ def test_parameter_gradients_match_finite_differences():
 
 
 def test_truncated_pull_back_closed_form():
-    """The truncated position pull-back (contact geometry held fixed within the step, the
+    """The truncated position pull-back (contact geometry a constant of the step, the
     terrain task of Sec. V) on a tripod at rest.  With the complete pull-back the three
     contacts pin the height, z+ = sz/2 whatever z- is, so dz+/dz- = 0; with the contact
     geometry held fixed no derivative with respect to q- passes through a contact, and the
@@ -764,7 +764,7 @@ def test_position_servo_closed_form():
     relative rate obeys I_eff (theta_dot+ - theta_dot-) = h lambda, i.e.
     theta_dot+ = (I_eff theta_dot- + h k_p (theta* - theta-)) / (I_eff + h k_d + h^2 k_p);
     each body turns about z by its own Cayley angle 2 atan(h w / 2).  Five steps, for
-    k_d = 0 (where b_c is the joint error divided by h) and k_d > 0."""
+    k_d = 0 (where b_c is the joint error at q- over the step length) and k_d > 0."""
     for kp, kd in ((3.0, 0.0), (2.0, 0.05)):
         th0, target = 0.4, -0.3
         b = scenes.pack([_hinge_z_world(th0, 1.5, kp, kd)])
