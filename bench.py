@@ -187,11 +187,12 @@ def uneven_measurement(n_stacks=2048, n_robots=2048, T=50, ckpt=10, seed=0):
     return res
 
 
-# Weights of the shaped loss, and the learning rate and servo gain of the control-synthesis
-# task, chosen by a small sweep (lr 0.3 / 1 / 3, gain 0.5 / 2, five weight sets).  The knots
-# are wheel speeds of 0.1 m wheels; the paper's lr 0.3 for 0.35 m wheels scales to about 1.
+# Weights of the shaped loss, and the learning rate, servo gain and initial guess of the
+# control-synthesis task, chosen by small sweeps (lr 0.3 / 0.5 / 0.7 / 1 / 2 / 3, gain 0.5 / 2,
+# several weight sets, knots from zero or from the nominal straight drive).  The knots are wheel
+# speeds of 0.1 m wheels.
 SHAPED_WEIGHTS = dict(w_pos=4.0, w_head=0.2, w_vel=4.0, w_ctrl=1e-3, w_track=0.05, w_yaw=0.0)
-SYNTHESIS_LR = 1.0
+SYNTHESIS_LR = 0.5
 SYNTHESIS_SERVO_KP = 2.0
 
 
@@ -234,8 +235,10 @@ def shaped_measurement(sim, q0, u0, knots, basis, T, batch, ckpt):
 def control_synthesis_measurement(trials=25, iters=50, lr=SYNTHESIS_LR, T=60, K=10, seed=0,
                                   servo_kp=SYNTHESIS_SERVO_KP, weights=None):
     """The control-synthesis task of Sec. IV-B on the robot over a pallet: open-loop
-    wheel-velocity splines (K knots per wheel, velocity servos) from zero, the shaped loss
-    towards a random goal at x = 3 m, 50 Adam iterations; per trial the iterate of least loss,
+    wheel-velocity splines (K knots per wheel, velocity servos) starting from the nominal
+    straight drive (every wheel at the speed that covers the distance to the goal in the
+    horizon), the shaped loss towards a random goal at x = 3 m, 50 Adam iterations; per
+    trial the iterate of least loss,
     success when its final position error is below 0.2 m and its terminal speed below
     0.3 m/s.  All trials run as one batch."""
     import torch
@@ -256,7 +259,11 @@ def control_synthesis_measurement(trials=25, iters=50, lr=SYNTHESIS_LR, T=60, K=
     lb = b.body_off[:-1] + b.loss_body
     ref = straight_line_ref(q0[lb, :2], goal, T)
     basis = torch.as_tensor(spline_basis(T, K, P["h"]), device=dev)
-    x = torch.zeros(sim.NCTRL, K, dtype=torch.float64, device=dev)
+    nominal = (goal[:, 0] - q0[lb, 0]) / (T * P["h"]) / scenes.WHEEL_R  # rad/s, per trial
+    x0 = np.zeros((sim.NCTRL, K))
+    for w in range(trials):
+        x0[b.ctrl_off[w]:b.ctrl_off[w + 1]] = nominal[w]
+    x = torch.as_tensor(x0, device=dev)
     m, v = torch.zeros_like(x), torch.zeros_like(x)
     ws = sim.new_workspace(T, 10)
     best = np.full(trials, np.inf)
