@@ -351,8 +351,8 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8}))
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU kernel "
-              "(worlds are independent; multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: it measures one GPU's share of worlds "
+              "(worlds are independent, so N GPUs would each run 1/N of the batch)", file=sys.stderr)
         sys.exit(2)
 
     import torch
