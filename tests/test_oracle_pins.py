@@ -165,6 +165,73 @@ def test_drop_and_inelastic_impact():
         assert abs(o["q"][0, 2] - 0.1) < 1e-9
 
 
+def _translation_cases(d, vm, g, mu, m, h):
+    """The three linear cases of one backward-Euler step of a translating body whose
+    contacts share the ground normal (open, or closed and sticking or sliding), each
+    solved on its own with its consistency test.  Returns [(consistent, v+, N, F_t)]."""
+    wt = vm[:2] + h * g[:2]                       # tangential speed without friction
+    cases = []
+    vz = vm[2] + h * g[2]                         # open: no force at all
+    cases.append((d + h * vz >= 0.0, np.array([wt[0], wt[1], vz]), 0.0, np.zeros(2)))
+    vz = -d / h                                   # closed: the gap at q+ is zero
+    N = m * (vz - vm[2] - h * g[2]) / h
+    Ft = -m * wt / h                              # stick: v_t+ = 0
+    cases.append((N >= 0.0 and np.linalg.norm(Ft) <= mu * N, np.array([0.0, 0.0, vz]), N, Ft))
+    nw = np.linalg.norm(wt)                       # slide: F_t = -mu N v_t+/|v_t+|
+    shrink = 1.0 - mu * N * h / (m * nw) if nw > 0 else -1.0
+    Fs = -mu * N * wt / nw if nw > 0 else np.zeros(2)
+    cases.append((N >= 0.0 and shrink > 0.0, np.array([wt[0] * shrink, wt[1] * shrink, vz]), N, Fs))
+    return cases
+
+
+def test_translating_box_matches_the_one_consistent_linear_case():
+    """Brute force over open/closed x stick/slide (Sec. III-A/B): for a flat, non-spinning
+    box whose four corners share the ground normal, each combination is a linear problem
+    with a closed-form solution; exactly one of them is consistent, and the converged step
+    is that one (net contact force and velocity; the per-corner split is indeterminate)."""
+    rng = np.random.default_rng(11)
+    h, m = 0.1, 1.0
+    checked = {"open": 0, "stick": 0, "slide": 0}
+    for gt in ((0.0, 0.0), (2.5, -1.0), (-4.0, 3.0)):
+        g = np.array([gt[0], gt[1], -G])
+        worlds, draws = [], []
+        while len(worlds) < 16:
+            d = rng.uniform(0.0, 0.015)           # within the activation margin: all 4 slots active
+            vm = np.array([rng.uniform(-2, 2), rng.uniform(-2, 2), rng.uniform(-1.0, 1.5)])
+            if rng.uniform() < 0.3:
+                vm[:2] *= 0.02                    # slow enough to stick
+            mu = rng.uniform(0.2, 1.0)
+            cases = _translation_cases(d, vm, g, mu, m, h)
+            N = cases[1][2]
+            margins = [abs(d + h * (vm[2] + h * g[2])),
+                       abs(np.linalg.norm(vm[:2] + h * g[:2]) * m / h - mu * N)]
+            if min(margins) < 1e-4:
+                continue                          # too close to a case boundary to decide
+            worlds.append(scenes.box_world(None, yaw=rng.uniform(-math.pi, math.pi), z=0.1 + d,
+                                           v=tuple(vm), mu=mu))
+            draws.append(cases)
+        b = scenes.pack(worlds)
+        # sticking impacts on the four (statically indeterminate) corners approach 1e-12
+        # slowly: a budget of 200 iterations lets every world reach it
+        P = scenes.solver_params(gravity=tuple(g), k_max=200, tol=1e-12)
+        o = run(b, P, 1)[0]
+        for w, cases in enumerate(draws):
+            ok = [c for c in cases if c[0]]
+            assert len(ok) == 1, (w, [c[0] for c in cases])
+            _, v, N, Ft = ok[0]
+            name = ("open", "stick", "slide")[[c[0] for c in cases].index(True)]
+            checked[name] += 1
+            assert o["status"][w] & 1, w
+            np.testing.assert_allclose(o["u"][w, :3], v, rtol=0, atol=1e-8, err_msg=name)
+            np.testing.assert_allclose(o["u"][w, 3:], 0.0, atol=1e-8, err_msg=name)
+            lam = contact_lams(b, w, o["lam"])
+            # tangent basis of the ground normal: t1 = e_y, t2 = -e_x
+            F = np.array([-lam[:, 2].sum(), lam[:, 1].sum()])
+            assert abs(lam[:, 0].sum() - N) < 1e-7 * max(1.0, N), (name, lam[:, 0].sum(), N)
+            np.testing.assert_allclose(F, Ft, rtol=0, atol=1e-7 * max(1.0, N), err_msg=name)
+    assert min(checked.values()) >= 3, checked
+
+
 def test_servo_two_body_closed_form():
     """Velocity servo (Eq. (8), alpha = 1/k_p): lambda = k_p (u_bar - w_rel-) / (1 + h k_p / I_eff)."""
     wd = scenes.World(contact_cap=0)
