@@ -479,6 +479,30 @@ def test_box_gradient_matches_finite_differences():
     _fd_check(b, P, 3, "u0")
 
 
+def test_paper_mode_gradient_deviation_is_reported():
+    """The lagged adjoint (Eq. (18): the stored Newton matrix with W frozen, no velocity
+    stiffness of J^T lambda) is a different linearisation from the one finite differences
+    measure, so its deviation is printed rather than bounded; the exact adjoint on the
+    same rollout stays within 1e-5."""
+    b = scenes.pack([tripod_world((0.9, 0.4, 0), (0.05, -0.05, 1.2), 0.2, (0.3, -0.2))])
+    P = scenes.solver_params(k_max=64, tol=1e-12)
+    exact = oracle.rollout(b, P, b.q0, b.u0, None, 3, mode=0)["g_u0"][0]
+    lagged = oracle.rollout(b, P, b.q0, b.u0, None, 3, mode=1)["g_u0"][0]
+    fd = np.zeros(6)
+    for i in range(6):
+        d = 1e-6 * max(1.0, abs(b.u0[0, i]))
+        up, um = b.u0.copy(), b.u0.copy()
+        up[0, i] += d
+        um[0, i] -= d
+        fd[i] = (oracle.rollout(b, P, b.q0, up, None, 3, grad=False)["loss"][0]
+                 - oracle.rollout(b, P, b.q0, um, None, 3, grad=False)["loss"][0]) / (2 * d)
+    dev_exact = np.linalg.norm(exact - fd) / np.linalg.norm(fd)
+    dev_lagged = np.linalg.norm(lagged - fd) / np.linalg.norm(fd)
+    print(f"tripod, 3 steps: exact adjoint {dev_exact:.2e}, lagged adjoint {dev_lagged:.2e} from central differences")
+    assert dev_exact <= 1e-5
+    assert np.all(np.isfinite(lagged))
+
+
 def test_four_corner_box_in_plane_gradient():
     """Four coplanar corners leave the normal-force split statically indeterminate: the
     converged state depends on the regularised Newton path at the 1e-4 level, so the
