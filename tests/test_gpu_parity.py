@@ -38,6 +38,48 @@ def rel_err(a, b):
     return np.max(np.abs(a - b) / np.maximum(1.0, np.abs(b))) if a.size else 0.0
 
 
+def _rot(qw):
+    x, y, z, w = np.asarray(qw, dtype=float) / np.linalg.norm(qw)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def plane_activation(b, P, q, u, w, s):
+    """gap + h min(v_n, 0) at q- of a ground-plane slot (local index s of world w), the
+    quantity the activation test compares with delta0; None for other slot kinds."""
+    gs = b.slot_off[w] + s
+    if b.slot_int[gs, 0] != scenes.SLOT_PLANE:
+        return None
+    a = b.body_off[w] + b.slot_int[gs, 1]
+    arm = _rot(q[a, 3:7]) @ b.slot_real[gs, :3]
+    vz = u[a, 2] + np.cross(u[a, 3:], arm)[2]
+    return q[a, 2] + arm[2] - b.slot_real[gs, 3] + P["h"] * min(vz, 0.0)
+
+
+def assert_same_active(b, P, q, u, got, ref, tag):
+    """Active slot lists bit for bit; on a mismatch, every slot chosen by one side only is
+    listed with its activation value against delta0 (ground-plane slots)."""
+    if np.array_equal(got["act_slot"], ref["act_slot"]) and np.array_equal(got["n_act"], ref["n_act"]):
+        return
+    lines = []
+    for w in range(b.n_worlds):
+        s0 = b.slot_off[w]
+        g = got["act_slot"][s0:s0 + got["n_act"][w]].tolist()
+        r = ref["act_slot"][s0:s0 + ref["n_act"][w]].tolist()
+        if g == r:
+            continue
+        for s in sorted(set(g) ^ set(r)):
+            a = plane_activation(b, P, q, u, w, s)
+            who = "GPU" if s in g else "oracle"
+            what = ("activation %.6e against delta0 %.6e" % (a, P["delta0"]) if a is not None
+                    else "slot kind %d" % b.slot_int[s0 + s, 0])
+            lines.append(f"world {w} slot {s}: {who} only, {what}")
+        if set(g) == set(r):
+            lines.append(f"world {w}: same slots in another order {g} / {r}")
+    raise AssertionError(f"{tag}: active slot lists differ\n" + "\n".join(lines))
+
+
 def check_states(b, got, ref, tol=STATE_TOL):
     """Worlds the oracle converged: states within tol.  Worlds that ran out of
     budget return their best iterate of a non-converging sequence, which
@@ -80,7 +122,7 @@ def test_position_servo_robot_steps_teacher_forced(torch):
         c = np.full(b.n_ctrl, 0.2 * (k + 1))
         ref = oracle.step_forward(b, P, q, u, lam, c)
         got = gpu_step(sim, q, u, lam, c)
-        assert np.array_equal(got["act_slot"], ref["act_slot"]), k
+        assert_same_active(b, P, q, u, got, ref, k)
         check_states(b, got, ref)
         q, u, lam = ref["q"], ref["u"], ref["lam"]
 
@@ -105,7 +147,7 @@ def test_robot_steps_teacher_forced(torch, team):
         ref = oracle.step_forward(b, P, q, u, lam, c)
         got = gpu_step(sim, q, u, lam, c)
         print("step", k, "status", ref["status"], flush=True)
-        assert np.array_equal(got["act_slot"], ref["act_slot"]), k
+        assert_same_active(b, P, q, u, got, ref, k)
         assert np.array_equal(got["n_act"], ref["n_act"]), k
         check_states(b, got, ref)
         q, u, lam = ref["q"], ref["u"], ref["lam"]
@@ -122,7 +164,7 @@ def test_box_steps_teacher_forced(torch):
     for k in range(8):
         ref = oracle.step_forward(b, P, q, u, lam, None)
         got = gpu_step(sim, q, u, lam, None)
-        assert np.array_equal(got["act_slot"], ref["act_slot"])
+        assert_same_active(b, P, q, u, got, ref, "step")
         assert np.array_equal(got["status"], ref["status"])
         for w in range(b.n_worlds):
             if not ref["status"][w] & 1:
@@ -153,7 +195,7 @@ def test_determinate_box_steps(torch):
     for k in range(6):
         ref = oracle.step_forward(b, P, q, u, lam, None)
         got = gpu_step(sim, q, u, lam, None)
-        assert np.array_equal(got["act_slot"], ref["act_slot"])
+        assert_same_active(b, P, q, u, got, ref, "step")
         check_states(b, got, ref)
         q, u, lam = ref["q"], ref["u"], ref["lam"]
 
@@ -476,7 +518,7 @@ def test_krylov_newton_step_reaches_the_oracle_root(torch, scene):
         tape = sim.new_tape()
         o = sim.step_forward(q, u, lam, c, tape=tape)
         got = {key: v.cpu().numpy() for key, v in o.items()}
-        assert np.array_equal(got["act_slot"], ref["act_slot"]), k
+        assert_same_active(b, P, q, u, got, ref, k)
         gqn, gun = rng.normal(size=q.shape), rng.normal(size=u.shape)
         gq, gu, gc = (x.cpu().numpy() for x in sim.step_adjoint(q, u, c, o["u"], o["lam"], tape, gqn, gun))
         rq, ru, rc = oracle.step_adjoint(b, P, q, u, lam, c, got["u"], got["lam"], gqn, gun, mode=0)
