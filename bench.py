@@ -292,7 +292,25 @@ def control_synthesis_measurement(trials=25, iters=50, lr=SYNTHESIS_LR, T=60, K=
             "servo_kp": servo_kp, "weights": wts}
 
 
-def serving_measurement(rate, duration, drain, seed=0, capacity=4096, budget_gb=96.0, hmap_slots=64):
+class _LazyRequestWorlds:
+    """A request's packed worlds, built when first read.  Admission only ever looks at
+    the head of the queue, so at high arrival rates the requests that never reach it
+    within the window are never built; the seed, and so the worlds, are the same."""
+
+    def __init__(self, seed, n_worlds):
+        self.n_worlds = n_worlds
+        self._seed = seed
+        self._b = None
+
+    def __getattr__(self, name):
+        if self._b is None:
+            import scenes
+            self._b = scenes.terrain_request_batch(self._seed, self.n_worlds)
+        return getattr(self._b, name)
+
+
+def serving_measurement(rate, duration, drain, seed=0, capacity=4096, budget_gb=96.0, hmap_slots=64,
+                        prebuilt=256):
     """Poisson arrivals of trajectory-optimisation requests (robots on their
     own value-noise terrain, 1..256 worlds, T in 20..100, 10 iterations of
     forward + adjoint + Adam) served with continuous batching; per-iteration
@@ -305,8 +323,13 @@ def serving_measurement(rate, duration, drain, seed=0, capacity=4096, budget_gb=
     be = GpuBackend(tmpl, capacity, P, scenes.ROBOT_KNOTS, heightmaps=[base], heightmap_slots=hmap_slots)
     rng = np.random.default_rng(seed)
     arrivals = poisson_arrivals(rate, duration, seed)
-    reqs = [Request(i, scenes.terrain_request_batch(1000 * seed + i, int(rng.integers(1, 257))),
-                    T=int(rng.integers(20, 101)), iters=10, lr=0.1, arrival=t) for i, t in enumerate(arrivals)]
+    reqs = []
+    for i, t in enumerate(arrivals):
+        n = int(rng.integers(1, 257))
+        # the first requests are built before the clock starts; later ones when they reach the queue's head
+        worlds = (scenes.terrain_request_batch(1000 * seed + i, n) if i < prebuilt
+                  else _LazyRequestWorlds(1000 * seed + i, n))
+        reqs.append(Request(i, worlds, T=int(rng.integers(20, 101)), iters=10, lr=0.1, arrival=t))
     eng = ServingEngine(be, budget_gb * 1e9)
     out = eng.run(reqs, deadline=duration + drain)
     lat = [x for r in out["requests"] + [r for r in out["unfinished"] if r.slot0 >= 0] for x in r.iter_latency]
