@@ -102,3 +102,23 @@ def test_deadline_reports_unfinished_and_frees_memory():
     assert len(out["unfinished"]) == 3 - len(out["requests"])
     assert out["unfinished"] and eng.used == 0.0 and eng.slots.n_free == 8
     assert out["iterations"] >= 1
+
+
+def test_lazy_request_worlds_are_built_once_and_only_when_read():
+    """The benchmark's deferred request worlds: the world count is known without building
+    them, the engine itself reads nothing else (only a backend's admission builds them),
+    and the worlds built are those of the same seed, built once."""
+    import bench
+    import scenes
+    lazy = [bench._LazyRequestWorlds(100 + i, 2) for i in range(6)]
+    reqs = [Request(i, w, T=3, iters=1, arrival=0.0) for i, w in enumerate(lazy)]
+    be = FakeBackend(4, tick_seconds=0.01)
+    eng = ServingEngine(be, 1e12, clock=be.clock)
+    out = eng.run(reqs)                     # the fake backend reads only the world count
+    assert len(out["requests"]) == 6 and all(w._b is None for w in lazy)
+    eager = scenes.terrain_request_batch(101, 2)
+    assert lazy[1].n_worlds == 2 and lazy[1]._b is None
+    assert np.array_equal(lazy[1].q0, eager.q0) and np.array_equal(lazy[1].hmap_heights, eager.hmap_heights)
+    built = lazy[1]._b
+    _ = lazy[1].u0
+    assert lazy[1]._b is built
