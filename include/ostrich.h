@@ -262,7 +262,9 @@ int ostrich_step_adjoint_plain(ostrich_ctx* ctx, const double* q_prev, const dou
  * and the adjoint of Sec. III-D over all steps) with controls from a spline
  * basis (ctrl_k = basis[k,:] . knots[c,:], basis [T*K] device, knots
  * [NCTRL*K]) and the loss |xy(loss_body) - target|^2 at step T (loss_body [W]
- * int32, target [W*2]).
+ * int32 device, loss_body[w] a body index of world w in [0, its body count):
+ * read on the device and not checked by the library, so the caller checks it;
+ * target [W*2]).
  * FORWARD writes loss [W], qT, uT and checkpoints into the workspace;
  * BACKWARD (after a FORWARD with the same arguments and workspace) recomputes
  * each segment from its checkpoint and runs the adjoint steps in reverse,

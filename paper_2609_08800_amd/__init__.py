@@ -88,6 +88,7 @@ class Simulator:
             self._dev[k] = t
             ptrs[k] = t.data_ptr()
         self.body_off = self._dev["body_off"]
+        self._bodies = np.diff(np.asarray(batch.body_off, dtype=np.int64))
         self._cb = _capi.make_batch(self.W, ptrs, int(batch.hmap_n), float(batch.hmap_spacing))
         if schedule not in ("fixed", "bucketed"):
             raise OstrichError("schedule must be 'fixed' or 'bucketed'")
@@ -132,7 +133,7 @@ class Simulator:
     def autotune(self, q, u, lam=None, ctrl=None, reps: int = 2, stream=None):
         """Pick each bucket's launch by timing forward steps from (q, u, lam, ctrl)."""
         q, u = self._f64(q, (self.NB, 7)), self._f64(u, (self.NB, 6))
-        lam = self._f64(lam) if lam is not None else self.torch.zeros(max(self.NL, 1), dtype=self.torch.float64,
+        lam = self._lam(lam) if lam is not None else self.torch.zeros(max(self.NL, 1), dtype=self.torch.float64,
                                                                       device=self.device)
         ctrl = self._ctrl(ctrl)
         _capi.check(self.lib.ostrich_autotune(self.ctx, q.data_ptr(), u.data_ptr(), lam.data_ptr(),
@@ -168,7 +169,60 @@ class Simulator:
                 torch.empty(max(self.NL, 1), dtype=torch.float64, device=self.device))
 
     def new_tape(self):
-        return self.torch.empty(self.tape_bytes // 8, dtype=self.torch.float64, device=self.device)
+        return self.torch.empty((self.tape_bytes + 7) // 8, dtype=self.torch.float64, device=self.device)
+
+    def _lam(self, lam):
+        """Multipliers in slot layout [NL] (a one-entry placeholder when NL is 0)."""
+        if self.NL == 0:
+            return self.torch.zeros(1, dtype=self.torch.float64, device=self.device)
+        return self._f64(lam, (self.NL,))
+
+    def _tape(self, tape):
+        """A tape must be a float64 device tensor of at least ostrich_tape_bytes."""
+        if tape is None:
+            return None
+        t = self.torch
+        if (not t.is_tensor(tape) or tape.dtype != t.float64 or tape.device != self.device
+                or not tape.is_contiguous() or tape.numel() * 8 < self.tape_bytes):
+            raise OstrichError("tape must be a contiguous float64 tensor on %s of at least %d bytes (new_tape())"
+                               % (self.device, self.tape_bytes))
+        return tape
+
+    def check_loss_body(self, lb):
+        """Host check of a loss-body array: one entry per world, each a body of that world."""
+        lb = np.asarray(lb)
+        if lb.shape != (self.W,):
+            raise OstrichError("loss_body must have one entry per world (%d), got shape %s" % (self.W, lb.shape))
+        if np.any(lb < 0) or np.any(lb >= self._bodies):
+            w = int(np.argmax((lb < 0) | (lb >= self._bodies)))
+            raise OstrichError("loss_body[%d] = %d is not a body of world %d (%d bodies)"
+                               % (w, int(lb[w]), w, int(self._bodies[w])))
+        return lb.astype(np.int32)
+
+    def _loss_body(self, loss_body):
+        """Device int32 [W].  Host arrays are checked value by value; a device tensor only by
+        shape (reading it back would synchronise, which graph capture forbids)."""
+        torch = self.torch
+        if loss_body is None:
+            raise OstrichError("loss_body is required: the loss body of every world")
+        if torch.is_tensor(loss_body):
+            if loss_body.shape != (self.W,):
+                raise OstrichError("loss_body must have shape (%d,)" % self.W)
+            return loss_body.to(self.device, torch.int32).contiguous()
+        return torch.as_tensor(self.check_loss_body(loss_body), device=self.device).contiguous()
+
+    def _check_out(self, out):
+        torch = self.torch
+        need = dict(q=(self.NB * 7, torch.float64), u=(self.NB * 6, torch.float64),
+                    lam=(max(self.NL, 1), torch.float64), act_slot=(max(self.NS, 1), torch.int32),
+                    n_act=(self.W, torch.int32), status=(self.W, torch.int32), iters=(self.W, torch.int32),
+                    resnorm=(self.W, torch.float64))
+        for k, (n, dt) in need.items():
+            x = out.get(k)
+            if (x is None or not torch.is_tensor(x) or x.dtype != dt or x.device != self.device
+                    or not x.is_contiguous() or x.numel() < n):
+                raise OstrichError("out[%r] must be a contiguous %s tensor on %s with at least %d entries"
+                                   % (k, dt, self.device, n))
 
     def _ctrl(self, ctrl):
         if self.NCTRL == 0:
@@ -180,9 +234,12 @@ class Simulator:
         """One backward-Euler step of every world; returns a dict of device tensors.
         plain=True runs the comparison baseline (one launch per world per Newton iteration)."""
         torch = self.torch
-        q, u, lam = self._f64(q, (self.NB, 7)), self._f64(u, (self.NB, 6)), self._f64(lam)
+        q, u, lam = self._f64(q, (self.NB, 7)), self._f64(u, (self.NB, 6)), self._lam(lam)
         ctrl = self._ctrl(ctrl)
-        if out is None:
+        tape = self._tape(tape)
+        if out is not None:
+            self._check_out(out)
+        else:
             qn, un, ln = self.empty_state()
             out = dict(q=qn, u=un, lam=ln,
                        act_slot=torch.empty(max(self.NS, 1), dtype=torch.int32, device=self.device),
@@ -205,8 +262,11 @@ class Simulator:
         torch = self.torch
         q, u = self._f64(q, (self.NB, 7)), self._f64(u, (self.NB, 6))
         ctrl = self._ctrl(ctrl)
-        u_next, lam_next = self._f64(u_next, (self.NB, 6)), self._f64(lam_next)
+        u_next, lam_next = self._f64(u_next, (self.NB, 6)), self._lam(lam_next)
         gq_next, gu_next = self._f64(gq_next, (self.NB, 7)), self._f64(gu_next, (self.NB, 6))
+        if tape is None:
+            raise OstrichError("the adjoint step needs the tape written by its forward step")
+        tape = self._tape(tape)
         gq = torch.empty_like(q)
         gu = torch.empty_like(u)
         gc = torch.zeros(max(self.NCTRL, 1), dtype=torch.float64, device=self.device)
@@ -224,8 +284,11 @@ class Simulator:
         torch = self.torch
         q, u = self._f64(q, (self.NB, 7)), self._f64(u, (self.NB, 6))
         ctrl = self._ctrl(ctrl)
-        u_next, lam_next = self._f64(u_next, (self.NB, 6)), self._f64(lam_next)
+        u_next, lam_next = self._f64(u_next, (self.NB, 6)), self._lam(lam_next)
         gq_next, gu_next = self._f64(gq_next, (self.NB, 7)), self._f64(gu_next, (self.NB, 6))
+        if tape is None:
+            raise OstrichError("the adjoint step needs the tape written by its forward step")
+        tape = self._tape(tape)
         f64 = dict(dtype=torch.float64, device=self.device)
         gq, gu = torch.empty_like(q), torch.empty_like(u)
         gc = torch.zeros(max(self.NCTRL, 1), **f64)
@@ -258,10 +321,7 @@ class Simulator:
             K = knots.numel() // self.NCTRL
             knots = knots.reshape(self.NCTRL, K)
             basis = self._f64(basis, (T, K))
-        if torch.is_tensor(loss_body):
-            lb = loss_body.to(self.device, torch.int32).contiguous()
-        else:
-            lb = torch.as_tensor(np.asarray(loss_body, dtype=np.int32), device=self.device).contiguous()
+        lb = self._loss_body(loss_body)
         tg = self._f64(target, (self.W, 2))
         lg = self._f64(loss_grad, (self.W,)) if loss_grad is not None else None
         ws = workspace if workspace is not None else self.new_workspace(T, ckpt_every)
@@ -293,10 +353,7 @@ class Simulator:
             K = knots.numel() // self.NCTRL
             knots = knots.reshape(self.NCTRL, K)
             basis = self._f64(basis, (T, K))
-        if torch.is_tensor(loss_body):
-            lb = loss_body.to(self.device, torch.int32).contiguous()
-        else:
-            lb = torch.as_tensor(np.asarray(loss_body, dtype=np.int32), device=self.device).contiguous()
+        lb = self._loss_body(loss_body)
         unknown = set(weights) - set(LOSS_WEIGHTS)
         if unknown:
             raise ValueError("unknown loss weights: %s" % sorted(unknown))
@@ -340,7 +397,7 @@ class GraphRollout:
         self.u0 = sim._f64(u0, (sim.NB, 6)).clone()
         self.knots = sim._f64(knots).clone() if sim.NCTRL else None
         self.basis = sim._f64(basis).clone() if sim.NCTRL else None
-        self.lb = torch.as_tensor(np.asarray(loss_body, dtype=np.int32), device=sim.device).contiguous()
+        self.lb = torch.as_tensor(sim.check_loss_body(loss_body), device=sim.device).contiguous()
         self.tg = sim._f64(target, (sim.W, 2)).clone()
         self.ws = sim.new_workspace(T, ckpt_every)
         self.T, self.ck = int(T), int(ckpt_every)

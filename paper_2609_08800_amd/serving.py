@@ -313,6 +313,9 @@ class GpuBackend:
             d0 = np.diff(getattr(self.pool, key))[:1]
             if not np.all(d == d0[0]):
                 raise ValueError(f"request {r.rid}: worlds do not match the pool topology ({key})")
+        lbh = np.asarray(b.loss_body)
+        if lbh.shape != (n,) or np.any((lbh < 0) | (lbh >= self.nb_w)):
+            raise ValueError(f"request {r.rid}: loss_body needs one body index in [0, {self.nb_w}) per world")
         for key, (off, per) in _SEG.items():
             src = np.asarray(getattr(b, key)).reshape(-1)
             if src.size == 0:

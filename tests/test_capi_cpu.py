@@ -58,3 +58,33 @@ def test_no_cpu_fallback_without_gpu():
     from paper_2609_08800_amd import OstrichError, Simulator
     with pytest.raises(OstrichError):
         Simulator(scenes.box_batch(1), scenes.solver_params(), device="cuda")
+
+
+def test_binding_checks_arguments_before_any_call():
+    """The binding's host checks (no GPU: a Simulator without a context): loss bodies must
+    name a body of their world, tapes must be large enough, multipliers must have NL
+    entries; each failure raises before anything reaches the library."""
+    import numpy as np
+    import torch
+    from paper_2609_08800_amd import OstrichError, Simulator
+    sim = Simulator.__new__(Simulator)
+    sim.torch, sim.device = torch, torch.device("cpu")
+    sim.W, sim.NB, sim.NL, sim.tape_bytes = 3, 9, 4, 800
+    sim._bodies = np.array([2, 3, 4])
+    assert sim.check_loss_body([1, 2, 3]).dtype == np.int32
+    for bad in ([0, 3, 0], [-1, 0, 0], [0, 0]):
+        with pytest.raises(OstrichError):
+            sim.check_loss_body(bad)
+    with pytest.raises(OstrichError):
+        sim._loss_body(None)
+    assert sim._tape(None) is None
+    sim._tape(torch.empty(100, dtype=torch.float64))
+    for bad in (torch.empty(99, dtype=torch.float64), torch.empty(200, dtype=torch.float32),
+                torch.empty(200, dtype=torch.float64)[::2]):
+        with pytest.raises(OstrichError):
+            sim._tape(bad)
+    assert sim._lam(np.zeros(4)).shape == (4,)
+    with pytest.raises(RuntimeError):
+        sim._lam(np.zeros(3))
+    sim.NL = 0
+    assert sim._lam(np.zeros(0)).shape == (1,)
