@@ -136,8 +136,9 @@ const char* ostrich_last_error(void);
  * joint_act and contact_cap to the host once to size the launches, and
  * allocates its own small tables (per-bucket world lists, per-world tape
  * offsets) and, for worlds whose Schur matrix does not fit on chip, one slice
- * of device memory per resident workgroup.  Fails with OSTRICH_E_UNSUPPORTED
- * if a world does not fit a workgroup even then. */
+ * of device memory per resident workgroup.  Fails with OSTRICH_E_ARG for an
+ * empty batch (n_worlds < 1), a world without bodies or decreasing offsets,
+ * and with OSTRICH_E_UNSUPPORTED if a world does not fit a workgroup even then. */
 int ostrich_ctx_create(const ostrich_batch* batch, const ostrich_params* params, ostrich_ctx** out);
 int ostrich_ctx_destroy(ostrich_ctx* ctx);
 

@@ -304,6 +304,19 @@ def test_status_edge_cases(torch):
         assert rel_err(got["u"][s], ref["u"][s]) <= 1e-6
 
 
+def test_empty_and_malformed_batches_are_rejected(torch):
+    """Context creation checks the batch on the host before any launch: no worlds, or a
+    world without bodies, is an argument error (the library's E_ARG), not a launch."""
+    from paper_2609_08800_amd import OstrichError
+    with pytest.raises(OstrichError, match="n_worlds"):
+        sim_for(scenes.pack([]), scenes.solver_params())
+    b = scenes.pack([scenes.box_world(None), scenes.box_world(None)])
+    b.body_off = b.body_off.copy()
+    b.body_off[1] = 0                     # world 0 without bodies
+    with pytest.raises(OstrichError, match="malformed"):
+        sim_for(b, scenes.solver_params())
+
+
 def test_step_timing_counts_launches_and_algorithmic_work(torch):
     """The measurement facility: one forward step with a tape and its adjoint
     are counted once each; the forward's flops and the adjoint's bytes follow
