@@ -95,6 +95,11 @@ def check_states(b, got, ref, tol=STATE_TOL):
             assert got["resnorm"][w] <= max(10 * ref["resnorm"][w], 1e-8), (w, got["resnorm"][w], ref["resnorm"][w])
 
 
+def world_rows(off, worlds):
+    """Indices of the rows (bodies, slots, joints or controls, by their offsets) of the given worlds."""
+    return np.concatenate([np.arange(off[w], off[w + 1]) for w in worlds] + [np.zeros(0, dtype=np.int64)])
+
+
 def gpu_step(sim, q, u, lam, ctrl, tape=None):
     o = sim.step_forward(q, u, lam, ctrl, tape=tape)
     return {k: v.cpu().numpy() for k, v in o.items()}
@@ -201,24 +206,34 @@ def test_determinate_box_steps(torch):
 
 
 def test_robot_adjoint_matches_exact_ift(torch):
+    """Each side linearises at its own root, so the gradients are compared where both
+    converged, to a residual of 1e-12: the two roots then agree far inside the state bar
+    and the gradient bar measures the adjoint, not the distance between two roots."""
     b = scenes.robot_batch(8, seed=5)
-    P = scenes.solver_params(k_max=64)
+    P = scenes.solver_params(k_max=64, tol=1e-12)
     sim = sim_for(b, P)
     ctrl = robot_ctrl(b)
     rng = np.random.default_rng(1)
     q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    both = 0
     for k in range(10):
         c = ctrl(k)
+        ref = oracle.step_forward(b, P, q, u, lam, c)     # the oracle linearises at its own root
         tape = sim.new_tape()
-        got = sim.step_forward(q, u, lam, c, tape=tape)
+        o = sim.step_forward(q, u, lam, c, tape=tape)
+        got = {key: v.cpu().numpy() for key, v in o.items()}
         gq_n, gu_n = rng.normal(size=q.shape), rng.normal(size=u.shape)
-        gq, gu, gc = sim.step_adjoint(q, u, c, got["u"], got["lam"], tape, gq_n, gu_n)
-        un, ln = got["u"].cpu().numpy(), got["lam"].cpu().numpy()
-        rq, ru, rc = oracle.step_adjoint(b, P, q, u, lam, c, un, ln, gq_n, gu_n, mode=0)
-        for g, r in ((gq, rq), (gu, ru), (gc, rc)):
-            g = g.cpu().numpy()
+        gq, gu, gc = sim.step_adjoint(q, u, c, o["u"], o["lam"], tape, gq_n, gu_n)
+        rq, ru, rc = oracle.step_adjoint(b, P, q, u, lam, c, ref["u"], ref["lam"], gq_n, gu_n, mode=0)
+        ok = [w for w in range(b.n_worlds) if ref["status"][w] & 1 and got["status"][w] & 1]
+        both += len(ok)
+        rb, rcs = world_rows(b.body_off, ok), world_rows(b.ctrl_off, ok)
+        assert rel_err(got["u"][rb], ref["u"][rb]) <= STATE_TOL, k
+        for g, r, rows in ((gq, rq, rb), (gu, ru, rb), (gc, rc, rcs)):
+            g, r = g.cpu().numpy()[rows], r[rows]
             assert np.linalg.norm(g - r) <= GRAD_TOL * np.linalg.norm(r), (k, np.linalg.norm(g - r) / np.linalg.norm(r))
-        q, u, lam = got["q"].cpu().numpy(), un, ln
+        q, u, lam = ref["q"], ref["u"], ref["lam"]
+    assert both >= 0.75 * 10 * b.n_worlds, both
 
 
 @pytest.mark.parametrize("ck", [0, 1, 5])
@@ -258,24 +273,54 @@ def test_checkpointing_is_bitwise_and_repeatable(torch):
 
 
 def test_full_size_step_sampled(torch):
-    """8,192 robot worlds in one launch; a sample of worlds checked against the oracle."""
+    """8,192 robot worlds in one launch (the benchmark's configuration), three steps of
+    forward with tape and adjoint.  A sample of worlds is checked against the oracle, which
+    runs each sampled world on its own from its own states; the GPU's input for a sampled
+    world is that oracle state, the other worlds carry the GPU's own states."""
     b = scenes.robot_batch(8192, seed=0)
     P = scenes.solver_params()
     sim = sim_for(b, P)
     ctrl = robot_ctrl(b)
-    got = gpu_step(sim, b.q0, b.u0, np.zeros(b.n_lam), ctrl(0))
     rng = np.random.default_rng(0)
-    for w in sorted(rng.choice(8192, 12, replace=False).tolist()) + [0, 8191]:
-        sub = scenes.pack([b.worlds[w]])
-        s = slice(b.body_off[w], b.body_off[w + 1])
-        c = ctrl(0)[b.ctrl_off[w]:b.ctrl_off[w + 1]]
-        ref = oracle.step_forward(sub, P, sub.q0, sub.u0, np.zeros(sub.n_lam), c)
-        assert got["status"][w] == ref["status"][0]
-        if ref["status"][0] & 1:
-            assert rel_err(got["q"][s], ref["q"]) <= STATE_TOL
-            assert rel_err(got["u"][s], ref["u"]) <= STATE_TOL
-        act = got["act_slot"][b.slot_off[w]:b.slot_off[w + 1]]
-        assert np.array_equal(act, ref["act_slot"][:len(act)])
+    sample = sorted(rng.choice(8192, 12, replace=False).tolist()) + [0, 8191]
+    subs = {w: scenes.pack([b.worlds[w]]) for w in sample}
+    own = {w: (subs[w].q0.copy(), subs[w].u0.copy(), np.zeros(subs[w].n_lam)) for w in sample}
+    q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    gr = np.random.default_rng(1)
+    checked = 0
+    for k in range(3):
+        c = ctrl(k)
+        for w in sample:
+            bs, ls = slice(b.body_off[w], b.body_off[w + 1]), slice(b.lam_off[w], b.lam_off[w + 1])
+            q[bs], u[bs], lam[ls] = own[w]
+        tape = sim.new_tape()
+        o = sim.step_forward(q, u, lam, c, tape=tape)
+        got = {key: v.cpu().numpy() for key, v in o.items()}
+        gqn, gun = gr.normal(size=q.shape), gr.normal(size=u.shape)
+        gq, gu, gc = (x.cpu().numpy() for x in sim.step_adjoint(q, u, c, o["u"], o["lam"], tape, gqn, gun))
+        for w in sample:
+            sub = subs[w]
+            bs = slice(b.body_off[w], b.body_off[w + 1])
+            cs = slice(b.ctrl_off[w], b.ctrl_off[w + 1])
+            qw, uw, lw = own[w]
+            ref = oracle.step_forward(sub, P, qw, uw, lw, c[cs])
+            print("step", k, "world", w, "status", ref["status"][0], got["status"][w], flush=True)
+            if k == 0:
+                assert got["status"][w] == ref["status"][0], w
+            if got["status"][w] & 1 and ref["status"][0] & 1:
+                act = got["act_slot"][b.slot_off[w]:b.slot_off[w + 1]]
+                assert np.array_equal(act, ref["act_slot"][:len(act)]), (k, w)
+                assert rel_err(got["q"][bs], ref["q"]) <= STATE_TOL, (k, w)
+                assert rel_err(got["u"][bs], ref["u"]) <= STATE_TOL, (k, w)
+                rq, ru, rc = oracle.step_adjoint(sub, P, qw, uw, lw, c[cs], ref["u"], ref["lam"], gqn[bs], gun[bs],
+                                                 mode=0)
+                g = np.concatenate([gq[bs].ravel(), gu[bs].ravel(), gc[cs]])
+                r = np.concatenate([rq.ravel(), ru.ravel(), rc])
+                assert np.linalg.norm(g - r) <= GRAD_TOL * np.linalg.norm(r), (k, w, np.linalg.norm(g - r))
+                checked += 1
+            own[w] = (ref["q"], ref["u"], ref["lam"])
+        q, u, lam = got["q"], got["u"], got["lam"]
+    assert checked >= 0.6 * 3 * len(sample), checked
 
 
 def test_status_edge_cases(torch):
@@ -360,13 +405,13 @@ def test_step_timing_counts_launches_and_algorithmic_work(torch):
 def test_parameter_gradients_match_oracle(torch, scene):
     """Cotangents of every body's mass, every slot's friction coefficient and every
     joint's servo gain (Eq. (17) with a model parameter as xi), and of the state
-    and controls, GPU against the oracle's dual-number pull-back at the same
-    converged step, over two steps.  The spinning, sliding tripods make the
+    and controls, GPU against the oracle's dual-number pull-back, each side at its own
+    root (residual 1e-12), compared where both converged, over two steps.  The spinning, sliding tripods make the
     geometric stiffness large: a fixed-point refinement on it contracts by about
     0.6 per sweep there, while the Krylov solve converges in four applications."""
     from paper_2609_08800_amd import spline_basis
     from test_oracle_pins import tripod_world
-    P = scenes.solver_params(k_max=64)
+    P = scenes.solver_params(k_max=64, tol=1e-12)
     ctrl_at = lambda k: None
     if scene == "robots":
         b = scenes.robot_batch(4, seed=21)
@@ -383,7 +428,7 @@ def test_parameter_gradients_match_oracle(torch, scene):
     elif scene == "hinges":
         from test_oracle_pins import _hinge_z_world
         b = scenes.pack([_hinge_z_world(0.4, 1.5, 3.0, 0.05), _hinge_z_world(-0.2, -0.7, 1.0, 0.0)])
-        P = scenes.solver_params(k_max=64, gravity=(0, 0, 0))
+        P = scenes.solver_params(k_max=64, gravity=(0, 0, 0), tol=1e-12)
         ctrl_at = lambda k: np.array([-0.3, 0.5])
     else:
         b = scenes.terrain_batch(3, seed=4, n_maps=2)
@@ -394,19 +439,32 @@ def test_parameter_gradients_match_oracle(torch, scene):
     sim = sim_for(b, P)
     q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
     rng = np.random.default_rng(5)
+    both = 0
     for k in range(2):
         c = ctrl_at(k)
+        ref = oracle.step_forward(b, P, q, u, lam, c)     # the oracle linearises at its own root
         tape = sim.new_tape()
         o = sim.step_forward(q, u, lam, c, tape=tape)
-        un, ln = o["u"].cpu().numpy(), o["lam"].cpu().numpy()
         gqn, gun = rng.normal(size=q.shape), rng.normal(size=u.shape)
-        gq, gu, gc, gm, gmu, gkp = sim.step_adjoint_params(q, u, c, un, ln, tape, gqn, gun)
-        R = oracle.step_adjoint_params(b, P, q, u, c, un, ln, gqn, gun, mode=0)
-        for g, r in ((gq, R["gq"]), (gu, R["gu"]), (gc, R["gc"]), (gm, R["g_mass"]), (gmu, R["g_mu"]),
-                     (gkp, R["g_kp"])):
-            g = g.cpu().numpy()
-            assert np.linalg.norm(g - r) <= GRAD_TOL * max(np.linalg.norm(r), 1e-12), (k, np.linalg.norm(g - r))
-        q, u, lam = o["q"].cpu().numpy(), un, ln
+        gq, gu, gc, gm, gmu, gkp = sim.step_adjoint_params(q, u, c, o["u"], o["lam"], tape, gqn, gun)
+        R = oracle.step_adjoint_params(b, P, q, u, c, ref["u"], ref["lam"], gqn, gun, mode=0)
+        st = o["status"].cpu().numpy()
+        ok = [w for w in range(b.n_worlds) if ref["status"][w] & 1 and st[w] & 1]   # both at their roots
+        both += len(ok)
+        rb, rcs = world_rows(b.body_off, ok), world_rows(b.ctrl_off, ok)
+        rs, rj = world_rows(b.slot_off, ok), world_rows(b.joint_off, ok)
+        blocks = [(g.cpu().numpy()[rows].ravel(), r[rows].ravel())
+                  for g, r, rows in ((gq, R["gq"], rb), (gu, R["gu"], rb), (gc, R["gc"], rcs), (gm, R["g_mass"], rb),
+                                     (gmu, R["g_mu"], rs), (gkp, R["g_kp"], rj))]
+        ga, ra = np.concatenate([x for x, _ in blocks]), np.concatenate([y for _, y in blocks])
+        assert np.linalg.norm(ga - ra) <= GRAD_TOL * max(np.linalg.norm(ra), 1e-12), k    # the step's whole gradient
+        # each block on its own as well; a block below a millionth of the whole (friction
+        # cotangents of a tripod that barely slides) sits at the roots' own distance there
+        for i, (g, r) in enumerate(blocks):
+            scale = max(np.linalg.norm(r), 1e-6 * np.linalg.norm(ra), 1e-12)
+            assert np.linalg.norm(g - r) <= GRAD_TOL * scale, (k, i, np.linalg.norm(g - r), np.linalg.norm(r))
+        q, u, lam = ref["q"], ref["u"], ref["lam"]
+    assert both >= 0.6 * 2 * b.n_worlds, both
 
 
 @pytest.mark.parametrize("ck", [0, 4])
@@ -534,7 +592,7 @@ def test_krylov_newton_step_reaches_the_oracle_root(torch, scene):
         assert_same_active(b, P, q, u, got, ref, k)
         gqn, gun = rng.normal(size=q.shape), rng.normal(size=u.shape)
         gq, gu, gc = (x.cpu().numpy() for x in sim.step_adjoint(q, u, c, o["u"], o["lam"], tape, gqn, gun))
-        rq, ru, rc = oracle.step_adjoint(b, P, q, u, lam, c, got["u"], got["lam"], gqn, gun, mode=0)
+        rq, ru, rc = oracle.step_adjoint(b, P, q, u, lam, c, ref["u"], ref["lam"], gqn, gun, mode=0)
         for w in range(b.n_worlds):
             total += 1
             if not (ref["status"][w] & 1 and got["status"][w] & 1):
