@@ -255,6 +255,32 @@ def test_robot_rollout_gradient_matches_oracle(torch, ck):
         assert np.linalg.norm(g - w) <= GRAD_TOL * np.linalg.norm(w), (key, np.linalg.norm(g - w) / np.linalg.norm(w))
 
 
+def test_box_rollout_gradient_with_respect_to_u0(torch):
+    """The box workload: a 50-step rollout with checkpoints every 10 steps, the loss
+    |xy_T - target|^2 and its gradient with respect to the initial velocity (and pose), on
+    boxes resting on three points so that every contact force is determinate.  Loss and
+    gradients against the oracle's rollout, on the worlds whose every step converged on
+    both sides (tolerance 1e-12, budget 200)."""
+    from test_oracle_pins import tripod_world
+    rng = np.random.default_rng(12)
+    worlds = [tripod_world(tuple(rng.uniform(-2, 2, 2)) + (0.0,), tuple(rng.normal(0, 0.5, 3)),
+                           float(rng.uniform(-3, 3)), tuple(rng.uniform(-1, 1, 2))) for _ in range(8)]
+    b = scenes.pack(worlds)
+    P = scenes.solver_params(k_max=200, tol=1e-12)
+    T = 50
+    sim = sim_for(b, P)
+    r = sim.rollout(b.q0, b.u0, None, None, T, ckpt_every=10, loss_body=b.loss_body, target=b.target)
+    ref = oracle.rollout(b, P, b.q0, b.u0, None, T)
+    gst = r["status"].cpu().numpy()
+    ok = [w for w in range(b.n_worlds) if not (ref["status"][w] & 6) and not (gst[w] & 6)]
+    assert len(ok) >= 6, (ref["status"], gst)
+    np.testing.assert_allclose(r["loss"].cpu().numpy()[ok], ref["loss"][ok], rtol=1e-9, atol=1e-12)
+    rows = world_rows(b.body_off, ok)
+    for key in ("g_u0", "g_q0"):
+        g, w = r[key].cpu().numpy()[rows], ref[key][rows]
+        assert np.linalg.norm(g - w) <= GRAD_TOL * np.linalg.norm(w), (key, np.linalg.norm(g - w) / np.linalg.norm(w))
+
+
 def test_checkpointing_is_bitwise_and_repeatable(torch):
     T = 23
     b = scenes.robot_batch(32, seed=9)
