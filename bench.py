@@ -355,8 +355,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="arrival window of the serving run")
     ap.add_argument("--serve-drain", type=float, default=40.0, help="extra time to finish admitted requests")
     ap.add_argument("--uneven", type=int, default=1, help="also measure the uneven stacks + robots batch")
-    ap.add_argument("--synthesis-trials", type=int, default=25,
-                    help="trials of the control-synthesis task (0: skip)")
+    ap.add_argument("--synthesis-trials", type=int, default=0,
+                    help="trials of the control-synthesis task (0: skip; not part of the default line)")
     ap.add_argument("--serve-sweep", type=str, default="",
                     help="comma-separated arrival rates (req/s) of an additional serving sweep")
     ap.add_argument("--roofline-only", action="store_true",

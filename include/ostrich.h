@@ -55,6 +55,11 @@ extern "C" {
 #define OSTRICH_ST_NONFINITE 4     /* non-finite residual or factor */
 #define OSTRICH_ST_REGULARIZED 8   /* Schur regularisation had to be raised */
 #define OSTRICH_ST_OVERFLOW 16     /* more active contacts than contact_cap */
+#define OSTRICH_ST_ADJ_INEXACT 32  /* adjoint: the Krylov solve of the exact system ended above its stop
+                                      (applications ran out or a value was not finite); the gradient is
+                                      the last iterate's */
+#define OSTRICH_ST_LOSS_BODY 64    /* rollout: loss_body[w] is not a body of world w (loss set to NaN,
+                                      no cotangent written) */
 
 /* Packed batch of worlds (device pointers).  Offsets have n_worlds+1 entries. */
 typedef struct {
@@ -96,7 +101,7 @@ typedef struct {
   int32_t k_min;       /* best-iterate floor (Sec. III-C) */
   double eps;          /* smoothing of the FB function and of norms */
   double delta_g;      /* guard of denominators */
-  double delta_reg;    /* relative Schur diagonal regularisation */
+  double delta_reg;    /* relative Schur diagonal regularisation of the Newton iterations (> 0) */
   double delta0;       /* contact activation margin (m) */
   int32_t ls_max;      /* step-length halvings of the residual-decrease test */
   int32_t refine;      /* most Krylov operator applications of the adjoint (0: factor only) */
@@ -104,7 +109,7 @@ typedef struct {
   int32_t schedule;    /* OSTRICH_SCHED_FIXED or OSTRICH_SCHED_BUCKETED */
   int32_t truncate;    /* 1: the adjoint treats the contact geometry as a constant of the step, so no
                           derivative with respect to q- passes through a contact row or its force
-                          (the truncated position pull-back of the terrain task, Sec. V); 0: the
+                          (the truncated position pull-back of the terrain task, Sec. IV-D); 0: the
                           complete pull-back of Eq. (17) */
   int32_t linear_solver; /* Newton step: OSTRICH_LIN_LU (0) the banded LU of the Schur matrix;
                           OSTRICH_LIN_KRYLOV (1) the paper's iterative alternative, a
@@ -114,6 +119,23 @@ typedef struct {
                           returns OSTRICH_E_UNSUPPORTED for it */
   int32_t krylov_iters; /* products with A per Newton step at most (0: 16, as the paper's 16
                           inner iterations); the solve stops earlier at 1e-12 of |rhs| */
+  int32_t tier_contacts; /* tiered on-chip launches (a launch shape, not arithmetic: results are the
+                          same bits either way).  A first launch carves each workgroup's LDS for
+                          at most this many active contacts, so that more worlds share a CU, and
+                          hands every world with more to a second, persistent launch with the full
+                          carve.  0: automatic (the largest count that raises the workgroups per
+                          CU, if any); -1: never; n > 0: n, if below the bucket's contact cap */
+  double delta_reg_adj; /* relative regularisation (> 0) of the factor written to the tape, the one the
+                          adjoint solves with: the multiplier block of the adjoint's system (Eq. (16))
+                          carries h delta_reg_adj diag(J M~^-1 J^T), so the gradient differs from the
+                          implicit-function derivative by O(delta_reg_adj).  The Newton iterations'
+                          delta_reg does not change the root and need not be small; this one should be.
+                          It cannot be arbitrarily small either: where a contact set is statically
+                          indeterminate (a robot on four wheels) the multiplier block has a null
+                          direction that only this term fixes, and the cotangents of q- that see it
+                          lose digits as 1 / delta_reg_adj.  1e-9 keeps both effects near 1e-7.
+                          Raised tenfold while the factor's pivot test fails, the value used being
+                          recorded in the tape */
 } ostrich_params;
 
 #define OSTRICH_LIN_LU 0
@@ -142,6 +164,12 @@ const char* ostrich_last_error(void);
 int ostrich_ctx_create(const ostrich_batch* batch, const ostrich_params* params, ostrich_ctx** out);
 int ostrich_ctx_destroy(ostrich_ctx* ctx);
 
+/* Bytes of device memory the context holds (its tables, the device scratch of
+ * worlds kept off chip, the plain path's workspace and the measurement
+ * counters), as allocated so far: ostrich_autotune and ostrich_ctx_timing may
+ * add to it. */
+size_t ostrich_ctx_device_bytes(const ostrich_ctx* ctx);
+
 /* Sizes the caller allocates: the per-step tape of all worlds (bytes; world w
  * holds mr_w^2 + 4 doubles, mr_w its row capacity), and
  * the rollout workspace for horizon T and checkpoint interval k (0: keep every
@@ -155,10 +183,11 @@ size_t ostrich_rollout_workspace_bytes(const ostrich_ctx* ctx, int32_t T, int32_
 int ostrich_ctx_caps(const ostrich_ctx* ctx, int64_t* out);
 
 /* Launch schedule: returns the number of buckets and, if out is not NULL,
- * writes for each of the first max_buckets buckets six int32 (row capacity,
+ * writes for each of the first max_buckets buckets eight int32 (row capacity,
  * number of worlds, threads per world, storage split: 0 on chip / 1 Schur
- * matrix and Jacobian blocks in device memory, LDS bytes per workgroup,
- * tuned flag). */
+ * matrix and Jacobian blocks in device memory, LDS bytes per workgroup of the
+ * full carve, tuned flag, the contact capacity of a tiered first launch (0:
+ * untiered), and that launch's LDS bytes per workgroup). */
 int ostrich_ctx_schedule(const ostrich_ctx* ctx, int32_t* out, int32_t max_buckets);
 
 /* Measurement of the forward and adjoint steps (a set-up facility, not for
@@ -207,11 +236,14 @@ int ostrich_step_forward(ostrich_ctx* ctx, const double* q_prev, const double* u
  * factor, with at most `refine` operator applications (params.refine if < 0)
  * and a stop at 1e-12 of the relative residual; refine = 0 keeps the factor's
  * solve alone.  The adjoint kernel's LDS adds the Krylov workspace,
- * 60 NB_cap + 106 doubles per world (NB_cap: most bodies of a world). */
+ * 60 NB_cap + 106 doubles per world (NB_cap: most bodies of a world).
+ * adj_status [W] int32 (device, may be NULL): OSTRICH_ST_ADJ_INEXACT is ORed
+ * into entry w when world w's Krylov solve ends above its stop (other entries
+ * and bits are left as they are). */
 int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, const double* u_prev, const double* ctrl,
                          const double* u_next, const double* lam_next, const void* tape, const double* gq_next,
                          const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl, int32_t refine,
-                         void* stream);
+                         int32_t* adj_status, void* stream);
 
 /* The adjoint of ostrich_step_adjoint together with the cotangents of the
  * model parameters (Eq. (17) with xi a parameter, the paper's system
@@ -225,7 +257,7 @@ int ostrich_step_adjoint_params(ostrich_ctx* ctx, const double* q_prev, const do
                                 const double* u_next, const double* lam_next, const void* tape,
                                 const double* gq_next, const double* gu_next, double* gq_prev, double* gu_prev,
                                 double* g_ctrl, double* g_mass, double* g_mu, double* g_kp, int32_t refine,
-                                void* stream);
+                                int32_t* adj_status, void* stream);
 
 /* The same two steps restricted to the worlds listed in `worlds` (device
  * int32 [n], distinct ids): only those worlds' entries of the state, status
@@ -238,7 +270,7 @@ int ostrich_step_forward_list(ostrich_ctx* ctx, const int32_t* worlds, int32_t n
 int ostrich_step_adjoint_list(ostrich_ctx* ctx, const int32_t* worlds, int32_t n, const double* q_prev,
                               const double* u_prev, const double* ctrl, const double* u_next, const double* lam_next,
                               const void* tape, const double* gq_next, const double* gu_next, double* gq_prev,
-                              double* gu_prev, double* g_ctrl, int32_t refine, void* stream);
+                              double* gu_prev, double* g_ctrl, int32_t refine, int32_t* adj_status, void* stream);
 
 /* The plain path, a comparison baseline with the same arguments and the same
  * results (the same arithmetic, bit for bit): ostrich_step_forward_plain makes
@@ -254,24 +286,26 @@ int ostrich_step_forward_plain(ostrich_ctx* ctx, const double* q_prev, const dou
 int ostrich_step_adjoint_plain(ostrich_ctx* ctx, const double* q_prev, const double* u_prev, const double* ctrl,
                                const double* u_next, const double* lam_next, const void* tape, const double* gq_next,
                                const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl,
-                               int32_t refine, void* stream);
+                               int32_t refine, int32_t* adj_status, void* stream);
 
 #define OSTRICH_FORWARD 1
 #define OSTRICH_BACKWARD 2
+#define OSTRICH_BOTH (OSTRICH_FORWARD | OSTRICH_BACKWARD) /* forward, then backward, in one call */
 
 /* T-step rollout (the optimisation workload of Sec. IV: a rollout, its loss
  * and the adjoint of Sec. III-D over all steps) with controls from a spline
  * basis (ctrl_k = basis[k,:] . knots[c,:], basis [T*K] device, knots
  * [NCTRL*K]) and the loss |xy(loss_body) - target|^2 at step T (loss_body [W]
  * int32 device, loss_body[w] a body index of world w in [0, its body count):
- * read on the device and not checked by the library, so the caller checks it;
- * target [W*2]).
+ * read on the device, where an index outside that range gives loss[w] = NaN,
+ * no cotangent, and OSTRICH_ST_LOSS_BODY in status_or[w]; target [W*2]).
  * FORWARD writes loss [W], qT, uT and checkpoints into the workspace;
  * BACKWARD (after a FORWARD with the same arguments and workspace) recomputes
  * each segment from its checkpoint and runs the adjoint steps in reverse,
  * writing g_q0, g_u0, g_knots: the gradients of sum_w loss_grad[w] loss[w]
- * (loss_grad [W] device, NULL for all ones).  status_or [W] ORs the step
- * status bits. */
+ * (loss_grad [W] device, NULL for all ones).  status_or [W] (device, may be
+ * NULL) is cleared by FORWARD and ORs the status bits of every forward step,
+ * OSTRICH_ST_ADJ_INEXACT of every adjoint step and OSTRICH_ST_LOSS_BODY. */
 int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0, const double* u0, const double* knots,
                     int32_t K, const double* basis, int32_t T, int32_t ckpt_every, const int32_t* loss_body,
                     const double* target, const double* loss_grad, double* loss, double* qT, double* uT,
@@ -280,7 +314,7 @@ int ostrich_rollout(ostrich_ctx* ctx, int32_t phase, const double* q0, const dou
 
 /* Shaped loss of the optimisation workloads (Sec. IV-B: errors of the final
  * position and heading, the speed at the end, the size of the controls, and
- * the distance from a straight path at every step; Sec. V: the distance from
+ * the distance from a straight path at every step; Sec. IV-D: the distance from
  * and the yaw difference to a reference trajectory at every step, and the size
  * of the controls).  The paper lists the terms without their forms; per world
  * w, with p_k the xy, psi_k the yaw (the
@@ -304,7 +338,7 @@ typedef struct {
  * read during the call) in place of the final-xy loss: the same phases,
  * workspace, checkpointing and outputs; loss [W] holds L_w, and the gradients
  * are those of sum_w loss_grad[w] L_w.  With P.truncate set every adjoint step
- * holds the contact geometry fixed (the terrain task of Sec. V). */
+ * holds the contact geometry fixed (the terrain task of Sec. IV-D). */
 int ostrich_rollout_shaped(ostrich_ctx* ctx, int32_t phase, const double* q0, const double* u0, const double* knots,
                            int32_t K, const double* basis, int32_t T, int32_t ckpt_every, const int32_t* loss_body,
                            const ostrich_loss* spec, const double* loss_grad, double* loss, double* qT, double* uT,
@@ -316,10 +350,12 @@ int ostrich_rollout_shaped(ostrich_ctx* ctx, int32_t phase, const double* q0, co
  * `stream`, device pointers:
  *   ostrich_spline_controls: ctrl[k*nctrl + c] = sum_j basis[k*K + j] knots[c*K + j], k < T.
  *   ostrich_final_loss: for the n_worlds worlds whose body offsets start at
- *     body_off (body_off[i] indexes qT rows), loss[i] = |xy - target[i]|^2 of
- *     body loss_body[i] (loss may be NULL), and, if gq is not NULL, its
- *     cotangent 2 (xy - target) loss_grad[i] (loss_grad NULL: 1) written into
- *     the x, y entries of gq (other entries untouched).
+ *     body_off (n_worlds + 1 entries; body_off[i] indexes qT rows), loss[i] =
+ *     |xy - target[i]|^2 of body loss_body[i] (loss may be NULL), and, if gq
+ *     is not NULL, its cotangent 2 (xy - target) loss_grad[i] (loss_grad NULL:
+ *     1) written into the x, y entries of gq (other entries untouched); a
+ *     loss_body[i] outside [0, body_off[i+1] - body_off[i]) gives loss[i] = NaN
+ *     and no cotangent.
  *   ostrich_knot_grad_accumulate: g_knots[c*K + j] += basis[k*K + j] g_ctrl[c].
  *   ostrich_adam: x -= lr mhat / (sqrt(vhat) + eps) with the moments m, v
  *     updated in place from g, bias corrections of step t >= 1; a non-finite

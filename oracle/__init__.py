@@ -47,7 +47,8 @@ class Params(ctypes.Structure):
                 ("k_max", c_int), ("k_min", c_int), ("eps", ctypes.c_double),
                 ("delta_g", ctypes.c_double), ("delta_reg", ctypes.c_double),
                 ("delta0", ctypes.c_double), ("sigma_mode", c_int), ("n_feat", c_int),
-                ("newton_mode", c_int), ("ls_max", c_int), ("truncate", c_int)]
+                ("newton_mode", c_int), ("ls_max", c_int), ("truncate", c_int),
+                ("delta_reg_adj", ctypes.c_double)]
 
 
 def lib():
@@ -107,6 +108,7 @@ class _Handle:
         self.cp.newton_mode = int(params.get("newton_mode", 0))
         self.cp.ls_max = int(params.get("ls_max", 0))
         self.cp.truncate = int(params.get("truncate", 0))
+        self.cp.delta_reg_adj = float(params.get("delta_reg_adj", params["delta_reg"]))
 
 
 def step_forward(batch, params, q, u, lam, ctrl):

@@ -224,7 +224,7 @@ WorldD load_world(const ostrich_ref_batch* B, int w) {
 }
 
 struct Prm {
-  double h, g[3], tol, eps, dg, dreg, d0;
+  double h, g[3], tol, eps, dg, dreg, d0, dreg_adj;
   int kmax, kmin, sigma_mode, newton_mode, ls_max, truncate;
 };
 Prm load_params(const ostrich_ref_params* p) {
@@ -235,6 +235,7 @@ Prm load_params(const ostrich_ref_params* p) {
   P.eps = p->eps;
   P.dg = p->delta_g;
   P.dreg = p->delta_reg;
+  P.dreg_adj = p->delta_reg_adj;
   P.d0 = p->delta0;
   P.kmax = p->k_max;
   P.kmin = std::min(p->k_min, p->k_max);
@@ -846,7 +847,7 @@ void evaluate(const WorldD& W, const Prm& P, const Layout& L, const std::vector<
     double sn = k == R_NORMAL ? sig_n[L.idx[g]] : 1.0, sf = k == R_NORMAL ? sig_f[L.idx[g]] : 1.0;
     const T* qa_m = qm + 7 * a;
     const T* qb_m = b >= 0 ? qm + 7 * b : zero7;
-    // truncated pull-back (Sec. V, terrain): a contact group sees its frame
+    // truncated pull-back (Sec. IV-D, terrain): a contact group sees its frame
     // and the bodies' poses at q- as constants, so no derivative with respect
     // to q- passes through it; values, and derivatives in u and lambda, are
     // those of the complete residual
@@ -1075,7 +1076,7 @@ void newton_rows(const StepCtx& X, const Eval<double>& E, int mode, std::vector<
     }
   }
 }
-void schur(const StepCtx& X, const Eval<double>& E, Schur& S, bool with_rhs, int mode) {
+void schur(const StepCtx& X, const Eval<double>& E, Schur& S, bool with_rhs, int mode, double dreg0 = -1.0) {
   int m = X.L.m, nu = X.L.nu;
   const double h = X.P.h;
   dense_J(X.L, E.J, S.Jd);
@@ -1112,7 +1113,7 @@ void schur(const StepCtx& X, const Eval<double>& E, Schur& S, bool with_rhs, int
       S.rhs[i] = (s - E.D[nu + i] * E.F[nu + i]) / h;
     }
   }
-  double dreg = X.P.dreg;
+  double dreg = dreg0 >= 0.0 ? dreg0 : X.P.dreg;
   S.regularized = false;
   S.ok = false;
   for (int attempt = 0; attempt < 8; ++attempt) {
@@ -1265,7 +1266,10 @@ void finalize_q(const double* qm, const double* u, int nb, double h, double* qn)
 }
 
 // Exact Jacobian of the scaled residual at an iterate:
-//   H = [[M~ - h d(J^T lambda)/du, -h J^T], [G_u, G_lambda + h dreg diag(Abar)]].
+//   H = [[M~ - h d(J^T lambda)/du, -h J^T], [G_u, G_lambda + h dreg_adj diag(Abar)]],
+// the multiplier block regularised by the adjoint's own delta_reg_adj (the
+// root does not depend on the regularisation of the Newton iterations, but
+// an adjoint solved with it would carry an O(delta_reg) bias).
 void exact_jacobian(const StepCtx& X, const Eval<double>& E, const Schur& S, const double* u,
                     const double* lam, std::vector<double>& H) {
   const Layout& L = X.L;
@@ -1324,7 +1328,7 @@ void exact_jacobian(const StepCtx& X, const Eval<double>& E, const Schur& S, con
     }
   for (int i = 0; i < m; ++i)
     for (int j = 0; j < m; ++j) H[(nu + i) * n + nu + j] = S.Gld[i * m + j];
-  for (int i = 0; i < m; ++i) H[(nu + i) * n + nu + i] += h * S.dreg_used * S.Abar[i * m + i];
+  for (int i = 0; i < m; ++i) H[(nu + i) * n + nu + i] += h * X.P.dreg_adj * S.Abar[i * m + i];
 }
 
 // ------------------------------------------------------- adjoint ---------
@@ -1342,7 +1346,7 @@ void adjoint_world(StepCtx& X, const double* u_star, const double* lam_slots, co
   evaluate<double>(W, P, X.L, X.C, X.sig_n, X.sig_f, X.qm.data(), X.um.data(), X.ctrl.data(), u_star,
                    lam.data(), E, true);
   Schur S;
-  schur(X, E, S, false, mode == 1 ? 1 : P.newton_mode);
+  schur(X, E, S, false, mode == 1 ? 1 : P.newton_mode, P.dreg_adj);
 
   // loss cotangent on the raw (unnormalised) q+, and the total u-cotangent
   // b = g_u + h G(q-)^T g_q (the kinematic substitution transposed)
@@ -1410,7 +1414,7 @@ void adjoint_world(StepCtx& X, const double* u_star, const double* lam_slots, co
     for (int i = 0; i < m; ++i) w[nu + i] = wl[i];
   } else {
     // Exact IFT, Eq. (16): H^T w = -[b; 0], H the full Jacobian of the scaled
-    // residual (with the same Schur regularisation as the forward factor).
+    // residual (its multiplier block regularised by delta_reg_adj).
     std::vector<double> H;
     exact_jacobian(X, E, S, u_star, lam.data(), H);
     std::vector<double> Ht(n * n);

@@ -59,6 +59,8 @@ typedef struct {
   int32_t newton_mode;/* 0: generalized Jacobian of the constraint rows, 1: W frozen (symmetric) */
   int32_t ls_max;    /* step halvings of the residual-decrease step length (0: full steps) */
   int32_t truncate;  /* 1: contact geometry held fixed within the step in the q- pull-back */
+  double delta_reg_adj; /* relative regularisation of the adjoint's system (Eq. (16)): h delta_reg_adj
+                          diag(J M~^-1 J^T) in its multiplier block; the Newton iterations use delta_reg */
 } ostrich_ref_params;
 
 /* status bits */

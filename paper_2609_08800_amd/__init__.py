@@ -103,6 +103,11 @@ class Simulator:
         self.caps = dict(zip(("bodies", "joints", "slots", "contacts", "rows", "lds_bytes"), list(caps)))
         self.tape_bytes = int(self.lib.ostrich_tape_bytes(self.ctx))
 
+    @property
+    def device_bytes(self) -> int:
+        """Device memory the library context holds (tables, off-chip scratch, counters)."""
+        return int(self.lib.ostrich_ctx_device_bytes(self.ctx))
+
     def __del__(self):
         try:
             if getattr(self, "ctx", None):
@@ -112,12 +117,13 @@ class Simulator:
             pass
 
     def schedule(self):
-        """Buckets of the launch schedule: list of dicts (rows, worlds, team, split, lds, tuned)."""
+        """Buckets of the launch schedule: list of dicts (rows, worlds, team, split, lds, tuned,
+        tier_contacts, tier_lds)."""
         n = int(self.lib.ostrich_ctx_schedule(self.ctx, None, 0))
-        buf = np.zeros(6 * max(n, 1), dtype=np.int32)
+        buf = np.zeros(8 * max(n, 1), dtype=np.int32)
         self.lib.ostrich_ctx_schedule(self.ctx, buf.ctypes.data, n)
-        keys = ("rows", "worlds", "team", "split", "lds", "tuned")
-        return [dict(zip(keys, map(int, buf[6 * i:6 * i + 6]))) for i in range(n)]
+        keys = ("rows", "worlds", "team", "split", "lds", "tuned", "tier_contacts", "tier_lds")
+        return [dict(zip(keys, map(int, buf[8 * i:8 * i + 8]))) for i in range(n)]
 
     def timing(self, mode: int):
         """Launch measurement: 1 start, 0 stop; 2 reads the forward steps (launches, total ms, algorithmic
@@ -176,6 +182,16 @@ class Simulator:
         if self.NL == 0:
             return self.torch.zeros(1, dtype=self.torch.float64, device=self.device)
         return self._f64(lam, (self.NL,))
+
+    def _status(self, st):
+        """An optional per-world int32 device tensor of status bits."""
+        if st is None:
+            return None
+        t = self.torch
+        if (not t.is_tensor(st) or st.dtype != t.int32 or st.device != self.device or not st.is_contiguous()
+                or st.numel() < self.W):
+            raise OstrichError("adj_status must be a contiguous int32 device tensor of at least W entries")
+        return st.data_ptr()
 
     def _tape(self, tape):
         """A tape must be a float64 device tensor of at least ostrich_tape_bytes."""
@@ -257,8 +273,10 @@ class Simulator:
         return out
 
     def step_adjoint(self, q, u, ctrl, u_next, lam_next, tape, gq_next, gu_next, refine=-1, stream=None,
-                     plain=False):
-        """Cotangents of (q-, u-, ctrl) from those of (q+, u+); plain=True: one launch per world."""
+                     plain=False, adj_status=None):
+        """Cotangents of (q-, u-, ctrl) from those of (q+, u+); plain=True: one launch per world.
+        adj_status: optional int32 [W] device tensor into which ST_ADJ_INEXACT is ORed for
+        worlds whose Krylov solve ended above its stop."""
         torch = self.torch
         q, u = self._f64(q, (self.NB, 7)), self._f64(u, (self.NB, 6))
         ctrl = self._ctrl(ctrl)
@@ -274,11 +292,12 @@ class Simulator:
         rc = fn(
             self.ctx, q.data_ptr(), u.data_ptr(), ctrl.data_ptr(), u_next.data_ptr(), lam_next.data_ptr(),
             tape.data_ptr(), gq_next.data_ptr(), gu_next.data_ptr(), gq.data_ptr(), gu.data_ptr(), gc.data_ptr(),
-            int(refine), self._stream(stream))
+            int(refine), self._status(adj_status), self._stream(stream))
         _capi.check(rc, "ostrich_step_adjoint")
         return gq, gu, gc[:self.NCTRL]
 
-    def step_adjoint_params(self, q, u, ctrl, u_next, lam_next, tape, gq_next, gu_next, refine=-1, stream=None):
+    def step_adjoint_params(self, q, u, ctrl, u_next, lam_next, tape, gq_next, gu_next, refine=-1, stream=None,
+                            adj_status=None):
         """step_adjoint and the cotangents of every body's mass, every slot's friction
         coefficient and every joint's servo gain: (gq, gu, g_ctrl, g_mass, g_mu, g_kp)."""
         torch = self.torch
@@ -298,7 +317,7 @@ class Simulator:
         rc = self.lib.ostrich_step_adjoint_params(
             self.ctx, q.data_ptr(), u.data_ptr(), ctrl.data_ptr(), u_next.data_ptr(), lam_next.data_ptr(),
             tape.data_ptr(), gq_next.data_ptr(), gu_next.data_ptr(), gq.data_ptr(), gu.data_ptr(), gc.data_ptr(),
-            gm.data_ptr(), gmu.data_ptr(), gkp.data_ptr(), int(refine), self._stream(stream))
+            gm.data_ptr(), gmu.data_ptr(), gkp.data_ptr(), int(refine), self._status(adj_status), self._stream(stream))
         _capi.check(rc, "ostrich_step_adjoint_params")
         return gq, gu, gc[:self.NCTRL], gm, gmu[:self.NS], gkp[:self.NJ]
 
@@ -309,7 +328,7 @@ class Simulator:
         n = self.workspace_bytes(T, ckpt_every)
         return self.torch.empty((n + 7) // 8, dtype=self.torch.float64, device=self.device)
 
-    def rollout(self, q0, u0, knots, basis, T, ckpt_every=10, loss_body=None, target=None, phase=3,
+    def rollout(self, q0, u0, knots, basis, T, ckpt_every=10, loss_body=None, target=None, phase=_capi.BOTH,
                 workspace=None, grads=True, loss_grad=None, stream=None):
         """T-step rollout with the final-xy loss; FORWARD (1), BACKWARD (2) or both (3).
         Gradients are those of sum_w loss_grad[w] loss[w] (all ones by default)."""
@@ -340,7 +359,7 @@ class Simulator:
         return dict(loss=loss, qT=qT, uT=uT, g_q0=g_q0, g_u0=g_u0, g_knots=g_knots, status=st, workspace=ws)
 
     def rollout_shaped(self, q0, u0, knots, basis, T, weights, goal, ref=None, ckpt_every=10, loss_body=None,
-                       phase=3, workspace=None, grads=True, loss_grad=None, stream=None):
+                       phase=_capi.BOTH, workspace=None, grads=True, loss_grad=None, stream=None):
         """T-step rollout with the shaped loss of ``ostrich_rollout_shaped``: ``weights``
         maps the names in LOSS_WEIGHTS to their values (missing: 0), ``goal`` is [W, 3]
         (x*, y*, psi*), ``ref`` [T, W, 3] the per-step reference (needed when w_track
@@ -414,7 +433,7 @@ class GraphRollout:
 
     def _run(self):
         return self.sim.rollout(self.q0, self.u0, self.knots, self.basis, self.T, ckpt_every=self.ck,
-                                loss_body=self.lb, target=self.tg, phase=3, workspace=self.ws)
+                                loss_body=self.lb, target=self.tg, phase=_capi.BOTH, workspace=self.ws)
 
     def replay(self, knots=None, q0=None, u0=None):
         if knots is not None:

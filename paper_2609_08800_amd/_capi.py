@@ -18,7 +18,8 @@ c_size = ctypes.c_size_t
 
 E_ARG, E_HIP, E_WORKSPACE, E_UNSUPPORTED = -1, -2, -3, -4
 ST_CONVERGED, ST_BUDGET, ST_NONFINITE, ST_REGULARIZED, ST_OVERFLOW = 1, 2, 4, 8, 16
-FORWARD, BACKWARD = 1, 2
+ST_ADJ_INEXACT, ST_LOSS_BODY = 32, 64
+FORWARD, BACKWARD, BOTH = 1, 2, 3
 SCHED_FIXED, SCHED_BUCKETED = 0, 1
 
 
@@ -35,7 +36,8 @@ class OstrichParams(ctypes.Structure):
     _fields_ = [("h", c_dbl), ("gravity", c_dbl * 3), ("tol", c_dbl), ("k_max", c_int), ("k_min", c_int),
                 ("eps", c_dbl), ("delta_g", c_dbl), ("delta_reg", c_dbl), ("delta0", c_dbl),
                 ("ls_max", c_int), ("refine", c_int), ("team", c_int), ("schedule", c_int),
-                ("truncate", c_int), ("linear_solver", c_int), ("krylov_iters", c_int)]
+                ("truncate", c_int), ("linear_solver", c_int), ("krylov_iters", c_int),
+                ("tier_contacts", c_int), ("delta_reg_adj", c_dbl)]
 
 
 class OstrichLoss(ctypes.Structure):
@@ -72,13 +74,15 @@ def load() -> ctypes.CDLL:
     L.ostrich_ctx_caps.restype = c_int
     L.ostrich_tape_bytes.argtypes = [c_vp]
     L.ostrich_tape_bytes.restype = c_size
+    L.ostrich_ctx_device_bytes.argtypes = [c_vp]
+    L.ostrich_ctx_device_bytes.restype = c_size
     L.ostrich_rollout_workspace_bytes.argtypes = [c_vp, c_int, c_int]
     L.ostrich_rollout_workspace_bytes.restype = c_size
     L.ostrich_step_forward.argtypes = [c_vp] + [c_vp] * 13 + [c_vp]
     L.ostrich_step_forward.restype = c_int
-    L.ostrich_step_adjoint.argtypes = [c_vp] + [c_vp] * 11 + [c_int, c_vp]
+    L.ostrich_step_adjoint.argtypes = [c_vp] + [c_vp] * 11 + [c_int, c_vp, c_vp]
     L.ostrich_step_adjoint.restype = c_int
-    L.ostrich_step_adjoint_params.argtypes = [c_vp] + [c_vp] * 14 + [c_int, c_vp]
+    L.ostrich_step_adjoint_params.argtypes = [c_vp] + [c_vp] * 14 + [c_int, c_vp, c_vp]
     L.ostrich_step_adjoint_params.restype = c_int
     L.ostrich_rollout.argtypes = ([c_vp, c_int, c_vp, c_vp, c_vp, c_int, c_vp, c_int, c_int, c_vp, c_vp, c_vp,
                                    c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp, c_vp])
@@ -95,11 +99,11 @@ def load() -> ctypes.CDLL:
     L.ostrich_autotune.restype = c_int
     L.ostrich_step_forward_list.argtypes = [c_vp, c_vp, c_int] + [c_vp] * 13 + [c_vp]
     L.ostrich_step_forward_list.restype = c_int
-    L.ostrich_step_adjoint_list.argtypes = [c_vp, c_vp, c_int] + [c_vp] * 11 + [c_int, c_vp]
+    L.ostrich_step_adjoint_list.argtypes = [c_vp, c_vp, c_int] + [c_vp] * 11 + [c_int, c_vp, c_vp]
     L.ostrich_step_adjoint_list.restype = c_int
     L.ostrich_step_forward_plain.argtypes = [c_vp] + [c_vp] * 13 + [c_vp]
     L.ostrich_step_forward_plain.restype = c_int
-    L.ostrich_step_adjoint_plain.argtypes = [c_vp] + [c_vp] * 11 + [c_int, c_vp]
+    L.ostrich_step_adjoint_plain.argtypes = [c_vp] + [c_vp] * 11 + [c_int, c_vp, c_vp]
     L.ostrich_step_adjoint_plain.restype = c_int
     L.ostrich_spline_controls.argtypes = [c_vp, c_vp, c_int, c_int, c_int, c_vp, c_vp]
     L.ostrich_spline_controls.restype = c_int
@@ -140,6 +144,8 @@ def make_params(p: dict, team: int = 0, schedule: int = SCHED_BUCKETED) -> Ostri
     cp.truncate = int(p.get("truncate", 0))
     cp.linear_solver = int(p.get("linear_solver", 0))
     cp.krylov_iters = int(p.get("krylov_iters", 16))
+    cp.tier_contacts = int(p.get("tier_contacts", 0))
+    cp.delta_reg_adj = float(p.get("delta_reg_adj", p["delta_reg"]))
     return cp
 
 

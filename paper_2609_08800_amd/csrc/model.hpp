@@ -157,6 +157,7 @@ struct Batch {
 
 struct Params {
   double h, g[3], tol, eps, dg, dreg, d0;
+  double dreg_adj;  // regularisation of the factor the adjoint solves with (the tape's)
   int32_t kmax, kmin, ls_max, refine;
   int32_t truncate;  // adjoint: contact geometry held fixed in the q- pull-back
   int32_t lin;       // Newton step: 0 banded LU of the Schur matrix, 1 matrix-free Krylov solve
@@ -164,7 +165,8 @@ struct Params {
 };
 
 enum { RK_ANCHOR = 0, RK_AXIS = 1, RK_SERVO = 2, RK_CONTACT = 3 };
-enum { ST_CONVERGED = 1, ST_BUDGET = 2, ST_NONFINITE = 4, ST_REGULARIZED = 8, ST_OVERFLOW = 16 };
+enum { ST_CONVERGED = 1, ST_BUDGET = 2, ST_NONFINITE = 4, ST_REGULARIZED = 8, ST_OVERFLOW = 16,
+       ST_ADJ_INEXACT = 32, ST_LOSS_BODY = 64 };
 
 // Contact frame decided at q-: which feature of the static box (clamp flags)
 // and the tangent seed axis.  Fixed for the whole step.

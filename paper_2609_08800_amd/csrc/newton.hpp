@@ -12,15 +12,18 @@ namespace ost {
 // World w's tape starts at tape_off[w]; tape_off[w+1] - tape_off[w] = mr_w^2 + 4.
 OST_HD size_t tape_doubles_world(int mr_w) { return (size_t)mr_w * mr_w + 4; }
 
-// Visit the band entries (|i - j| <= bw) of an m x m row-major array.
+// Visit the band entries (i, j), |i - j| <= bw, of an m x m matrix.
 template <class Team, class F> OST_HD void for_band(Team& t, int m, int bw, F f) {
   const int wd = 2 * bw + 1;
   if (wd >= m) {
-    for (int e = t.rank(); e < m * m; e += t.size()) f(e);
+    for (int e = t.rank(); e < m * m; e += t.size()) {
+      const int i = e / m;
+      f(i, e - i * m);
+    }
   } else {
     for (int e = t.rank(); e < m * wd; e += t.size()) {
       int i = e / wd, j = i - bw + (e - i * wd);
-      if (j >= 0 && j < m) f(i * m + j);
+      if (j >= 0 && j < m) f(i, j);
     }
   }
 }
@@ -59,11 +62,12 @@ struct FwState {
 };
 
 // Step set-up of world w: contact refresh, warm start, FB scales and the
-// residual at the warm start (Sec. III-A, III-B).
+// residual at the warm start (Sec. III-A, III-B).  Returns false when the
+// world's active contacts do not fit the carve (nothing else is done).
 template <class Team>
-OST_HD void fw_begin(Team& t, const Batch& B, const Params& P, WorldRef& R, const double* q_prev,
+OST_HD bool fw_begin(Team& t, const Batch& B, const Params& P, WorldRef& R, const double* q_prev,
                      const double* u_prev, const double* lam_prev, const double* ctrl, WorldMem& M, FwState& S) {
-  prologue(t, B, P, R, q_prev, u_prev, ctrl, lam_prev, M);
+  if (!prologue(t, B, P, R, q_prev, u_prev, ctrl, lam_prev, M)) return false;
   clamp_all(t, P, R, M, M.lam);
   fb_scales(t, B, P, R, M, ctrl);
   S.st = M.iscal[1] ? ST_OVERFLOW : 0;
@@ -83,6 +87,7 @@ OST_HD void fw_begin(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
     S.done = 1;
   }
   t.sync();
+  return true;
 }
 
 // Dot product over a fixed partition into 64 lanes (independent of the team size).
@@ -251,7 +256,7 @@ OST_HD void fw_iteration(Team& t, const Batch& B, const Params& P, const WorldRe
     }
   } else {
     double dreg;
-    if (!factor(t, P, R, M, true, &dreg, &S.st)) {
+    if (!factor(t, P, R, M, true, P.dreg, &dreg, &S.st)) {
       S.st |= ST_NONFINITE;
       S.done = 1;
       return;
@@ -354,11 +359,14 @@ OST_HD void fw_end(Team& t, const Batch& B, const Params& P, const WorldRef& R, 
     for (int i = t.rank(); i < m; i += t.size()) M.lam[i] = M.lambest[i];
     t.sync();
     evaluate(t, B, P, R, M, ctrl, M.u, M.lam, true);
-    double dreg = P.dreg;
+    // the adjoint's factor, regularised by its own dreg_adj: the root does not
+    // depend on the Newton iterations' regularisation, the adjoint would
+    double dreg = P.dreg_adj;
     int fst = 0;
-    bool ok = factor(t, P, R, M, false, &dreg, &fst);
+    bool ok = factor(t, P, R, M, false, P.dreg_adj, &dreg, &fst);
     double* tw = tape + tape_off[w];
-    for_band(t, m, R.bw, [&](int e) { tw[e] = M.A[e]; });
+    const int ld = lda(m);  // the tape keeps row stride m
+    for_band(t, m, R.bw, [&](int i, int j) { tw[i * m + j] = M.A[i * ld + j]; });
     if (t.rank() == 0) {
       double* tr = tape + tape_off[w + 1] - 4;
       tr[0] = dreg;
@@ -407,20 +415,22 @@ OST_HD void fw_end(Team& t, const Batch& B, const Params& P, const WorldRef& R, 
 }
 
 // One backward-Euler step of world w (Sec. III-A..C), fused: set-up, the
-// Newton loop and finalisation in one pass of the team.
+// Newton loop and finalisation in one pass of the team.  Returns false, with
+// no output written, when the world's active contacts exceed the carve.
 template <class Team, bool kKrylov = false>
-OST_HD void forward_world(Team& t, const Batch& B, const Params& P, const Caps& caps, int w, const double* q_prev,
+OST_HD bool forward_world(Team& t, const Batch& B, const Params& P, const Caps& caps, int w, const double* q_prev,
                           const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
                           double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
                           int32_t* iters_out, double* resnorm, double* tape, const int64_t* tape_off,
                           WorldMem& M) {
   WorldRef R = world_ref(B, w);
   FwState S;
-  fw_begin(t, B, P, R, q_prev, u_prev, lam_prev, ctrl, M, S);
-  const int room = caps.mr * caps.mr + kPadA;  // doubles of the Schur matrix's storage
+  if (!fw_begin(t, B, P, R, q_prev, u_prev, lam_prev, ctrl, M, S)) return false;
+  const int room = (int)M.a_room;  // doubles of the Schur matrix's storage
   for (int k = 1; k <= P.kmax && !S.done; ++k) fw_iteration<Team, kKrylov>(t, B, P, R, ctrl, M, S, k, room);
   fw_end(t, B, P, R, w, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters_out, resnorm, tape, tape_off,
          M, S);
+  return true;
 }
 
 // Loop state kept in the world's workspace between the launches of the plain
@@ -579,10 +589,11 @@ constexpr double kKryTol = 1e-12;
 // Gram-Schmidt, Givens rotations) from x = 0, at most `max_apply` operator
 // applications, stopping at a residual of kKryTol |c|.  The residual never
 // grows, whatever the spectral radius of S h K^T (a fixed-point iteration
-// on the same operator diverges once that radius reaches one).  Returns the
-// number of applications.
+// on the same operator diverges once that radius reaches one).  Returns
+// whether the stop was reached (or the Krylov space holds the solution);
+// false when the applications ran out first or a value was not finite.
 template <class Team>
-OST_HD int adjoint_krylov(Team& t, const Batch& B, const Params& P, const WorldRef& R, WorldMem& M,
+OST_HD bool adjoint_krylov(Team& t, const Batch& B, const Params& P, const WorldRef& R, WorldMem& M,
                           const double* ctrl, const double* c, int max_apply) {
   const int n = 6 * R.nb;
   double *V = M.kv, *x = M.kx, *H = M.kh, *cs = M.kcs, *sn = M.ksn, *gv = M.kgv, *y = M.ky;
@@ -592,6 +603,7 @@ OST_HD int adjoint_krylov(Team& t, const Batch& B, const Params& P, const WorldR
   t.sync();
   double beta = cn;  // |c - A x| at x = 0
   int used = 0;
+  bool ok = cn <= stop;
   while (used < max_apply && beta > stop) {
     for (int e = t.rank(); e < n; e += t.size()) V[e] = V[e] / beta;
     if (t.rank() == 0) {
@@ -634,6 +646,7 @@ OST_HD int adjoint_krylov(Team& t, const Batch& B, const Params& P, const WorldR
       }
       t.sync();
       res = ::fabs(gv[k + 1]);
+      ok = res <= stop || hn == 0.0;
       ++k;
     }
     if (t.rank() == 0)  // the k x k triangle: H y = g
@@ -655,8 +668,9 @@ OST_HD int adjoint_krylov(Team& t, const Batch& B, const Params& P, const WorldR
     for (int e = t.rank(); e < n; e += t.size()) V[e] = c[e] - V[e];
     t.sync();
     beta = ::sqrt(dot64(t, M, V, V, n));
+    ok = beta <= stop;
   }
-  return used;
+  return ok;
 }
 
 // Dual input of a group with body data recomputed from q- (seeded), used by
@@ -670,16 +684,20 @@ OST_HD void dual_pose(const double* q, int seeded, int comp, v3<dual>& x, m3<dua
 
 // Implicit adjoint of one world-step (Sec. III-D): loss cotangents on s+ to
 // cotangents on q-, u- and the controls, through the exact implicit-function
-// Jacobian reached by `refine` sweeps on the stored factor.
+// Jacobian, solved by the Krylov method on the stored factor with at most
+// `refine` operator applications (ST_ADJ_INEXACT is ORed into adj_status[w]
+// when it ends above its stop).  Returns false, with no output written, when
+// the world's active contacts exceed the carve.
 template <class Team>
-OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& caps, int w, const double* q_prev,
+OST_HD bool adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& caps, int w, const double* q_prev,
                           const double* u_prev, const double* ctrl, const double* u_next, const double* lam_next,
                           const double* tape, const int64_t* tape_off, const double* gq_next,
                           const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl, int refine,
-                          WorldMem& M, double* g_mass = nullptr, double* g_mu = nullptr, double* g_kp = nullptr) {
+                          WorldMem& M, double* g_mass = nullptr, double* g_mu = nullptr, double* g_kp = nullptr,
+                          int32_t* adj_status = nullptr) {
   WorldRef R = world_ref(B, w);
   const double h = P.h;
-  prologue(t, B, P, R, q_prev, u_prev, ctrl, lam_next, M);
+  if (!prologue(t, B, P, R, q_prev, u_prev, ctrl, lam_next, M)) return false;
   fb_scales(t, B, P, R, M, ctrl);
   const int nb = R.nb, m = R.m;
   for (int i = t.rank(); i < 6 * nb; i += t.size()) M.u[i] = u_next[6 * R.b0 + i];
@@ -688,12 +706,13 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
   const double* tw = tape + tape_off[w];
   const double* tr = tape + tape_off[w + 1] - 4;
   if (tr[2] == 1.0 && (int)tr[1] == m && (int)tr[3] == R.bw) {
-    for_band(t, m, R.bw, [&](int e) { M.A[e] = tw[e]; });
+    const int ld = lda(m);
+    for_band(t, m, R.bw, [&](int i, int j) { M.A[i * ld + j] = tw[i * m + j]; });
     t.sync();
   } else {  // no usable stored factor: factor here
     double dreg;
     int fst = 0;
-    factor(t, P, R, M, false, &dreg, &fst);
+    factor(t, P, R, M, false, P.dreg_adj, &dreg, &fst);
   }
   // loss cotangent on the raw q+ (through the renormalisation) and the total
   // velocity cotangent b = g_u + h G(q-)^T g_q
@@ -729,7 +748,8 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
   // geometric stiffness h K that the factor leaves out: the Krylov solve gives
   // the velocity part x, then one solve with [b - h K^T x; 0] gives w_u, w_l
   if (refine > 0 && M.kv) {
-    adjoint_krylov(t, B, P, R, M, ctrl, wu, refine);
+    const bool solved = adjoint_krylov(t, B, P, R, M, ctrl, wu, refine);
+    if (!solved && adj_status && t.rank() == 0) adj_status[w] |= ST_ADJ_INEXACT;
     stiffness_t(t, B, P, R, M, ctrl, M.kx, M.kg);
     for (int p = t.rank(); p < 6 * nb; p += t.size()) M.ubest[p] = M.rdyn[p] - h * M.kg[p];
     t.sync();
@@ -938,6 +958,7 @@ OST_HD void adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
       g_mu[R.s0 + s] = g;
     }
   t.sync();
+  return true;
 }
 
 }  // namespace ost

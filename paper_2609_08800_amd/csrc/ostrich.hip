@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <memory>
 #include <cstring>
 #include <string>
@@ -149,9 +150,22 @@ struct Launch {
   int split;             // ost::SPLIT_LDS or ost::SPLIT_GLOBAL
   double* gscr;          // SPLIT_GLOBAL: per-workgroup slices of gstride doubles
   size_t gstride;
+  const int32_t* nlist_dev;  // not null: the list length is read from device memory here
+  int32_t* defer;        // not null: a world whose active contacts exceed the carve is appended to
+                         // defer[1..] (defer[0] counts them) for a launch with the full carve
 };
 
-template <class TeamT, bool kKrylov>
+// Number of worlds of a launch's list.
+__device__ __forceinline__ int list_len(const Launch& L) { return L.nlist_dev ? *L.nlist_dev : L.nlist; }
+
+// Hand world w to the launch that follows (one thread of the team).
+__device__ __forceinline__ void defer_world(const Launch& L, int w) {
+  if (L.defer && threadIdx.x == 0) L.defer[1 + atomicAdd(L.defer, 1)] = w;
+}
+
+// kRest marks the launch over the deferred worlds of a tiered bucket (the same
+// code under its own name, so that profiles tell the two launches apart).
+template <class TeamT, bool kKrylov, bool kRest = false>
 __global__ void __launch_bounds__(256) k_forward(ost::Batch B, ost::Params P, ost::Caps caps, Launch L,
                                                  const double* q_prev, const double* u_prev, const double* lam_prev,
                                                  const double* ctrl, double* q_next, double* u_next,
@@ -165,21 +179,24 @@ __global__ void __launch_bounds__(256) k_forward(ost::Batch B, ost::Params P, os
   ost::WorldMem M = TeamT::kGlobal
                         ? ost::carve(smem, caps, blockDim.x, L.split, L.gscr ? L.gscr + blockIdx.x * L.gstride : nullptr)
                         : ost::carve(smem, caps, blockDim.x, ost::SPLIT_LDS, nullptr);
-  for (int i = blockIdx.x; i < L.nlist; i += gridDim.x) {
-    ost::forward_world<TeamT, kKrylov>(t, B, P, caps, L.wlist[i], q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
-                       act_slot, n_act, status, iters, resnorm, tape, tape_off, M);
+  const int n = list_len(L);
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int w = L.wlist[i];
+    if (!ost::forward_world<TeamT, kKrylov>(t, B, P, caps, w, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
+                                            act_slot, n_act, status, iters, resnorm, tape, tape_off, M))
+      defer_world(L, w);
     __syncthreads();
   }
 }
 
-template <class TeamT>
+template <class TeamT, bool kRest = false>
 __global__ void __launch_bounds__(256) k_adjoint(ost::Batch B, ost::Params P, ost::Caps caps, Launch L,
                                                  const double* q_prev, const double* u_prev, const double* ctrl,
                                                  const double* u_next, const double* lam_next, const double* tape,
                                                  const int64_t* tape_off, const double* gq_next,
                                                  const double* gu_next, double* gq_prev, double* gu_prev,
                                                  double* g_ctrl, int refine, double* g_mass, double* g_mu,
-                                                 double* g_kp) {
+                                                 double* g_kp, int32_t* adj_status) {
   extern __shared__ __align__(16) char smem[];
   TeamT t;
   // the on-chip instantiation carves with a constant split, so that every
@@ -188,9 +205,12 @@ __global__ void __launch_bounds__(256) k_adjoint(ost::Batch B, ost::Params P, os
                         ? ost::carve(smem, caps, blockDim.x, L.split, L.gscr ? L.gscr + blockIdx.x * L.gstride : nullptr,
                                       true)
                         : ost::carve(smem, caps, blockDim.x, ost::SPLIT_LDS, nullptr, true);
-  for (int i = blockIdx.x; i < L.nlist; i += gridDim.x) {
-    ost::adjoint_world(t, B, P, caps, L.wlist[i], q_prev, u_prev, ctrl, u_next, lam_next, tape, tape_off,
-                       gq_next, gu_next, gq_prev, gu_prev, g_ctrl, refine, M, g_mass, g_mu, g_kp);
+  const int n = list_len(L);
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int w = L.wlist[i];
+    if (!ost::adjoint_world(t, B, P, caps, w, q_prev, u_prev, ctrl, u_next, lam_next, tape, tape_off, gq_next,
+                            gu_next, gq_prev, gu_prev, g_ctrl, refine, M, g_mass, g_mu, g_kp, adj_status))
+      defer_world(L, w);
     __syncthreads();
   }
 }
@@ -300,12 +320,26 @@ __global__ void k_fill(double* p, long n, double v) {
   if (i < n) p[i] = v;
 }
 
-// loss |xy(loss_body) - target|^2 and its cotangent on q_T
+// Body row of world w's loss body, or -1 (status bit ST_LOSS_BODY) when
+// loss_body[w] is not one of the world's bodies.
+__device__ int loss_row(const int32_t* body_off, const int32_t* loss_body, int w, int32_t* status) {
+  const int lb = loss_body[w];
+  if (lb >= 0 && lb < body_off[w + 1] - body_off[w]) return body_off[w] + lb;
+  if (status) status[w] |= ost::ST_LOSS_BODY;
+  return -1;
+}
+
+// loss |xy(loss_body) - target|^2 and its cotangent on q_T (NaN loss and no
+// cotangent for a loss body outside its world)
 __global__ void k_loss(const int32_t* body_off, int W, const double* qT, const int32_t* loss_body,
-                       const double* target, const double* loss_grad, double* loss, double* gq) {
+                       const double* target, const double* loss_grad, double* loss, double* gq, int32_t* status) {
   int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
-  int b = body_off[w] + loss_body[w];
+  const int b = loss_row(body_off, loss_body, w, status);
+  if (b < 0) {
+    if (loss) loss[w] = NAN;
+    return;
+  }
   double dx = qT[7 * b] - target[2 * w], dy = qT[7 * b + 1] - target[2 * w + 1];
   if (loss) loss[w] = dx * dx + dy * dy;
   if (gq) {
@@ -347,10 +381,14 @@ __device__ double yaw_term(const double* qb, double rho, double wt, double* dq) 
 // times loss_grad[w], to the state's gq, gu (if gq).
 __global__ void k_state_loss(const int32_t* body_off, int W, const double* q, const double* u,
                              const int32_t* loss_body, LossDev L, int k, int T, const double* loss_grad,
-                             double* loss, double* gq, double* gu) {
+                             double* loss, double* gq, double* gu, int32_t* status) {
   int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
-  const int b = body_off[w] + loss_body[w];
+  const int b = loss_row(body_off, loss_body, w, status);
+  if (b < 0) {
+    if (loss) loss[w] = NAN;
+    return;
+  }
   const double* qb = q + 7 * b;
   const double* ub = u + 6 * b;
   double dq[7] = {0, 0, 0, 0, 0, 0, 0}, du[3] = {0, 0, 0};
@@ -442,6 +480,14 @@ struct Bucket {
   double* gscr = nullptr;
   size_t gstride = 0;
   bool tuned = false;
+  // Tiered on-chip launch: a first launch carves for at most caps1.nc active
+  // contacts (more workgroups per CU), and the worlds with more are done by a
+  // second, persistent launch with the full carve.
+  bool tier = false;
+  ost::Caps caps1{0, 0, 0, 0, 0, 0};
+  size_t lds1 = 0, lds1_adj = 0;
+  int grid2 = 0;
+  int32_t* d_defer = nullptr;  // [0] deferred count, [1..] their world ids
 };
 
 // Row capacity edges of the buckets: a world with row cap mr goes to the first
@@ -456,6 +502,7 @@ struct ostrich_ctx {
   ost::Caps caps;  // maxima over the batch
   int team;
   int schedule;
+  int tier_contacts;  // ostrich_params::tier_contacts
   size_t lds_limit;
   int n_cu;
   int W, NB, NL, NS, NCTRL;
@@ -478,10 +525,12 @@ struct ostrich_ctx {
   size_t n_eva = 0;
   int64_t* d_tape_off = nullptr;
   size_t tape_total = 0;  // doubles
+  std::map<void*, size_t> allocs;  // device memory held by the context, by allocation
   ~ostrich_ctx() {
     for (auto& b : buckets) {
       if (b.d_worlds) (void)hipFree(b.d_worlds);
       if (b.gscr) (void)hipFree(b.gscr);
+      if (b.d_defer) (void)hipFree(b.d_defer);
     }
     if (all.gscr) (void)hipFree(all.gscr);
     if (all.d_worlds) (void)hipFree(all.d_worlds);
@@ -507,9 +556,54 @@ static ost::Caps caps_max(const ost::Caps& a, const ost::Caps& b) {
 
 static bool team_ok(int t) { return t == 64 || t == 128 || t == 256; }
 
-// Decide the storage split of a bucket for a team size and (re)allocate its
-// device scratch; fails if the world does not fit either way.
-static int configure_bucket(ostrich_ctx* ctx, Bucket& bk, int team, int split) {
+// Device allocations owned by the context, counted for ostrich_ctx_device_bytes.
+template <class T> static hipError_t ctx_malloc(ostrich_ctx* ctx, T** p, size_t bytes) {
+  hipError_t e = hipMalloc((void**)p, bytes);
+  if (e == hipSuccess) ctx->allocs[(void*)*p] = bytes;
+  return e;
+}
+static hipError_t ctx_free(ostrich_ctx* ctx, void* p) {
+  if (!p) return hipSuccess;
+  ctx->allocs.erase(p);
+  return hipFree(p);
+}
+
+// Fewest active contacts a tiered first launch carves for.
+const int kTierMinContacts = 4;
+
+// Carve of a tiered first launch: the largest contact capacity below the
+// bucket's whose adjoint workspace lets more workgroups share a CU than the
+// full carve does, up to the limit the kernels' registers set (two wavefronts
+// per SIMD).  False when no such carve exists.
+static bool tier_caps(const ostrich_ctx* ctx, const Bucket& bk, int team, ost::Caps* out) {
+  if (ctx->tier_contacts < 0) return false;
+  if (ctx->tier_contacts > 0) {  // a requested count
+    if (ctx->tier_contacts >= bk.caps.nc) return false;
+    ost::Caps c = bk.caps;
+    c.nc = ctx->tier_contacts;
+    c.mr = std::min(bk.caps.mr, 5 * bk.caps.nj + bk.caps.nsv + 3 * c.nc);
+    *out = c;
+    return true;
+  }
+  const int occ_full = (int)(ctx->lds_limit / std::max<size_t>(1, ost::world_lds_bytes(bk.caps, team, ost::SPLIT_LDS, true)));
+  const int occ_max = std::max(1, 8 / (team / 64));
+  for (int occ = occ_max; occ > occ_full; --occ)
+    for (int nc = bk.caps.nc - 1; nc >= kTierMinContacts; --nc) {
+      ost::Caps c = bk.caps;
+      c.nc = nc;
+      c.mr = std::min(bk.caps.mr, 5 * bk.caps.nj + bk.caps.nsv + 3 * nc);
+      if (ost::world_lds_bytes(c, team, ost::SPLIT_LDS, true) * occ <= ctx->lds_limit) {
+        *out = c;
+        return true;
+      }
+    }
+  return false;
+}
+
+// Decide the storage split (and, on chip, the tiering) of a bucket for a team
+// size and (re)allocate its device scratch; fails if the world does not fit
+// either way.
+static int configure_bucket(ostrich_ctx* ctx, Bucket& bk, int team, int split, bool tier = true) {
   size_t lds = ost::world_lds_bytes(bk.caps, team, split);
   size_t lds_adj = ost::world_lds_bytes(bk.caps, team, split, true);
   if (lds_adj > ctx->lds_limit) return fail(OSTRICH_E_UNSUPPORTED, "bucket does not fit in LDS");
@@ -517,15 +611,23 @@ static int configure_bucket(ostrich_ctx* ctx, Bucket& bk, int team, int split) {
   bk.split = split;
   bk.lds = lds;
   bk.lds_adj = lds_adj;
+  bk.tier = split == ost::SPLIT_LDS && tier && tier_caps(ctx, bk, team, &bk.caps1);
+  if (bk.tier) {
+    bk.lds1 = ost::world_lds_bytes(bk.caps1, team, ost::SPLIT_LDS);
+    bk.lds1_adj = ost::world_lds_bytes(bk.caps1, team, ost::SPLIT_LDS, true);
+    const size_t per_cu = std::max<size_t>(1, ctx->lds_limit / lds_adj);
+    bk.grid2 = (int)std::min<size_t>(bk.worlds.size(), per_cu * ctx->n_cu);
+    if (!bk.d_defer) HIP_OK(ctx_malloc(ctx, &bk.d_defer, (bk.worlds.size() + 1) * sizeof(int32_t)));
+  }
   if (split == ost::SPLIT_GLOBAL) {
     size_t per_cu = std::max<size_t>(1, ctx->lds_limit / std::max<size_t>(lds, 1));
     per_cu = std::min<size_t>(per_cu, 2048 / team);
     int slots = (int)std::min<size_t>(bk.worlds.size(), per_cu * ctx->n_cu);
     size_t stride = (ost::world_glob_doubles(bk.caps, split) + 31) & ~size_t(31);
     if (!bk.gscr || slots * stride > (size_t)bk.slots * bk.gstride) {
-      if (bk.gscr) HIP_OK(hipFree(bk.gscr));
+      if (bk.gscr) HIP_OK(ctx_free(ctx, bk.gscr));
       bk.gscr = nullptr;
-      HIP_OK(hipMalloc(&bk.gscr, sizeof(double) * stride * slots));
+      HIP_OK(ctx_malloc(ctx, &bk.gscr, sizeof(double) * stride * slots));
     }
     bk.slots = slots;
     bk.gstride = stride;
@@ -543,7 +645,15 @@ static int default_config(ostrich_ctx* ctx, Bucket& bk) {
 
 static Launch launch_of(const Bucket& bk) {
   return Launch{bk.d_worlds, (int)bk.worlds.size(), bk.split, bk.split == ost::SPLIT_GLOBAL ? bk.gscr : nullptr,
-                bk.gstride};
+                bk.gstride, nullptr, nullptr};
+}
+// The two launches of a tiered bucket: the whole list with the first carve,
+// deferring to the list it fills; then that list with the full carve.
+static Launch launch_tier1(const Bucket& bk) {
+  return Launch{bk.d_worlds, (int)bk.worlds.size(), ost::SPLIT_LDS, nullptr, 0, nullptr, bk.d_defer};
+}
+static Launch launch_tier2(const Bucket& bk) {
+  return Launch{bk.d_defer + 1, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_defer, nullptr};
 }
 
 static int grid_of(const Bucket& bk) {
@@ -554,7 +664,8 @@ static int grid_of(const Bucket& bk) {
 extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* p, ostrich_ctx** out) {
   if (!b || !p || !out) return fail(OSTRICH_E_ARG, "null argument");
   if (b->n_worlds < 1) return fail(OSTRICH_E_ARG, "n_worlds must be >= 1");
-  if (!(p->h > 0.0) || p->k_max < 0 || p->k_min < 0 || p->ls_max < 0 || !(p->tol >= 0.0) || !(p->eps > 0.0))
+  if (!(p->h > 0.0) || p->k_max < 0 || p->k_min < 0 || p->ls_max < 0 || !(p->tol >= 0.0) || !(p->eps > 0.0) ||
+      !(p->delta_reg > 0.0) || !(p->delta_reg_adj > 0.0))
     return fail(OSTRICH_E_ARG, "invalid solver parameters");
   if (p->schedule != OSTRICH_SCHED_FIXED && p->schedule != OSTRICH_SCHED_BUCKETED)
     return fail(OSTRICH_E_ARG, "schedule must be OSTRICH_SCHED_FIXED or OSTRICH_SCHED_BUCKETED");
@@ -600,7 +711,8 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   ctx->lds_limit = prop.sharedMemPerBlock;
   ctx->n_cu = std::max(1, prop.multiProcessorCount);
   for (auto f : {(const void*)k_forward<GpuTeam, false>, (const void*)k_adjoint<GpuTeam>,
-                 (const void*)k_forward<GpuTeamG, false>, (const void*)k_adjoint<GpuTeamG>})
+                 (const void*)k_forward<GpuTeamG, false>, (const void*)k_adjoint<GpuTeamG>,
+                 (const void*)k_forward<GpuTeam, false, true>, (const void*)k_adjoint<GpuTeam, true>})
     HIP_OK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctx->lds_limit));
   std::memcpy(&ctx->B, b, sizeof(ost::Batch));
   static_assert(sizeof(ost::Batch) == sizeof(ostrich_batch), "batch layouts differ");
@@ -610,6 +722,7 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   ctx->P.eps = p->eps;
   ctx->P.dg = p->delta_g;
   ctx->P.dreg = p->delta_reg;
+  ctx->P.dreg_adj = p->delta_reg_adj;
   ctx->P.d0 = p->delta0;
   ctx->P.kmax = p->k_max;
   ctx->P.kmin = std::min(p->k_min, p->k_max);
@@ -624,6 +737,7 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   ctx->P.lin = p->linear_solver;
   ctx->P.lin_iters = p->krylov_iters > 0 ? p->krylov_iters : 16;
   ctx->refine = p->refine;
+  ctx->tier_contacts = p->tier_contacts;
   ctx->caps = c;
   ctx->team = team;
   ctx->schedule = p->schedule;
@@ -652,7 +766,7 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
       if (!x.worlds.empty()) ctx->buckets.push_back(std::move(x));
   }
   for (auto& x : ctx->buckets) {
-    HIP_OK(hipMalloc(&x.d_worlds, x.worlds.size() * sizeof(int32_t)));
+    HIP_OK(ctx_malloc(ctx.get(), &x.d_worlds, x.worlds.size() * sizeof(int32_t)));
     HIP_OK(hipMemcpy(x.d_worlds, x.worlds.data(), x.worlds.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     int rc = default_config(ctx.get(), x);
     if (rc) return fail(OSTRICH_E_UNSUPPORTED, "a world with " + std::to_string(x.caps.mr) +
@@ -660,11 +774,11 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   }
   for (int w = 0; w < W; ++w) ctx->all.worlds.push_back(w);
   ctx->all.caps = c;
-  HIP_OK(hipMalloc(&ctx->all.d_worlds, W * sizeof(int32_t)));
+  HIP_OK(ctx_malloc(ctx.get(), &ctx->all.d_worlds, W * sizeof(int32_t)));
   HIP_OK(hipMemcpy(ctx->all.d_worlds, ctx->all.worlds.data(), W * sizeof(int32_t), hipMemcpyHostToDevice));
   if (default_config(ctx.get(), ctx->all))
     return fail(OSTRICH_E_UNSUPPORTED, "the batch does not fit a workgroup");
-  HIP_OK(hipMalloc(&ctx->plain_ws, ost::world_lds_bytes(c, kPlainTeam) + 256));
+  HIP_OK(ctx_malloc(ctx.get(), &ctx->plain_ws, ost::world_lds_bytes(c, kPlainTeam) + 256));
   if (ctx->buckets.size() > 1) {  // streams of default priority, events without timing
     HIP_OK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
     for (size_t i = 0; i < ctx->buckets.size(); ++i) {
@@ -676,7 +790,7 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
       ctx->ev_join.push_back(e);
     }
   }
-  HIP_OK(hipMalloc(&ctx->d_tape_off, (W + 1) * sizeof(int64_t)));
+  HIP_OK(ctx_malloc(ctx.get(), &ctx->d_tape_off, (W + 1) * sizeof(int64_t)));
   HIP_OK(hipMemcpy(ctx->d_tape_off, toff.data(), (W + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
   *out = ctx.release();
   return 0;
@@ -685,6 +799,13 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
 extern "C" int ostrich_ctx_destroy(ostrich_ctx* ctx) {
   delete ctx;
   return 0;
+}
+
+extern "C" size_t ostrich_ctx_device_bytes(const ostrich_ctx* ctx) {
+  if (!ctx) return 0;
+  size_t n = 0;
+  for (const auto& a : ctx->allocs) n += a.second;
+  return n;
 }
 
 extern "C" int ostrich_ctx_caps(const ostrich_ctx* ctx, int64_t* out) {
@@ -706,13 +827,15 @@ extern "C" int ostrich_ctx_schedule(const ostrich_ctx* ctx, int32_t* out, int32_
   if (out)
     for (int i = 0; i < std::min(n, (int)max_buckets); ++i) {
       const Bucket& b = ctx->buckets[i];
-      int32_t* o = out + 6 * i;
+      int32_t* o = out + 8 * i;
       o[0] = b.caps.mr;
       o[1] = (int32_t)b.worlds.size();
       o[2] = b.team;
       o[3] = b.split;
       o[4] = (int32_t)b.lds;
       o[5] = b.tuned ? 1 : 0;
+      o[6] = b.tier ? b.caps1.nc : 0;
+      o[7] = b.tier ? (int32_t)b.lds1 : 0;
     }
   return n;
 }
@@ -748,6 +871,16 @@ static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, c
                            const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
                            double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
                            int32_t* iters, double* resnorm, double* tape) {
+  if (bk.tier) {
+    hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, st, bk.d_defer, 1);
+    hipLaunchKernelGGL((k_forward<GpuTeam, false, false>), dim3(grid_of(bk)), dim3(bk.team), bk.lds1, st, ctx->B,
+                       ctx->P, bk.caps1, launch_tier1(bk), q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
+                       act_slot, n_act, status, iters, resnorm, tape, (const int64_t*)ctx->d_tape_off);
+    hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(bk.grid2), dim3(bk.team), bk.lds, st, ctx->B, ctx->P,
+                       bk.caps, launch_tier2(bk), q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot,
+                       n_act, status, iters, resnorm, tape, (const int64_t*)ctx->d_tape_off);
+    return;
+  }
   auto kf = forward_kernel(ctx, bk);
   hipLaunchKernelGGL(kf, dim3(grid_of(bk)), dim3(bk.team), bk.lds, st, ctx->B, ctx->P, bk.caps,
                      launch_of(bk), q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act,
@@ -790,7 +923,7 @@ extern "C" int ostrich_step_forward(ostrich_ctx* ctx, const double* q_prev, cons
 extern "C" int ostrich_ctx_timing(ostrich_ctx* ctx, int32_t mode, double* out) {
   if (!ctx) return fail(OSTRICH_E_ARG, "null context");
   if (mode == 1 || mode == 0) {  // start (reset) or stop
-    if (!ctx->d_flops) HIP_OK(hipMalloc(&ctx->d_flops, 2 * sizeof(double)));
+    if (!ctx->d_flops) HIP_OK(ctx_malloc(ctx, &ctx->d_flops, 2 * sizeof(double)));
     if (mode == 1) {
       HIP_OK(hipDeviceSynchronize());
       const double z[2] = {0.0, 0.0};
@@ -826,7 +959,7 @@ extern "C" int ostrich_ctx_timing(ostrich_ctx* ctx, int32_t mode, double* out) {
 static int adjoint_step(ostrich_ctx* ctx, const double* q_prev, const double* u_prev, const double* ctrl,
                         const double* u_next, const double* lam_next, const void* tape, const double* gq_next,
                         const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl, double* g_mass,
-                        double* g_mu, double* g_kp, int32_t refine, void* stream) {
+                        double* g_mu, double* g_kp, int32_t refine, int32_t* adj_status, void* stream) {
   if (!ctx || !q_prev || !u_prev || !u_next || !lam_next || !tape || !gq_next || !gu_next || !gq_prev || !gu_prev)
     return fail(OSTRICH_E_ARG, "null pointer");
   if (ctx->NCTRL > 0 && (!ctrl || !g_ctrl)) return fail(OSTRICH_E_ARG, "controls required");
@@ -843,11 +976,23 @@ static int adjoint_step(ostrich_ctx* ctx, const double* q_prev, const double* u_
     HIP_OK(hipEventRecord(ctx->eva[ctx->n_eva], (hipStream_t)stream));
   }
   int rc = for_buckets(ctx, (hipStream_t)stream, [&](const Bucket& bk, hipStream_t s) {
+    if (bk.tier) {
+      hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, s, bk.d_defer, 1);
+      hipLaunchKernelGGL((k_adjoint<GpuTeam, false>), dim3(grid_of(bk)), dim3(bk.team), bk.lds1_adj, s, ctx->B,
+                         ctx->P, bk.caps1, launch_tier1(bk), q_prev, u_prev, ctrl, u_next, lam_next,
+                         (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev,
+                         g_ctrl, rf, g_mass, g_mu, g_kp, adj_status);
+      hipLaunchKernelGGL((k_adjoint<GpuTeam, true>), dim3(bk.grid2), dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P,
+                         bk.caps, launch_tier2(bk), q_prev, u_prev, ctrl, u_next, lam_next, (const double*)tape,
+                         (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass,
+                         g_mu, g_kp, adj_status);
+      return;
+    }
     hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>, dim3(grid_of(bk)),
                        dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P,
                        bk.caps, launch_of(bk), q_prev, u_prev, ctrl, u_next, lam_next, (const double*)tape,
                        (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass,
-                       g_mu, g_kp);
+                       g_mu, g_kp, adj_status);
   });
   if (rc) return rc;
   if (timed) {
@@ -863,19 +1008,21 @@ static int adjoint_step(ostrich_ctx* ctx, const double* q_prev, const double* u_
 extern "C" int ostrich_step_adjoint(ostrich_ctx* ctx, const double* q_prev, const double* u_prev,
                                     const double* ctrl, const double* u_next, const double* lam_next,
                                     const void* tape, const double* gq_next, const double* gu_next, double* gq_prev,
-                                    double* gu_prev, double* g_ctrl, int32_t refine, void* stream) {
+                                    double* gu_prev, double* g_ctrl, int32_t refine, int32_t* adj_status,
+                                    void* stream) {
   return adjoint_step(ctx, q_prev, u_prev, ctrl, u_next, lam_next, tape, gq_next, gu_next, gq_prev, gu_prev, g_ctrl,
-                      nullptr, nullptr, nullptr, refine, stream);
+                      nullptr, nullptr, nullptr, refine, adj_status, stream);
 }
 
 extern "C" int ostrich_step_adjoint_params(ostrich_ctx* ctx, const double* q_prev, const double* u_prev,
                                            const double* ctrl, const double* u_next, const double* lam_next,
                                            const void* tape, const double* gq_next, const double* gu_next,
                                            double* gq_prev, double* gu_prev, double* g_ctrl, double* g_mass,
-                                           double* g_mu, double* g_kp, int32_t refine, void* stream) {
+                                           double* g_mu, double* g_kp, int32_t refine, int32_t* adj_status,
+                                           void* stream) {
   if (!g_mass || !g_mu || !g_kp) return fail(OSTRICH_E_ARG, "parameter cotangent outputs required");
   return adjoint_step(ctx, q_prev, u_prev, ctrl, u_next, lam_next, tape, gq_next, gu_next, gq_prev, gu_prev, g_ctrl,
-                      g_mass, g_mu, g_kp, refine, stream);
+                      g_mass, g_mu, g_kp, refine, adj_status, stream);
 }
 
 static Launch list_launch(const ostrich_ctx* ctx, const int32_t* worlds, int n) {
@@ -909,7 +1056,7 @@ extern "C" int ostrich_step_adjoint_list(ostrich_ctx* ctx, const int32_t* worlds
                                          const double* u_prev, const double* ctrl, const double* u_next,
                                          const double* lam_next, const void* tape, const double* gq_next,
                                          const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl,
-                                         int32_t refine, void* stream) {
+                                         int32_t refine, int32_t* adj_status, void* stream) {
   if (!ctx || !worlds || n < 0 || n > ctx->W) return fail(OSTRICH_E_ARG, "world list");
   if (!q_prev || !u_prev || !u_next || !lam_next || !tape || !gq_next || !gu_next || !gq_prev || !gu_prev)
     return fail(OSTRICH_E_ARG, "null pointer");
@@ -921,7 +1068,7 @@ extern "C" int ostrich_step_adjoint_list(ostrich_ctx* ctx, const int32_t* worlds
                      dim3(list_grid(ctx, n)), dim3(bk.team), bk.lds_adj, (hipStream_t)stream, ctx->B, ctx->P,
                      bk.caps, list_launch(ctx, worlds, n), q_prev, u_prev, ctrl, u_next, lam_next,
                      (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev,
-                     g_ctrl, rf, (double*)nullptr, (double*)nullptr, (double*)nullptr);
+                     g_ctrl, rf, (double*)nullptr, (double*)nullptr, (double*)nullptr, adj_status);
   HIP_OK(hipGetLastError());
   return 0;
 }
@@ -955,7 +1102,7 @@ extern "C" int ostrich_step_adjoint_plain(ostrich_ctx* ctx, const double* q_prev
                                           const double* ctrl, const double* u_next, const double* lam_next,
                                           const void* tape, const double* gq_next, const double* gu_next,
                                           double* gq_prev, double* gu_prev, double* g_ctrl, int32_t refine,
-                                          void* stream) {
+                                          int32_t* adj_status, void* stream) {
   if (!ctx || !q_prev || !u_prev || !u_next || !lam_next || !tape || !gq_next || !gu_next || !gq_prev || !gu_prev)
     return fail(OSTRICH_E_ARG, "null pointer");
   if (ctx->NCTRL > 0 && (!ctrl || !g_ctrl)) return fail(OSTRICH_E_ARG, "controls required");
@@ -967,7 +1114,7 @@ extern "C" int ostrich_step_adjoint_plain(ostrich_ctx* ctx, const double* q_prev
                        dim3(bk.team), bk.lds_adj, (hipStream_t)stream, ctx->B, ctx->P, bk.caps,
                        list_launch(ctx, bk.d_worlds + w, 1), q_prev, u_prev, ctrl, u_next, lam_next,
                        (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev,
-                       g_ctrl, rf, (double*)nullptr, (double*)nullptr, (double*)nullptr);
+                       g_ctrl, rf, (double*)nullptr, (double*)nullptr, (double*)nullptr, adj_status);
   HIP_OK(hipGetLastError());
   return 0;
 }
@@ -1005,25 +1152,33 @@ extern "C" int ostrich_autotune(ostrich_ctx* ctx, const double* q, const double*
   for (Bucket& bk : ctx->buckets) {
     float best = 1e30f;
     int bt = bk.team, bs = bk.split;
+    bool btier = bk.tier;
+    struct Cand { int split, team; bool tier; };
+    std::vector<Cand> cands;
     for (int split : {ost::SPLIT_LDS, ost::SPLIT_GLOBAL})
-      for (int team : {64, 128, 256}) {
-        if (ost::world_lds_bytes(bk.caps, team, split, true) > ctx->lds_limit) continue;
-        if ((rc = configure_bucket(ctx, bk, team, split))) break;
-        launch_forward(ctx, bk, st, q, u, lam, ctrl, qn, un, ln, as, na, ss, it, rn, nullptr);  // warm
-        (void)hipEventRecord(e0, st);
-        for (int r = 0; r < reps; ++r)
-          launch_forward(ctx, bk, st, q, u, lam, ctrl, qn, un, ln, as, na, ss, it, rn, nullptr);
-        (void)hipEventRecord(e1, st);
-        if (hipEventSynchronize(e1) != hipSuccess || hipGetLastError() != hipSuccess) {
-          rc = fail(OSTRICH_E_HIP, "autotune launch failed");
-          break;
-        }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) { best = ms; bt = team; bs = split; }
+      for (int team : {64, 128, 256})
+        for (bool tier : {true, false})
+          if (ost::world_lds_bytes(bk.caps, team, split, true) <= ctx->lds_limit &&
+              (split == ost::SPLIT_LDS || !tier))
+            cands.push_back(Cand{split, team, tier});
+    for (const Cand& cd : cands) {
+      if ((rc = configure_bucket(ctx, bk, cd.team, cd.split, cd.tier))) break;
+      if (cd.tier && !bk.tier) continue;  // no tiered carve for this team: its untiered candidate follows
+      launch_forward(ctx, bk, st, q, u, lam, ctrl, qn, un, ln, as, na, ss, it, rn, nullptr);  // warm
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < reps; ++r)
+        launch_forward(ctx, bk, st, q, u, lam, ctrl, qn, un, ln, as, na, ss, it, rn, nullptr);
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess || hipGetLastError() != hipSuccess) {
+        rc = fail(OSTRICH_E_HIP, "autotune launch failed");
+        break;
       }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; bt = cd.team; bs = cd.split; btier = bk.tier; }
+    }
     if (rc) break;
-    if ((rc = configure_bucket(ctx, bk, bt, bs))) break;
+    if ((rc = configure_bucket(ctx, bk, bt, bs, btier))) break;
     bk.tuned = true;
   }
   (void)hipEventDestroy(e0);
@@ -1147,7 +1302,7 @@ static int rollout_run(ostrich_ctx* ctx, int32_t phase, const double* q0, const 
       if (loss && (per_step || (spec && k + 1 == T)))
         hipLaunchKernelGGL(k_state_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.body_off, W, st_q(nxt),
                            st_u(nxt), loss_body, LD, k + 1, (int)T, (const double*)nullptr, loss, (double*)nullptr,
-                           (double*)nullptr);
+                           (double*)nullptr, status_or);
       cur = nxt;
       if (ckpt_every > 0 && (k + 1) % ckpt_every == 0 && k + 1 < T) {
         double* dst = ck + (size_t)((k + 1) / ckpt_every) * L.S;
@@ -1163,7 +1318,7 @@ static int rollout_run(ostrich_ctx* ctx, int32_t phase, const double* q0, const 
     }
     if (!spec)
       hipLaunchKernelGGL(k_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.body_off, W, st_q(cur), loss_body,
-                         target, (const double*)nullptr, loss, (double*)nullptr);
+                         target, (const double*)nullptr, loss, (double*)nullptr, status_or);
     else if (ctrl_reg && loss)
       hipLaunchKernelGGL(k_ctrl_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.ctrl_off, W, ctrl, (int)T,
                          ctx->NCTRL, LD.w_ctrl / T, loss);
@@ -1178,16 +1333,16 @@ static int rollout_run(ostrich_ctx* ctx, int32_t phase, const double* q0, const 
                          (long)ctx->NCTRL * K, 0.0);
     if (!spec)
       hipLaunchKernelGGL(k_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.body_off, W, st_q(fin), loss_body,
-                         target, loss_grad, (double*)nullptr, gqa);
+                         target, loss_grad, (double*)nullptr, gqa, status_or);
     else
       hipLaunchKernelGGL(k_state_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.body_off, W, st_q(fin),
-                         st_u(fin), loss_body, LD, (int)T, (int)T, loss_grad, (double*)nullptr, gqa, gua);
+                         st_u(fin), loss_body, LD, (int)T, (int)T, loss_grad, (double*)nullptr, gqa, gua, status_or);
     double *gq = gqa, *gq2 = gqb, *gu = gua, *gu2 = gub;
     // adjoint of step k: cotangents of state k + 1 (its own loss terms included)
     // to those of state k, to which state k's loss terms are then added
     auto adj = [&](double* sm, double* sp, double* tp, int k) -> int {
       int r = ostrich_step_adjoint(ctx, st_q(sm), st_u(sm), ctrl_at(k), st_u(sp), st_l(sp), tp, gq, gu, gq2, gu2,
-                                   gc, -1, st);
+                                   gc, -1, status_or, st);
       if (r) return r;
       if (ctrl_reg)
         hipLaunchKernelGGL(k_ctrl_reg_grad, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.ctrl_off, W, ctrl_at(k),
@@ -1199,7 +1354,7 @@ static int rollout_run(ostrich_ctx* ctx, int32_t phase, const double* q0, const 
       std::swap(gu, gu2);
       if (per_step && k >= 1)
         hipLaunchKernelGGL(k_state_loss, dim3(nblk(W, 256)), dim3(256), 0, st, ctx->B.body_off, W, st_q(sm),
-                           st_u(sm), loss_body, LD, k, (int)T, loss_grad, (double*)nullptr, gq, gu);
+                           st_u(sm), loss_body, LD, k, (int)T, loss_grad, (double*)nullptr, gq, gu, status_or);
       return 0;
     };
     if (ckpt_every <= 0) {
@@ -1280,7 +1435,7 @@ extern "C" int ostrich_final_loss(const int32_t* body_off, int32_t n_worlds, con
   if (!body_off || !qT || !loss_body || !target || n_worlds < 0) return fail(OSTRICH_E_ARG, "final loss");
   if (n_worlds == 0) return 0;
   hipLaunchKernelGGL(k_loss, dim3(nblk(n_worlds, 256)), dim3(256), 0, (hipStream_t)stream, body_off, n_worlds, qT,
-                     loss_body, target, loss_grad, loss, gq);
+                     loss_body, target, loss_grad, loss, gq, (int32_t*)nullptr);
   HIP_OK(hipGetLastError());
   return 0;
 }

@@ -136,8 +136,7 @@ OST_HD long long bits_ll(double d) {
 template <class Team>
 OST_HD bool terrain_candidates(Team& t, const Batch& B, const Params& P, const WorldRef& R, const WorldMem& M) {
   if (R.hm.n < 2) return false;
-  const int mrw = 5 * R.nj + R.nsv + 3 * R.cap;
-  const size_t room = (size_t)mrw * mrw + kPadA;
+  const size_t room = M.a_room;  // the Schur matrix's storage in this carve
   if (t.rank() == 0) {
     int n = 0;
     for (int s = 0; s < R.ns; ++s)
@@ -191,8 +190,11 @@ OST_HD bool terrain_candidates(Team& t, const Batch& B, const Params& P, const W
   return true;
 }
 
+// Returns false, with only the workspace touched, when the world's active
+// contacts exceed the carve's contact capacity (M.nc_cap): the launch then
+// hands the world to one whose workspace holds them.
 template <class Team>
-OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, const double* q_prev,
+OST_HD bool prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, const double* q_prev,
                      const double* u_prev, const double* ctrl, const double* lam_prev, WorldMem& M) {
   const int nb = R.nb;
   for (int b = t.rank(); b < nb; b += t.size()) {
@@ -272,8 +274,10 @@ OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
   }
   t.sync();
   if (t.rank() == 0) {  // ascending-slot compaction, at most contact_cap; s_act becomes the position or -1
-    int nc = 0, of = 0;
-    for (int s = 0; s < R.ns; ++s)
+    int nc = 0, of = 0, na = 0;
+    for (int s = 0; s < R.ns; ++s) na += M.s_act[s];
+    M.iscal[10] = (na < R.cap ? na : R.cap) > M.nc_cap;
+    for (int s = 0; s < R.ns && !M.iscal[10]; ++s)
       if (M.s_act[s]) {
         if (nc < R.cap) {
           M.c_slot[nc] = s;
@@ -289,6 +293,7 @@ OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
     M.iscal[1] = of;
   }
   t.sync();
+  if (M.iscal[10]) return false;
   R.nc = M.iscal[0];
   R.m = 5 * R.nj + R.nsv + 3 * R.nc;
   for (int c = t.rank(); c < R.nc; c += t.size()) {
@@ -388,6 +393,7 @@ OST_HD void prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
   // servo inputs: the target speed, or the angle error theta* - theta(q-)
   for (int s = t.rank(); s < R.nsv; s += t.size()) M.sv_in[s] = servo_input(B, R, M, ctrl, M.r_idx[5 * R.nj + s]);
   t.sync();
+  return true;
 }
 
 // Clamp of the friction multipliers to the Coulomb disk of radius
@@ -513,7 +519,7 @@ OST_HD double evaluate(Team& t, const Batch& B, const Params& P, const WorldRef&
 // + G_lambda / h + dreg diag(J M~^-1 J^T), and its right-hand side.
 template <class Team>
 OST_HD void assemble(Team& t, const Params& P, const WorldRef& R, const WorldMem& M, double dreg, bool with_rhs) {
-  const int m = R.m, bw = R.bw, wd = 2 * bw + 1;
+  const int m = R.m, bw = R.bw, wd = 2 * bw + 1, ld = lda(m);
   const bool dense = wd >= m;
   const double ih = 1.0 / P.h;
   const int n_e = dense ? m * m : m * wd;
@@ -538,7 +544,7 @@ OST_HD void assemble(Team& t, const Params& P, const WorldRef& R, const WorldMem
     int gi = M.r_g[i];
     if (M.r_g[j] == gi) s += M.Gl[3 * i + (j - gi)] * ih;
     if (i == j) s += dreg * M.Abar[i];
-    M.A[i * m + j] = s;
+    M.A[i * ld + j] = s;
   }
   if (with_rhs)
     for (int i = t.rank(); i < m; i += t.size()) {
@@ -577,7 +583,7 @@ constexpr int kMaxRows = 384;  // largest row count of a world (six rows per lan
 // first), so the per-pivot work costs no workgroup barrier; the row maxima
 // needed by the pivot test are kept as the rows are updated.
 template <class Team> OST_HD bool lu_factor(Team& t, const WorldRef& R, const WorldMem& M) {
-  const int m = R.m, bw = R.bw, W = t.wsize();
+  const int m = R.m, bw = R.bw, W = t.wsize(), ld = lda(m);
   double* A = M.A;
   double* rmax = M.rmax;
   if (t.rank() < W) {
@@ -585,7 +591,7 @@ template <class Team> OST_HD bool lu_factor(Team& t, const WorldRef& R, const Wo
     for (int i = lane; i < m; i += W) {  // row maxima of the assembled band
       const int lo = i - bw > 0 ? i - bw : 0, hi = i + bw + 1 < m ? i + bw + 1 : m;
       double v = 0.0;
-      for (int j = lo; j < hi; ++j) v = fmax(v, fabs(A[i * m + j]));
+      for (int j = lo; j < hi; ++j) v = fmax(v, fabs(A[i * ld + j]));
       rmax[i] = v;
     }
     t.wsync();
@@ -594,15 +600,15 @@ template <class Team> OST_HD bool lu_factor(Team& t, const WorldRef& R, const Wo
       const int hi = k + bw + 1 < m ? k + bw + 1 : m;
       // the lane's first row below the pivot: its column-k entry is read with the pivot
       const int i1 = k + 1 + (lane + W - (k + 1) % W) % W;
-      const double piv = A[k * m + k], rk = rmax[k], a1 = i1 < hi ? A[i1 * m + k] : 0.0;
+      const double piv = A[k * ld + k], rk = rmax[k], a1 = i1 < hi ? A[i1 * ld + k] : 0.0;
       if (!(isfinite(piv) && fabs(piv) > 1e-14 * rk && rk > 0.0)) {
         ok = 0;
         break;
       }
       const double ip = 1.0 / piv;
-      const double* Ak = A + k * m;
+      const double* Ak = A + k * ld;
       for (int i = i1; i < hi; i += W) {
-        double* Ai = A + i * m;
+        double* Ai = A + i * ld;
         const double l = (i == i1 ? a1 : Ai[k]) * ip;
         Ai[k] = l;
         double v = 0.0;
@@ -653,7 +659,7 @@ template <class Team> OST_HD bool lu_factor(Team& t, const WorldRef& R, const Wo
 // entries of four steps loaded ahead; beyond, x stays in LDS and each segment
 // between wavefront syncs writes an entry from one lane and reads it from none.
 template <class Team> OST_HD void lu_solve(Team& t, const WorldRef& R, const WorldMem& M, double* x, bool trans) {
-  const int m = R.m, bw = R.bw, W = t.wsize();
+  const int m = R.m, bw = R.bw, W = t.wsize(), ld = lda(m);
   const double* A = M.A;
   if (t.rank() < W) {
     const int lane = t.rank();
@@ -662,7 +668,7 @@ template <class Team> OST_HD void lu_solve(Team& t, const WorldRef& R, const Wor
       double x0 = i0 < m ? x[i0] : 0.0, x1 = i1 < m ? x[i1] : 0.0;
       auto get = [&](int k) { return k < 64 ? t.bcast(x0, k) : t.bcast(x1, k - 64); };
       // entry (row i, step k) of the operator: L or U by rows (plain) or by columns (transposed)
-      auto ent = [&](int i, int k) { return trans ? A[k * m + i] : A[i * m + k]; };
+      auto ent = [&](int i, int k) { return trans ? A[k * ld + i] : A[i * ld + k]; };
       if (!trans) {
         for (int k0 = 0; k0 < m; k0 += 4) {  // L y = b (unit lower)
           double e0[4], e1[4];
@@ -685,7 +691,7 @@ template <class Team> OST_HD void lu_solve(Team& t, const WorldRef& R, const Wor
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int k = k0 - q, lo = k - bw > 0 ? k - bw : 0;
-            d[q] = k >= 0 ? A[k * m + k] : 1.0;
+            d[q] = k >= 0 ? A[k * ld + k] : 1.0;
             e0[q] = (k >= 0 && i0 >= lo && i0 < k) ? ent(i0, k) : 0.0;
             e1[q] = (k >= 0 && i1 >= lo && i1 < k) ? ent(i1, k) : 0.0;
           }
@@ -706,7 +712,7 @@ template <class Team> OST_HD void lu_solve(Team& t, const WorldRef& R, const Wor
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int k = k0 + q, hi = k + bw + 1 < m ? k + bw + 1 : m;
-            d[q] = k < m ? A[k * m + k] : 1.0;
+            d[q] = k < m ? A[k * ld + k] : 1.0;
             e0[q] = (k < m && i0 > k && i0 < hi) ? ent(i0, k) : 0.0;
             e1[q] = (k < m && i1 > k && i1 < hi) ? ent(i1, k) : 0.0;
           }
@@ -744,28 +750,28 @@ template <class Team> OST_HD void lu_solve(Team& t, const WorldRef& R, const Wor
       for (int k = 0; k < m; ++k) {  // L y = b (unit lower)
         const double yk = x[k];
         const int hi = k + bw + 1 < m ? k + bw + 1 : m;
-        for (int i = k + 1 + lane; i < hi; i += W) x[i] -= A[i * m + k] * yk;
+        for (int i = k + 1 + lane; i < hi; i += W) x[i] -= A[i * ld + k] * yk;
         t.wsync();
       }
       for (int k = m - 1; k >= 0; --k) {  // U x = y
-        const double xk = x[k] / A[k * m + k];
+        const double xk = x[k] / A[k * ld + k];
         t.wsync();
         if (lane == k % W) x[k] = xk;
-        for (int i = (k - bw > 0 ? k - bw : 0) + lane; i < k; i += W) x[i] -= A[i * m + k] * xk;
+        for (int i = (k - bw > 0 ? k - bw : 0) + lane; i < k; i += W) x[i] -= A[i * ld + k] * xk;
         t.wsync();
       }
     } else {
       for (int k = 0; k < m; ++k) {  // U^T z = b
-        const double zk = x[k] / A[k * m + k];
+        const double zk = x[k] / A[k * ld + k];
         const int hi = k + bw + 1 < m ? k + bw + 1 : m;
         t.wsync();
         if (lane == k % W) x[k] = zk;
-        for (int i = k + 1 + lane; i < hi; i += W) x[i] -= A[k * m + i] * zk;
+        for (int i = k + 1 + lane; i < hi; i += W) x[i] -= A[k * ld + i] * zk;
         t.wsync();
       }
       for (int k = m - 1; k >= 0; --k) {  // L^T x = z (unit)
         const double xk = x[k];
-        for (int i = (k - bw > 0 ? k - bw : 0) + lane; i < k; i += W) x[i] -= A[k * m + i] * xk;
+        for (int i = (k - bw > 0 ? k - bw : 0) + lane; i < k; i += W) x[i] -= A[k * ld + i] * xk;
         t.wsync();
       }
     }
@@ -773,11 +779,12 @@ template <class Team> OST_HD void lu_solve(Team& t, const WorldRef& R, const Wor
   t.sync();
 }
 
-// Assemble and factor with the regularisation raised tenfold on failure.
+// Assemble and factor with the regularisation dreg0 (relative to the Delassus
+// diagonal), raised tenfold on failure.
 template <class Team>
-OST_HD bool factor(Team& t, const Params& P, const WorldRef& R, const WorldMem& M, bool with_rhs, double* dreg_used,
-                   int* status) {
-  double dreg = P.dreg;
+OST_HD bool factor(Team& t, const Params& P, const WorldRef& R, const WorldMem& M, bool with_rhs, double dreg0,
+                   double* dreg_used, int* status) {
+  double dreg = dreg0;
   for (int attempt = 0; attempt < 8; ++attempt) {
     assemble(t, P, R, M, dreg, with_rhs && attempt == 0);
     if (lu_factor(t, R, M)) {

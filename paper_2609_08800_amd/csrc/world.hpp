@@ -40,6 +40,9 @@ struct WorldMem {
   double* red;
   int* iscal;
   double* dscal;
+  // capacities of this carve: doubles at A, active contacts
+  size_t a_room;
+  int nc_cap;
 };
 
 OST_HD size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
@@ -54,6 +57,15 @@ enum { SPLIT_LDS = 0, SPLIT_GLOBAL = 1 };
 // read whole rounds of eight entries past the end of a row.
 constexpr int kPadA = 8;
 
+// Row stride of an m-row Schur matrix in the workspace: m rounded up to an odd
+// count of doubles.  The factor and the solves give each lane its own row, so
+// with an even stride (m = 36 for a robot on four wheels) the lanes of a
+// wavefront meet on a quarter of the LDS banks; an odd stride spreads them
+// over all banks.
+OST_HD int lda(int m) { return m | 1; }
+// Doubles of the Schur matrix's storage for up to mr rows.
+OST_HD size_t schur_doubles(int mr) { return (size_t)mr * lda(mr) + kPadA; }
+
 // Restart length of the adjoint's Krylov solve and the doubles its workspace
 // takes: kKry + 1 basis vectors and the iterate over the 6 nb velocities, the
 // (kKry + 1) x kKry Hessenberg matrix, and four short vectors.
@@ -63,7 +75,7 @@ OST_HD size_t kry_doubles(const Caps& c) {
 }
 
 OST_HD size_t world_glob_doubles(const Caps& c, int split) {
-  return split == SPLIT_GLOBAL ? (size_t)c.mr * c.mr + kPadA + (size_t)27 * c.mr : 0;
+  return split == SPLIT_GLOBAL ? schur_doubles(c.mr) + (size_t)27 * c.mr : 0;
 }
 
 // Bytes of LDS one world needs for the given capacities, team size and split;
@@ -73,7 +85,7 @@ OST_HD size_t world_lds_bytes(const Caps& c, int team, int split = SPLIT_LDS, bo
   d += (size_t)c.nb * (3 + 7 + 9 + 9 + 9 + 1 + 3 + 6 * 7 + 7 + 6);
   d += (size_t)c.nc * 20;
   d += (size_t)c.mr * 8;
-  if (split == SPLIT_LDS) d += (size_t)c.mr * 27 + (size_t)c.mr * c.mr + kPadA;
+  if (split == SPLIT_LDS) d += (size_t)c.mr * 27 + schur_doubles(c.mr);
   d += c.mr;
   d += c.nsv;
   d += (size_t)team + 8;
@@ -104,7 +116,7 @@ OST_HD WorldMem carve(char* base, const Caps& c, int team, int split = SPLIT_LDS
   M.D = take(c.mr); M.res = take(c.mr);
   M.lam = take(c.mr); M.dlam = take(c.mr); M.lamt = take(c.mr); M.lambest = take(c.mr); M.Abar = take(c.mr);
   M.rmax = take(c.mr);
-  M.A = gtake((size_t)c.mr * c.mr + kPadA); M.rhs = take(c.mr); M.sv_in = take(c.nsv);
+  M.A = gtake(schur_doubles(c.mr)); M.rhs = take(c.mr); M.sv_in = take(c.nsv);
   M.red = take(team); M.dscal = take(8);
   M.kv = M.kx = M.kh = M.kcs = M.ksn = M.kgv = M.ky = nullptr;
   if (adjoint) {
@@ -121,6 +133,8 @@ OST_HD WorldMem carve(char* base, const Caps& c, int team, int split = SPLIT_LDS
   char* f = (char*)(((uintptr_t)q + 7) & ~uintptr_t(7));
   M.c_feat = (Feature*)f;
   M.s_feat = M.c_feat + c.nc;
+  M.a_room = schur_doubles(c.mr);
+  M.nc_cap = c.nc;
   return M;
 }
 

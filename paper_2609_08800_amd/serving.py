@@ -20,8 +20,10 @@ are in flight join at the next tick (continuous batching, not a queue).  Each
 world's arithmetic does not depend on which other worlds share the launch, so
 a request's results are the same alone and in the mix.
 
-Two backends share the scheduling logic: ``GpuBackend`` (the HIP library) and
-``FakeBackend`` (host arithmetic, for testing the scheduler without a GPU).
+The device work goes through ``GpuBackend`` (the HIP library); the engine
+talks to it through a small interface (admit, tick, end_forward,
+end_iteration, release and the clock), so the scheduler can also be driven by
+a host stand-in in tests.
 """
 from __future__ import annotations
 
@@ -34,7 +36,7 @@ import numpy as np
 
 from . import _capi
 
-__all__ = ["Request", "ServingEngine", "GpuBackend", "FakeBackend", "poisson_arrivals", "percentile"]
+__all__ = ["Request", "ServingEngine", "GpuBackend", "poisson_arrivals", "percentile"]
 
 
 @dataclasses.dataclass
@@ -437,7 +439,7 @@ class GpuBackend:
                 self.sim.ctx, wl.data_ptr(), wl.numel(), self.qp_b.data_ptr(), self.up_b.data_ptr(),
                 self.ctrl_b.data_ptr(), self.un_b.data_ptr(), self.ln_b.data_ptr(), self.tape_b.data_ptr(),
                 self.gqn.data_ptr(), self.gun.data_ptr(), self.gqp.data_ptr(), self.gup.data_ptr(),
-                self.gctrl.data_ptr(), -1, self.stream), "ostrich_step_adjoint_list")
+                self.gctrl.data_ptr(), -1, None, self.stream), "ostrich_step_adjoint_list")
             for r in bw:
                 s = self.state[r.rid]
                 b_ = self._b(r)
@@ -457,59 +459,3 @@ def _knots_of(b, K):
         if w.n_ctrl and w.knots is not None:
             out[b.ctrl_off[wi]:b.ctrl_off[wi] + w.n_ctrl] = w.knots[:, :K]
     return out
-
-
-# --------------------------------------------------------------------------
-# Host backend for testing the scheduler (no GPU, no simulation)
-# --------------------------------------------------------------------------
-class FakeBackend:
-    """Deterministic stand-in with the GpuBackend interface: the 'rollout' of a
-    world is a scalar walk x_{k+1} = x_k + knot-mean, so scheduling, admission
-    and latency accounting can be checked on the host."""
-
-    def __init__(self, capacity: int, bytes_per_world_step: float = 1.0, tick_seconds: float = 0.01):
-        self.capacity = capacity
-        self.bpws = bytes_per_world_step
-        self.tick_seconds = tick_seconds
-        self.state = {}
-        self.log = []
-        self.vtime = 0.0   # virtual clock: advanced by ticks and idling
-
-    def clock(self):
-        return self.vtime
-
-    def request_bytes(self, r):
-        return self.bpws * r.n_worlds * (r.T + 1)
-
-    def can_admit(self, r):
-        return True
-
-    def idle(self, seconds):
-        self.vtime += max(seconds, 0.0)
-
-    def admit(self, r):
-        self.state[r.rid] = {"knots": np.full(r.n_worlds, 1.0), "x": np.zeros(r.n_worlds), "g": np.zeros(r.n_worlds)}
-
-    def begin_iteration(self, r):
-        self.state[r.rid]["x"][:] = 0.0
-
-    def tick(self, fw, bw):
-        self.log.append(([r.rid for r in fw], [r.rid for r in bw]))
-        for r in fw:
-            s = self.state[r.rid]
-            s["x"] += s["knots"]
-        for r in bw:
-            s = self.state[r.rid]
-            s["g"] = 2.0 * (s["x"] - 3.0) * r.T
-        self.vtime += self.tick_seconds
-
-    def end_forward(self, r):
-        s = self.state[r.rid]
-        return (s["x"] - 3.0) ** 2
-
-    def end_iteration(self, r):
-        s = self.state[r.rid]
-        s["knots"] = s["knots"] - r.lr * np.sign(s["g"])
-
-    def release(self, r):
-        return self.state.pop(r.rid)["knots"]

@@ -569,7 +569,9 @@ def solver_params(**over) -> dict:
     h: step (s); tol: Newton tolerance on the residual norm; k_max / k_min:
     iteration budget and best-iterate floor; eps: smoothing of the FB function
     and of norms; delta_g: guard of denominators; delta_reg: relative Schur
-    diagonal regularisation; delta0: contact activation margin (m);
+    diagonal regularisation of the Newton iterations; delta_reg_adj: that of the
+    adjoint's system (the factor the adjoint solves with); delta0: contact
+    activation margin (m);
     sigma_mode: 1 scales the FB multiplier argument by the Delassus diagonal,
     0 keeps the literal unit scale; n_feat: heightmap features per proxy;
     newton_mode: 0 uses the generalized Jacobian of the constraint rows, 1
@@ -584,7 +586,7 @@ def solver_params(**over) -> dict:
     solves exactly: the root, not the path, is compared).
     """
     p = dict(h=0.1, gravity=GRAVITY, tol=1e-10, k_max=16, k_min=4, eps=1e-8,
-             delta_g=1e-12, delta_reg=1e-6, delta0=0.02, sigma_mode=1, n_feat=4,
+             delta_g=1e-12, delta_reg=1e-6, delta_reg_adj=1e-9, delta0=0.02, sigma_mode=1, n_feat=4,
              newton_mode=0, ls_max=4, refine=8, truncate=0,
              linear_solver=0, krylov_iters=16)
     p.update(over)

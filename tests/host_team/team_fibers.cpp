@@ -142,6 +142,7 @@ extern "C" void* tf_create(const ostrich_batch* b, const ostrich_params* p, cons
   c->P.eps = p->eps;
   c->P.dg = p->delta_g;
   c->P.dreg = p->delta_reg;
+  c->P.dreg_adj = p->delta_reg_adj;
   c->P.d0 = p->delta0;
   c->P.kmax = p->k_max;
   c->P.kmin = p->k_min < p->k_max ? p->k_min : p->k_max;

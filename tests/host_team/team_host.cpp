@@ -30,6 +30,12 @@ struct HostCtx {
   int fill;
   std::vector<char> ws;
   std::vector<int64_t> toff;
+  // tiered carve (tier_nc > 0): every world is first run with a workspace for
+  // tier_nc active contacts and, if it does not fit, again with the full one
+  int tier_nc = 0;
+  Caps caps1;
+  std::vector<char> ws1;
+  int deferred = 0;
 };
 
 extern "C" void* th_create(const ostrich_batch* b, const ostrich_params* p, const int* caps6, const int64_t* toff) {
@@ -41,6 +47,7 @@ extern "C" void* th_create(const ostrich_batch* b, const ostrich_params* p, cons
   c->P.eps = p->eps;
   c->P.dg = p->delta_g;
   c->P.dreg = p->delta_reg;
+  c->P.dreg_adj = p->delta_reg_adj;
   c->P.d0 = p->delta0;
   c->P.kmax = p->k_max;
   c->P.kmin = p->k_min < p->k_max ? p->k_min : p->k_max;
@@ -56,6 +63,19 @@ extern "C" void* th_create(const ostrich_batch* b, const ostrich_params* p, cons
   return c;
 }
 extern "C" void th_destroy(void* h) { delete (HostCtx*)h; }
+extern "C" void th_set_tier(void* h, int nc) {
+  HostCtx* c = (HostCtx*)h;
+  c->tier_nc = nc;
+  c->caps1 = c->caps;
+  if (nc > 0) {
+    c->caps1.nc = nc;
+    const int mr = 5 * c->caps.nj + c->caps.nsv + 3 * nc;
+    c->caps1.mr = mr < c->caps.mr ? mr : c->caps.mr;
+    c->ws1.assign(world_lds_bytes(c->caps1, 1, SPLIT_LDS, true) + 64, 0);
+  }
+  c->deferred = 0;
+}
+extern "C" int th_deferred(void* h) { return ((HostCtx*)h)->deferred; }
 // 0: zeros, 1: all bits set (NaN doubles, -1 integers), 2: 0x7f bytes (huge values)
 extern "C" void th_set_fill(void* h, int f) { ((HostCtx*)h)->fill = f; }
 static void refill(HostCtx* c) {
@@ -69,6 +89,14 @@ extern "C" void th_forward(void* h, const double* q, const double* u, const doub
   WorldMem M = carve(c->ws.data(), c->caps, 1);
   for (int w = 0; w < c->B.n_worlds; ++w) {
     refill(c);
+    if (c->tier_nc > 0) {
+      std::memset(c->ws1.data(), c->fill == 1 ? 0xFF : (c->fill == 2 ? 0x7F : 0), c->ws1.size());
+      WorldMem M1 = carve(c->ws1.data(), c->caps1, 1);
+      if (forward_world(t, c->B, c->P, c->caps1, w, q, u, lam, ctrl, qn, un, ln, act, nact, st, it, rn, tape,
+                        c->toff.data(), M1))
+        continue;
+      c->deferred++;
+    }
     if (c->P.lin)
       forward_world<SerialTeam, true>(t, c->B, c->P, c->caps, w, q, u, lam, ctrl, qn, un, ln, act, nact, st, it, rn,
                                       tape, c->toff.data(), M);
@@ -86,6 +114,14 @@ extern "C" void th_adjoint(void* h, const double* q, const double* u, const doub
   WorldMem M = carve(c->ws.data(), c->caps, 1, SPLIT_LDS, nullptr, true);
   for (int w = 0; w < c->B.n_worlds; ++w) {
     refill(c);
+    if (c->tier_nc > 0) {
+      std::memset(c->ws1.data(), c->fill == 1 ? 0xFF : (c->fill == 2 ? 0x7F : 0), c->ws1.size());
+      WorldMem M1 = carve(c->ws1.data(), c->caps1, 1, SPLIT_LDS, nullptr, true);
+      if (adjoint_world(t, c->B, c->P, c->caps1, w, q, u, ctrl, un, ln, tape, c->toff.data(), gqn, gun, gq, gu, gc,
+                        refine, M1, gm, gmu, gkp))
+        continue;
+      c->deferred++;
+    }
     adjoint_world(t, c->B, c->P, c->caps, w, q, u, ctrl, un, ln, tape, c->toff.data(), gqn, gun, gq, gu, gc, refine, M,
                   gm, gmu, gkp);
   }

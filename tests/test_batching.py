@@ -231,3 +231,46 @@ def test_checkpointed_rollout_bits_agree_across_schedules(torch):
         if x.dtype == torch.float64:
             x, y = x.view(torch.int64), y.view(torch.int64)
         assert torch.equal(x, y), key
+
+
+def test_tiered_launches_are_bitwise_identical(torch):
+    """Robots and stacks under tiered launches (automatic, and a first carve of
+    four contacts, which defers every world touching the obstacle, the ground
+    with a chassis point, or a box on a box) and untiered launches: rollout
+    loss, final state and every gradient are the same bits."""
+    from paper_2609_08800_amd import spline_basis
+    worlds = list(scenes.robot_batch(96, seed=8).worlds)
+    rng = scenes.world_rngs(9, 8)
+    worlds += [scenes.stack_world(r, n) for r, n in zip(rng, (1, 2, 3, 4, 1, 2, 3, 5))]
+    b = scenes.pack(worlds)
+    P = scenes.solver_params()
+    T, K = 40, scenes.ROBOT_KNOTS
+    dev = torch.device("cuda:0")
+    knots = torch.as_tensor(scenes.knots_array(b, K), device=dev)
+    basis = torch.as_tensor(spline_basis(T, K, P["h"]), device=dev)
+    tg = torch.as_tensor(b.target, device=dev)
+    res, nact = [], None
+    for tier in (-1, 0, 4):
+        sim = sim_for(b, dict(P, tier_contacts=tier))
+        sched = sim.schedule()
+        if tier == -1:
+            assert all(x["tier_contacts"] == 0 for x in sched), sched
+        else:
+            assert any(x["tier_contacts"] > 0 for x in sched), sched
+        q0, u0 = torch.as_tensor(b.q0, device=dev), torch.as_tensor(b.u0, device=dev)
+        out = sim.rollout(q0, u0, knots, basis, T, ckpt_every=10, loss_body=b.loss_body, target=tg, phase=3,
+                          workspace=sim.new_workspace(T, 10))
+        res.append([out[k].clone() for k in ("loss", "qT", "uT", "g_q0", "g_u0", "g_knots")])
+        if tier == 4:  # the first carve's contact count is exceeded on some steps
+            q, u, lam = q0.clone(), u0.clone(), torch.zeros(max(sim.NL, 1), dtype=torch.float64, device=dev)
+            ctrl_all = basis @ knots.t()
+            nact = []
+            for k in range(T):
+                o = sim.step_forward(q, u, lam, ctrl_all[k])
+                nact.append(o["n_act"].cpu().numpy())
+                q, u, lam = o["q"], o["u"], o["lam"]
+            nact = np.array(nact)
+    assert np.any(nact > 4) and np.any(nact <= 4)
+    for other in res[1:]:
+        for x, y in zip(res[0], other):
+            assert torch.equal(x.view(torch.int64), y.view(torch.int64))

@@ -521,7 +521,7 @@ def test_shaped_rollout_matches_oracle(torch, ck):
 
 
 def test_shaped_terrain_rollout_with_truncated_pull_back(torch):
-    """The terrain workload (Sec. V): position tracking, yaw alignment and control
+    """The terrain workload (Sec. IV-D): position tracking, yaw alignment and control
     regularisation against the trajectory of a target spline (simulated by the oracle), with
     the truncated position pull-back; GPU rollout against the oracle's."""
     from paper_2609_08800_amd import spline_basis

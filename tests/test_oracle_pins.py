@@ -383,7 +383,7 @@ def test_exact_jacobian_matches_finite_differences(kind):
     Mi = np.linalg.inv(mass_matrix(b, 0, q))
     Abar = r["J"] @ Mi @ r["J"].T
     H = r["H"].copy()
-    H[nu:, nu:] -= P["h"] * P["delta_reg"] * np.diag(np.diag(Abar))
+    H[nu:, nu:] -= P["h"] * P["delta_reg_adj"] * np.diag(np.diag(Abar))
     x0 = np.concatenate([uu, lam])
     Hfd = np.zeros_like(H)
     for j in range(nu + m):
@@ -582,8 +582,7 @@ def test_flat_terrain_reproduces_the_plane():
     pw.q0 = [list(q) for q in tw.q0]
     bt, bp = scenes.pack([tw], [hm]), scenes.pack([pw])
     P = scenes.solver_params(k_max=64)
-    from paper_2609_08800_amd import spline_basis
-    B = spline_basis(20, scenes.ROBOT_KNOTS, P["h"])
+    B = oracle.spline_basis(20, scenes.ROBOT_KNOTS, P["h"])
     qt, ut, lt = bt.q0.copy(), bt.u0.copy(), np.zeros(bt.n_lam)
     qp, up, lp = bp.q0.copy(), bp.u0.copy(), np.zeros(bp.n_lam)
     for k in range(8):
@@ -684,33 +683,34 @@ def test_parameter_gradients_match_finite_differences():
     """Eq. (17) with a model parameter as xi: the cotangents of the body masses, the slots'
     friction coefficients and the servo gains, against central differences, on determinate
     contact sets (sliding, spinning tripods) and a robot in flight (joints and axle servos
-    only).  The Schur regularisation is switched off here: the adjoint solves with the
-    forward's regularised matrix, whose bias (of order delta_reg) would show on small
-    cotangents."""
-    P = scenes.solver_params(k_max=200, tol=1e-14, delta_reg=0.0)
+    only), at the benchmark's regularisations: the Newton iterations' delta_reg = 1e-6
+    does not move the root, and the adjoint's own delta_reg_adj = 1e-9 leaves a bias far
+    below the 1e-5 bar (with delta_reg in the adjoint's system the smallest cotangents
+    would be off by about 4e-4)."""
+    P = scenes.solver_params(k_max=200, tol=1e-14)
     tb = scenes.pack([tripod_world((0.9, 0.4, 0), (0.05, -0.05, 1.2), 0.2, (0.3, -0.2)),
                       tripod_world((-0.5, 0.7, 0), (0.0, 0.02, -0.6), 1.1, (0.0, 0.0))])
     assert _param_fd(tb, P, None) >= 8  # 2 masses, 6 friction coefficients
-    from paper_2609_08800_amd import spline_basis
     rb = scenes.robot_batch(1, seed=7)
     q0 = rb.q0.copy()
     q0[:, 2] += 0.5
     rb.q0 = q0
     K = scenes.ROBOT_KNOTS
-    ctrl = scenes.knots_array(rb, K) @ spline_basis(20, K, P["h"])[3]
+    ctrl = scenes.knots_array(rb, K) @ oracle.spline_basis(20, K, P["h"])[3]
     assert _param_fd(rb, P, ctrl) >= 8  # of 5 masses and 4 axle servo gains
 
 
 def test_truncated_pull_back_closed_form():
     """The truncated position pull-back (contact geometry a constant of the step, the
-    terrain task of Sec. V) on a tripod at rest.  With the complete pull-back the three
+    terrain task of Sec. IV-D) on a tripod at rest.  With the complete pull-back the three
     contacts pin the height, z+ = sz/2 whatever z- is, so dz+/dz- = 0; with the contact
     geometry held fixed no derivative with respect to q- passes through a contact, and the
     height passes straight through the kinematic update, dz+/dz- = 1.  Sideways, static
     friction keeps u+ = 0, so dx+/dx- = 1 either way.  Truncation changes only the q-
     cotangent: those of u- and of the controls keep their bits."""
     b = scenes.pack([tripod_world((0, 0, 0), (0, 0, 0), 0.3, (0.0, 0.0))])
-    P = scenes.solver_params(k_max=200, tol=1e-14, delta_reg=0.0)
+    # a resting tripod to 1e-14, its contact set determinate (no null direction to regularise)
+    P = scenes.solver_params(k_max=200, tol=1e-14, delta_reg=0.0, delta_reg_adj=1e-13)
     q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
     for _ in range(3):  # settle the contact forces
         o = oracle.step_forward(b, P, q, u, lam, None)
@@ -901,7 +901,7 @@ def test_position_servo_closed_form():
 def test_position_servo_gradients_match_finite_differences():
     """Cotangents of the gains (Eq. (17) with k_p as xi, one step) and of the target angles
     (a rollout whose shaped loss sees the rotor's heading), against central differences."""
-    P = scenes.solver_params(gravity=(0, 0, 0), k_max=200, tol=1e-14, delta_reg=0.0)
+    P = scenes.solver_params(gravity=(0, 0, 0), k_max=200, tol=1e-14)
     b = scenes.pack([_hinge_z_world(0.4, 1.5, 3.0, 0.05), _hinge_z_world(-0.2, -0.7, 1.0, 0.0)])
     # the two gains; the masses do not enter (no gravity, no translation), and all agree
     assert _param_fd(b, P, np.array([-0.3, 0.5])) == 2

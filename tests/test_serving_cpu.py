@@ -4,7 +4,8 @@ accounting."""
 import numpy as np
 import pytest
 
-from paper_2609_08800_amd.serving import FakeBackend, Request, ServingEngine, SlotAllocator, percentile, \
+from serving_fake import FakeBackend
+from paper_2609_08800_amd.serving import Request, ServingEngine, SlotAllocator, percentile, \
     poisson_arrivals
 
 

@@ -60,7 +60,7 @@ def test_terrain_steps_teacher_forced(torch):
 def test_terrain_adjoint_matches_exact_ift(torch, truncate):
     """The step adjoint on terrain against the oracle's exact one, with the complete
     position pull-back and with the truncated one (contact geometry a constant of the
-    step, as on the long terrain horizons of Sec. V)."""
+    step, as on the long terrain horizons of Sec. IV-D)."""
     from paper_2609_08800_amd import Simulator, spline_basis
     b = scenes.terrain_batch(4, seed=5, n_maps=2)
     P = scenes.solver_params(k_max=200, truncate=truncate)
