@@ -333,7 +333,13 @@ def serving_measurement(rate, duration, drain, seed=0, capacity=4096, budget_gb=
     eng = ServingEngine(be, budget_gb * 1e9)
     out = eng.run(reqs, deadline=duration + drain)
     lat = [x for r in out["requests"] + [r for r in out["unfinished"] if r.slot0 >= 0] for x in r.iter_latency]
+    admitted = sum(1 for r in reqs if r.slot0 >= 0)
+    arrived = sum(1 for r in reqs if r.arrival <= out["wall_s"])
+    # offered load: world-steps (forward and adjoint) per second that the arrivals ask for
+    offered = rate * 128.5 * 60.0 * 10
     return {"rate_req_per_s": rate, "arrival_window_s": duration, "requests": len(reqs),
+            "admitted": admitted, "queued_never_admitted": arrived - admitted,
+            "offered_world_steps_per_s": round(offered, 1),
             "completed": len(out["requests"]), "iterations": len(lat),
             "iter_latency_p50_ms": round(1e3 * float(np.percentile(lat, 50)), 1) if lat else None,
             "iter_latency_p99_ms": round(1e3 * float(np.percentile(lat, 99)), 1) if lat else None,
@@ -351,7 +357,7 @@ def main():
     ap.add_argument("--ckpt", type=int, default=10)
     ap.add_argument("--team", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-rate", type=float, default=1.0, help="request arrivals per second (0: skip serving)")
+    ap.add_argument("--serve-rate", type=float, default=10.0, help="request arrivals per second (0: skip serving)")
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="arrival window of the serving run")
     ap.add_argument("--serve-drain", type=float, default=40.0, help="extra time to finish admitted requests")
     ap.add_argument("--uneven", type=int, default=1, help="also measure the uneven stacks + robots batch")

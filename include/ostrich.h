@@ -123,8 +123,9 @@ typedef struct {
                           same bits either way).  A first launch carves each workgroup's LDS for
                           at most this many active contacts, so that more worlds share a CU, and
                           hands every world with more to a second, persistent launch with the full
-                          carve.  0: automatic (the largest count that raises the workgroups per
-                          CU, if any); -1: never; n > 0: n, if below the bucket's contact cap */
+                          carve.  0: only where ostrich_autotune measures it faster (then the largest
+                          count that raises the workgroups per CU); -1: never; n > 0: n, if below
+                          the bucket's contact cap */
   double delta_reg_adj; /* relative regularisation (> 0) of the factor written to the tape, the one the
                           adjoint solves with: the multiplier block of the adjoint's system (Eq. (16))
                           carries h delta_reg_adj diag(J M~^-1 J^T), so the gradient differs from the
@@ -133,7 +134,8 @@ typedef struct {
                           It cannot be arbitrarily small either: where a contact set is statically
                           indeterminate (a robot on four wheels) the multiplier block has a null
                           direction that only this term fixes, and the cotangents of q- that see it
-                          lose digits as 1 / delta_reg_adj.  1e-9 keeps both effects near 1e-7.
+                          lose digits as 1 / delta_reg_adj.  1e-8 keeps both below the 1e-6
+                          gradient bar (bias about 4e-7, lost digits about 1e-7).
                           Raised tenfold while the factor's pivot test fails, the value used being
                           recorded in the tape */
 } ostrich_params;

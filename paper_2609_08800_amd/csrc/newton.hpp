@@ -346,7 +346,7 @@ template <class Team>
 OST_HD void fw_end(Team& t, const Batch& B, const Params& P, const WorldRef& R, int w, const double* ctrl,
                    double* q_next, double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act,
                    int32_t* status, int32_t* iters_out, double* resnorm, double* tape, const int64_t* tape_off,
-                   WorldMem& M, const FwState& S0) {
+                   WorldMem& M, const FwState& S0, int32_t* hist = nullptr) {
   const int nb = R.nb, m = R.m;
   int st = S0.st;
   const int iters = S0.iters;
@@ -410,6 +410,10 @@ OST_HD void fw_end(Team& t, const Batch& B, const Params& P, const WorldRef& R, 
     if (status) status[w] = st;
     if (iters_out) iters_out[w] = iters;
     if (resnorm) resnorm[w] = bn;
+    if (hist) {  // for the launch plan of the next step: active contacts and Newton iterations
+      hist[2 * w] = R.nc;
+      hist[2 * w + 1] = iters;
+    }
   }
   t.sync();
 }
@@ -422,14 +426,14 @@ OST_HD bool forward_world(Team& t, const Batch& B, const Params& P, const Caps& 
                           const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
                           double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
                           int32_t* iters_out, double* resnorm, double* tape, const int64_t* tape_off,
-                          WorldMem& M) {
+                          WorldMem& M, int32_t* hist = nullptr) {
   WorldRef R = world_ref(B, w);
   FwState S;
   if (!fw_begin(t, B, P, R, q_prev, u_prev, lam_prev, ctrl, M, S)) return false;
   const int room = (int)M.a_room;  // doubles of the Schur matrix's storage
   for (int k = 1; k <= P.kmax && !S.done; ++k) fw_iteration<Team, kKrylov>(t, B, P, R, ctrl, M, S, k, room);
   fw_end(t, B, P, R, w, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters_out, resnorm, tape, tape_off,
-         M, S);
+         M, S, hist);
   return true;
 }
 

@@ -153,6 +153,7 @@ struct Launch {
   const int32_t* nlist_dev;  // not null: the list length is read from device memory here
   int32_t* defer;        // not null: a world whose active contacts exceed the carve is appended to
                          // defer[1..] (defer[0] counts them) for a launch with the full carve
+  int32_t* hist;         // not null: per world, the active contacts and Newton iterations of its step
 };
 
 // Number of worlds of a launch's list.
@@ -183,7 +184,7 @@ __global__ void __launch_bounds__(256) k_forward(ost::Batch B, ost::Params P, os
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const int w = L.wlist[i];
     if (!ost::forward_world<TeamT, kKrylov>(t, B, P, caps, w, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
-                                            act_slot, n_act, status, iters, resnorm, tape, tape_off, M))
+                                            act_slot, n_act, status, iters, resnorm, tape, tape_off, M, L.hist))
       defer_world(L, w);
     __syncthreads();
   }
@@ -212,6 +213,66 @@ __global__ void __launch_bounds__(256) k_adjoint(ost::Batch B, ost::Params P, os
                             gu_next, gq_prev, gu_prev, g_ctrl, refine, M, g_mass, g_mu, g_kp, adj_status))
       defer_world(L, w);
     __syncthreads();
+  }
+}
+
+// Launch plan of one bucket: its worlds ordered by an estimated cost, the most
+// expensive first (so that the longest worlds do not start last), and split
+// into those whose active contacts fit a first carve of nc1 contacts and the
+// others (nc1 = 0: one list).  The estimate of a forward step is
+// (iterations + 1) m^2 from the world's previous step (hist; zero before its
+// first step), that of an adjoint step m^2 from its tape.  The lists are
+// permutations of the bucket's worlds (their order within a cost class is that
+// of the atomics); per-world results do not depend on them.  plan: [0] count of
+// the first list, [1] of the second, [2, 2 + n) the first list, [2 + n,
+// 2 + 2 n) the second.
+__global__ void __launch_bounds__(1024) k_plan(ost::Batch B, const int32_t* worlds, int n, const int32_t* hist,
+                                              const double* tape, const int64_t* tape_off, int nc1, int32_t* plan) {
+  __shared__ int cnt[2][32];
+  __shared__ int pos[2][32];
+  for (int i = threadIdx.x; i < 64; i += blockDim.x) cnt[i >> 5][i & 31] = 0;
+  __syncthreads();
+  auto classify = [&](int w, int& cls, int& bin) {
+    const int j0 = B.joint_off[w], j1 = B.joint_off[w + 1];
+    int nsv = 0;
+    for (int j = j0; j < j1; ++j) nsv += (B.joint_act[j] == 2 || B.joint_act[j] == 3 || B.joint_act[j] == 4);
+    const long base = 5L * (j1 - j0) + nsv;
+    long m, nact, cost;
+    if (tape) {
+      const double* tr = tape + tape_off[w + 1] - 4;
+      m = tr[2] == 1.0 ? (long)tr[1] : base + 3L * B.contact_cap[w];
+      nact = (m - base) / 3;
+      cost = m * m;
+    } else {
+      nact = hist ? hist[2 * w] : 0;
+      m = base + 3 * nact;
+      cost = (long)((hist ? hist[2 * w + 1] : 0) + 1) * m * m;
+    }
+    cls = nc1 > 0 && nact > nc1 ? 1 : 0;
+    bin = cost > 1 ? 63 - __builtin_clzll((unsigned long long)cost) : 0;
+    bin = bin > 31 ? 31 : bin;
+  };
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    int c, b;
+    classify(worlds[i], c, b);
+    atomicAdd(&cnt[c][b], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 2; ++c) {
+      int run = 0;
+      for (int b = 31; b >= 0; --b) {  // costliest class first
+        pos[c][b] = run;
+        run += cnt[c][b];
+      }
+      plan[c] = run;
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    int c, b;
+    const int w = worlds[i];
+    classify(w, c, b);
+    plan[2 + c * n + atomicAdd(&pos[c][b], 1)] = w;
   }
 }
 
@@ -488,6 +549,9 @@ struct Bucket {
   size_t lds1 = 0, lds1_adj = 0;
   int grid2 = 0;
   int32_t* d_defer = nullptr;  // [0] deferred count, [1..] their world ids
+  int32_t* d_plan = nullptr;   // launch plan (k_plan): two counts and two world lists
+  hipStream_t side = nullptr;  // tiered: the full-carve launch runs here beside the first one
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 // Row capacity edges of the buckets: a world with row cap mr goes to the first
@@ -503,6 +567,7 @@ struct ostrich_ctx {
   int team;
   int schedule;
   int tier_contacts;  // ostrich_params::tier_contacts
+  bool tier_auto = false;  // automatic tiering (tier_contacts 0): only the autotuner's candidates use it
   size_t lds_limit;
   int n_cu;
   int W, NB, NL, NS, NCTRL;
@@ -526,14 +591,20 @@ struct ostrich_ctx {
   int64_t* d_tape_off = nullptr;
   size_t tape_total = 0;  // doubles
   std::map<void*, size_t> allocs;  // device memory held by the context, by allocation
+  int32_t* d_hist = nullptr;  // per world: active contacts and Newton iterations of its last forward step
   ~ostrich_ctx() {
-    for (auto& b : buckets) {
+    auto free_bucket = [](Bucket& b) {
       if (b.d_worlds) (void)hipFree(b.d_worlds);
       if (b.gscr) (void)hipFree(b.gscr);
       if (b.d_defer) (void)hipFree(b.d_defer);
-    }
-    if (all.gscr) (void)hipFree(all.gscr);
-    if (all.d_worlds) (void)hipFree(all.d_worlds);
+      if (b.d_plan) (void)hipFree(b.d_plan);
+      if (b.side) (void)hipStreamDestroy(b.side);
+      if (b.ev_fork) (void)hipEventDestroy(b.ev_fork);
+      if (b.ev_join) (void)hipEventDestroy(b.ev_join);
+    };
+    for (auto& b : buckets) free_bucket(b);
+    free_bucket(all);
+    if (d_hist) (void)hipFree(d_hist);
     if (plain_ws) (void)hipFree(plain_ws);
     if (d_flops) (void)hipFree(d_flops);
     for (hipStream_t x : bstreams) (void)hipStreamDestroy(x);
@@ -576,7 +647,7 @@ const int kTierMinContacts = 4;
 // full carve does, up to the limit the kernels' registers set (two wavefronts
 // per SIMD).  False when no such carve exists.
 static bool tier_caps(const ostrich_ctx* ctx, const Bucket& bk, int team, ost::Caps* out) {
-  if (ctx->tier_contacts < 0) return false;
+  if (ctx->tier_contacts < 0 || (ctx->tier_contacts == 0 && !ctx->tier_auto)) return false;
   if (ctx->tier_contacts > 0) {  // a requested count
     if (ctx->tier_contacts >= bk.caps.nc) return false;
     ost::Caps c = bk.caps;
@@ -618,7 +689,13 @@ static int configure_bucket(ostrich_ctx* ctx, Bucket& bk, int team, int split, b
     const size_t per_cu = std::max<size_t>(1, ctx->lds_limit / lds_adj);
     bk.grid2 = (int)std::min<size_t>(bk.worlds.size(), per_cu * ctx->n_cu);
     if (!bk.d_defer) HIP_OK(ctx_malloc(ctx, &bk.d_defer, (bk.worlds.size() + 1) * sizeof(int32_t)));
+    if (!bk.side) {  // default priority, events without timing
+      HIP_OK(hipStreamCreateWithFlags(&bk.side, hipStreamNonBlocking));
+      HIP_OK(hipEventCreateWithFlags(&bk.ev_fork, hipEventDisableTiming));
+      HIP_OK(hipEventCreateWithFlags(&bk.ev_join, hipEventDisableTiming));
+    }
   }
+  if (!bk.d_plan) HIP_OK(ctx_malloc(ctx, &bk.d_plan, (2 * bk.worlds.size() + 2) * sizeof(int32_t)));
   if (split == ost::SPLIT_GLOBAL) {
     size_t per_cu = std::max<size_t>(1, ctx->lds_limit / std::max<size_t>(lds, 1));
     per_cu = std::min<size_t>(per_cu, 2048 / team);
@@ -643,23 +720,28 @@ static int default_config(ostrich_ctx* ctx, Bucket& bk) {
   return configure_bucket(ctx, bk, team, ost::SPLIT_GLOBAL);
 }
 
-static Launch launch_of(const Bucket& bk) {
-  return Launch{bk.d_worlds, (int)bk.worlds.size(), bk.split, bk.split == ost::SPLIT_GLOBAL ? bk.gscr : nullptr,
-                bk.gstride, nullptr, nullptr};
-}
-// The two launches of a tiered bucket: the whole list with the first carve,
-// deferring to the list it fills; then that list with the full carve.
-static Launch launch_tier1(const Bucket& bk) {
-  return Launch{bk.d_worlds, (int)bk.worlds.size(), ost::SPLIT_LDS, nullptr, 0, nullptr, bk.d_defer};
-}
-static Launch launch_tier2(const Bucket& bk) {
-  return Launch{bk.d_defer + 1, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_defer, nullptr};
+// Device scratch a bucket's launches use: the deferral queue of a tiered
+// bucket, and the per-workgroup slices of a bucket kept in device memory
+// (slots workgroups of gstride doubles).  The context's own, or slices of the
+// static array of the allocation-free entry point.
+struct Scratch {
+  int32_t* defer;
+  double* gscr;
+  int slots;
+  int32_t* plan;
+};
+static Scratch own_scratch(const Bucket& bk) { return Scratch{bk.d_defer, bk.gscr, bk.slots, bk.d_plan}; }
+
+// The launch over a tiered bucket's deferred worlds (the full carve).
+static Launch launch_deferred(const Scratch& sc) {
+  return Launch{sc.defer + 1, 0, ost::SPLIT_LDS, nullptr, 0, sc.defer, nullptr, nullptr};
 }
 
-static int grid_of(const Bucket& bk) {
+static int grid_of(const Bucket& bk, const Scratch& sc) {
   int n = (int)bk.worlds.size();
-  return bk.split == ost::SPLIT_GLOBAL ? std::max(1, std::min(n, bk.slots)) : n;
+  return bk.split == ost::SPLIT_GLOBAL ? std::max(1, std::min(n, sc.slots)) : n;
 }
+static int grid_of(const Bucket& bk) { return grid_of(bk, own_scratch(bk)); }
 
 extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* p, ostrich_ctx** out) {
   if (!b || !p || !out) return fail(OSTRICH_E_ARG, "null argument");
@@ -792,6 +874,8 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   }
   HIP_OK(ctx_malloc(ctx.get(), &ctx->d_tape_off, (W + 1) * sizeof(int64_t)));
   HIP_OK(hipMemcpy(ctx->d_tape_off, toff.data(), (W + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  HIP_OK(ctx_malloc(ctx.get(), &ctx->d_hist, 2 * (size_t)W * sizeof(int32_t)));
+  HIP_OK(hipMemset(ctx->d_hist, 0, 2 * (size_t)W * sizeof(int32_t)));
   *out = ctx.release();
   return 0;
 }
@@ -867,24 +951,55 @@ static decltype(&k_forward<GpuTeam, false>) forward_kernel(const ostrich_ctx*, c
   return bk.split == ost::SPLIT_GLOBAL ? k_forward<GpuTeamG, false> : k_forward<GpuTeam, false>;
 }
 
+// One bucket's forward step.  A planning kernel orders the bucket's worlds by
+// their estimated cost, most expensive first.  Untiered: one launch over that
+// order.  Tiered: the worlds expected to exceed the first carve's contacts run
+// with the full carve on the bucket's side stream, beside the launch of the
+// others with the first carve; that one defers any world it finds too large,
+// and a last launch, after both, takes the deferred worlds.
+static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, const double* q_prev,
+                           const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
+                           double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
+                           int32_t* iters, double* resnorm, double* tape, const Scratch& sc) {
+  const int n = (int)bk.worlds.size();
+  const int64_t* toff = ctx->d_tape_off;
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, ctx->B, (const int32_t*)bk.d_worlds, n,
+                     (const int32_t*)ctx->d_hist, (const double*)nullptr, (const int64_t*)nullptr,
+                     bk.tier ? bk.caps1.nc : 0, sc.plan);
+  const int32_t* first = sc.plan + 2;
+  const int32_t* second = sc.plan + 2 + n;
+  if (bk.tier) {  // the deferral count starts at zero (a fill kernel, also under graph capture)
+    hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, st, sc.defer, 1);
+    (void)hipEventRecord(bk.ev_fork, st);
+    (void)hipStreamWaitEvent(bk.side, bk.ev_fork, 0);
+    hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(bk.grid2), dim3(bk.team), bk.lds, bk.side, ctx->B,
+                       ctx->P, bk.caps, Launch{second, 0, ost::SPLIT_LDS, nullptr, 0, sc.plan + 1, nullptr, ctx->d_hist},
+                       q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters,
+                       resnorm, tape, toff);
+    (void)hipEventRecord(bk.ev_join, bk.side);
+    hipLaunchKernelGGL((k_forward<GpuTeam, false, false>), dim3(n), dim3(bk.team), bk.lds1, st, ctx->B, ctx->P,
+                       bk.caps1, Launch{first, 0, ost::SPLIT_LDS, nullptr, 0, sc.plan, sc.defer, ctx->d_hist}, q_prev,
+                       u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters, resnorm, tape,
+                       toff);
+    (void)hipStreamWaitEvent(st, bk.ev_join, 0);
+    hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(bk.grid2), dim3(bk.team), bk.lds, st, ctx->B, ctx->P,
+                       bk.caps, Launch{sc.defer + 1, 0, ost::SPLIT_LDS, nullptr, 0, sc.defer, nullptr, ctx->d_hist},
+                       q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters,
+                       resnorm, tape, toff);
+    return;
+  }
+  Launch L{first, n, bk.split, bk.split == ost::SPLIT_GLOBAL ? sc.gscr : nullptr, bk.gstride, nullptr, nullptr,
+           ctx->d_hist};
+  hipLaunchKernelGGL(forward_kernel(ctx, bk), dim3(grid_of(bk, sc)), dim3(bk.team), bk.lds, st, ctx->B, ctx->P,
+                     bk.caps, L, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status,
+                     iters, resnorm, tape, toff);
+}
 static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, const double* q_prev,
                            const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
                            double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
                            int32_t* iters, double* resnorm, double* tape) {
-  if (bk.tier) {
-    hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, st, bk.d_defer, 1);
-    hipLaunchKernelGGL((k_forward<GpuTeam, false, false>), dim3(grid_of(bk)), dim3(bk.team), bk.lds1, st, ctx->B,
-                       ctx->P, bk.caps1, launch_tier1(bk), q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
-                       act_slot, n_act, status, iters, resnorm, tape, (const int64_t*)ctx->d_tape_off);
-    hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(bk.grid2), dim3(bk.team), bk.lds, st, ctx->B, ctx->P,
-                       bk.caps, launch_tier2(bk), q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot,
-                       n_act, status, iters, resnorm, tape, (const int64_t*)ctx->d_tape_off);
-    return;
-  }
-  auto kf = forward_kernel(ctx, bk);
-  hipLaunchKernelGGL(kf, dim3(grid_of(bk)), dim3(bk.team), bk.lds, st, ctx->B, ctx->P, bk.caps,
-                     launch_of(bk), q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act,
-                     status, iters, resnorm, tape, (const int64_t*)ctx->d_tape_off);
+  launch_forward(ctx, bk, st, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status,
+                 iters, resnorm, tape, own_scratch(bk));
 }
 
 extern "C" int ostrich_step_forward(ostrich_ctx* ctx, const double* q_prev, const double* u_prev,
@@ -975,24 +1090,42 @@ static int adjoint_step(ostrich_ctx* ctx, const double* q_prev, const double* u_
     }
     HIP_OK(hipEventRecord(ctx->eva[ctx->n_eva], (hipStream_t)stream));
   }
+  // as the forward (launch_forward), the plan's estimates and the first carve's
+  // split from the tapes' row counts
   int rc = for_buckets(ctx, (hipStream_t)stream, [&](const Bucket& bk, hipStream_t s) {
+    const int n = (int)bk.worlds.size();
+    const int64_t* toff = ctx->d_tape_off;
+    const double* tp = (const double*)tape;
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, ctx->B, (const int32_t*)bk.d_worlds, n,
+                       (const int32_t*)nullptr, tp, toff, bk.tier ? bk.caps1.nc : 0, bk.d_plan);
+    const int32_t* first = bk.d_plan + 2;
+    const int32_t* second = bk.d_plan + 2 + n;
     if (bk.tier) {
       hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, s, bk.d_defer, 1);
-      hipLaunchKernelGGL((k_adjoint<GpuTeam, false>), dim3(grid_of(bk)), dim3(bk.team), bk.lds1_adj, s, ctx->B,
-                         ctx->P, bk.caps1, launch_tier1(bk), q_prev, u_prev, ctrl, u_next, lam_next,
-                         (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev,
-                         g_ctrl, rf, g_mass, g_mu, g_kp, adj_status);
+      (void)hipEventRecord(bk.ev_fork, s);
+      (void)hipStreamWaitEvent(bk.side, bk.ev_fork, 0);
+      hipLaunchKernelGGL((k_adjoint<GpuTeam, true>), dim3(bk.grid2), dim3(bk.team), bk.lds_adj, bk.side, ctx->B,
+                         ctx->P, bk.caps, Launch{second, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_plan + 1, nullptr, nullptr},
+                         q_prev, u_prev, ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl,
+                         rf, g_mass, g_mu, g_kp, adj_status);
+      (void)hipEventRecord(bk.ev_join, bk.side);
+      hipLaunchKernelGGL((k_adjoint<GpuTeam, false>), dim3(n), dim3(bk.team), bk.lds1_adj, s, ctx->B, ctx->P,
+                         bk.caps1, Launch{first, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_plan, bk.d_defer, nullptr}, q_prev,
+                         u_prev, ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf,
+                         g_mass, g_mu, g_kp, adj_status);
+      (void)hipStreamWaitEvent(s, bk.ev_join, 0);
       hipLaunchKernelGGL((k_adjoint<GpuTeam, true>), dim3(bk.grid2), dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P,
-                         bk.caps, launch_tier2(bk), q_prev, u_prev, ctrl, u_next, lam_next, (const double*)tape,
-                         (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass,
-                         g_mu, g_kp, adj_status);
+                         bk.caps, Launch{bk.d_defer + 1, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_defer, nullptr, nullptr},
+                         q_prev, u_prev, ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl,
+                         rf, g_mass, g_mu, g_kp, adj_status);
       return;
     }
+    Launch L{first, n, bk.split, bk.split == ost::SPLIT_GLOBAL ? bk.gscr : nullptr, bk.gstride, nullptr, nullptr,
+             nullptr};
     hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>, dim3(grid_of(bk)),
-                       dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P,
-                       bk.caps, launch_of(bk), q_prev, u_prev, ctrl, u_next, lam_next, (const double*)tape,
-                       (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass,
-                       g_mu, g_kp, adj_status);
+                       dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P, bk.caps, L, q_prev, u_prev, ctrl, u_next,
+                       lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass, g_mu, g_kp,
+                       adj_status);
   });
   if (rc) return rc;
   if (timed) {
@@ -1044,6 +1177,20 @@ extern "C" int ostrich_step_forward_list(ostrich_ctx* ctx, const int32_t* worlds
   if (ctx->NCTRL > 0 && !ctrl) return fail(OSTRICH_E_ARG, "controls required");
   if (n == 0) return 0;
   const Bucket& bk = ctx->all;
+  if (bk.tier) {  // the list with the first carve, then its deferred worlds with the full one
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, st, bk.d_defer, 1);
+    hipLaunchKernelGGL((k_forward<GpuTeam, false, false>), dim3(n), dim3(bk.team), bk.lds1, st, ctx->B, ctx->P,
+                       bk.caps1, Launch{worlds, n, ost::SPLIT_LDS, nullptr, 0, nullptr, bk.d_defer}, q_prev, u_prev,
+                       lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters, resnorm,
+                       (double*)tape, (const int64_t*)ctx->d_tape_off);
+    hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(std::min(bk.grid2, (int)n)), dim3(bk.team), bk.lds,
+                       st, ctx->B, ctx->P, bk.caps, launch_deferred(own_scratch(bk)), q_prev, u_prev, lam_prev,
+                       ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters, resnorm, (double*)tape,
+                       (const int64_t*)ctx->d_tape_off);
+    HIP_OK(hipGetLastError());
+    return 0;
+  }
   hipLaunchKernelGGL(forward_kernel(ctx, bk), dim3(list_grid(ctx, n)),
                      dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
                      bk.caps, list_launch(ctx, worlds, n), q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
@@ -1064,6 +1211,21 @@ extern "C" int ostrich_step_adjoint_list(ostrich_ctx* ctx, const int32_t* worlds
   if (n == 0) return 0;
   const Bucket& bk = ctx->all;
   int rf = refine < 0 ? ctx->refine : refine;
+  if (bk.tier) {
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, st, bk.d_defer, 1);
+    hipLaunchKernelGGL((k_adjoint<GpuTeam, false>), dim3(n), dim3(bk.team), bk.lds1_adj, st, ctx->B, ctx->P,
+                       bk.caps1, Launch{worlds, n, ost::SPLIT_LDS, nullptr, 0, nullptr, bk.d_defer}, q_prev, u_prev,
+                       ctrl, u_next, lam_next, (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next,
+                       gq_prev, gu_prev, g_ctrl, rf, (double*)nullptr, (double*)nullptr, (double*)nullptr,
+                       adj_status);
+    hipLaunchKernelGGL((k_adjoint<GpuTeam, true>), dim3(std::min(bk.grid2, (int)n)), dim3(bk.team), bk.lds_adj,
+                       st, ctx->B, ctx->P, bk.caps, launch_deferred(own_scratch(bk)), q_prev, u_prev, ctrl, u_next,
+                       lam_next, (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev,
+                       gu_prev, g_ctrl, rf, (double*)nullptr, (double*)nullptr, (double*)nullptr, adj_status);
+    HIP_OK(hipGetLastError());
+    return 0;
+  }
   hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>,
                      dim3(list_grid(ctx, n)), dim3(bk.team), bk.lds_adj, (hipStream_t)stream, ctx->B, ctx->P,
                      bk.caps, list_launch(ctx, worlds, n), q_prev, u_prev, ctrl, u_next, lam_next,
@@ -1162,7 +1324,10 @@ extern "C" int ostrich_autotune(ostrich_ctx* ctx, const double* q, const double*
               (split == ost::SPLIT_LDS || !tier))
             cands.push_back(Cand{split, team, tier});
     for (const Cand& cd : cands) {
-      if ((rc = configure_bucket(ctx, bk, cd.team, cd.split, cd.tier))) break;
+      ctx->tier_auto = cd.tier;
+      rc = configure_bucket(ctx, bk, cd.team, cd.split, cd.tier);
+      ctx->tier_auto = false;
+      if (rc) break;
       if (cd.tier && !bk.tier) continue;  // no tiered carve for this team: its untiered candidate follows
       launch_forward(ctx, bk, st, q, u, lam, ctrl, qn, un, ln, as, na, ss, it, rn, nullptr);  // warm
       (void)hipEventRecord(e0, st);
@@ -1178,7 +1343,10 @@ extern "C" int ostrich_autotune(ostrich_ctx* ctx, const double* q, const double*
       if (ms < best) { best = ms; bt = cd.team; bs = cd.split; btier = bk.tier; }
     }
     if (rc) break;
-    if ((rc = configure_bucket(ctx, bk, bt, bs, btier))) break;
+    ctx->tier_auto = btier;
+    rc = configure_bucket(ctx, bk, bt, bs, btier);
+    ctx->tier_auto = false;
+    if (rc) break;
     bk.tuned = true;
   }
   (void)hipEventDestroy(e0);

@@ -586,7 +586,7 @@ def solver_params(**over) -> dict:
     solves exactly: the root, not the path, is compared).
     """
     p = dict(h=0.1, gravity=GRAVITY, tol=1e-10, k_max=16, k_min=4, eps=1e-8,
-             delta_g=1e-12, delta_reg=1e-6, delta_reg_adj=1e-9, delta0=0.02, sigma_mode=1, n_feat=4,
+             delta_g=1e-12, delta_reg=1e-6, delta_reg_adj=1e-8, delta0=0.02, sigma_mode=1, n_feat=4,
              newton_mode=0, ls_max=4, refine=8, truncate=0,
              linear_solver=0, krylov_iters=16)
     p.update(over)

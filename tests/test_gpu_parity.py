@@ -205,10 +205,21 @@ def test_determinate_box_steps(torch):
         q, u, lam = ref["q"], ref["u"], ref["lam"]
 
 
+# The q- cotangent of a robot standing on four wheels: the split of its weight over the
+# wheels (and of the chassis load over the four axles) is not unique, the two sides'
+# Newton iterations end on different splits inside the tolerance, and the q- pull-back
+# sees the split through d(J^T lambda)/dq-.  The adjoint's regularisation delta_reg_adj
+# fixes the null direction; the spread of this block between the two roots grows as it
+# shrinks (on the CPU with the kernel's team code: 2.9e-7 at 1e-6, 2.1e-6 at 1e-7,
+# 3.5e-6 at 1e-8).  The velocity and control cotangents do not see the split.
+GRAD_TOL_Q_INDETERMINATE = 3e-5
+
+
 def test_robot_adjoint_matches_exact_ift(torch):
     """Each side linearises at its own root, so the gradients are compared where both
     converged, to a residual of 1e-12: the two roots then agree far inside the state bar
-    and the gradient bar measures the adjoint, not the distance between two roots."""
+    and the gradient bar measures the adjoint, not the distance between two roots.  The
+    q- cotangent takes the bar of indeterminate contact sets (robots on four wheels)."""
     b = scenes.robot_batch(8, seed=5)
     P = scenes.solver_params(k_max=64, tol=1e-12)
     sim = sim_for(b, P)
@@ -229,9 +240,10 @@ def test_robot_adjoint_matches_exact_ift(torch):
         both += len(ok)
         rb, rcs = world_rows(b.body_off, ok), world_rows(b.ctrl_off, ok)
         assert rel_err(got["u"][rb], ref["u"][rb]) <= STATE_TOL, k
-        for g, r, rows in ((gq, rq, rb), (gu, ru, rb), (gc, rc, rcs)):
+        for g, r, rows, bar in ((gq, rq, rb, GRAD_TOL_Q_INDETERMINATE), (gu, ru, rb, GRAD_TOL),
+                                (gc, rc, rcs, GRAD_TOL)):
             g, r = g.cpu().numpy()[rows], r[rows]
-            assert np.linalg.norm(g - r) <= GRAD_TOL * np.linalg.norm(r), (k, np.linalg.norm(g - r) / np.linalg.norm(r))
+            assert np.linalg.norm(g - r) <= bar * np.linalg.norm(r), (k, np.linalg.norm(g - r) / np.linalg.norm(r))
         q, u, lam = ref["q"], ref["u"], ref["lam"]
     assert both >= 0.75 * 10 * b.n_worlds, both
 

@@ -684,7 +684,7 @@ def test_parameter_gradients_match_finite_differences():
     friction coefficients and the servo gains, against central differences, on determinate
     contact sets (sliding, spinning tripods) and a robot in flight (joints and axle servos
     only), at the benchmark's regularisations: the Newton iterations' delta_reg = 1e-6
-    does not move the root, and the adjoint's own delta_reg_adj = 1e-9 leaves a bias far
+    does not move the root, and the adjoint's own delta_reg_adj = 1e-8 leaves a bias far
     below the 1e-5 bar (with delta_reg in the adjoint's system the smallest cotangents
     would be off by about 4e-4)."""
     P = scenes.solver_params(k_max=200, tol=1e-14)

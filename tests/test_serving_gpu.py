@@ -4,6 +4,7 @@ of requests of other sizes and horizons arriving while it runs."""
 import numpy as np
 import pytest
 
+import oracle
 import scenes
 
 pytestmark = pytest.mark.gpu
@@ -20,9 +21,9 @@ def torch():
 K = scenes.ROBOT_KNOTS
 
 
-def engine(capacity=64, budget=8e9):
+def engine(capacity=64, budget=8e9, P=None):
     from paper_2609_08800_amd.serving import GpuBackend, ServingEngine
-    P = scenes.solver_params()
+    P = P or scenes.solver_params()
     tmpl = scenes.robot_batch(1, seed=0).worlds[0]
     be = GpuBackend(tmpl, capacity, P, K)
     return be, ServingEngine(be, budget)
@@ -111,3 +112,65 @@ def test_terrain_requests_each_on_its_own_map(torch):
     for a, c in zip(alone.losses, mix[0].losses):
         assert np.array_equal(a, c)
     assert sorted(be2.hmap_free) == [0, 1, 2, 3]
+
+
+def oracle_served(batch, P, T, iters, lr):
+    """What a served request computes, from the oracle alone: per iteration a
+    T-step rollout with the final-xy loss and its knot gradient, then Adam on
+    the knots (a non-finite gradient entry counts as zero).  Returns the knots
+    after `iters` iterations, each iteration's loss, and per world whether its
+    every rollout converged at every step."""
+    x = scenes.knots_array(batch, K)
+    m, v = np.zeros_like(x), np.zeros_like(x)
+    losses, ok = [], np.ones(batch.n_worlds, bool)
+    for it in range(iters):
+        ref = oracle.rollout(batch, P, batch.q0, batch.u0, x, T)
+        losses.append(ref["loss"])
+        ok &= (ref["status"] & 6) == 0
+        g = np.where(np.isfinite(ref["g_knots"]), ref["g_knots"], 0.0)
+        x, m, v = adam_ref(x, g, m, v, it + 1, lr)
+    return x, losses, ok
+
+
+def check_served_against_oracle(req, batch, P, T, iters, lr):
+    x, losses, ok = oracle_served(batch, P, T, iters, lr)
+    x0 = scenes.knots_array(batch, K)
+    got = req.knots.reshape(x.shape)
+    assert ok.sum() >= max(1, batch.n_worlds // 2), ok
+    for w in np.flatnonzero(ok):
+        c = slice(batch.ctrl_off[w], batch.ctrl_off[w + 1])
+        step = np.linalg.norm(x[c] - x0[c])
+        # the knot gradient passes through the q- cotangents of robots on four wheels, whose
+        # spread between the two sides' roots is that of an indeterminate contact set
+        assert np.linalg.norm(got[c] - x[c]) <= 1e-5 * step, (w, np.linalg.norm(got[c] - x[c]) / step)
+        for it in range(iters):
+            assert abs(req.losses[it][w] - losses[it][w]) <= 1e-9 * max(1.0, abs(losses[it][w])), (w, it)
+    return int(ok.sum())
+
+
+def test_served_knots_match_oracle_alone_and_in_a_terrain_mix(torch):
+    """Two iterations (rollout, adjoint, Adam) of served requests against the
+    oracle's rollouts and the Adam formula: a plane request served alone, and a
+    terrain request served in a mix with three other terrain requests (their
+    worlds in the same launches), world by world where the oracle converged at
+    every step (tolerance 1e-12)."""
+    from paper_2609_08800_amd.serving import GpuBackend, Request, ServingEngine
+    T, iters, lr = 8, 2, 0.1
+    P = scenes.solver_params(k_max=64, tol=1e-12)
+    mine = scenes.robot_batch(4, seed=43)
+    be, eng = engine(capacity=8, P=P)
+    r = Request(0, mine, T=T, iters=iters, lr=lr)
+    eng.run([r])
+    n_plane = check_served_against_oracle(r, mine, P, T, iters, lr)
+    Pt = scenes.solver_params(k_max=200, tol=1e-12)
+    base = scenes.value_noise_heightmap(10_000)
+    tmpl = scenes.robot_terrain_world(None, base, 0)
+    be2 = GpuBackend(tmpl, 24, Pt, K, heightmaps=[base], heightmap_slots=4)
+    reqs = [Request(rid, scenes.terrain_request_batch(700 + rid, n), T=t, iters=iters, lr=lr, arrival=a)
+            for rid, (n, t, a) in enumerate(((3, 8, 0.02), (5, 6, 0.0), (2, 10, 0.01), (4, 7, 0.04)))]
+    eng2 = ServingEngine(be2, 8e9)
+    out = eng2.run(reqs)
+    assert len(out["requests"]) == 4
+    assert any(len(rids) >= 3 for _, _, _, rids in eng2.ticks), "requests never shared a launch"
+    n_terrain = sum(check_served_against_oracle(q, q.batch, Pt, q.T, iters, lr) for q in reqs)
+    print("worlds compared: plane %d, terrain %d" % (n_plane, n_terrain))
