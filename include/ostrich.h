@@ -228,6 +228,24 @@ int ostrich_step_forward(ostrich_ctx* ctx, const double* q_prev, const double* u
                          int32_t* n_act, int32_t* status, int32_t* iters, double* resnorm, void* tape,
                          void* stream);
 
+/* ostrich_step_forward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results, but the device scratch
+ * the launches need (the deferral queues of tiered buckets and the
+ * per-workgroup slices of worlds kept in device memory) comes from a static
+ * device array of 32 MiB inside the library (one per GPU, held until the
+ * process ends) instead of the context's allocations.  The call allocates
+ * nothing and records no timing.  A bucket kept in device memory runs on as
+ * many persistent workgroups as its slices that fit (at least one), which
+ * changes the time, not the results.  Errors: as ostrich_step_forward, and
+ * OSTRICH_E_WORKSPACE when the batch needs more than the static scratch.
+ * Every call on a GPU shares that GPU's array, so calls that overlap on one
+ * GPU (other streams, other threads, other contexts) race: serialise them. */
+int ostrich_step_forward_noalloc(ostrich_ctx* ctx, const double* q_prev, const double* u_prev,
+                                 const double* lam_prev, const double* ctrl, double* q_next, double* u_next,
+                                 double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
+                                 int32_t* iters, double* resnorm, void* tape, void* stream);
+
 /* Adjoint of one step (Sec. III-D, Eqs. (16)-(19)): given s-, the controls,
  * s+ (u_next, lam_next) and the tape written by the forward call, map the
  * loss cotangents (gq_next [NB*7], gu_next [NB*6]) to gq_prev, gu_prev and

@@ -80,6 +80,8 @@ def load() -> ctypes.CDLL:
     L.ostrich_rollout_workspace_bytes.restype = c_size
     L.ostrich_step_forward.argtypes = [c_vp] + [c_vp] * 13 + [c_vp]
     L.ostrich_step_forward.restype = c_int
+    L.ostrich_step_forward_noalloc.argtypes = [c_vp] + [c_vp] * 13 + [c_vp]
+    L.ostrich_step_forward_noalloc.restype = c_int
     L.ostrich_step_adjoint.argtypes = [c_vp] + [c_vp] * 11 + [c_int, c_vp, c_vp]
     L.ostrich_step_adjoint.restype = c_int
     L.ostrich_step_adjoint_params.argtypes = [c_vp] + [c_vp] * 14 + [c_int, c_vp, c_vp]

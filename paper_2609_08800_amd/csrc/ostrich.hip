@@ -11,6 +11,7 @@
 #include <cmath>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -743,6 +744,38 @@ static int grid_of(const Bucket& bk, const Scratch& sc) {
 }
 static int grid_of(const Bucket& bk) { return grid_of(bk, own_scratch(bk)); }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point: a file-scope device array (one
+// copy per GPU, held until the process ends).  Host code never uses the
+// array's name as an address: each device's address comes from
+// hipGetSymbolAddress, taken once per device (at context creation, or at the
+// entry point's first call on a device) and kept in scratch_dev.
+namespace {
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+char* g_scratch_dev[kMaxDevices] = {};
+
+// The current device's copy of the scratch array (set up on first use).
+int scratch_dev(char** out) {
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(OSTRICH_E_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(OSTRICH_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_dev[dev] = (char*)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return 0;
+}
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace
+
 extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* p, ostrich_ctx** out) {
   if (!b || !p || !out) return fail(OSTRICH_E_ARG, "null argument");
   if (b->n_worlds < 1) return fail(OSTRICH_E_ARG, "n_worlds must be >= 1");
@@ -792,6 +825,10 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   HIP_OK(hipGetDeviceProperties(&prop, dev));
   ctx->lds_limit = prop.sharedMemPerBlock;
   ctx->n_cu = std::max(1, prop.multiProcessorCount);
+  {  // this device's address of the allocation-free entry point's scratch array
+    char* scr = nullptr;
+    if (int rc = scratch_dev(&scr)) return rc;
+  }
   for (auto f : {(const void*)k_forward<GpuTeam, false>, (const void*)k_adjoint<GpuTeam>,
                  (const void*)k_forward<GpuTeamG, false>, (const void*)k_adjoint<GpuTeamG>,
                  (const void*)k_forward<GpuTeam, false, true>, (const void*)k_adjoint<GpuTeam, true>})
@@ -1031,6 +1068,64 @@ extern "C" int ostrich_step_forward(ostrich_ctx* ctx, const double* q_prev, cons
     hipLaunchKernelGGL(k_flops, dim3(1), dim3(256), 0, (hipStream_t)stream, ctx->B, n_act, iters, tape ? 1 : 0,
                        ctx->d_flops);
   }
+  HIP_OK(hipGetLastError());
+  return 0;
+}
+
+// ostrich_step_forward with the launches' scratch (deferral queues of tiered
+// buckets, slices of buckets kept in device memory) in the static array: no
+// allocation, no timing.  A bucket kept in device memory gets as many
+// persistent workgroups as its slices that fit, at least one.
+extern "C" int ostrich_step_forward_noalloc(ostrich_ctx* ctx, const double* q_prev, const double* u_prev,
+                                            const double* lam_prev, const double* ctrl, double* q_next,
+                                            double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act,
+                                            int32_t* status, int32_t* iters, double* resnorm, void* tape,
+                                            void* stream) {
+  if (!ctx || !q_prev || !u_prev || !lam_prev || !q_next || !u_next || !lam_next)
+    return fail(OSTRICH_E_ARG, "null state pointer");
+  if (ctx->NCTRL > 0 && !ctrl) return fail(OSTRICH_E_ARG, "controls required");
+  constexpr int kMaxBuckets = 16;
+  if ((int)ctx->buckets.size() > kMaxBuckets) return fail(OSTRICH_E_UNSUPPORTED, "too many buckets");
+  char* base = nullptr;
+  if (int rc = scratch_dev(&base)) return rc;
+  Scratch sc[kMaxBuckets];
+  size_t off = 0;
+  for (size_t i = 0; i < ctx->buckets.size(); ++i) {
+    const Bucket& bk = ctx->buckets[i];
+    sc[i] = Scratch{nullptr, nullptr, 0, nullptr};
+    {  // the launch plan
+      const size_t n = al256((2 * bk.worlds.size() + 2) * sizeof(int32_t));
+      if (off + n > kScratchBytes)
+        return fail(OSTRICH_E_WORKSPACE, "the batch needs more than the " + std::to_string(kScratchBytes >> 20) +
+                                             " MiB of static scratch");
+      sc[i].plan = (int32_t*)(base + off);
+      off += n;
+    }
+    if (bk.tier) {
+      const size_t n = al256((bk.worlds.size() + 1) * sizeof(int32_t));
+      if (off + n > kScratchBytes)
+        return fail(OSTRICH_E_WORKSPACE, "the batch needs more than the " + std::to_string(kScratchBytes >> 20) +
+                                             " MiB of static scratch");
+      sc[i].defer = (int32_t*)(base + off);
+      off += n;
+    }
+    if (bk.split == ost::SPLIT_GLOBAL) {
+      const size_t per = bk.gstride * sizeof(double);
+      const size_t fit = off < kScratchBytes ? (kScratchBytes - off) / per : 0;
+      const int slots = (int)std::min<size_t>(std::max(bk.slots, 1), fit);
+      if (slots < 1)
+        return fail(OSTRICH_E_WORKSPACE, "a world kept in device memory needs more than the " +
+                                             std::to_string(kScratchBytes >> 20) + " MiB of static scratch");
+      sc[i].gscr = (double*)(base + off);
+      sc[i].slots = slots;
+      off += al256((size_t)slots * per);
+    }
+  }
+  int rc = for_buckets(ctx, (hipStream_t)stream, [&](const Bucket& bk, hipStream_t s) {
+    launch_forward(ctx, bk, s, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status,
+                   iters, resnorm, (double*)tape, sc[&bk - ctx->buckets.data()]);
+  });
+  if (rc) return rc;
   HIP_OK(hipGetLastError());
   return 0;
 }
