@@ -123,9 +123,12 @@ typedef struct {
                           same bits either way).  A first launch carves each workgroup's LDS for
                           at most this many active contacts, so that more worlds share a CU, and
                           hands every world with more to a second, persistent launch with the full
-                          carve.  0: only where ostrich_autotune measures it faster (then the largest
-                          count that raises the workgroups per CU); -1: never; n > 0: n, if below
-                          the bucket's contact cap */
+                          carve.  The two launches run side by side: a planning pass counts each
+                          world's active contacts at q- (the adjoint reads them from the tape) and
+                          sends the worlds that exceed the first carve to the second launch from the
+                          start.  0: automatic, the largest count that raises the workgroups per CU
+                          (two wavefronts per SIMD), if any; -1: never; n > 0: n, if below the
+                          bucket's contact cap.  ostrich_autotune also times the untiered launch */
   double delta_reg_adj; /* relative regularisation (> 0) of the factor written to the tape, the one the
                           adjoint solves with: the multiplier block of the adjoint's system (Eq. (16))
                           carries h delta_reg_adj diag(J M~^-1 J^T), so the gradient differs from the

@@ -168,7 +168,7 @@ __device__ __forceinline__ void defer_world(const Launch& L, int w) {
 // kRest marks the launch over the deferred worlds of a tiered bucket (the same
 // code under its own name, so that profiles tell the two launches apart).
 template <class TeamT, bool kKrylov, bool kRest = false>
-__global__ void __launch_bounds__(256) k_forward(ost::Batch B, ost::Params P, ost::Caps caps, Launch L,
+__global__ void __launch_bounds__(256, 2) k_forward(ost::Batch B, ost::Params P, ost::Caps caps, Launch L,
                                                  const double* q_prev, const double* u_prev, const double* lam_prev,
                                                  const double* ctrl, double* q_next, double* u_next,
                                                  double* lam_next, int32_t* act_slot, int32_t* n_act,
@@ -192,7 +192,7 @@ __global__ void __launch_bounds__(256) k_forward(ost::Batch B, ost::Params P, os
 }
 
 template <class TeamT, bool kRest = false>
-__global__ void __launch_bounds__(256) k_adjoint(ost::Batch B, ost::Params P, ost::Caps caps, Launch L,
+__global__ void __launch_bounds__(256, 2) k_adjoint(ost::Batch B, ost::Params P, ost::Caps caps, Launch L,
                                                  const double* q_prev, const double* u_prev, const double* ctrl,
                                                  const double* u_next, const double* lam_next, const double* tape,
                                                  const int64_t* tape_off, const double* gq_next,
@@ -222,18 +222,21 @@ __global__ void __launch_bounds__(256) k_adjoint(ost::Batch B, ost::Params P, os
 // into those whose active contacts fit a first carve of nc1 contacts and the
 // others (nc1 = 0: one list).  The estimate of a forward step is
 // (iterations + 1) m^2 from the world's previous step (hist; zero before its
-// first step), that of an adjoint step m^2 from its tape.  The lists are
+// first step), with m from nact_now (indexed like worlds) when given, that of
+// an adjoint step m^2 from its tape.  The lists are
 // permutations of the bucket's worlds (their order within a cost class is that
 // of the atomics); per-world results do not depend on them.  plan: [0] count of
 // the first list, [1] of the second, [2, 2 + n) the first list, [2 + n,
-// 2 + 2 n) the second.
+// 2 + 2 n) the second, and [2 + 2 n, 2 + 3 n) room for nact_now.
 __global__ void __launch_bounds__(1024) k_plan(ost::Batch B, const int32_t* worlds, int n, const int32_t* hist,
-                                              const double* tape, const int64_t* tape_off, int nc1, int32_t* plan) {
+                                              const int32_t* nact_now, const double* tape, const int64_t* tape_off,
+                                              int nc1, int32_t* plan) {
   __shared__ int cnt[2][32];
   __shared__ int pos[2][32];
   for (int i = threadIdx.x; i < 64; i += blockDim.x) cnt[i >> 5][i & 31] = 0;
   __syncthreads();
-  auto classify = [&](int w, int& cls, int& bin) {
+  auto classify = [&](int i, int& cls, int& bin) {
+    const int w = worlds[i];
     const int j0 = B.joint_off[w], j1 = B.joint_off[w + 1];
     int nsv = 0;
     for (int j = j0; j < j1; ++j) nsv += (B.joint_act[j] == 2 || B.joint_act[j] == 3 || B.joint_act[j] == 4);
@@ -245,7 +248,7 @@ __global__ void __launch_bounds__(1024) k_plan(ost::Batch B, const int32_t* worl
       nact = (m - base) / 3;
       cost = m * m;
     } else {
-      nact = hist ? hist[2 * w] : 0;
+      nact = nact_now ? nact_now[i] : (hist ? hist[2 * w] : 0);
       m = base + 3 * nact;
       cost = (long)((hist ? hist[2 * w + 1] : 0) + 1) * m * m;
     }
@@ -255,7 +258,7 @@ __global__ void __launch_bounds__(1024) k_plan(ost::Batch B, const int32_t* worl
   };
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     int c, b;
-    classify(worlds[i], c, b);
+    classify(i, c, b);
     atomicAdd(&cnt[c][b], 1);
   }
   __syncthreads();
@@ -271,10 +274,20 @@ __global__ void __launch_bounds__(1024) k_plan(ost::Batch B, const int32_t* worl
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     int c, b;
-    const int w = worlds[i];
-    classify(w, c, b);
-    plan[2 + c * n + atomicAdd(&pos[c][b], 1)] = w;
+    classify(i, c, b);
+    plan[2 + c * n + atomicAdd(&pos[c][b], 1)] = worlds[i];
   }
+}
+
+// Active contacts at q- of each world of a list (the refresh's activation
+// test; terrain slots counted active), capped at the world's contact cap:
+// out[i] for worlds[i].  One 64-thread workgroup per world.
+__global__ void __launch_bounds__(64) k_count_active(ost::Batch B, ost::Params P, const int32_t* worlds,
+                                                     const double* q_prev, const double* u_prev, int32_t* out) {
+  const ost::WorldRef R = ost::world_ref(B, worlds[blockIdx.x]);
+  int c = ost::count_active(B, P, R, q_prev, u_prev, threadIdx.x, 64);
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if (threadIdx.x == 0) out[blockIdx.x] = c < R.cap ? c : R.cap;
 }
 
 // Plain path (the comparison baseline): one launch for a world's set-up, one
@@ -568,7 +581,6 @@ struct ostrich_ctx {
   int team;
   int schedule;
   int tier_contacts;  // ostrich_params::tier_contacts
-  bool tier_auto = false;  // automatic tiering (tier_contacts 0): only the autotuner's candidates use it
   size_t lds_limit;
   int n_cu;
   int W, NB, NL, NS, NCTRL;
@@ -648,7 +660,7 @@ const int kTierMinContacts = 4;
 // full carve does, up to the limit the kernels' registers set (two wavefronts
 // per SIMD).  False when no such carve exists.
 static bool tier_caps(const ostrich_ctx* ctx, const Bucket& bk, int team, ost::Caps* out) {
-  if (ctx->tier_contacts < 0 || (ctx->tier_contacts == 0 && !ctx->tier_auto)) return false;
+  if (ctx->tier_contacts < 0) return false;
   if (ctx->tier_contacts > 0) {  // a requested count
     if (ctx->tier_contacts >= bk.caps.nc) return false;
     ost::Caps c = bk.caps;
@@ -696,7 +708,7 @@ static int configure_bucket(ostrich_ctx* ctx, Bucket& bk, int team, int split, b
       HIP_OK(hipEventCreateWithFlags(&bk.ev_join, hipEventDisableTiming));
     }
   }
-  if (!bk.d_plan) HIP_OK(ctx_malloc(ctx, &bk.d_plan, (2 * bk.worlds.size() + 2) * sizeof(int32_t)));
+  if (!bk.d_plan) HIP_OK(ctx_malloc(ctx, &bk.d_plan, (3 * bk.worlds.size() + 2) * sizeof(int32_t)));
   if (split == ost::SPLIT_GLOBAL) {
     size_t per_cu = std::max<size_t>(1, ctx->lds_limit / std::max<size_t>(lds, 1));
     per_cu = std::min<size_t>(per_cu, 2048 / team);
@@ -963,18 +975,26 @@ extern "C" int ostrich_ctx_schedule(const ostrich_ctx* ctx, int32_t* out, int32_
 
 extern "C" size_t ostrich_tape_bytes(const ostrich_ctx* ctx) { return ctx ? ctx->tape_total * sizeof(double) : 0; }
 
-// Run f(bucket, stream) for every bucket: on the caller's stream when there is
-// one bucket, else each on its own stream between a fork and a join event, so
-// that the buckets' launches overlap on the device.
+// Run f(bucket, stream, tier_ok) for every bucket: on the caller's stream when
+// there is one bucket, else each on its own stream between a fork and a join
+// event, so that the buckets' launches overlap on the device.  tier_ok says
+// whether a tiered bucket may fork once more onto its side stream: not when
+// the buckets' streams are themselves forked inside a graph capture (a second
+// level of forks under capture has ended the capture with a host crash in the
+// HIP runtime; tiered and untiered launches give the same bits, so the graph
+// takes the untiered launch).
 template <class F> static int for_buckets(ostrich_ctx* ctx, hipStream_t st, F f) {
   if (ctx->buckets.size() == 1) {
-    f(ctx->buckets[0], st);
+    f(ctx->buckets[0], st, true);
     return 0;
   }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_OK(hipStreamIsCapturing(st, &cs));
+  const bool tier_ok = cs == hipStreamCaptureStatusNone;
   HIP_OK(hipEventRecord(ctx->ev_fork, st));
   for (size_t i = 0; i < ctx->buckets.size(); ++i) {
     HIP_OK(hipStreamWaitEvent(ctx->bstreams[i], ctx->ev_fork, 0));
-    f(ctx->buckets[i], ctx->bstreams[i]);
+    f(ctx->buckets[i], ctx->bstreams[i], tier_ok);
     HIP_OK(hipEventRecord(ctx->ev_join[i], ctx->bstreams[i]));
   }
   for (size_t i = 0; i < ctx->buckets.size(); ++i) HIP_OK(hipStreamWaitEvent(st, ctx->ev_join[i], 0));
@@ -994,22 +1014,29 @@ static decltype(&k_forward<GpuTeam, false>) forward_kernel(const ostrich_ctx*, c
 // with the full carve on the bucket's side stream, beside the launch of the
 // others with the first carve; that one defers any world it finds too large,
 // and a last launch, after both, takes the deferred worlds.
+// The worlds of the step are the list wl of n worlds (the bucket's, or a
+// caller's list of the context's worlds with the context-wide bucket).
 static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, const double* q_prev,
                            const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
                            double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
-                           int32_t* iters, double* resnorm, double* tape, const Scratch& sc) {
-  const int n = (int)bk.worlds.size();
+                           int32_t* iters, double* resnorm, double* tape, const Scratch& sc, const int32_t* wl,
+                           int n, bool tier_ok) {
   const int64_t* toff = ctx->d_tape_off;
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, ctx->B, (const int32_t*)bk.d_worlds, n,
-                     (const int32_t*)ctx->d_hist, (const double*)nullptr, (const int64_t*)nullptr,
-                     bk.tier ? bk.caps1.nc : 0, sc.plan);
+  const int grid2 = std::min(bk.grid2, n);
+  const bool tier = bk.tier && tier_ok;
+  int32_t* nact_now = tier ? sc.plan + 2 + 2 * n : nullptr;  // the split by this step's contacts
+  if (nact_now)
+    hipLaunchKernelGGL(k_count_active, dim3(n), dim3(64), 0, st, ctx->B, ctx->P, wl, q_prev, u_prev, nact_now);
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, ctx->B, wl, n,
+                     (const int32_t*)ctx->d_hist, (const int32_t*)nact_now, (const double*)nullptr,
+                     (const int64_t*)nullptr, tier ? bk.caps1.nc : 0, sc.plan);
   const int32_t* first = sc.plan + 2;
   const int32_t* second = sc.plan + 2 + n;
-  if (bk.tier) {  // the deferral count starts at zero (a fill kernel, also under graph capture)
+  if (tier) {  // the deferral count starts at zero (a fill kernel, also under graph capture)
     hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, st, sc.defer, 1);
     (void)hipEventRecord(bk.ev_fork, st);
     (void)hipStreamWaitEvent(bk.side, bk.ev_fork, 0);
-    hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(bk.grid2), dim3(bk.team), bk.lds, bk.side, ctx->B,
+    hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(grid2), dim3(bk.team), bk.lds, bk.side, ctx->B,
                        ctx->P, bk.caps, Launch{second, 0, ost::SPLIT_LDS, nullptr, 0, sc.plan + 1, nullptr, ctx->d_hist},
                        q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters,
                        resnorm, tape, toff);
@@ -1019,7 +1046,7 @@ static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, c
                        u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters, resnorm, tape,
                        toff);
     (void)hipStreamWaitEvent(st, bk.ev_join, 0);
-    hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(bk.grid2), dim3(bk.team), bk.lds, st, ctx->B, ctx->P,
+    hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(grid2), dim3(bk.team), bk.lds, st, ctx->B, ctx->P,
                        bk.caps, Launch{sc.defer + 1, 0, ost::SPLIT_LDS, nullptr, 0, sc.defer, nullptr, ctx->d_hist},
                        q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters,
                        resnorm, tape, toff);
@@ -1027,16 +1054,24 @@ static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, c
   }
   Launch L{first, n, bk.split, bk.split == ost::SPLIT_GLOBAL ? sc.gscr : nullptr, bk.gstride, nullptr, nullptr,
            ctx->d_hist};
-  hipLaunchKernelGGL(forward_kernel(ctx, bk), dim3(grid_of(bk, sc)), dim3(bk.team), bk.lds, st, ctx->B, ctx->P,
-                     bk.caps, L, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status,
-                     iters, resnorm, tape, toff);
+  const int grid = bk.split == ost::SPLIT_GLOBAL ? std::max(1, std::min(n, sc.slots)) : n;
+  hipLaunchKernelGGL(forward_kernel(ctx, bk), dim3(grid), dim3(bk.team), bk.lds, st, ctx->B, ctx->P, bk.caps, L,
+                     q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters, resnorm,
+                     tape, toff);
 }
 static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, const double* q_prev,
                            const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
                            double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
-                           int32_t* iters, double* resnorm, double* tape) {
+                           int32_t* iters, double* resnorm, double* tape, const Scratch& sc, bool tier_ok) {
   launch_forward(ctx, bk, st, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status,
-                 iters, resnorm, tape, own_scratch(bk));
+                 iters, resnorm, tape, sc, bk.d_worlds, (int)bk.worlds.size(), tier_ok);
+}
+static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, const double* q_prev,
+                           const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
+                           double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
+                           int32_t* iters, double* resnorm, double* tape, bool tier_ok) {
+  launch_forward(ctx, bk, st, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status,
+                 iters, resnorm, tape, own_scratch(bk), tier_ok);
 }
 
 extern "C" int ostrich_step_forward(ostrich_ctx* ctx, const double* q_prev, const double* u_prev,
@@ -1057,9 +1092,9 @@ extern "C" int ostrich_step_forward(ostrich_ctx* ctx, const double* q_prev, cons
     }
     HIP_OK(hipEventRecord(ctx->ev[ctx->n_ev], (hipStream_t)stream));
   }
-  int rc = for_buckets(ctx, (hipStream_t)stream, [&](const Bucket& bk, hipStream_t s) {
+  int rc = for_buckets(ctx, (hipStream_t)stream, [&](const Bucket& bk, hipStream_t s, bool tier_ok) {
     launch_forward(ctx, bk, s, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status,
-                   iters, resnorm, (double*)tape);
+                   iters, resnorm, (double*)tape, tier_ok);
   });
   if (rc) return rc;
   if (timed) {
@@ -1094,7 +1129,7 @@ extern "C" int ostrich_step_forward_noalloc(ostrich_ctx* ctx, const double* q_pr
     const Bucket& bk = ctx->buckets[i];
     sc[i] = Scratch{nullptr, nullptr, 0, nullptr};
     {  // the launch plan
-      const size_t n = al256((2 * bk.worlds.size() + 2) * sizeof(int32_t));
+      const size_t n = al256((3 * bk.worlds.size() + 2) * sizeof(int32_t));
       if (off + n > kScratchBytes)
         return fail(OSTRICH_E_WORKSPACE, "the batch needs more than the " + std::to_string(kScratchBytes >> 20) +
                                              " MiB of static scratch");
@@ -1121,9 +1156,9 @@ extern "C" int ostrich_step_forward_noalloc(ostrich_ctx* ctx, const double* q_pr
       off += al256((size_t)slots * per);
     }
   }
-  int rc = for_buckets(ctx, (hipStream_t)stream, [&](const Bucket& bk, hipStream_t s) {
+  int rc = for_buckets(ctx, (hipStream_t)stream, [&](const Bucket& bk, hipStream_t s, bool tier_ok) {
     launch_forward(ctx, bk, s, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status,
-                   iters, resnorm, (double*)tape, sc[&bk - ctx->buckets.data()]);
+                   iters, resnorm, (double*)tape, sc[&bk - ctx->buckets.data()], tier_ok);
   });
   if (rc) return rc;
   HIP_OK(hipGetLastError());
@@ -1166,6 +1201,49 @@ extern "C" int ostrich_ctx_timing(ostrich_ctx* ctx, int32_t mode, double* out) {
   return 0;
 }
 
+// One bucket's adjoint step over the list wl of n worlds, as the forward
+// (launch_forward): the plan's estimates and the first carve's split come from
+// the row counts the tape records, which are this step's.
+static void launch_adjoint(ostrich_ctx* ctx, const Bucket& bk, hipStream_t s, const int32_t* wl, int n,
+                           const double* q_prev, const double* u_prev, const double* ctrl, const double* u_next,
+                           const double* lam_next, const double* tp, const double* gq_next, const double* gu_next,
+                           double* gq_prev, double* gu_prev, double* g_ctrl, int rf, double* g_mass, double* g_mu,
+                           double* g_kp, int32_t* adj_status, bool tier_ok) {
+  const int64_t* toff = ctx->d_tape_off;
+  const int grid2 = std::min(bk.grid2, n);
+  const bool tier = bk.tier && tier_ok;
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, ctx->B, wl, n, (const int32_t*)nullptr,
+                     (const int32_t*)nullptr, tp, toff, tier ? bk.caps1.nc : 0, bk.d_plan);
+  const int32_t* first = bk.d_plan + 2;
+  const int32_t* second = bk.d_plan + 2 + n;
+  if (tier) {
+    hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, s, bk.d_defer, 1);
+    (void)hipEventRecord(bk.ev_fork, s);
+    (void)hipStreamWaitEvent(bk.side, bk.ev_fork, 0);
+    hipLaunchKernelGGL((k_adjoint<GpuTeam, true>), dim3(grid2), dim3(bk.team), bk.lds_adj, bk.side, ctx->B, ctx->P,
+                       bk.caps, Launch{second, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_plan + 1, nullptr, nullptr}, q_prev,
+                       u_prev, ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf,
+                       g_mass, g_mu, g_kp, adj_status);
+    (void)hipEventRecord(bk.ev_join, bk.side);
+    hipLaunchKernelGGL((k_adjoint<GpuTeam, false>), dim3(n), dim3(bk.team), bk.lds1_adj, s, ctx->B, ctx->P, bk.caps1,
+                       Launch{first, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_plan, bk.d_defer, nullptr}, q_prev, u_prev,
+                       ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass, g_mu,
+                       g_kp, adj_status);
+    (void)hipStreamWaitEvent(s, bk.ev_join, 0);
+    hipLaunchKernelGGL((k_adjoint<GpuTeam, true>), dim3(grid2), dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P,
+                       bk.caps, Launch{bk.d_defer + 1, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_defer, nullptr, nullptr},
+                       q_prev, u_prev, ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl,
+                       rf, g_mass, g_mu, g_kp, adj_status);
+    return;
+  }
+  Launch L{first, n, bk.split, bk.split == ost::SPLIT_GLOBAL ? bk.gscr : nullptr, bk.gstride, nullptr, nullptr,
+           nullptr};
+  const int grid = bk.split == ost::SPLIT_GLOBAL ? std::max(1, std::min(n, bk.slots)) : n;
+  hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>, dim3(grid),
+                     dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P, bk.caps, L, q_prev, u_prev, ctrl, u_next, lam_next,
+                     tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass, g_mu, g_kp, adj_status);
+}
+
 static int adjoint_step(ostrich_ctx* ctx, const double* q_prev, const double* u_prev, const double* ctrl,
                         const double* u_next, const double* lam_next, const void* tape, const double* gq_next,
                         const double* gu_next, double* gq_prev, double* gu_prev, double* g_ctrl, double* g_mass,
@@ -1185,42 +1263,10 @@ static int adjoint_step(ostrich_ctx* ctx, const double* q_prev, const double* u_
     }
     HIP_OK(hipEventRecord(ctx->eva[ctx->n_eva], (hipStream_t)stream));
   }
-  // as the forward (launch_forward), the plan's estimates and the first carve's
-  // split from the tapes' row counts
-  int rc = for_buckets(ctx, (hipStream_t)stream, [&](const Bucket& bk, hipStream_t s) {
-    const int n = (int)bk.worlds.size();
-    const int64_t* toff = ctx->d_tape_off;
-    const double* tp = (const double*)tape;
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, ctx->B, (const int32_t*)bk.d_worlds, n,
-                       (const int32_t*)nullptr, tp, toff, bk.tier ? bk.caps1.nc : 0, bk.d_plan);
-    const int32_t* first = bk.d_plan + 2;
-    const int32_t* second = bk.d_plan + 2 + n;
-    if (bk.tier) {
-      hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, s, bk.d_defer, 1);
-      (void)hipEventRecord(bk.ev_fork, s);
-      (void)hipStreamWaitEvent(bk.side, bk.ev_fork, 0);
-      hipLaunchKernelGGL((k_adjoint<GpuTeam, true>), dim3(bk.grid2), dim3(bk.team), bk.lds_adj, bk.side, ctx->B,
-                         ctx->P, bk.caps, Launch{second, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_plan + 1, nullptr, nullptr},
-                         q_prev, u_prev, ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl,
-                         rf, g_mass, g_mu, g_kp, adj_status);
-      (void)hipEventRecord(bk.ev_join, bk.side);
-      hipLaunchKernelGGL((k_adjoint<GpuTeam, false>), dim3(n), dim3(bk.team), bk.lds1_adj, s, ctx->B, ctx->P,
-                         bk.caps1, Launch{first, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_plan, bk.d_defer, nullptr}, q_prev,
-                         u_prev, ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf,
-                         g_mass, g_mu, g_kp, adj_status);
-      (void)hipStreamWaitEvent(s, bk.ev_join, 0);
-      hipLaunchKernelGGL((k_adjoint<GpuTeam, true>), dim3(bk.grid2), dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P,
-                         bk.caps, Launch{bk.d_defer + 1, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_defer, nullptr, nullptr},
-                         q_prev, u_prev, ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl,
-                         rf, g_mass, g_mu, g_kp, adj_status);
-      return;
-    }
-    Launch L{first, n, bk.split, bk.split == ost::SPLIT_GLOBAL ? bk.gscr : nullptr, bk.gstride, nullptr, nullptr,
-             nullptr};
-    hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>, dim3(grid_of(bk)),
-                       dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P, bk.caps, L, q_prev, u_prev, ctrl, u_next,
-                       lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass, g_mu, g_kp,
-                       adj_status);
+  int rc = for_buckets(ctx, (hipStream_t)stream, [&](const Bucket& bk, hipStream_t s, bool tier_ok) {
+    launch_adjoint(ctx, bk, s, bk.d_worlds, (int)bk.worlds.size(), q_prev, u_prev, ctrl, u_next, lam_next,
+                   (const double*)tape, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass, g_mu, g_kp,
+                   adj_status, tier_ok);
   });
   if (rc) return rc;
   if (timed) {
@@ -1271,25 +1317,8 @@ extern "C" int ostrich_step_forward_list(ostrich_ctx* ctx, const int32_t* worlds
     return fail(OSTRICH_E_ARG, "null state pointer");
   if (ctx->NCTRL > 0 && !ctrl) return fail(OSTRICH_E_ARG, "controls required");
   if (n == 0) return 0;
-  const Bucket& bk = ctx->all;
-  if (bk.tier) {  // the list with the first carve, then its deferred worlds with the full one
-    hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, st, bk.d_defer, 1);
-    hipLaunchKernelGGL((k_forward<GpuTeam, false, false>), dim3(n), dim3(bk.team), bk.lds1, st, ctx->B, ctx->P,
-                       bk.caps1, Launch{worlds, n, ost::SPLIT_LDS, nullptr, 0, nullptr, bk.d_defer}, q_prev, u_prev,
-                       lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters, resnorm,
-                       (double*)tape, (const int64_t*)ctx->d_tape_off);
-    hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(std::min(bk.grid2, (int)n)), dim3(bk.team), bk.lds,
-                       st, ctx->B, ctx->P, bk.caps, launch_deferred(own_scratch(bk)), q_prev, u_prev, lam_prev,
-                       ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters, resnorm, (double*)tape,
-                       (const int64_t*)ctx->d_tape_off);
-    HIP_OK(hipGetLastError());
-    return 0;
-  }
-  hipLaunchKernelGGL(forward_kernel(ctx, bk), dim3(list_grid(ctx, n)),
-                     dim3(bk.team), bk.lds, (hipStream_t)stream, ctx->B, ctx->P,
-                     bk.caps, list_launch(ctx, worlds, n), q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
-                     act_slot, n_act, status, iters, resnorm, (double*)tape, (const int64_t*)ctx->d_tape_off);
+  launch_forward(ctx, ctx->all, (hipStream_t)stream, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
+                 act_slot, n_act, status, iters, resnorm, (double*)tape, own_scratch(ctx->all), worlds, n, true);
   HIP_OK(hipGetLastError());
   return 0;
 }
@@ -1304,28 +1333,10 @@ extern "C" int ostrich_step_adjoint_list(ostrich_ctx* ctx, const int32_t* worlds
     return fail(OSTRICH_E_ARG, "null pointer");
   if (ctx->NCTRL > 0 && (!ctrl || !g_ctrl)) return fail(OSTRICH_E_ARG, "controls required");
   if (n == 0) return 0;
-  const Bucket& bk = ctx->all;
-  int rf = refine < 0 ? ctx->refine : refine;
-  if (bk.tier) {
-    hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, st, bk.d_defer, 1);
-    hipLaunchKernelGGL((k_adjoint<GpuTeam, false>), dim3(n), dim3(bk.team), bk.lds1_adj, st, ctx->B, ctx->P,
-                       bk.caps1, Launch{worlds, n, ost::SPLIT_LDS, nullptr, 0, nullptr, bk.d_defer}, q_prev, u_prev,
-                       ctrl, u_next, lam_next, (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next,
-                       gq_prev, gu_prev, g_ctrl, rf, (double*)nullptr, (double*)nullptr, (double*)nullptr,
-                       adj_status);
-    hipLaunchKernelGGL((k_adjoint<GpuTeam, true>), dim3(std::min(bk.grid2, (int)n)), dim3(bk.team), bk.lds_adj,
-                       st, ctx->B, ctx->P, bk.caps, launch_deferred(own_scratch(bk)), q_prev, u_prev, ctrl, u_next,
-                       lam_next, (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev,
-                       gu_prev, g_ctrl, rf, (double*)nullptr, (double*)nullptr, (double*)nullptr, adj_status);
-    HIP_OK(hipGetLastError());
-    return 0;
-  }
-  hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>,
-                     dim3(list_grid(ctx, n)), dim3(bk.team), bk.lds_adj, (hipStream_t)stream, ctx->B, ctx->P,
-                     bk.caps, list_launch(ctx, worlds, n), q_prev, u_prev, ctrl, u_next, lam_next,
-                     (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev,
-                     g_ctrl, rf, (double*)nullptr, (double*)nullptr, (double*)nullptr, adj_status);
+  const int rf = refine < 0 ? ctx->refine : refine;
+  launch_adjoint(ctx, ctx->all, (hipStream_t)stream, worlds, n, q_prev, u_prev, ctrl, u_next, lam_next,
+                 (const double*)tape, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, nullptr, nullptr, nullptr,
+                 adj_status, true);
   HIP_OK(hipGetLastError());
   return 0;
 }
@@ -1419,15 +1430,12 @@ extern "C" int ostrich_autotune(ostrich_ctx* ctx, const double* q, const double*
               (split == ost::SPLIT_LDS || !tier))
             cands.push_back(Cand{split, team, tier});
     for (const Cand& cd : cands) {
-      ctx->tier_auto = cd.tier;
-      rc = configure_bucket(ctx, bk, cd.team, cd.split, cd.tier);
-      ctx->tier_auto = false;
-      if (rc) break;
+      if ((rc = configure_bucket(ctx, bk, cd.team, cd.split, cd.tier))) break;
       if (cd.tier && !bk.tier) continue;  // no tiered carve for this team: its untiered candidate follows
-      launch_forward(ctx, bk, st, q, u, lam, ctrl, qn, un, ln, as, na, ss, it, rn, nullptr);  // warm
+      launch_forward(ctx, bk, st, q, u, lam, ctrl, qn, un, ln, as, na, ss, it, rn, nullptr, true);  // warm
       (void)hipEventRecord(e0, st);
       for (int r = 0; r < reps; ++r)
-        launch_forward(ctx, bk, st, q, u, lam, ctrl, qn, un, ln, as, na, ss, it, rn, nullptr);
+        launch_forward(ctx, bk, st, q, u, lam, ctrl, qn, un, ln, as, na, ss, it, rn, nullptr, true);
       (void)hipEventRecord(e1, st);
       if (hipEventSynchronize(e1) != hipSuccess || hipGetLastError() != hipSuccess) {
         rc = fail(OSTRICH_E_HIP, "autotune launch failed");
@@ -1438,10 +1446,7 @@ extern "C" int ostrich_autotune(ostrich_ctx* ctx, const double* q, const double*
       if (ms < best) { best = ms; bt = cd.team; bs = cd.split; btier = bk.tier; }
     }
     if (rc) break;
-    ctx->tier_auto = btier;
-    rc = configure_bucket(ctx, bk, bt, bs, btier);
-    ctx->tier_auto = false;
-    if (rc) break;
+    if ((rc = configure_bucket(ctx, bk, bt, bs, btier))) break;
     bk.tuned = true;
   }
   (void)hipEventDestroy(e0);

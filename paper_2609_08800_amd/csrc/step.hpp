@@ -193,6 +193,52 @@ OST_HD bool terrain_candidates(Team& t, const Batch& B, const Params& P, const W
 // Returns false, with only the workspace touched, when the world's active
 // contacts exceed the carve's contact capacity (M.nc_cap): the launch then
 // hands the world to one whose workspace holds them.
+// Activation test of the contact refresh: the slot's gap at q- plus one step
+// of its approach speed along the normal (relative velocity of the contact
+// point) within delta0.  ub is body b's velocity for a body-face slot.
+OST_HD bool approach_active(const Params& P, int kind, const double* sr, const Frame<double>& C, double gap,
+                            const v3<double>& xa, const double* ua, const v3<double>& xb, const double* ub) {
+  v3<double> pc = xa + C.la - C.n * sr[3];
+  v3<double> vr = ldv(ua) + cross(ldv(ua + 3), pc - xa);
+  if (kind == 2) vr = vr - (ldv(ub) + cross(ldv(ub + 3), pc - xb));
+  double vn = dot(C.n, vr);
+  return gap + P.h * (vn < 0.0 ? vn : 0.0) <= P.d0;
+}
+
+// Active contacts of world R at q- by the refresh's test, for a launch plan:
+// slots s0, s0 + ds, ... of the world (a team's share), terrain slots counted
+// active (their search is left to the step).  Returns the share's count.
+OST_HD int count_active(const Batch& B, const Params& P, const WorldRef& R, const double* q_prev,
+                        const double* u_prev, int s0, int ds) {
+  int n = 0;
+  for (int s = s0; s < R.ns; s += ds) {
+    const int* si = B.slot_int + 4 * (R.s0 + s);
+    const double* sr = B.slot_real + 6 * (R.s0 + s);
+    const int kind = si[0], a = si[1], b = si[2];
+    if (kind == 3) {
+      ++n;
+      continue;
+    }
+    const double* qa = q_prev + 7 * (R.b0 + a);
+    const v3<double> xa = ldv(qa);
+    const m3<double> Ra = quat_to_R(qa[3], qa[4], qa[5], qa[6]);
+    v3<double> xb{0, 0, 0};
+    m3<double> Rb = Ra;
+    if (kind == 2) {
+      const double* qb = q_prev + 7 * (R.b0 + b);
+      xb = ldv(qb);
+      Rb = quat_to_R(qb[3], qb[4], qb[5], qb[6]);
+    }
+    const double* obs = kind == 1 ? B.obs_box + 6 * (R.o0 + si[3]) : nullptr;
+    Feature F{};
+    double gap;
+    Frame<double> C = slot_frame<double>(kind, sr, obs, xa, Ra, xb, Rb, F, true, &gap, &R.hm, si[3], 0.0, false);
+    n += approach_active(P, kind, sr, C, gap, xa, u_prev + 6 * (R.b0 + a), xb,
+                         kind == 2 ? u_prev + 6 * (R.b0 + b) : nullptr);
+  }
+  return n;
+}
+
 template <class Team>
 OST_HD bool prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, const double* q_prev,
                      const double* u_prev, const double* ctrl, const double* lam_prev, WorldMem& M) {
@@ -260,16 +306,8 @@ OST_HD bool prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
     }
     Frame<double> C = slot_frame<double>(kind, sr, obs, ldv(M.xm + 3 * a), ldm(M.Rm + 9 * a), xb, Rb, F, true, &gap,
                                          &R.hm, si[3], rc, kind == 3 && keyed);
-    // relative velocity of the contact point at q-, approach along n
-    v3<double> pc = ldv(M.xm + 3 * a) + C.la - C.n * sr[3];
-    const double* ua = M.um + 6 * a;
-    v3<double> vr = ldv(ua) + cross(ldv(ua + 3), pc - ldv(M.xm + 3 * a));
-    if (kind == 2) {
-      const double* ub = M.um + 6 * b;
-      vr = vr - (ldv(ub) + cross(ldv(ub + 3), pc - xb));
-    }
-    double vn = dot(C.n, vr);
-    M.s_act[s] = (gap + P.h * (vn < 0.0 ? vn : 0.0) <= P.d0) ? 1 : 0;
+    M.s_act[s] = approach_active(P, kind, sr, C, gap, ldv(M.xm + 3 * a), M.um + 6 * a, xb,
+                                 kind == 2 ? M.um + 6 * b : nullptr) ? 1 : 0;
     M.s_feat[s] = F;
   }
   t.sync();
@@ -447,21 +485,27 @@ OST_HD double evaluate(Team& t, const Batch& B, const Params& P, const WorldRef&
     }
     if (!want_G) continue;
     int a = M.r_a[row], b = M.r_b[row];
-    double Gu[36], Gl[9];
+    // the generalized Jacobian goes straight to the workspace: G_u into the rows
+    // of Y (turned into Y = G_u M~^-1 in place below), G_lambda into Gl
+    double* Gu = M.Y + 12 * row;
+    double* Gl = M.Gl + 3 * row;
     if (kind == RK_CONTACT) {
       int c = M.r_idx[row];
       contact_G(P, in, b >= 0, M.c_r[c], M.c_mu[c], M.c_sn[c], M.c_sf[c], M.c_kind[c], Jg, D, Gu, Gl);
     } else {  // joint rows: D r = c(q(u)) / h, so D dr/du = J; servo rows: dr/du = J, dr/dlambda = alpha
       for (int q = 0; q < 12; ++q) Gu[q] = Jg[q];
       Gl[0] = kind == RK_SERVO ? servo_compliance(B, R, M.r_idx[row], P.h) : 0.0;
+      Gl[1] = 0.0;
+      Gl[2] = 0.0;
     }
     #pragma unroll
     for (int k = 0; k < 3; ++k) if (k < n) {
       double* Y = M.Y + 12 * (row + k);
-      minv6(M, a, Gu + 12 * k, Y);
-      if (b >= 0) minv6(M, b, Gu + 12 * k + 6, Y + 6);
+      double g[12];
+      for (int q = 0; q < 12; ++q) g[q] = Y[q];
+      minv6(M, a, g, Y);
+      if (b >= 0) minv6(M, b, g + 6, Y + 6);
       else for (int q = 6; q < 12; ++q) Y[q] = 0.0;
-      for (int q = 0; q < 3; ++q) M.Gl[3 * (row + k) + q] = q < n ? Gl[3 * k + q] : 0.0;
       const double* Jr = Jg + 12 * k;
       double MJ[12], s = 0.0;
       minv6(M, a, Jr, MJ);
