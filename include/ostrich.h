@@ -199,15 +199,20 @@ int ostrich_ctx_schedule(const ostrich_ctx* ctx, int32_t* out, int32_t max_bucke
  * the hot path).  mode 1: reset and start: every later ostrich_step_forward
  * call with n_act and iters, and every ostrich_step_adjoint call (including
  * those inside ostrich_rollout), is bracketed by a pair of HIP events on its
- * stream, and a one-workgroup kernel adds the step's algorithmic work to a
- * device counter: for a forward step its FP64 flops (from each world's rows m
- * and Newton iteration count k: k (26 m^2 + 2 m^3 / 3 + 800 m) + 400 m, plus
- * 24 m^2 + 2 m^3 / 3 when a tape is written); for an adjoint step its bytes
- * (the factor's band read from the tape, m (2 bw + 1) - bw (bw + 1) doubles
- * with the half band bw recorded there, and the states, multipliers and
- * cotangents read and written).  mode 0: stop.  mode 2 (forward) and mode 3
- * (adjoint): synchronise the device and write out[3] = (timed calls, their
- * total duration in ms, their algorithmic flops or bytes). */
+ * stream, and a one-workgroup kernel adds the step's algorithmic work to
+ * device counters.  A forward step counts FP64 flops from each world's rows m
+ * and Newton iteration count k (Sec. III-C, one Schur factor and solve per
+ * iteration): the roofline count k (m^3/3 + 14 m^2 + 170 m), and this
+ * implementation's finer count k (26 m^2 + 2 m^3 / 3 + 800 m) + 400 m, plus
+ * 24 m^2 + 2 m^3 / 3 when a tape is written.  An adjoint step counts bytes
+ * (Sec. III-D, one solve with the stored factor): the roofline count, states
+ * read and written (2 x 13 doubles per body), multipliers read and a
+ * triangular factor of m (m + 1) / 2 doubles; and the finer count, the band
+ * the tape stores, m (2 bw + 1) - bw (bw + 1) doubles for the half band bw
+ * recorded there, with the states, multipliers and cotangents read and
+ * written.  mode 0: stop.  mode 2 (forward) and mode 3 (adjoint): synchronise
+ * the device and write out[4] = (timed calls, their total duration in ms,
+ * the roofline count, the finer count). */
 int ostrich_ctx_timing(ostrich_ctx* ctx, int32_t mode, double* out);
 
 /* Autotuner of the batching system: times `reps` forward steps of every bucket

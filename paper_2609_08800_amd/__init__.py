@@ -127,13 +127,15 @@ class Simulator:
 
     def timing(self, mode: int):
         """Launch measurement: 1 start, 0 stop; 2 reads the forward steps (launches, total ms, algorithmic
-        flops), 3 the adjoint steps (launches, total ms, algorithmic bytes)."""
-        out = np.zeros(3)
+        flops by the roofline count and by the finer count), 3 the adjoint steps (the same with bytes)."""
+        out = np.zeros(4)
         _capi.check(self.lib.ostrich_ctx_timing(self.ctx, int(mode), out.ctypes.data), "ostrich_ctx_timing")
         if mode == 2:
-            return {"launches": int(out[0]), "ms": float(out[1]), "flops": float(out[2])}
+            return {"launches": int(out[0]), "ms": float(out[1]), "flops": float(out[2]),
+                    "flops_fine": float(out[3])}
         if mode == 3:
-            return {"launches": int(out[0]), "ms": float(out[1]), "bytes": float(out[2])}
+            return {"launches": int(out[0]), "ms": float(out[1]), "bytes": float(out[2]),
+                    "bytes_fine": float(out[3])}
         return None
 
     def autotune(self, q, u, lam=None, ctrl=None, reps: int = 2, stream=None):

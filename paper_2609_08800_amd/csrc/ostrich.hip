@@ -334,49 +334,68 @@ __global__ void __launch_bounds__(256) k_plain_end(ost::Batch B, ost::Params P, 
 
 // Measurement: algorithmic FP64 flops of the forward steps just taken, from
 // each world's rows m = 5 joints + servo rows + 3 contacts and its Newton
-// iteration count k: k (24 m^2 + 2 m^3 / 3 + 2 m^2 + 800 m) per step, plus the
-// factor at the returned iterate when a tape is written (24 m^2 + 2 m^3 / 3)
-// and 400 m for the set-up.  One workgroup sums in a fixed order.
+// iteration count k (Sec. III-C: one Schur-complement factor and solve per
+// iteration).  acc[0] takes the dense per-iteration count k (m^3/3 + 14 m^2 +
+// 170 m) of the roofline; acc[2] the finer count of this implementation's
+// operations: k (26 m^2 + 2 m^3 / 3 + 800 m) + 400 m for the set-up, plus the
+// factor at the returned iterate when a tape is written (24 m^2 + 2 m^3 / 3).
+// One workgroup sums in a fixed order.
 __global__ void k_flops(ost::Batch B, const int32_t* n_act, const int32_t* iters, int with_tape, double* acc) {
-  __shared__ double part[256];
-  double s = 0.0;
+  __shared__ double part[2][256];
+  double s = 0.0, f = 0.0;
   for (int w = threadIdx.x; w < B.n_worlds; w += blockDim.x) {
     int nsv = 0;
     for (int j = B.joint_off[w]; j < B.joint_off[w + 1]; ++j) nsv += (B.joint_act[j] == 2 || B.joint_act[j] == 3 || B.joint_act[j] == 4);
     const double m = 5.0 * (B.joint_off[w + 1] - B.joint_off[w]) + nsv + 3.0 * n_act[w];
+    s += iters[w] * (m * m * m / 3.0 + 14.0 * m * m + 170.0 * m);
     const double per_it = 24.0 * m * m + 2.0 * m * m * m / 3.0 + 2.0 * m * m + 800.0 * m;
-    s += iters[w] * per_it + 400.0 * m + (with_tape ? 24.0 * m * m + 2.0 * m * m * m / 3.0 : 0.0);
+    f += iters[w] * per_it + 400.0 * m + (with_tape ? 24.0 * m * m + 2.0 * m * m * m / 3.0 : 0.0);
   }
-  part[threadIdx.x] = s;
+  part[0][threadIdx.x] = s;
+  part[1][threadIdx.x] = f;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int i = 0; i < (int)blockDim.x; ++i) t += part[i];
+    double t = 0.0, u = 0.0;
+    for (int i = 0; i < (int)blockDim.x; ++i) {
+      t += part[0][i];
+      u += part[1][i];
+    }
     acc[0] += t;
+    acc[2] += u;
   }
 }
 
-// Algorithmic bytes of one adjoint step of every world: the factor's band read
-// from the tape (rows m and half band bw from the tape's trailer), the states
-// and multipliers read, the cotangents read and written, and the control
+// Algorithmic bytes of one adjoint step of every world (Sec. III-D: one solve
+// with the stored factor).  acc[1] takes the roofline's count: the states read
+// and written (2 x 13 doubles per body), the multipliers read, and a
+// triangular factor of the world's m rows, m (m + 1) / 2 doubles.  acc[3] the
+// bytes of this implementation: the factor's band as the tape stores it
+// (rows m and half band bw from the tape's trailer), the states and
+// multipliers read, the cotangents read and written, and the control
 // cotangents written.
 __global__ void k_abytes(ost::Batch B, const double* tape, const int64_t* tape_off, double* acc) {
-  __shared__ double part[256];
-  double s = 0.0;
+  __shared__ double part[2][256];
+  double s = 0.0, f = 0.0;
   for (int w = threadIdx.x; w < B.n_worlds; w += blockDim.x) {
     const double* tr = tape + tape_off[w + 1] - 4;
     const double m = tr[1], bw = tr[3] < tr[1] - 1 ? tr[3] : tr[1] - 1;
     const double band = m > 0 ? m * (2.0 * bw + 1.0) - bw * (bw + 1.0) : 0.0;
     const double nb = B.body_off[w + 1] - B.body_off[w];
     const double nl = B.lam_off[w + 1] - B.lam_off[w], nc = B.ctrl_off[w + 1] - B.ctrl_off[w];
-    s += 8.0 * (band + 4 + 13.0 * nb + 6.0 * nb + nl + 2.0 * 13.0 * nb + nc);
+    s += 8.0 * (2.0 * 13.0 * nb + nl + m * (m + 1.0) / 2.0);
+    f += 8.0 * (band + 4 + 13.0 * nb + 6.0 * nb + nl + 2.0 * 13.0 * nb + nc);
   }
-  part[threadIdx.x] = s;
+  part[0][threadIdx.x] = s;
+  part[1][threadIdx.x] = f;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int i = 0; i < (int)blockDim.x; ++i) t += part[i];
-    acc[0] += t;
+    double t = 0.0, u = 0.0;
+    for (int i = 0; i < (int)blockDim.x; ++i) {
+      t += part[0][i];
+      u += part[1][i];
+    }
+    acc[1] += t;
+    acc[3] += u;
   }
 }
 
@@ -598,7 +617,7 @@ struct ostrich_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev;  // forward start / stop pairs
   size_t n_ev = 0;
-  double* d_flops = nullptr;   // [0] forward algorithmic flops, [1] adjoint algorithmic bytes
+  double* d_flops = nullptr;  // forward flops, adjoint bytes (roofline counts), then the same by finer counts
   std::vector<hipEvent_t> eva;  // adjoint start / stop pairs
   size_t n_eva = 0;
   int64_t* d_tape_off = nullptr;
@@ -1010,10 +1029,10 @@ static decltype(&k_forward<GpuTeam, false>) forward_kernel(const ostrich_ctx*, c
 
 // One bucket's forward step.  A planning kernel orders the bucket's worlds by
 // their estimated cost, most expensive first.  Untiered: one launch over that
-// order.  Tiered: the worlds expected to exceed the first carve's contacts run
-// with the full carve on the bucket's side stream, beside the launch of the
-// others with the first carve; that one defers any world it finds too large,
-// and a last launch, after both, takes the deferred worlds.
+// order.  Tiered: the worlds whose contacts exceed the first carve's run with
+// the full carve, beside the launch of the others with the first carve on the
+// bucket's side stream; that one defers any world it finds too large, and a
+// last launch, after both, takes the deferred worlds.
 // The worlds of the step are the list wl of n worlds (the bucket's, or a
 // caller's list of the context's worlds with the context-wide bucket).
 static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, const double* q_prev,
@@ -1036,15 +1055,19 @@ static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, c
     hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, st, sc.defer, 1);
     (void)hipEventRecord(bk.ev_fork, st);
     (void)hipStreamWaitEvent(bk.side, bk.ev_fork, 0);
-    hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(grid2), dim3(bk.team), bk.lds, bk.side, ctx->B,
-                       ctx->P, bk.caps, Launch{second, 0, ost::SPLIT_LDS, nullptr, 0, sc.plan + 1, nullptr, ctx->d_hist},
+    // The full carve's launch stays on the caller's stream and the first carve's
+    // goes to the side stream, behind its wait for the fork: so the few large
+    // workgroups reach the dispatcher first and find room, instead of waiting
+    // for the many small ones to leave a CU with enough free LDS.
+    hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(grid2), dim3(bk.team), bk.lds, st, ctx->B, ctx->P,
+                       bk.caps, Launch{second, 0, ost::SPLIT_LDS, nullptr, 0, sc.plan + 1, nullptr, ctx->d_hist},
                        q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters,
                        resnorm, tape, toff);
-    (void)hipEventRecord(bk.ev_join, bk.side);
-    hipLaunchKernelGGL((k_forward<GpuTeam, false, false>), dim3(n), dim3(bk.team), bk.lds1, st, ctx->B, ctx->P,
+    hipLaunchKernelGGL((k_forward<GpuTeam, false, false>), dim3(n), dim3(bk.team), bk.lds1, bk.side, ctx->B, ctx->P,
                        bk.caps1, Launch{first, 0, ost::SPLIT_LDS, nullptr, 0, sc.plan, sc.defer, ctx->d_hist}, q_prev,
                        u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters, resnorm, tape,
                        toff);
+    (void)hipEventRecord(bk.ev_join, bk.side);
     (void)hipStreamWaitEvent(st, bk.ev_join, 0);
     hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(grid2), dim3(bk.team), bk.lds, st, ctx->B, ctx->P,
                        bk.caps, Launch{sc.defer + 1, 0, ost::SPLIT_LDS, nullptr, 0, sc.defer, nullptr, ctx->d_hist},
@@ -1168,10 +1191,10 @@ extern "C" int ostrich_step_forward_noalloc(ostrich_ctx* ctx, const double* q_pr
 extern "C" int ostrich_ctx_timing(ostrich_ctx* ctx, int32_t mode, double* out) {
   if (!ctx) return fail(OSTRICH_E_ARG, "null context");
   if (mode == 1 || mode == 0) {  // start (reset) or stop
-    if (!ctx->d_flops) HIP_OK(ctx_malloc(ctx, &ctx->d_flops, 2 * sizeof(double)));
+    if (!ctx->d_flops) HIP_OK(ctx_malloc(ctx, &ctx->d_flops, 4 * sizeof(double)));
     if (mode == 1) {
       HIP_OK(hipDeviceSynchronize());
-      const double z[2] = {0.0, 0.0};
+      const double z[4] = {0.0, 0.0, 0.0, 0.0};
       HIP_OK(hipMemcpy(ctx->d_flops, z, sizeof(z), hipMemcpyHostToDevice));
       ctx->n_ev = 0;
       ctx->n_eva = 0;
@@ -1181,7 +1204,7 @@ extern "C" int ostrich_ctx_timing(ostrich_ctx* ctx, int32_t mode, double* out) {
   }
   if ((mode != 2 && mode != 3) || !out) return fail(OSTRICH_E_ARG, "timing mode");
   if (!ctx->d_flops) {
-    out[0] = out[1] = out[2] = 0.0;
+    out[0] = out[1] = out[2] = out[3] = 0.0;
     return 0;
   }
   HIP_OK(hipDeviceSynchronize());
@@ -1193,11 +1216,12 @@ extern "C" int ostrich_ctx_timing(ostrich_ctx* ctx, int32_t mode, double* out) {
     HIP_OK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
     total += ms;
   }
-  double acc[2] = {0.0, 0.0};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   HIP_OK(hipMemcpy(acc, ctx->d_flops, sizeof(acc), hipMemcpyDeviceToHost));
   out[0] = (double)(n_ev / 2);
   out[1] = total;
   out[2] = acc[mode - 2];
+  out[3] = acc[mode];
   return 0;
 }
 
@@ -1220,15 +1244,15 @@ static void launch_adjoint(ostrich_ctx* ctx, const Bucket& bk, hipStream_t s, co
     hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, s, bk.d_defer, 1);
     (void)hipEventRecord(bk.ev_fork, s);
     (void)hipStreamWaitEvent(bk.side, bk.ev_fork, 0);
-    hipLaunchKernelGGL((k_adjoint<GpuTeam, true>), dim3(grid2), dim3(bk.team), bk.lds_adj, bk.side, ctx->B, ctx->P,
+    hipLaunchKernelGGL((k_adjoint<GpuTeam, true>), dim3(grid2), dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P,
                        bk.caps, Launch{second, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_plan + 1, nullptr, nullptr}, q_prev,
                        u_prev, ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf,
                        g_mass, g_mu, g_kp, adj_status);
+    hipLaunchKernelGGL((k_adjoint<GpuTeam, false>), dim3(n), dim3(bk.team), bk.lds1_adj, bk.side, ctx->B, ctx->P,
+                       bk.caps1, Launch{first, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_plan, bk.d_defer, nullptr}, q_prev,
+                       u_prev, ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass,
+                       g_mu, g_kp, adj_status);
     (void)hipEventRecord(bk.ev_join, bk.side);
-    hipLaunchKernelGGL((k_adjoint<GpuTeam, false>), dim3(n), dim3(bk.team), bk.lds1_adj, s, ctx->B, ctx->P, bk.caps1,
-                       Launch{first, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_plan, bk.d_defer, nullptr}, q_prev, u_prev,
-                       ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass, g_mu,
-                       g_kp, adj_status);
     (void)hipStreamWaitEvent(s, bk.ev_join, 0);
     hipLaunchKernelGGL((k_adjoint<GpuTeam, true>), dim3(grid2), dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P,
                        bk.caps, Launch{bk.d_defer + 1, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_defer, nullptr, nullptr},
@@ -1273,7 +1297,7 @@ static int adjoint_step(ostrich_ctx* ctx, const double* q_prev, const double* u_
     HIP_OK(hipEventRecord(ctx->eva[ctx->n_eva + 1], (hipStream_t)stream));
     ctx->n_eva += 2;
     hipLaunchKernelGGL(k_abytes, dim3(1), dim3(256), 0, (hipStream_t)stream, ctx->B, (const double*)tape,
-                       (const int64_t*)ctx->d_tape_off, ctx->d_flops + 1);
+                       (const int64_t*)ctx->d_tape_off, ctx->d_flops);
   }
   HIP_OK(hipGetLastError());
   return 0;

@@ -403,8 +403,8 @@ def test_empty_and_malformed_batches_are_rejected(torch):
 def test_step_timing_counts_launches_and_algorithmic_work(torch):
     """The measurement facility: one forward step with a tape and its adjoint
     are counted once each; the forward's flops and the adjoint's bytes follow
-    the documented formulas from each world's rows m, half band and Newton
-    iterations."""
+    the documented formulas (the roofline counts and the finer ones) from each
+    world's rows m, half band and Newton iterations."""
     b = scenes.robot_batch(6, seed=12)
     P = scenes.solver_params()
     sim = sim_for(b, P)
@@ -422,21 +422,25 @@ def test_step_timing_counts_launches_and_algorithmic_work(torch):
     toff = np.cumsum([0] + [max(min(x.contact_cap, len(x.slots)) * 3 + 5 * len(x.joints) + x.n_servo, 1) ** 2 + 4
                             for x in b.worlds])
     tp = tape.cpu().numpy()
-    flops, nbytes = 0.0, 0.0
+    flops, flops_fine, nbytes, nbytes_fine = 0.0, 0.0, 0.0, 0.0
     for w in range(b.n_worlds):
         nj = b.joint_off[w + 1] - b.joint_off[w]
         nsv = b.worlds[w].n_servo
         m = 5.0 * nj + nsv + 3.0 * n_act[w]
-        flops += iters[w] * (26 * m * m + 2 * m ** 3 / 3 + 800 * m) + 400 * m + 24 * m * m + 2 * m ** 3 / 3
+        flops += iters[w] * (m ** 3 / 3 + 14 * m * m + 170 * m)
+        flops_fine += iters[w] * (26 * m * m + 2 * m ** 3 / 3 + 800 * m) + 400 * m + 24 * m * m + 2 * m ** 3 / 3
         nb = b.body_off[w + 1] - b.body_off[w]
         nl = b.lam_off[w + 1] - b.lam_off[w]
         nc = b.ctrl_off[w + 1] - b.ctrl_off[w]
         tm, bw = tp[toff[w + 1] - 3], min(tp[toff[w + 1] - 1], m - 1)
         assert tm == m
         band = m * (2 * bw + 1) - bw * (bw + 1)
-        nbytes += 8.0 * (band + 4 + 13 * nb + 6 * nb + nl + 26 * nb + nc)
+        nbytes += 8.0 * (26 * nb + nl + m * (m + 1) / 2)
+        nbytes_fine += 8.0 * (band + 4 + 13 * nb + 6 * nb + nl + 26 * nb + nc)
     assert abs(fwd["flops"] - flops) <= 1e-9 * flops
+    assert abs(fwd["flops_fine"] - flops_fine) <= 1e-9 * flops_fine
     assert abs(adj["bytes"] - nbytes) <= 1e-9 * nbytes
+    assert abs(adj["bytes_fine"] - nbytes_fine) <= 1e-9 * nbytes_fine
 
 
 @pytest.mark.parametrize("scene", ["robots", "boxes", "tripods", "terrain", "position_servos", "hinges"])
