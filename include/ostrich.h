@@ -75,8 +75,16 @@ typedef struct {
   const double* joint_kp;      /* [NJ] servo gain k_p (compliance 1/k_p of a velocity servo, Eq. (8)) */
   const int32_t* ctrl_off;     /* controls: one per actuated joint, in joint order */
   const int32_t* slot_off;     /* contact candidate slots */
-  const int32_t* slot_int;     /* [NS*4] kind (0 plane, 1 static box, 2 face of body b), body a, body b, obstacle */
-  const double* slot_real;     /* [NS*6] proxy offset in body a (3), proxy radius, mu, face half-height */
+  const int32_t* slot_int;     /* [NS*4] kind (0 plane, 1 static box, 2 face of body b, 3 heightmap mesh),
+                                  body a, body b, obstacle (kind 1) or candidate rank (kind 3) */
+  const double* slot_real;     /* [NS*9] proxy offset in body a (3), proxy radius, mu, face half-height,
+                                  rim-circle axis in body a (3).  A zero axis makes the proxy a sphere
+                                  (a point for radius 0).  A unit axis makes it the circle of that radius
+                                  about the offset, normal to the axis: an edge of a cylindrical wheel
+                                  (Sec. IV-D's wheels), which reaches r sqrt(1 - (n . a)^2) below its
+                                  centre along a contact normal n; static features only (kinds 0, 1, 3).
+                                  Context creation fails with OSTRICH_E_ARG for an axis that is not a
+                                  unit vector, a rim circle of radius <= 0 or one on a kind-2 slot. */
   const int32_t* obs_off;
   const double* obs_box;       /* [NO*6] centre (3), half extents (3): axis-aligned static boxes */
   const int32_t* lam_off;      /* multiplier layout described above */

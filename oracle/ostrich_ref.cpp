@@ -129,6 +129,8 @@ struct JointD {
 struct SlotD {
   int kind, a, b, feat;
   double loc[3], r, mu, face_h;
+  double ax[3];  // rim circle: unit axis in body a's frame; zero for a sphere or point
+  bool disc;
 };
 // Heightmap terrain: an n x n vertex grid, vertex (i, j) at (ox + i sp,
 // oy + j sp, z[i n + j]); each grid cell is cut along the diagonal from
@@ -201,11 +203,13 @@ WorldD load_world(const ostrich_ref_batch* B, int w) {
     S.a = B->slot_int[4 * s + 1];
     S.b = B->slot_int[4 * s + 2];
     S.feat = B->slot_int[4 * s + 3];
-    const double* r = B->slot_real + 6 * s;
+    const double* r = B->slot_real + 9 * s;
     for (int k = 0; k < 3; ++k) S.loc[k] = r[k];
     S.r = r[3];
     S.mu = r[4];
     S.face_h = r[5];
+    for (int k = 0; k < 3; ++k) S.ax[k] = r[6 + k];
+    S.disc = r[6] != 0.0 || r[7] != 0.0 || r[8] != 0.0;
     W.slots.push_back(S);
   }
   if (B->world_hmap && B->world_hmap[w] >= 0 && B->hmap_n >= 2) {
@@ -409,7 +413,28 @@ template <class T> struct Contact {
   V3<double> loc;
   V3<T> n, t1, t2, lb;
   T noff;
+  bool disc;       // the proxy is a rim circle of axis ax (body a's frame)
+  V3<double> ax;
 };
+
+// Support of a rim circle (radius r, unit axis a in the world) in direction
+// -n: the circle's points are c + r p for unit p perpendicular to a, and
+// n . p is least for p = -(n - (n . a) a) / |n - (n . a) a|, so the circle
+// reaches r sqrt(1 - (n . a)^2) below its centre along n.  Returns that depth
+// and the unit direction d = (n - (n . a) a) / |...| (the support point is
+// c - r d).  A circle facing n (1 - (n . a)^2 at most 1e-12) touches with its
+// whole rim: depth 0 and d = 0 (the centre stands for the rim).
+template <class S> S rim_depth(const V3<S>& n, const V3<S>& a, double r, V3<S>* d) {
+  S na = dot(n, a);
+  S s2 = 1.0 - na * na;
+  if (!(val(s2) > 1e-12)) {
+    if (d) *d = cst3<S>(0, 0, 0);
+    return S(0.0);
+  }
+  S sn = sqrt(s2);
+  if (d) *d = (n - a * na) * (1.0 / sn);
+  return sn * r;
+}
 
 template <class T>
 Contact<T> contact_frame(const WorldD& W, const T* qprev, Feature& F, bool decide, double* gap_out,
@@ -423,6 +448,8 @@ Contact<T> contact_frame(const WorldD& W, const T* qprev, Feature& F, bool decid
   C.r = S.r;
   C.mu = S.mu;
   C.loc = {S.loc[0], S.loc[1], S.loc[2]};
+  C.disc = S.disc;
+  C.ax = {S.ax[0], S.ax[1], S.ax[2]};
   const T* qa = qprev + 7 * S.a;
   Q4<T> Ra = prev_rot(qa);
   V3<T> P = V3<T>{qa[0], qa[1], qa[2]} + qrot(Ra, cst3<T>(S.loc));
@@ -494,6 +521,9 @@ Contact<T> contact_frame(const WorldD& W, const T* qprev, Feature& F, bool decid
     C.lb = qrot_inv(Rb, pc - xb);
     gap = h0 - S.r;
   }
+  // a rim circle reaches r sqrt(1 - (n . a)^2) below its centre, not r
+  V3<T> dsup = C.n;
+  if (S.disc && S.kind != 2 && val(gap) < 1e29) gap = gap + S.r - rim_depth(C.n, qrot(Ra, cst3<T>(S.ax)), S.r, &dsup);
   if (decide) F.tan_e = std::fabs(val(C.n.x)) > 0.9 ? 1 : 0;
   V3<T> e = F.tan_e ? cst3<T>(0, 1, 0) : cst3<T>(1, 0, 0);
   V3<T> t = cross(C.n, e);
@@ -501,7 +531,7 @@ Contact<T> contact_frame(const WorldD& W, const T* qprev, Feature& F, bool decid
   C.t2 = cross(C.n, C.t1);
   if (gap_out) *gap_out = val(gap);
   if (pc_out) {
-    V3<T> pc = P - C.n * S.r;
+    V3<T> pc = P - dsup * S.r;
     *pc_out = {val(pc.x), val(pc.y), val(pc.z)};
   }
   return C;
@@ -625,6 +655,7 @@ S position_row(const WorldD& W, const Layout& L, int row, int sub, const Contact
   // normal contact: signed gap at q (first argument of the FB function, Eq. (4))
   V3<S> P = xa + qrot(qa, V3<S>{S(C.loc.x), S(C.loc.y), S(C.loc.z)});
   if (C.kind == 2) return dot(C.n, P - (xb + qrot(qb, C.lb))) - C.r;
+  if (C.disc) return dot(C.n, P) - C.noff - rim_depth(C.n, qrot(qa, cst3<S>(C.ax.x, C.ax.y, C.ax.z)), C.r, (V3<S>*)nullptr);
   return dot(C.n, P) - C.noff - C.r;
 }
 
@@ -642,6 +673,8 @@ template <class T> Contact<Dual<T>> lift_contact(const Contact<T>& C) {
   D.t2 = lift3(C.t2);
   D.lb = lift3(C.lb);
   D.noff = lift(C.noff);
+  D.disc = C.disc;
+  D.ax = C.ax;
   return D;
 }
 
@@ -658,7 +691,10 @@ inline int sub_index(const Layout& L, int row) {
 template <class S>
 void friction_rows(const Contact<S>& C, int b, const V3<S>& xa, const Q4<S>& qa, const V3<S>& xb,
                    const S* ua, const S* ub, S* Jf, S* vt) {
-  V3<S> la = qrot(qa, V3<S>{S(C.loc.x), S(C.loc.y), S(C.loc.z)}) - C.n * C.r;
+  // lever of the contact point: the proxy's support point in direction -n
+  V3<S> dsup = C.n;
+  if (C.disc) rim_depth(C.n, qrot(qa, cst3<S>(C.ax.x, C.ax.y, C.ax.z)), C.r, &dsup);
+  V3<S> la = qrot(qa, V3<S>{S(C.loc.x), S(C.loc.y), S(C.loc.z)}) - dsup * C.r;
   V3<S> pc = xa + la;
   V3<S> lbv = b >= 0 ? pc - xb : cst3<S>(0, 0, 0);
   for (int r = 0; r < 2; ++r) {
@@ -1476,8 +1512,10 @@ extern "C" int ostrich_ref_step_forward(const ostrich_ref_batch* b, const ostric
     StepCtx X;
     X.W = load_world(b, w);
     X.P = P;
-    for (const SlotD& s : X.W.slots)
+    for (const SlotD& s : X.W.slots) {
       if (s.kind == 3 && X.W.hm.n < 2) return -3;  // terrain slot without a heightmap
+      if (s.disc && s.kind == 2) return -4;         // rim circles touch static features only
+    }
     int b0 = b->body_off[w], c0 = b->ctrl_off[w], l0 = b->lam_off[w], s0 = b->slot_off[w];
     prepare(X, q_prev + 7 * b0, u_prev + 6 * b0, ctrl ? ctrl + c0 : nullptr);
     StepResult R = newton(X, lam_prev + l0);

@@ -31,7 +31,8 @@ typedef struct {
   const int32_t* ctrl_off;     /* [W+1] */
   const int32_t* slot_off;     /* [W+1] */
   const int32_t* slot_int;     /* [NS*4] kind, body_a, body_b, feature */
-  const double*  slot_real;    /* [NS*6] local offset(3), radius, mu, face half-height */
+  const double*  slot_real;    /* [NS*9] local offset(3), radius, mu, face half-height, rim-circle axis(3)
+                                  (body frame, unit; all zero for a sphere or point proxy) */
   const int32_t* obs_off;      /* [W+1] */
   const double*  obs_box;      /* [NO*6] centre(3), half extents(3) */
   const int32_t* lam_off;      /* [W+1] */

@@ -339,7 +339,42 @@ template <class T> struct Frame {
   T noff;       // static features: plane offset n . c0
   v3<T> la;     // world offset of the proxy centre from body a at q-
   v3<T> lb;     // body-face contacts: world offset of the contact point from body b at q-
+  int disc;     // the proxy is a rim circle (a cylindrical wheel's edge), not a sphere
+  v3<T> ax;     // rim circle: its unit axis in the world at q-
 };
+
+// A frame of constants as one of dual numbers with zero tangents (every field).
+OST_HD v3<dual> lift3(const v3<double>& a) { return v3<dual>{dual(a.x), dual(a.y), dual(a.z)}; }
+OST_HD Frame<dual> lift_frame(const Frame<double>& f) {
+  Frame<dual> g;
+  g.n = lift3(f.n);
+  g.t1 = lift3(f.t1);
+  g.t2 = lift3(f.t2);
+  g.noff = dual(f.noff);
+  g.la = lift3(f.la);
+  g.lb = lift3(f.lb);
+  g.disc = f.disc;
+  g.ax = lift3(f.ax);
+  return g;
+}
+
+// Depth of a rim circle of radius r and unit axis a below its centre along the
+// unit normal n: its points are c + r p with p a unit vector normal to a, and
+// n . p is least at p = -d, d = (n - (n . a) a) / |n - (n . a) a|, which gives
+// r sqrt(1 - (n . a)^2).  Writes d (the contact point is c - r d).  A circle
+// facing n (1 - (n . a)^2 at most 1e-12) touches with its whole rim: depth 0,
+// d = 0.
+template <class T> OST_HD T rim_depth(const v3<T>& n, const v3<T>& a, double r, v3<T>* d) {
+  const T na = dot(n, a);
+  const T s2 = 1.0 - na * na;
+  if (!(val(s2) > 1e-12)) {
+    *d = mk(T(0.0), T(0.0), T(0.0));
+    return T(0.0);
+  }
+  const T sn = ssqrt(s2);
+  *d = (n - a * na) * (1.0 / sn);
+  return sn * r;
+}
 
 // Frame of a slot at q-.  With `decide`, the feature choice is made (value
 // arithmetic) and written to F; otherwise F is used as given.
@@ -356,6 +391,8 @@ OST_HD Frame<T> slot_frame(int kind, const double* sreal, const double* obs, con
   double r = sreal[3];
   C.noff = T(0.0);
   C.lb = mk(T(0.0), T(0.0), T(0.0));
+  C.disc = kind != 2 && (sreal[6] != 0.0 || sreal[7] != 0.0 || sreal[8] != 0.0);
+  C.ax = C.disc ? mul(Ra, ld3<T>(sreal + 6)) : mk(T(0.0), T(0.0), T(0.0));
   T gap;
   if (kind == 3) {  // heightmap feature
     if (decide && !keyed) F.hkey = hm ? hm_select(*hm, v3<double>{val(P.x), val(P.y), val(P.z)}, rc, rank) : -1;
@@ -408,6 +445,11 @@ OST_HD Frame<T> slot_frame(int kind, const double* sreal, const double* obs, con
     T h0 = dot(C.n, P - f0);
     C.lb = P - C.n * h0 - xb;
     gap = h0 - r;
+  }
+  // a rim circle reaches rim_depth below its centre along n, not r
+  if (C.disc && val(gap) < 1e29) {
+    v3<T> d;
+    gap = gap + r - rim_depth(C.n, C.ax, r, &d);
   }
   if (decide) F.tan_e = fabs(val(C.n.x)) > 0.9 ? 1 : 0;
   v3<T> e = F.tan_e ? mk(T(0.0), T(1.0), T(0.0)) : mk(T(1.0), T(0.0), T(0.0));

@@ -549,15 +549,10 @@ OST_HD void stiffness_t(Team& t, const Batch& B, const Params& P, const WorldRef
       ind.ub = c >= 0 ? ub : nullptr;
       ind.lg = lg;
       ind.target = dual(target);
-      ind.fr.n = v3<dual>{in.fr.n.x, in.fr.n.y, in.fr.n.z};
-      ind.fr.t1 = v3<dual>{in.fr.t1.x, in.fr.t1.y, in.fr.t1.z};
-      ind.fr.t2 = v3<dual>{in.fr.t2.x, in.fr.t2.y, in.fr.t2.z};
-      ind.fr.noff = dual(in.fr.noff);
-      ind.fr.la = v3<dual>{in.fr.la.x, in.fr.la.y, in.fr.la.z};
-      ind.fr.lb = v3<dual>{in.fr.lb.x, in.fr.lb.y, in.fr.lb.z};
+      ind.fr = lift_frame(in.fr);
       dual rd[3], Jd[36];
       double Dd[3];
-      eval_row_group<dual>(B, P, R, M, row, ind, rd, Jd, Dd);
+      eval_row_group<dual, Team::kRim>(B, P, R, M, row, ind, rd, Jd, Dd);
       #pragma unroll
       for (int k = 0; k < 3; ++k) if (k < n) {
         double jw = 0.0;
@@ -862,7 +857,7 @@ OST_HD bool adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
         int ci = M.r_idx[row];
         int s_ = M.c_slot[ci];
         const int* si = B.slot_int + 4 * (R.s0 + s_);
-        const double* sr = B.slot_real + 6 * (R.s0 + s_);
+        const double* sr = B.slot_real + 9 * (R.s0 + s_);
         const double* obs = si[0] == 1 ? B.obs_box + 6 * (R.o0 + si[3]) : nullptr;
         Feature F = M.c_feat[ci];
         m3<dual> Rb2 = ind.Rb;
@@ -872,7 +867,7 @@ OST_HD bool adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
       }
       dual rd[3], Jd[36];
       double Dd[3];
-      eval_row_group<dual>(B, P, R, M, row, ind, rd, Jd, Dd);
+      eval_row_group<dual, Team::kRim>(B, P, R, M, row, ind, rd, Jd, Dd);
       #pragma unroll
       for (int k = 0; k < 3; ++k) if (k < n) {
         s += wl[row + k] * M.D[row + k] * rd[k].d;
@@ -947,15 +942,10 @@ OST_HD bool adjoint_world(Team& t, const Batch& B, const Params& P, const Caps& 
         ind.ub = b >= 0 ? ub : nullptr;
         ind.lg = lg;
         ind.target = dual(0.0);
-        ind.fr.n = v3<dual>{in.fr.n.x, in.fr.n.y, in.fr.n.z};
-        ind.fr.t1 = v3<dual>{in.fr.t1.x, in.fr.t1.y, in.fr.t1.z};
-        ind.fr.t2 = v3<dual>{in.fr.t2.x, in.fr.t2.y, in.fr.t2.z};
-        ind.fr.noff = dual(in.fr.noff);
-        ind.fr.la = v3<dual>{in.fr.la.x, in.fr.la.y, in.fr.la.z};
-        ind.fr.lb = v3<dual>{in.fr.lb.x, in.fr.lb.y, in.fr.lb.z};
+        ind.fr = lift_frame(in.fr);
         dual rd[3], Jd[36];
         double Dd[3];
-        eval_group<dual>(B, P, R, RK_CONTACT, M.r_idx[row], M.r_sub[row], b >= 0, M.c_r[c], dual(M.c_mu[c], 1.0),
+        eval_group<dual, Team::kRim>(B, P, R, RK_CONTACT, M.r_idx[row], M.r_sub[row], b >= 0, M.c_r[c], dual(M.c_mu[c], 1.0),
                          M.c_sn[c], M.c_sf[c], M.c_kind[c], ind, rd, Jd, Dd);
         for (int k = 1; k < 3; ++k) g += wl[row + k] * M.D[row + k] * rd[k].d;
       }

@@ -36,6 +36,9 @@ int fail(int code, const std::string& msg) {
 
 struct GpuTeam {
   static constexpr bool kGlobal = false;  // workspace entirely in LDS
+  // whether the rim-circle contact terms are compiled in: only batches with a
+  // rim-circle slot run the kernels that carry them (the *Rim team types)
+  static constexpr bool kRim = false;
   __device__ int rank() const { return threadIdx.x; }
   __device__ int size() const { return blockDim.x; }
   __device__ void sync() const { __syncthreads(); }
@@ -141,6 +144,12 @@ struct GpuTeamG : GpuTeam {
     sync();
     return r;
   }
+};
+struct GpuTeamRim : GpuTeam {
+  static constexpr bool kRim = true;
+};
+struct GpuTeamGRim : GpuTeamG {
+  static constexpr bool kRim = true;
 };
 
 // Launch shape of one bucket of worlds: the worlds of the list are taken by
@@ -297,7 +306,7 @@ __global__ void __launch_bounds__(64) k_count_active(ost::Batch B, ost::Params P
 __global__ void __launch_bounds__(256) k_plain_begin(ost::Batch B, ost::Params P, ost::Caps caps, int w,
                                                      const double* q_prev, const double* u_prev,
                                                      const double* lam_prev, const double* ctrl, char* ws) {
-  GpuTeamG t;
+  GpuTeamGRim t;
   ost::WorldMem M = ost::carve(ws, caps, blockDim.x);
   ost::WorldRef R = ost::world_ref(B, w);
   ost::FwState S;
@@ -308,7 +317,7 @@ __global__ void __launch_bounds__(256) k_plain_begin(ost::Batch B, ost::Params P
 
 __global__ void __launch_bounds__(256) k_plain_iteration(ost::Batch B, ost::Params P, ost::Caps caps, int w,
                                                          const double* ctrl, char* ws, int k) {
-  GpuTeamG t;
+  GpuTeamGRim t;
   ost::WorldMem M = ost::carve(ws, caps, blockDim.x);
   ost::WorldRef R = ost::world_ref_after(B, M, w);
   ost::FwState S = ost::fw_load(M);
@@ -323,7 +332,7 @@ __global__ void __launch_bounds__(256) k_plain_end(ost::Batch B, ost::Params P, 
                                                    double* lam_next, int32_t* act_slot, int32_t* n_act,
                                                    int32_t* status, int32_t* iters, double* resnorm, double* tape,
                                                    const int64_t* tape_off, char* ws) {
-  GpuTeamG t;
+  GpuTeamGRim t;
   ost::WorldMem M = ost::carve(ws, caps, blockDim.x);
   ost::WorldRef R = ost::world_ref_after(B, M, w);
   ost::FwState S = ost::fw_load(M);
@@ -600,6 +609,7 @@ struct ostrich_ctx {
   int team;
   int schedule;
   int tier_contacts;  // ostrich_params::tier_contacts
+  bool rim = false;   // the batch has rim-circle slots: launch the kernels with those terms
   size_t lds_limit;
   int n_cu;
   int W, NB, NL, NS, NCTRL;
@@ -831,7 +841,27 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   HIP_OK(hipMemcpy(cap.data(), b->contact_cap, W * 4, hipMemcpyDeviceToHost));
   std::vector<int32_t> act(std::max(jo[W], 1), 0);
   if (jo[W] > 0) HIP_OK(hipMemcpy(act.data(), b->joint_act, jo[W] * 4, hipMemcpyDeviceToHost));
+  bool rim = false;
+  if (so[W] > 0) {  // rim circles: a unit axis, and static features only
+    if (!is_ptr_ok(b->slot_int) || !is_ptr_ok(b->slot_real)) return fail(OSTRICH_E_ARG, "null slot arrays");
+    std::vector<int32_t> si(4 * (size_t)so[W]);
+    std::vector<double> sr(9 * (size_t)so[W]);
+    HIP_OK(hipMemcpy(si.data(), b->slot_int, si.size() * 4, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(sr.data(), b->slot_real, sr.size() * 8, hipMemcpyDeviceToHost));
+    for (int32_t s = 0; s < so[W]; ++s) {
+      const double* a = sr.data() + 9 * (size_t)s;
+      const double n2 = a[6] * a[6] + a[7] * a[7] + a[8] * a[8];
+      if (n2 == 0.0) continue;
+      rim = true;
+      if (!(std::fabs(n2 - 1.0) <= 1e-12)) return fail(OSTRICH_E_ARG, "slot " + std::to_string(s) +
+                                                                         ": a rim circle's axis must be a unit vector");
+      if (si[4 * (size_t)s] == 2 || !(a[3] > 0.0))
+        return fail(OSTRICH_E_ARG, "slot " + std::to_string(s) +
+                                       ": a rim circle needs a positive radius and a static feature");
+    }
+  }
   std::unique_ptr<ostrich_ctx> ctx(new ostrich_ctx());
+  ctx->rim = rim;
   ctx->wcaps.resize(W);
   ost::Caps c{0, 0, 0, 0, 0, 0};
   std::vector<int64_t> toff(W + 1, 0);
@@ -862,7 +892,10 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   }
   for (auto f : {(const void*)k_forward<GpuTeam, false>, (const void*)k_adjoint<GpuTeam>,
                  (const void*)k_forward<GpuTeamG, false>, (const void*)k_adjoint<GpuTeamG>,
-                 (const void*)k_forward<GpuTeam, false, true>, (const void*)k_adjoint<GpuTeam, true>})
+                 (const void*)k_forward<GpuTeam, false, true>, (const void*)k_adjoint<GpuTeam, true>,
+                 (const void*)k_forward<GpuTeamRim, false>, (const void*)k_adjoint<GpuTeamRim>,
+                 (const void*)k_forward<GpuTeamGRim, false>, (const void*)k_adjoint<GpuTeamGRim>,
+                 (const void*)k_forward<GpuTeamRim, false, true>, (const void*)k_adjoint<GpuTeamRim, true>})
     HIP_OK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctx->lds_limit));
   std::memcpy(&ctx->B, b, sizeof(ost::Batch));
   static_assert(sizeof(ost::Batch) == sizeof(ostrich_batch), "batch layouts differ");
@@ -1023,8 +1056,8 @@ template <class F> static int for_buckets(ostrich_ctx* ctx, hipStream_t st, F f)
 // The forward kernel of a bucket (team kind by the storage split).  Only the
 // banded-LU Newton step is instantiated for the GPU: the matrix-free Krylov
 // step is rejected at context creation.
-static decltype(&k_forward<GpuTeam, false>) forward_kernel(const ostrich_ctx*, const Bucket& bk) {
-  return bk.split == ost::SPLIT_GLOBAL ? k_forward<GpuTeamG, false> : k_forward<GpuTeam, false>;
+template <class TL, class TG> static decltype(&k_forward<TL, false>) forward_kernel(const Bucket& bk) {
+  return bk.split == ost::SPLIT_GLOBAL ? k_forward<TG, false> : k_forward<TL, false>;
 }
 
 // One bucket's forward step.  A planning kernel orders the bucket's worlds by
@@ -1035,11 +1068,12 @@ static decltype(&k_forward<GpuTeam, false>) forward_kernel(const ostrich_ctx*, c
 // last launch, after both, takes the deferred worlds.
 // The worlds of the step are the list wl of n worlds (the bucket's, or a
 // caller's list of the context's worlds with the context-wide bucket).
-static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, const double* q_prev,
-                           const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
-                           double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
-                           int32_t* iters, double* resnorm, double* tape, const Scratch& sc, const int32_t* wl,
-                           int n, bool tier_ok) {
+template <class TL, class TG>
+static void launch_forward_t(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, const double* q_prev,
+                             const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
+                             double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
+                             int32_t* iters, double* resnorm, double* tape, const Scratch& sc, const int32_t* wl,
+                             int n, bool tier_ok) {
   const int64_t* toff = ctx->d_tape_off;
   const int grid2 = std::min(bk.grid2, n);
   const bool tier = bk.tier && tier_ok;
@@ -1059,17 +1093,17 @@ static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, c
     // goes to the side stream, behind its wait for the fork: so the few large
     // workgroups reach the dispatcher first and find room, instead of waiting
     // for the many small ones to leave a CU with enough free LDS.
-    hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(grid2), dim3(bk.team), bk.lds, st, ctx->B, ctx->P,
+    hipLaunchKernelGGL((k_forward<TL, false, true>), dim3(grid2), dim3(bk.team), bk.lds, st, ctx->B, ctx->P,
                        bk.caps, Launch{second, 0, ost::SPLIT_LDS, nullptr, 0, sc.plan + 1, nullptr, ctx->d_hist},
                        q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters,
                        resnorm, tape, toff);
-    hipLaunchKernelGGL((k_forward<GpuTeam, false, false>), dim3(n), dim3(bk.team), bk.lds1, bk.side, ctx->B, ctx->P,
+    hipLaunchKernelGGL((k_forward<TL, false, false>), dim3(n), dim3(bk.team), bk.lds1, bk.side, ctx->B, ctx->P,
                        bk.caps1, Launch{first, 0, ost::SPLIT_LDS, nullptr, 0, sc.plan, sc.defer, ctx->d_hist}, q_prev,
                        u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters, resnorm, tape,
                        toff);
     (void)hipEventRecord(bk.ev_join, bk.side);
     (void)hipStreamWaitEvent(st, bk.ev_join, 0);
-    hipLaunchKernelGGL((k_forward<GpuTeam, false, true>), dim3(grid2), dim3(bk.team), bk.lds, st, ctx->B, ctx->P,
+    hipLaunchKernelGGL((k_forward<TL, false, true>), dim3(grid2), dim3(bk.team), bk.lds, st, ctx->B, ctx->P,
                        bk.caps, Launch{sc.defer + 1, 0, ost::SPLIT_LDS, nullptr, 0, sc.defer, nullptr, ctx->d_hist},
                        q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters,
                        resnorm, tape, toff);
@@ -1078,9 +1112,23 @@ static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, c
   Launch L{first, n, bk.split, bk.split == ost::SPLIT_GLOBAL ? sc.gscr : nullptr, bk.gstride, nullptr, nullptr,
            ctx->d_hist};
   const int grid = bk.split == ost::SPLIT_GLOBAL ? std::max(1, std::min(n, sc.slots)) : n;
-  hipLaunchKernelGGL(forward_kernel(ctx, bk), dim3(grid), dim3(bk.team), bk.lds, st, ctx->B, ctx->P, bk.caps, L,
+  hipLaunchKernelGGL((forward_kernel<TL, TG>(bk)), dim3(grid), dim3(bk.team), bk.lds, st, ctx->B, ctx->P, bk.caps, L,
                      q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next, act_slot, n_act, status, iters, resnorm,
                      tape, toff);
+}
+// The kernels of the context's batch: with the rim-circle terms compiled in
+// only when the batch has rim-circle slots.
+static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, const double* q_prev,
+                           const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
+                           double* u_next, double* lam_next, int32_t* act_slot, int32_t* n_act, int32_t* status,
+                           int32_t* iters, double* resnorm, double* tape, const Scratch& sc, const int32_t* wl,
+                           int n, bool tier_ok) {
+  if (ctx->rim)
+    launch_forward_t<GpuTeamRim, GpuTeamGRim>(ctx, bk, st, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
+                                              act_slot, n_act, status, iters, resnorm, tape, sc, wl, n, tier_ok);
+  else
+    launch_forward_t<GpuTeam, GpuTeamG>(ctx, bk, st, q_prev, u_prev, lam_prev, ctrl, q_next, u_next, lam_next,
+                                        act_slot, n_act, status, iters, resnorm, tape, sc, wl, n, tier_ok);
 }
 static void launch_forward(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st, const double* q_prev,
                            const double* u_prev, const double* lam_prev, const double* ctrl, double* q_next,
@@ -1228,11 +1276,12 @@ extern "C" int ostrich_ctx_timing(ostrich_ctx* ctx, int32_t mode, double* out) {
 // One bucket's adjoint step over the list wl of n worlds, as the forward
 // (launch_forward): the plan's estimates and the first carve's split come from
 // the row counts the tape records, which are this step's.
-static void launch_adjoint(ostrich_ctx* ctx, const Bucket& bk, hipStream_t s, const int32_t* wl, int n,
-                           const double* q_prev, const double* u_prev, const double* ctrl, const double* u_next,
-                           const double* lam_next, const double* tp, const double* gq_next, const double* gu_next,
-                           double* gq_prev, double* gu_prev, double* g_ctrl, int rf, double* g_mass, double* g_mu,
-                           double* g_kp, int32_t* adj_status, bool tier_ok) {
+template <class TL, class TG>
+static void launch_adjoint_t(ostrich_ctx* ctx, const Bucket& bk, hipStream_t s, const int32_t* wl, int n,
+                             const double* q_prev, const double* u_prev, const double* ctrl, const double* u_next,
+                             const double* lam_next, const double* tp, const double* gq_next, const double* gu_next,
+                             double* gq_prev, double* gu_prev, double* g_ctrl, int rf, double* g_mass, double* g_mu,
+                             double* g_kp, int32_t* adj_status, bool tier_ok) {
   const int64_t* toff = ctx->d_tape_off;
   const int grid2 = std::min(bk.grid2, n);
   const bool tier = bk.tier && tier_ok;
@@ -1244,17 +1293,17 @@ static void launch_adjoint(ostrich_ctx* ctx, const Bucket& bk, hipStream_t s, co
     hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, s, bk.d_defer, 1);
     (void)hipEventRecord(bk.ev_fork, s);
     (void)hipStreamWaitEvent(bk.side, bk.ev_fork, 0);
-    hipLaunchKernelGGL((k_adjoint<GpuTeam, true>), dim3(grid2), dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P,
+    hipLaunchKernelGGL((k_adjoint<TL, true>), dim3(grid2), dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P,
                        bk.caps, Launch{second, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_plan + 1, nullptr, nullptr}, q_prev,
                        u_prev, ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf,
                        g_mass, g_mu, g_kp, adj_status);
-    hipLaunchKernelGGL((k_adjoint<GpuTeam, false>), dim3(n), dim3(bk.team), bk.lds1_adj, bk.side, ctx->B, ctx->P,
+    hipLaunchKernelGGL((k_adjoint<TL, false>), dim3(n), dim3(bk.team), bk.lds1_adj, bk.side, ctx->B, ctx->P,
                        bk.caps1, Launch{first, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_plan, bk.d_defer, nullptr}, q_prev,
                        u_prev, ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass,
                        g_mu, g_kp, adj_status);
     (void)hipEventRecord(bk.ev_join, bk.side);
     (void)hipStreamWaitEvent(s, bk.ev_join, 0);
-    hipLaunchKernelGGL((k_adjoint<GpuTeam, true>), dim3(grid2), dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P,
+    hipLaunchKernelGGL((k_adjoint<TL, true>), dim3(grid2), dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P,
                        bk.caps, Launch{bk.d_defer + 1, 0, ost::SPLIT_LDS, nullptr, 0, bk.d_defer, nullptr, nullptr},
                        q_prev, u_prev, ctrl, u_next, lam_next, tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl,
                        rf, g_mass, g_mu, g_kp, adj_status);
@@ -1263,9 +1312,23 @@ static void launch_adjoint(ostrich_ctx* ctx, const Bucket& bk, hipStream_t s, co
   Launch L{first, n, bk.split, bk.split == ost::SPLIT_GLOBAL ? bk.gscr : nullptr, bk.gstride, nullptr, nullptr,
            nullptr};
   const int grid = bk.split == ost::SPLIT_GLOBAL ? std::max(1, std::min(n, bk.slots)) : n;
-  hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>, dim3(grid),
+  hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<TG> : k_adjoint<TL>, dim3(grid),
                      dim3(bk.team), bk.lds_adj, s, ctx->B, ctx->P, bk.caps, L, q_prev, u_prev, ctrl, u_next, lam_next,
                      tp, toff, gq_next, gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass, g_mu, g_kp, adj_status);
+}
+static void launch_adjoint(ostrich_ctx* ctx, const Bucket& bk, hipStream_t s, const int32_t* wl, int n,
+                           const double* q_prev, const double* u_prev, const double* ctrl, const double* u_next,
+                           const double* lam_next, const double* tp, const double* gq_next, const double* gu_next,
+                           double* gq_prev, double* gu_prev, double* g_ctrl, int rf, double* g_mass, double* g_mu,
+                           double* g_kp, int32_t* adj_status, bool tier_ok) {
+  if (ctx->rim)
+    launch_adjoint_t<GpuTeamRim, GpuTeamGRim>(ctx, bk, s, wl, n, q_prev, u_prev, ctrl, u_next, lam_next, tp, gq_next,
+                                              gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass, g_mu, g_kp, adj_status,
+                                              tier_ok);
+  else
+    launch_adjoint_t<GpuTeam, GpuTeamG>(ctx, bk, s, wl, n, q_prev, u_prev, ctrl, u_next, lam_next, tp, gq_next,
+                                        gu_next, gq_prev, gu_prev, g_ctrl, rf, g_mass, g_mu, g_kp, adj_status,
+                                        tier_ok);
 }
 
 static int adjoint_step(ostrich_ctx* ctx, const double* q_prev, const double* u_prev, const double* ctrl,
@@ -1402,7 +1465,9 @@ extern "C" int ostrich_step_adjoint_plain(ostrich_ctx* ctx, const double* q_prev
   const Bucket& bk = ctx->all;
   if (!bk.d_worlds || (int)bk.worlds.size() != ctx->W) return fail(OSTRICH_E_ARG, "context world list missing");
   for (int w = 0; w < ctx->W; ++w)  // one launch per world, over the one-world list {w}
-    hipLaunchKernelGGL(bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>, dim3(1),
+    hipLaunchKernelGGL(ctx->rim ? (bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamGRim> : k_adjoint<GpuTeamRim>)
+                                : (bk.split == ost::SPLIT_GLOBAL ? k_adjoint<GpuTeamG> : k_adjoint<GpuTeam>),
+                       dim3(1),
                        dim3(bk.team), bk.lds_adj, (hipStream_t)stream, ctx->B, ctx->P, bk.caps,
                        list_launch(ctx, bk.d_worlds + w, 1), q_prev, u_prev, ctrl, u_next, lam_next,
                        (const double*)tape, (const int64_t*)ctx->d_tape_off, gq_next, gu_next, gq_prev, gu_prev,

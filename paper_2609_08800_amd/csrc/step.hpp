@@ -51,6 +51,8 @@ OST_HD GroupIn<double> group_in_lds(const WorldMem& M, int row, const double* u,
     in.fr.noff = M.c_noff[c];
     in.fr.la = ldv(M.c_la + 3 * c);
     in.fr.lb = ldv(M.c_lb + 3 * c);
+    in.fr.ax = ldv(M.c_ax + 3 * c);
+    in.fr.disc = M.c_ax[3 * c] != 0.0 || M.c_ax[3 * c + 1] != 0.0 || M.c_ax[3 * c + 2] != 0.0;
   }
   return in;
 }
@@ -83,12 +85,12 @@ OST_HD double servo_target(const Batch& B, const WorldRef& R, const double* ctrl
   return ctrl[R.c0 + c];
 }
 
-template <class T>
+template <class T, bool kRim = true>
 OST_HD void eval_row_group(const Batch& B, const Params& P, const WorldRef& R, const WorldMem& M, int row,
                            const GroupIn<T>& in, T* r, T* J, double* D) {
   int kind = M.r_kind[row];
   int c = kind == RK_CONTACT ? M.r_idx[row] : 0;
-  eval_group<T>(B, P, R, kind, M.r_idx[row], M.r_sub[row], M.r_b[row] >= 0, kind == RK_CONTACT ? M.c_r[c] : 0.0,
+  eval_group<T, kRim>(B, P, R, kind, M.r_idx[row], M.r_sub[row], M.r_b[row] >= 0, kind == RK_CONTACT ? M.c_r[c] : 0.0,
                 kind == RK_CONTACT ? M.c_mu[c] : 0.0, kind == RK_CONTACT ? M.c_sn[c] : 1.0,
                 kind == RK_CONTACT ? M.c_sf[c] : 1.0, kind == RK_CONTACT ? M.c_kind[c] : 0, in, r, J, D);
 }
@@ -105,8 +107,8 @@ OST_HD int hm_leader(const Batch& B, const WorldRef& R, int s) {
   if (r <= 0 || r >= 4 || s - r < 0) return s;
   const int l = s - r;
   const int* li = B.slot_int + 4 * (R.s0 + l);
-  const double* sr = B.slot_real + 6 * (R.s0 + s);
-  const double* lr = B.slot_real + 6 * (R.s0 + l);
+  const double* sr = B.slot_real + 9 * (R.s0 + s);
+  const double* lr = B.slot_real + 9 * (R.s0 + l);
   if (li[0] != 3 || li[3] != 0 || li[1] != si[1]) return s;
   for (int k = 0; k < 4; ++k)
     if (!(lr[k] == sr[k])) return s;
@@ -158,7 +160,7 @@ OST_HD bool terrain_candidates(Team& t, const Batch& B, const Params& P, const W
   for (int u = t.rank(); u < ntask * G; u += t.size()) {
     const int task = u / G, part = u - task * G, s = M.s_act[task];
     const int* si = B.slot_int + 4 * (R.s0 + s);
-    const double* sr = B.slot_real + 6 * (R.s0 + s);
+    const double* sr = B.slot_real + 9 * (R.s0 + s);
     const int a = si[1];
     // the proxy centre and search radius of the slot loop below
     const v3<double> la = mul(ldm(M.Rm + 9 * a), ldv(sr));
@@ -198,7 +200,9 @@ OST_HD bool terrain_candidates(Team& t, const Batch& B, const Params& P, const W
 // point) within delta0.  ub is body b's velocity for a body-face slot.
 OST_HD bool approach_active(const Params& P, int kind, const double* sr, const Frame<double>& C, double gap,
                             const v3<double>& xa, const double* ua, const v3<double>& xb, const double* ub) {
-  v3<double> pc = xa + C.la - C.n * sr[3];
+  v3<double> d = C.n;  // from the proxy's contact point to its centre
+  if (C.disc) rim_depth(C.n, C.ax, sr[3], &d);
+  v3<double> pc = xa + C.la - d * sr[3];
   v3<double> vr = ldv(ua) + cross(ldv(ua + 3), pc - xa);
   if (kind == 2) vr = vr - (ldv(ub) + cross(ldv(ub + 3), pc - xb));
   double vn = dot(C.n, vr);
@@ -213,7 +217,7 @@ OST_HD int count_active(const Batch& B, const Params& P, const WorldRef& R, cons
   int n = 0;
   for (int s = s0; s < R.ns; s += ds) {
     const int* si = B.slot_int + 4 * (R.s0 + s);
-    const double* sr = B.slot_real + 6 * (R.s0 + s);
+    const double* sr = B.slot_real + 9 * (R.s0 + s);
     const int kind = si[0], a = si[1], b = si[2];
     if (kind == 3) {
       ++n;
@@ -288,7 +292,7 @@ OST_HD bool prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
   const bool keyed = terrain_candidates(t, B, P, R, M);
   for (int s = t.rank(); s < R.ns; s += t.size()) {
     const int* si = B.slot_int + 4 * (R.s0 + s);
-    const double* sr = B.slot_real + 6 * (R.s0 + s);
+    const double* sr = B.slot_real + 9 * (R.s0 + s);
     int kind = si[0], a = si[1], b = si[2];
     Feature F{};
     double gap;
@@ -337,7 +341,7 @@ OST_HD bool prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
   for (int c = t.rank(); c < R.nc; c += t.size()) {
     int s = M.c_slot[c];
     const int* si = B.slot_int + 4 * (R.s0 + s);
-    const double* sr = B.slot_real + 6 * (R.s0 + s);
+    const double* sr = B.slot_real + 9 * (R.s0 + s);
     int kind = si[0], a = si[1], b = si[2];
     Feature F = M.s_feat[s];
     v3<double> xb{0, 0, 0};
@@ -358,6 +362,7 @@ OST_HD bool prologue(Team& t, const Batch& B, const Params& P, WorldRef& R, cons
     M.c_noff[c] = C.noff;
     stv(M.c_la + 3 * c, C.la);
     stv(M.c_lb + 3 * c, C.lb);
+    stv(M.c_ax + 3 * c, C.ax);
     M.c_sn[c] = 1.0;
     M.c_sf[c] = 1.0;
   }
@@ -477,7 +482,7 @@ OST_HD double evaluate(Team& t, const Batch& B, const Params& P, const WorldRef&
     GroupIn<double> in = group_in_lds(M, row, u, lam, target);
     double r[3], D[3];
     double* Jg = M.J + 12 * row;
-    eval_row_group<double>(B, P, R, M, row, in, r, Jg, D);
+    eval_row_group<double, Team::kRim>(B, P, R, M, row, in, r, Jg, D);
     #pragma unroll
     for (int k = 0; k < 3; ++k) if (k < n) {
       M.res[row + k] = r[k];
@@ -491,7 +496,7 @@ OST_HD double evaluate(Team& t, const Batch& B, const Params& P, const WorldRef&
     double* Gl = M.Gl + 3 * row;
     if (kind == RK_CONTACT) {
       int c = M.r_idx[row];
-      contact_G(P, in, b >= 0, M.c_r[c], M.c_mu[c], M.c_sn[c], M.c_sf[c], M.c_kind[c], Jg, D, Gu, Gl);
+      contact_G<Team::kRim>(P, in, b >= 0, M.c_r[c], M.c_mu[c], M.c_sn[c], M.c_sf[c], M.c_kind[c], Jg, D, Gu, Gl);
     } else {  // joint rows: D r = c(q(u)) / h, so D dr/du = J; servo rows: dr/du = J, dr/dlambda = alpha
       for (int q = 0; q < 12; ++q) Gu[q] = Jg[q];
       Gl[0] = kind == RK_SERVO ? servo_compliance(B, R, M.r_idx[row], P.h) : 0.0;

@@ -22,6 +22,7 @@ struct WorldMem {
   int *c_slot, *c_kind, *c_a, *c_b;
   Feature* c_feat;
   double *c_n, *c_t1, *c_t2, *c_noff, *c_la, *c_lb, *c_r, *c_mu, *c_sn, *c_sf;
+  double* c_ax;  // rim circles: world axis at q- (zero for a sphere or point proxy)
   // rows
   int *r_kind, *r_a, *r_b, *r_idx, *r_sub, *r_g;
   double *J, *Y, *Gl, *D, *res, *lam, *dlam, *lamt, *lambest, *Abar, *rmax;
@@ -83,7 +84,7 @@ OST_HD size_t world_glob_doubles(const Caps& c, int split) {
 OST_HD size_t world_lds_bytes(const Caps& c, int team, int split = SPLIT_LDS, bool adjoint = false) {
   size_t d = adjoint ? kry_doubles(c) : 0, i = 0;
   d += (size_t)c.nb * (3 + 7 + 9 + 9 + 9 + 1 + 3 + 6 * 7 + 7 + 6);
-  d += (size_t)c.nc * 20;
+  d += (size_t)c.nc * 23;
   d += (size_t)c.mr * 8;
   if (split == SPLIT_LDS) d += (size_t)c.mr * 27 + schur_doubles(c.mr);
   d += c.mr;
@@ -111,7 +112,7 @@ OST_HD WorldMem carve(char* base, const Caps& c, int team, int split = SPLIT_LDS
   M.ubest = take(6 * c.nb); M.ut = take(6 * c.nb); M.gq = take(7 * c.nb); M.kg = take(6 * c.nb);
   M.c_n = take(3 * c.nc); M.c_t1 = take(3 * c.nc); M.c_t2 = take(3 * c.nc); M.c_noff = take(c.nc);
   M.c_la = take(3 * c.nc); M.c_lb = take(3 * c.nc); M.c_r = take(c.nc); M.c_mu = take(c.nc);
-  M.c_sn = take(c.nc); M.c_sf = take(c.nc);
+  M.c_sn = take(c.nc); M.c_sf = take(c.nc); M.c_ax = take(3 * c.nc);
   M.J = gtake(12 * c.mr); M.Y = gtake(12 * c.mr); M.Gl = gtake(3 * c.mr);
   M.D = take(c.mr); M.res = take(c.mr);
   M.lam = take(c.mr); M.dlam = take(c.mr); M.lamt = take(c.mr); M.lambest = take(c.mr); M.Abar = take(c.mr);
@@ -220,7 +221,7 @@ OST_HD double joint_angle_der(const m3<dual>& Ra, const m3<dual>& Rb, const doub
   return (x.v * y.d - y.v * x.d) / (x.v * x.v + y.v * y.v);
 }
 
-template <class T>
+template <class T, bool kRim = true>
 OST_HD void eval_group(const Batch& B, const Params& P, const WorldRef& R, int kind, int idx, int sub,
                        int has_b, double r_prox, T mu, double sn, double sf, int ckind,
                        const GroupIn<T>& in, T* r, T* J, double* D) {
@@ -271,12 +272,27 @@ OST_HD void eval_group(const Batch& B, const Params& P, const WorldRef& R, int k
   }
   // contact group: normal row (Eq. (4), eps-smoothed FB) and friction rows (Eq. (7))
   const Frame<T>& F = in.fr;
+  // the proxy reaches `depth` below its centre along n; dsup points from its
+  // contact point to its centre (a rim circle's contact point turns with body
+  // a's axis at q+)
+  T depth = T(r_prox);
+  v3<T> dsup = F.n;
+  v3<T> a1 = zero;
+  if (kRim && F.disc) {
+    a1 = cay(Ba.k, F.ax);
+    depth = rim_depth(F.n, a1, r_prox, &dsup);
+  }
   T gap;
   if (ckind == 2) {
     gap = pos_term(Ba, F.la, F.n, J) - pos_term(Bb, F.lb, F.n, J + 6) - r_prox;
     for (int t = 6; t < 12; ++t) J[t] = -J[t];
   } else {
-    gap = pos_term(Ba, F.la, F.n, J) - F.noff - r_prox;
+    gap = pos_term(Ba, F.la, F.n, J) - F.noff - depth;
+    if (kRim && F.disc && val(depth) > 0.0) {
+      // depth = r sqrt(1 - (n . a)^2), a = Cay(k) ax: d(-depth)/dk = (r^2 (n . a) / depth) grad_k(n . a)
+      const v3<T> g = cay_grad(Ba.k, F.ax, F.n) * (dot(F.n, a1) * (r_prox * r_prox) / depth);
+      J[3] += g.x * 0.5; J[4] += g.y * 0.5; J[5] += g.z * 0.5;
+    }
   }
   T Bq = sn * in.lg[0];
   T S = ssqrt(gap * gap + Bq * Bq + P.eps * P.eps);
@@ -284,7 +300,7 @@ OST_HD void eval_group(const Batch& B, const Params& P, const WorldRef& R, int k
   double pa = 1.0 - val(gap) / val(S);
   D[0] = 1.0 / (h * (pa > P.dg ? pa : P.dg));
   // tangential velocity of the material points at the contact point at q+
-  v3<T> lev_a = cay(Ba.k, F.la) - F.n * r_prox;
+  v3<T> lev_a = cay(Ba.k, F.la) - dsup * r_prox;
   v3<T> pc = Ba.x + lev_a;
   v3<T> lev_b = has_b ? pc - Bb.x : zero;
   T vt[2];
@@ -321,6 +337,7 @@ OST_HD void eval_group(const Batch& B, const Params& P, const WorldRef& R, int k
 // rows): G_u = D dr/du (3 x 12) and G_lambda = D dr/d(lambda_n, lambda_t1,
 // lambda_t2) (3 x 3), in closed form.  J and D are the outputs of eval_group
 // at the same point.
+template <bool kRim = true>
 OST_HD void contact_G(const Params& P, const GroupIn<double>& in, int has_b, double r_prox, double mu, double sn,
                       double sf, int ckind, const double* J, const double* D, double* Gu, double* Gl) {
   const double h = P.h;
@@ -328,11 +345,17 @@ OST_HD void contact_G(const Params& P, const GroupIn<double>& in, int has_b, dou
   BodyIt<double> Ba = body_it(in.xa, in.ua, h);
   BodyIt<double> Bb = body_it(in.xb, in.ub ? in.ub : zu, h);
   const Frame<double>& F = in.fr;
+  double depth = r_prox;
+  v3<double> dsup = F.n, a1{0.0, 0.0, 0.0};
+  if (kRim && F.disc) {
+    a1 = cay(Ba.k, F.ax);
+    depth = rim_depth(F.n, a1, r_prox, &dsup);
+  }
   // normal row: r_n = gap + B - S, S = sqrt(gap^2 + B^2 + eps^2), B = sigma_n lambda_n
   double gap = dot(F.n, Ba.x + cay(Ba.k, F.la));
   if (ckind == 2) gap -= dot(F.n, Bb.x + cay(Bb.k, F.lb));
   else gap -= F.noff;
-  gap -= r_prox;
+  gap -= depth;  // r_prox but for a rim circle
   double Bq = sn * in.lg[0];
   double S = ::sqrt(gap * gap + Bq * Bq + P.eps * P.eps);
   double pa = 1.0 - gap / S, pb = 1.0 - Bq / S;
@@ -342,7 +365,7 @@ OST_HD void contact_G(const Params& P, const GroupIn<double>& in, int has_b, dou
   Gl[1] = 0.0;
   Gl[2] = 0.0;
   // friction rows: r_f = v_t + W lambda_f
-  v3<double> lev_a = cay(Ba.k, F.la) - F.n * r_prox;
+  v3<double> lev_a = cay(Ba.k, F.la) - dsup * r_prox;
   v3<double> pc = Ba.x + lev_a;
   v3<double> lev_b = has_b ? pc - Bb.x : v3<double>{0, 0, 0};
   double vt[2], dv[2][12];
@@ -357,6 +380,15 @@ OST_HD void contact_G(const Params& P, const GroupIn<double>& in, int has_b, dou
     v3<double> twa = cross(t, Ba.w);
     v3<double> gwa = cay_grad(Ba.k, F.la, twa) * (0.5 * h);
     v3<double> dva = t, dwa = cross(lev_a, t) + gwa;
+    if (kRim && F.disc && depth > 0.0) {
+      // the rim's contact point turns with the axis a = Cay(k) ax: with
+      // d = t x w, al = n . a, be = d . a, si = sqrt(1 - al^2), the lever's
+      // part -r dsup gives -r grad_k (d . dsup), d . dsup = (d . n - al be) / si
+      const double al = dot(F.n, a1), be = dot(twa, a1), si = depth / r_prox;
+      const v3<double> ga = cay_grad(Ba.k, F.ax, F.n), gb = cay_grad(Ba.k, F.ax, twa);
+      const v3<double> gf = ga * ((al * dot(twa, F.n) - be) / (si * si * si)) - gb * (al / si);
+      dwa = dwa - gf * (r_prox * 0.5 * h);
+    }
     for (int q = 6; q < 12; ++q) dv[s][q] = 0.0;
     if (has_b) {
       v3<double> twb = cross(t, Bb.w);

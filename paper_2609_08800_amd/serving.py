@@ -220,7 +220,7 @@ _SEG = {  # batch array -> (offset array, entries per item): per-world ranges co
     "body_mass": ("body_off", 1), "body_inertia": ("body_off", 3), "joint_body": ("joint_off", 2),
     "joint_frame": ("joint_off", 18), "joint_act": ("joint_off", 1), "joint_kp": ("joint_off", 1),
     "joint_kd": ("joint_off", 1),
-    "slot_int": ("slot_off", 4), "slot_real": ("slot_off", 6), "obs_box": ("obs_off", 6),
+    "slot_int": ("slot_off", 4), "slot_real": ("slot_off", 9), "obs_box": ("obs_off", 6),
 }
 
 

@@ -41,7 +41,7 @@ ACT_SERVO_POS = 4       # position servo: the control is the target joint angle 
 
 JOINT_FRAME_LEN = 18   # anchor_a, anchor_b, axis_b, perp1_a, perp2_a, axis_a
 SLOT_INT_LEN = 4       # kind, body_a, body_b, feature index
-SLOT_REAL_LEN = 6      # local offset (3), radius, mu, face half-height
+SLOT_REAL_LEN = 9      # local offset (3), radius, mu, face half-height, rim-circle axis (3; zero: sphere)
 
 GRAVITY = (0.0, 0.0, -9.81)
 
@@ -98,9 +98,21 @@ class World:
         return len(self.joints) - 1
 
     def add_slot(self, kind, a, local=(0, 0, 0), radius=0.0, mu=0.5, b=-1,
-                 feature=-1, face_h=0.0) -> int:
+                 feature=-1, face_h=0.0, axis=(0.0, 0.0, 0.0)) -> int:
+        """A contact proxy of body a: a sphere of `radius` at `local` (a point
+        for radius 0), or, with a non-zero `axis` (body frame), the circle of
+        that radius about `local` in the plane normal to the axis (a rim of a
+        cylindrical wheel).  Rim circles touch static features only."""
+        ax = np.asarray(axis, dtype=np.float64)
+        na = float(np.linalg.norm(ax))
+        if na > 0.0:
+            if kind == SLOT_BODYFACE:
+                raise ValueError("a rim circle touches static features only")
+            if not radius > 0.0:
+                raise ValueError("a rim circle needs a positive radius")
+            ax = ax / na
         self.slots.append(dict(kind=kind, a=a, b=b, feature=feature, local=local,
-                               radius=radius, mu=mu, face_h=face_h))
+                               radius=radius, mu=mu, face_h=face_h, axis=tuple(float(v) for v in ax)))
         return len(self.slots) - 1
 
     def add_obstacle(self, center, half) -> int:
@@ -226,7 +238,7 @@ def pack(worlds: Sequence[World], heightmaps: Sequence[Heightmap] = ()) -> Batch
     for w in worlds:
         for s in w.slots:
             si.append((s["kind"], s["a"], s["b"], s["feature"]))
-            sr.append(tuple(s["local"]) + (s["radius"], s["mu"], s["face_h"]))
+            sr.append(tuple(s["local"]) + (s["radius"], s["mu"], s["face_h"]) + tuple(s.get("axis", (0.0, 0.0, 0.0))))
     obs = cat([o for w in worlds for o in w.obstacles], 6, np.float64)
     if heightmaps:
         n = heightmaps[0].n
@@ -316,41 +328,50 @@ AXLE_DAMPING = 0.05    # N m s / rad: gain of the axle's zero-speed servo row
 
 def robot_world(rng=None, *, yaw=0.0, obstacle_x=1.0, knots=None, mu=ROBOT_MU,
                 servo_kp=None, with_obstacle=True, contact_cap=16,
-                axle_damping=AXLE_DAMPING, obstacle_size=OBSTACLE_SIZE) -> World:
+                axle_damping=AXLE_DAMPING, obstacle_size=OBSTACLE_SIZE, wheels: str = "sphere") -> World:
     """Wheeled robot: 10 kg chassis box and four 0.5 kg wheels on revolute joints.
 
     The wheels are driven by torques (8 spline knots per wheel) with viscous
     axle damping expressed as the implicit servo row of the paper with a zero
     speed target (gain ``axle_damping``; 0 gives pure torque), or, with
     ``servo_kp``, by velocity servos.  Wheel contact uses a sphere proxy of the
-    wheel radius at the wheel centre (rotation invariant about the axle); the
-    chassis uses its 8 corners and 5 bottom-face points.  ``obstacle_x`` is the
-    x of the obstacle's near face; the obstacle (``obstacle_size``, 1.2 x 0.8 x
-    0.15 m by default) is centred at y = 0.
+    wheel radius at the wheel centre (rotation invariant about the axle), or
+    with ``wheels="cylinder"`` the wheel's two rim circles (radius WHEEL_R,
+    WHEEL_W apart, about the wheel's y axis); the chassis uses its 8 corners
+    and 5 bottom-face points.  ``obstacle_x`` is the x of the obstacle's near
+    face; the obstacle (``obstacle_size``, 1.2 x 0.8 x 0.15 m by default) is
+    centred at y = 0.
     """
+    if wheels not in ("cylinder", "sphere"):
+        raise ValueError("wheels: 'cylinder' or 'sphere'")
     cx, cy, cz = CHASSIS_SIZE
     wd = World(contact_cap=contact_cap)
     zc = WHEEL_R
     qc = (0.0, 0.0, zc) + yaw_quat(yaw)
     c = wd.add_body(CHASSIS_MASS, box_inertia(CHASSIS_MASS, cx, cy, cz), qc)
     cyaw, syaw = math.cos(yaw), math.sin(yaw)
-    wheels = []
+    wheel_bodies = []
     for (wx, wy) in WHEEL_POS:
         px, py = cyaw * wx - syaw * wy, syaw * wx + cyaw * wy
-        wheels.append(wd.add_body(WHEEL_MASS, cylinder_inertia_y(WHEEL_MASS, WHEEL_R, WHEEL_W),
-                                  (px, py, zc) + yaw_quat(yaw)))
+        wheel_bodies.append(wd.add_body(WHEEL_MASS, cylinder_inertia_y(WHEEL_MASS, WHEEL_R, WHEEL_W),
+                                        (px, py, zc) + yaw_quat(yaw)))
     if servo_kp is not None:
         act, kp = ACT_SERVO_VEL, float(servo_kp)
     elif axle_damping:
         act, kp = ACT_TORQUE_DAMPED, float(axle_damping)
     else:
         act, kp = ACT_TORQUE, 0.0
-    for b, (wx, wy) in zip(wheels, WHEEL_POS):
+    for b, (wx, wy) in zip(wheel_bodies, WHEEL_POS):
         wd.add_revolute(c, b, anchor_a=(wx, wy, 0.0), anchor_b=(0.0, 0.0, 0.0), act=act, kp=kp)
     kinds = [SLOT_PLANE] + ([SLOT_BOX] if with_obstacle else [])
-    for b in wheels:
+    for b in wheel_bodies:
         for k in kinds:
-            wd.add_slot(k, b, radius=WHEEL_R, mu=mu, feature=0 if k == SLOT_BOX else -1)
+            if wheels == "cylinder":
+                for o in (-0.5 * WHEEL_W, 0.5 * WHEEL_W):
+                    wd.add_slot(k, b, local=(0.0, o, 0.0), radius=WHEEL_R, mu=mu,
+                                feature=0 if k == SLOT_BOX else -1, axis=(0.0, 1.0, 0.0))
+            else:
+                wd.add_slot(k, b, radius=WHEEL_R, mu=mu, feature=0 if k == SLOT_BOX else -1)
     pts = [(sx * 0.5 * cx, sy * 0.5 * cy, sz * 0.5 * cz)
            for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)]
     pts += [(0.0, 0.0, -0.5 * cz), (0.5 * cx, 0.0, -0.5 * cz), (-0.5 * cx, 0.0, -0.5 * cz),
@@ -460,18 +481,24 @@ def terrain_height(hm: Heightmap, x: float, y: float) -> float:
 
 def robot_terrain_world(rng=None, hm: Heightmap = None, hmap_index: int = 0, *, yaw=0.0, knots=None,
                         mu=ROBOT_MU, n_feat: int = TERRAIN_FEATURES, contact_cap=24,
-                        axle_damping=AXLE_DAMPING, start=(0.0, 0.0)) -> World:
-    """The wheeled robot on heightmap terrain: each wheel sphere has n_feat
-    terrain slots (its nearest candidate mesh features), each chassis point
-    one; placed at `start` with its wheels just above the surface."""
+                        axle_damping=AXLE_DAMPING, start=(0.0, 0.0), wheels: str = "cylinder") -> World:
+    """The wheeled robot on heightmap terrain, placed at `start` with its
+    wheels just above the surface.  Cylindrical wheels (the default; radius
+    WHEEL_R, width WHEEL_W, axis the wheel body's y axis) touch the mesh with
+    their two rim circles, each with n_feat terrain slots (its nearest
+    candidate mesh features); with wheels="sphere" each wheel is one sphere of
+    the wheel radius with n_feat slots.  Each chassis point has one slot."""
+    if wheels not in ("cylinder", "sphere"):
+        raise ValueError("wheels: 'cylinder' or 'sphere'")
     cx, cy, cz = CHASSIS_SIZE
     wd = World(contact_cap=contact_cap)
     cyaw, syaw = math.cos(yaw), math.sin(yaw)
     wxy = [(start[0] + cyaw * wx - syaw * wy, start[1] + syaw * wx + cyaw * wy) for (wx, wy) in WHEEL_POS]
-    # clear the surface under the wheels and under the chassis bottom (sampled every 5 cm)
+    rims = (-0.5 * WHEEL_W, 0.5 * WHEEL_W) if wheels == "cylinder" else (0.0,)
+    # clear the surface under the wheels' rims and under the chassis bottom (sampled every 5 cm)
     zc = 0.0
     if hm is not None:
-        zc = max(terrain_height(hm, x, y) + WHEEL_R for (x, y) in wxy)
+        zc = max(terrain_height(hm, x - syaw * o, y + cyaw * o) + WHEEL_R for (x, y) in wxy for o in rims)
         for sx in np.linspace(-0.5 * cx, 0.5 * cx, 13):
             for sy in np.linspace(-0.5 * cy, 0.5 * cy, 9):
                 x = start[0] + cyaw * sx - syaw * sy
@@ -479,14 +506,19 @@ def robot_terrain_world(rng=None, hm: Heightmap = None, hmap_index: int = 0, *, 
                 zc = max(zc, terrain_height(hm, x, y) + 0.5 * cz)
     zc += 1e-3
     c = wd.add_body(CHASSIS_MASS, box_inertia(CHASSIS_MASS, cx, cy, cz), (start[0], start[1], zc) + yaw_quat(yaw))
-    wheels = [wd.add_body(WHEEL_MASS, cylinder_inertia_y(WHEEL_MASS, WHEEL_R, WHEEL_W), (px, py, zc) + yaw_quat(yaw))
-              for (px, py) in wxy]
+    wheel_bodies = [wd.add_body(WHEEL_MASS, cylinder_inertia_y(WHEEL_MASS, WHEEL_R, WHEEL_W),
+                                (px, py, zc) + yaw_quat(yaw)) for (px, py) in wxy]
     act, kp = (ACT_TORQUE_DAMPED, float(axle_damping)) if axle_damping else (ACT_TORQUE, 0.0)
-    for b, (wx, wy) in zip(wheels, WHEEL_POS):
+    for b, (wx, wy) in zip(wheel_bodies, WHEEL_POS):
         wd.add_revolute(c, b, anchor_a=(wx, wy, 0.0), anchor_b=(0.0, 0.0, 0.0), act=act, kp=kp)
-    for b in wheels:
-        for k in range(n_feat):
-            wd.add_slot(SLOT_HEIGHTMAP, b, radius=WHEEL_R, mu=mu, feature=k)
+    for b in wheel_bodies:
+        for o in rims:
+            for k in range(n_feat):
+                if wheels == "cylinder":
+                    wd.add_slot(SLOT_HEIGHTMAP, b, local=(0.0, o, 0.0), radius=WHEEL_R, mu=mu, feature=k,
+                                axis=(0.0, 1.0, 0.0))
+                else:
+                    wd.add_slot(SLOT_HEIGHTMAP, b, radius=WHEEL_R, mu=mu, feature=k)
     pts = [(sx * 0.5 * cx, sy * 0.5 * cy, sz * 0.5 * cz)
            for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)]
     pts += [(0.0, 0.0, -0.5 * cz), (0.5 * cx, 0.0, -0.5 * cz), (-0.5 * cx, 0.0, -0.5 * cz),
@@ -503,21 +535,22 @@ def robot_terrain_world(rng=None, hm: Heightmap = None, hmap_index: int = 0, *, 
     return wd
 
 
-def terrain_batch(n_worlds: int, seed: int = 0, n_maps: int = 1, n: int = TERRAIN_N) -> Batch:
+def terrain_batch(n_worlds: int, seed: int = 0, n_maps: int = 1, n: int = TERRAIN_N,
+                  wheels: str = "cylinder") -> Batch:
     """Robots on n_maps value-noise terrains (world w on map w % n_maps)."""
     maps = [value_noise_heightmap(seed * 1000 + k, n=n) for k in range(n_maps)]
     worlds = []
     for w, r in enumerate(world_rngs(seed, n_worlds)):
         k = w % n_maps
-        worlds.append(robot_terrain_world(r, maps[k], k, yaw=float(r.uniform(-0.3, 0.3))))
+        worlds.append(robot_terrain_world(r, maps[k], k, yaw=float(r.uniform(-0.3, 0.3)), wheels=wheels))
     return pack(worlds, maps)
 
 
-def terrain_request_batch(seed: int, n_worlds: int) -> Batch:
+def terrain_request_batch(seed: int, n_worlds: int, wheels: str = "cylinder") -> Batch:
     """One trajectory-optimisation request: n_worlds robots (seeded yaw and
     knots) on the request's own value-noise terrain (heightmap index 0)."""
     hm = value_noise_heightmap(10_000 + seed)
-    worlds = [robot_terrain_world(r, hm, 0, yaw=float(r.uniform(-0.3, 0.3)))
+    worlds = [robot_terrain_world(r, hm, 0, yaw=float(r.uniform(-0.3, 0.3)), wheels=wheels)
               for r in world_rngs(seed, n_worlds)]
     return pack(worlds, [hm])
 

@@ -29,6 +29,7 @@ static Sched* gS = nullptr;
 
 struct FiberTeam {
   static constexpr bool kGlobal = false;
+  static constexpr bool kRim = true;   // rim-circle contacts compiled in
   Sched* S;
   int r;
   int rank() const { return r; }

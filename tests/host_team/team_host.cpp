@@ -11,6 +11,7 @@ using namespace ost;
 
 struct SerialTeam {
   static constexpr bool kGlobal = false;
+  static constexpr bool kRim = true;   // rim-circle contacts compiled in
   int rank() const { return 0; }
   int size() const { return 1; }
   void sync() const {}

@@ -577,7 +577,7 @@ def test_flat_terrain_reproduces_the_plane():
     hm = _flat_map()
     rng = np.random.default_rng(0)
     knots = rng.uniform(-2, 2, size=(4, scenes.ROBOT_KNOTS))
-    tw = scenes.robot_terrain_world(None, hm, 0, yaw=0.2, knots=knots, start=(0.1, 0.05))
+    tw = scenes.robot_terrain_world(None, hm, 0, yaw=0.2, knots=knots, start=(0.1, 0.05), wheels="sphere")
     pw = scenes.robot_world(None, yaw=0.2, knots=knots, with_obstacle=False)
     pw.q0 = [list(q) for q in tw.q0]
     bt, bp = scenes.pack([tw], [hm]), scenes.pack([pw])

@@ -153,7 +153,11 @@ def test_served_knots_match_oracle_alone_and_in_a_terrain_mix(torch):
     oracle's rollouts and the Adam formula: a plane request served alone, and a
     terrain request served in a mix with three other terrain requests (their
     worlds in the same launches), world by world where the oracle converged at
-    every step (tolerance 1e-12)."""
+    every step (tolerance 1e-12).  The terrain robots here have sphere wheels:
+    with cylinder wheels (both rims, four mesh candidates each) most worlds
+    have a landing step that exhausts 200 Newton iterations at tolerance
+    1e-12, which leaves too few worlds to compare; the cylinder wheels' steps
+    and adjoints are compared with the oracle in the terrain tests."""
     from paper_2609_08800_amd.serving import GpuBackend, Request, ServingEngine
     T, iters, lr = 8, 2, 0.1
     P = scenes.solver_params(k_max=64, tol=1e-12)
@@ -164,9 +168,10 @@ def test_served_knots_match_oracle_alone_and_in_a_terrain_mix(torch):
     n_plane = check_served_against_oracle(r, mine, P, T, iters, lr)
     Pt = scenes.solver_params(k_max=200, tol=1e-12)
     base = scenes.value_noise_heightmap(10_000)
-    tmpl = scenes.robot_terrain_world(None, base, 0)
+    tmpl = scenes.robot_terrain_world(None, base, 0, wheels="sphere")
     be2 = GpuBackend(tmpl, 24, Pt, K, heightmaps=[base], heightmap_slots=4)
-    reqs = [Request(rid, scenes.terrain_request_batch(700 + rid, n), T=t, iters=iters, lr=lr, arrival=a)
+    reqs = [Request(rid, scenes.terrain_request_batch(700 + rid, n, wheels="sphere"), T=t, iters=iters, lr=lr,
+                    arrival=a)
             for rid, (n, t, a) in enumerate(((3, 8, 0.02), (5, 6, 0.0), (2, 10, 0.01), (4, 7, 0.04)))]
     eng2 = ServingEngine(be2, 8e9)
     out = eng2.run(reqs)

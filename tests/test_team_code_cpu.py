@@ -139,7 +139,7 @@ def _scene(name):
         b = _position_servo_robots(2, seed=1)
         return b, scenes.solver_params(k_max=64), lambda k: np.full(b.n_ctrl, 0.3 * (k + 1))
     if name == "terrain":
-        b = scenes.terrain_batch(2, seed=5, n_maps=2)
+        b = scenes.terrain_batch(2, seed=5, n_maps=2, wheels="sphere")
         return b, scenes.solver_params(k_max=200, truncate=1), _robots_ctrl(b)
     b = scenes.pack([_hinge_z_world(0.4, 1.5, 3.0, 0.05), _hinge_z_world(-0.2, -0.7, 1.0, 0.0)])
     return b, scenes.solver_params(k_max=64, gravity=(0, 0, 0)), lambda k: np.array([-0.3, 0.5])
@@ -180,6 +180,64 @@ def test_team_code_matches_oracle(lib, name):
                 assert np.linalg.norm(got - ref) <= bar, (k, w, key)
         q, u, lam = r["q"], r["u"], r["lam"]
     assert checked >= 2 * b.n_worlds
+
+
+def _root_residual(b, P, w, q, u, c, o):
+    """|F| of the oracle's residual of world w at the team code's (u, lambda)."""
+    s0 = b.slot_off[w]
+    act = o["act_slot"][s0:s0 + o["n_act"][w]]
+    lw = o["lam"][b.lam_off[w]:b.lam_off[w + 1]]
+    base = b.lam_off[w + 1] - b.lam_off[w] - 3 * (b.slot_off[w + 1] - b.slot_off[w])
+    rows = np.array(list(lw[:base]) + [lw[base + 3 * s + k] for s in act for k in range(3)])
+    k = int(b.world_hmap[w])
+    hm = scenes.Heightmap(n=int(b.hmap_n), spacing=float(b.hmap_spacing), origin=tuple(b.hmap_origin[k]),
+                          heights=b.hmap_heights[k])
+    one = scenes.pack([b.worlds[w]], [hm])
+    one.world_hmap[:] = 0
+    bs, cs = slice(b.body_off[w], b.body_off[w + 1]), slice(b.ctrl_off[w], b.ctrl_off[w + 1])
+    r = oracle.inspect(one, P, 0, q[bs], u[bs], c[cs], o["u"][bs].reshape(-1), rows)
+    return float(np.linalg.norm(r["F"]))
+
+
+def test_team_code_on_cylinder_wheel_terrain(lib):
+    """Cylinder wheels (two rim circles each, Sec. IV-D) on terrain: contact sets
+    bit for bit; where both sides converge to the same state, that state to
+    STATE_TOL and every gradient block as in the test above; on a landing step
+    whose residual has several roots, or where only one side converges within
+    its budget, the team code's converged state is a root of the oracle's
+    residual (within ten times the tolerance)."""
+    b = scenes.terrain_batch(3, seed=5, n_maps=2)
+    P = scenes.solver_params(k_max=200, truncate=1)
+    ctrl_at = _robots_ctrl(b)
+    T = Team(lib, b, P)
+    q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    rng = np.random.default_rng(5)
+    same = 0
+    for k in range(4):
+        c = ctrl_at(k)
+        o = T.forward(q, u, lam, c)
+        r = oracle.step_forward(b, P, q, u, lam, c)
+        assert np.array_equal(o["act_slot"], r["act_slot"]), k
+        gqn, gun = rng.normal(size=q.shape), rng.normal(size=u.shape)
+        g = T.adjoint(q, u, c, o, gqn, gun)
+        R = oracle.step_adjoint_params(b, P, q, u, c, o["u"], o["lam"], gqn, gun, mode=0)
+        for w in range(b.n_worlds):
+            bs, js = slice(b.body_off[w], b.body_off[w + 1]), slice(b.joint_off[w], b.joint_off[w + 1])
+            ss, cs = slice(b.slot_off[w], b.slot_off[w + 1]), slice(b.ctrl_off[w], b.ctrl_off[w + 1])
+            close = (np.max(np.abs(o["u"][bs] - r["u"][bs]) / np.maximum(1.0, np.abs(r["u"][bs]))) <= STATE_TOL and
+                     np.max(np.abs(o["q"][bs] - r["q"][bs]) / np.maximum(1.0, np.abs(r["q"][bs]))) <= STATE_TOL)
+            if o["status"][w] & 1 and r["status"][w] & 1 and close:
+                same += 1
+                blocks = (("gq", bs), ("gu", bs), ("g_mass", bs), ("g_kp", js), ("g_mu", ss), ("gc", cs))
+                whole = np.linalg.norm(np.concatenate([R[key][sl].ravel() for key, sl in blocks]))
+                for key, sl in blocks:
+                    got, ref = g[key][sl].ravel(), R[key][sl].ravel()
+                    bar = GRAD_TOL * max(np.linalg.norm(ref), 1e-6 * whole, 1e-12)
+                    assert np.linalg.norm(got - ref) <= bar, (k, w, key)
+            elif o["status"][w] & 1:
+                assert _root_residual(b, P, w, q, u, c, o) <= 10 * P["tol"], (k, w)
+        q, u, lam = r["q"], r["u"], r["lam"]
+    assert same >= 2 * b.n_worlds
 
 
 def test_fixed_point_refinement_would_miss_the_tripod_adjoint(lib):
