@@ -406,6 +406,22 @@ int ostrich_knot_grad_accumulate(const double* basis, const double* g_ctrl, int3
 int ostrich_adam(double* x, const double* g, double* m, double* v, int64_t n, double lr, double beta1, double beta2,
                  double eps, int32_t t, void* stream);
 
+/* A contiguous copy of n doubles between device buffers. */
+typedef struct {
+  const double* src;
+  double* dst;
+  int64_t n;
+} ostrich_copy_seg;
+
+/* Moves of the serving loop (states, multipliers, tapes, controls and
+ * cotangents between a request's arena and the pool's working arrays): copies
+ * every segment segs[i] (n >= 0 doubles, device pointers; segments must not
+ * overlap one another) asynchronously on `stream`, 32 segments per launch.
+ * segs itself is host memory, read before the call returns.  Fails with
+ * OSTRICH_E_ARG on n_segs < 0, a NULL segs with n_segs > 0, n < 0, or a NULL
+ * pointer in a segment with n > 0 (then nothing is launched). */
+int ostrich_copy_segments(const ostrich_copy_seg* segs, int32_t n_segs, void* stream);
+
 /* Natural cubic spline basis on the host: B [T*K] (host), knots at
  * t_j = j T h / (K - 1), step k samples t = k h. */
 int ostrich_spline_basis(int32_t T, int32_t K, double h, double* B);

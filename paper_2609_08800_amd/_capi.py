@@ -52,6 +52,10 @@ BATCH_ARRAYS = ("body_off", "body_mass", "body_inertia", "joint_off", "joint_bod
 _lib = None
 
 
+class OstrichCopySeg(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
 class OstrichError(RuntimeError):
     pass
 
@@ -115,6 +119,8 @@ def load() -> ctypes.CDLL:
     L.ostrich_knot_grad_accumulate.restype = c_int
     L.ostrich_adam.argtypes = [c_vp, c_vp, c_vp, c_vp, ctypes.c_int64, c_dbl, c_dbl, c_dbl, c_dbl, c_int, c_vp]
     L.ostrich_adam.restype = c_int
+    L.ostrich_copy_segments.argtypes = [c_vp, c_int, c_vp]
+    L.ostrich_copy_segments.restype = c_int
     L.ostrich_spline_basis.argtypes = [c_int, c_int, c_dbl, c_vp]
     L.ostrich_spline_basis.restype = c_int
     _lib = L

@@ -1807,6 +1807,50 @@ extern "C" int ostrich_knot_grad_accumulate(const double* basis, const double* g
   return 0;
 }
 
+namespace {
+// Segment copies: the segments of one launch are its grid's y index, each
+// copied by a grid-stride loop over its doubles (coalesced 8-byte accesses).
+constexpr int kSegsPerLaunch = 32;
+struct SegPack {
+  const double* src[kSegsPerLaunch];
+  double* dst[kSegsPerLaunch];
+  int64_t n[kSegsPerLaunch];
+};
+__global__ void __launch_bounds__(256) k_copy_segments(SegPack p) {
+  const int s = blockIdx.y;
+  const double* src = p.src[s];
+  double* dst = p.dst[s];
+  const int64_t n = p.n[s];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+}  // namespace
+
+extern "C" int ostrich_copy_segments(const ostrich_copy_seg* segs, int32_t n_segs, void* stream) {
+  if (n_segs < 0 || (n_segs > 0 && !segs)) return fail(OSTRICH_E_ARG, "copy segments: count or list");
+  for (int32_t i = 0; i < n_segs; ++i)
+    if (segs[i].n < 0 || (segs[i].n > 0 && (!segs[i].src || !segs[i].dst)))
+      return fail(OSTRICH_E_ARG, "copy segment " + std::to_string(i) + ": length or pointer");
+  bool launched = false;
+  for (int32_t i0 = 0; i0 < n_segs; i0 += kSegsPerLaunch) {
+    SegPack p{};
+    const int cnt = std::min<int>(kSegsPerLaunch, n_segs - i0);
+    int64_t nmax = 0;
+    for (int j = 0; j < cnt; ++j) {
+      p.src[j] = segs[i0 + j].src;
+      p.dst[j] = segs[i0 + j].dst;
+      p.n[j] = segs[i0 + j].n;
+      nmax = std::max(nmax, segs[i0 + j].n);
+    }
+    if (nmax == 0) continue;
+    const int bx = (int)std::min<int64_t>((nmax + 1023) / 1024, 64);
+    hipLaunchKernelGGL(k_copy_segments, dim3(bx, cnt), dim3(256), 0, (hipStream_t)stream, p);
+    launched = true;
+  }
+  if (launched) HIP_OK(hipGetLastError());
+  return 0;
+}
+
 extern "C" int ostrich_adam(double* x, const double* g, double* m, double* v, int64_t n, double lr, double beta1,
                             double beta2, double eps, int32_t t, void* stream) {
   if (!x || !g || !m || !v || n < 0 || t < 1) return fail(OSTRICH_E_ARG, "adam");

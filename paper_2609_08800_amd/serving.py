@@ -22,11 +22,18 @@ a request's results are the same alone and in the mix.
 
 The device work goes through ``GpuBackend`` (the HIP library); the engine
 talks to it through a small interface (admit, tick, end_forward,
-end_iteration, release and the clock), so the scheduler can also be driven by
-a host stand-in in tests.
+end_iteration, release, mark / wait / seconds_between, to_host and the
+clock), so the scheduler can also be driven by a host stand-in in tests.
+
+The host does not wait for every tick: after issuing tick t it waits only for
+the end of tick t - LOOKAHEAD, so its bookkeeping and the next launches
+overlap the device's work.  An iteration's latency is measured on the device
+stream, between a marker recorded when the iteration is issued and the marker
+of its last tick.  Losses stay on the device until the engine returns.
 """
 from __future__ import annotations
 
+import collections
 import dataclasses
 import math
 import time
@@ -59,6 +66,8 @@ class Request:
     phase: int = 0           # 0 forward, 1 backward
     k: int = 0
     iter_started: float = math.nan
+    iter_mark: object = None
+    iter_marks: list = dataclasses.field(default_factory=list)
 
     @property
     def n_worlds(self) -> int:
@@ -122,6 +131,8 @@ class SlotAllocator:
 class ServingEngine:
     """Admission, continuous batching and latency accounting over a backend."""
 
+    LOOKAHEAD = 2  # ticks the host may issue before the device has finished them
+
     def __init__(self, backend, hbm_budget: float, clock: Callable[[], float] = time.perf_counter,
                  max_ticks: int = 10 ** 9):
         self.be = backend
@@ -142,6 +153,7 @@ class ServingEngine:
         done: List[Request] = []
         t0 = self.clock()
         tick = 0
+        inflight = collections.deque()  # markers of the ticks issued but not yet waited for
         while (pending or active) and tick < self.max_ticks:
             now = self.clock() - t0
             if now > deadline:
@@ -167,12 +179,17 @@ class ServingEngine:
                 self.be.admit(r)
                 self.be.begin_iteration(r)
                 r.iter_started = now
+                r.iter_mark = self.be.mark()
                 active.append(r)
             if not active:
                 continue
             fw = [r for r in active if r.phase == 0]
             bw = [r for r in active if r.phase == 1]
             self.be.tick(fw, bw)
+            mark = self.be.mark()
+            inflight.append(mark)
+            if len(inflight) > self.LOOKAHEAD:
+                self.be.wait(inflight.popleft())
             self.world_steps += sum(r.n_worlds for r in fw)  # each forward step gets one adjoint step
             now = self.clock() - t0
             self.ticks.append((now, sum(r.n_worlds for r in fw), sum(r.n_worlds for r in bw),
@@ -188,7 +205,7 @@ class ServingEngine:
                     r.k -= 1
                     if r.k < 0:
                         self.be.end_iteration(r)
-                        r.iter_latency.append(now - r.iter_started)
+                        r.iter_marks.append((r.iter_mark, mark))
                         r.it += 1
                         if r.it == r.iters:
                             r.knots = self.be.release(r)
@@ -201,11 +218,17 @@ class ServingEngine:
                             self.be.begin_iteration(r)
                             r.phase, r.k = 0, 0
                             r.iter_started = now
+                            r.iter_mark = self.be.mark()
+        while inflight:
+            self.be.wait(inflight.popleft())
         wall = self.clock() - t0
         for r in active:
             self.be.release(r)
             self.used -= self.be.request_bytes(r)
             self.slots.release(r.slot0, r.n_worlds)
+        for r in done + active:  # device-side iteration latencies and losses, now that the device is done
+            r.iter_latency = [self.be.seconds_between(a, b) for a, b in r.iter_marks]
+            r.losses = [self.be.to_host(x) for x in r.losses]
         lat = [x for r in done + active for x in r.iter_latency]
         return {"requests": done, "unfinished": active + pending, "wall_s": wall, "ticks": len(self.ticks),
                 "iterations": len(lat),
@@ -273,6 +296,7 @@ class GpuBackend:
         self.gctrl = torch.zeros(NC, **f64)
         self.loss_buf = torch.zeros(W, **f64)
         self.state = {}
+        self._wl_cache = {}
         self.stream = torch.cuda.current_stream(self.dev).cuda_stream
 
     # -- sizes
@@ -285,6 +309,40 @@ class GpuBackend:
 
     def idle(self, seconds: float):
         time.sleep(max(0.0, min(seconds, 0.05)))
+
+    # -- device markers: events on the pool's stream
+    def mark(self):
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record(self.torch.cuda.current_stream(self.dev))
+        return ev
+
+    def wait(self, marker):
+        marker.synchronize()
+
+    def seconds_between(self, a, b) -> float:
+        return a.elapsed_time(b) * 1e-3
+
+    def to_host(self, x):
+        return x.cpu().numpy()
+
+    def _copy(self, pairs):
+        """One launch (per 32) for the listed (src, dst) tensor pairs: contiguous, float64, same size."""
+        if not pairs:
+            return
+        segs = (_capi.OstrichCopySeg * len(pairs))()
+        for i, (src, dst) in enumerate(pairs):
+            segs[i].src, segs[i].dst, segs[i].n = src.data_ptr(), dst.data_ptr(), src.numel()
+        _capi.check(self.L.ostrich_copy_segments(segs, len(pairs), self.stream), "ostrich_copy_segments")
+
+    def _wlist(self, reqs):
+        key = tuple(r.rid for r in reqs)
+        wl = self._wl_cache.get(key)
+        if wl is None:
+            if len(self._wl_cache) > 64:
+                self._wl_cache.clear()
+            wl = self.torch.cat([self.state[r.rid]["wl"] for r in reqs])
+            self._wl_cache[key] = wl
+        return wl
 
     def can_admit(self, r: Request) -> bool:
         b = r.batch
@@ -357,6 +415,7 @@ class GpuBackend:
 
     def release(self, r: Request) -> np.ndarray:
         s = self.state.pop(r.rid)
+        self._wl_cache.clear()
         if getattr(r, "_hmap", None) is not None:
             self.hmap_free.append(r._hmap)
             self.hmap_free.sort()
@@ -387,7 +446,7 @@ class GpuBackend:
                                               self.stream), "ostrich_final_loss")
         s["gq"].copy_(self.gqn[self._b(r)])
         s["gu"].zero_()
-        return self.loss_buf[self._w(r)].cpu().numpy()
+        return self.loss_buf[self._w(r)].clone()
 
     def end_iteration(self, r: Request):
         s = self.state[r.rid]
@@ -398,59 +457,63 @@ class GpuBackend:
 
     # -- one tick: forward step of `fw` requests and adjoint step of `bw` requests
     def tick(self, fw: List[Request], bw: List[Request]):
-        torch = self.torch
+        """Issue one tick on the pool's stream without waiting for it.  The
+        moves between request arenas and the working arrays are batched into
+        segment-copy launches; the forward's current and next state arrays
+        swap roles after the step instead of being copied (every world that
+        reads the current state in a tick is one that the last forward step
+        wrote, or one that begin_iteration has just set)."""
         if fw:
-            for r in fw:
-                s = self.state[r.rid]
-                if self.nc_w:
-                    self.ctrl_f[self._c(r)].copy_(s["ctrl"][r.k])
-            wl = torch.cat([self.state[r.rid]["wl"] for r in fw])
+            if self.nc_w:
+                self._copy([(self.state[r.rid]["ctrl"][r.k], self.ctrl_f[self._c(r)]) for r in fw])
+            wl = self._wlist(fw)
             _capi.check(self.L.ostrich_step_forward_list(
                 self.sim.ctx, wl.data_ptr(), wl.numel(), self.q_cur.data_ptr(), self.u_cur.data_ptr(),
                 self.l_cur.data_ptr(), self.ctrl_f.data_ptr(), self.q_nxt.data_ptr(), self.u_nxt.data_ptr(),
                 self.l_nxt.data_ptr(), self.act.data_ptr(), self.nact.data_ptr(), self.st.data_ptr(),
                 self.its.data_ptr(), self.res.data_ptr(), self.tape_f.data_ptr(), self.stream),
                 "ostrich_step_forward_list")
+            pairs = []
             for r in fw:
                 s = self.state[r.rid]
                 b_, l_ = self._b(r), self._l(r)
-                s["hq"][r.k + 1].copy_(self.q_nxt[b_])
-                s["hu"][r.k + 1].copy_(self.u_nxt[b_])
-                s["hl"][r.k + 1][:l_.stop - l_.start].copy_(self.l_nxt[l_])
-                s["tapes"][r.k].copy_(self.tape_f[self._t(r)])
-                self.q_cur[b_].copy_(self.q_nxt[b_])
-                self.u_cur[b_].copy_(self.u_nxt[b_])
-                self.l_cur[l_].copy_(self.l_nxt[l_])
+                pairs += [(self.q_nxt[b_], s["hq"][r.k + 1]), (self.u_nxt[b_], s["hu"][r.k + 1]),
+                          (self.l_nxt[l_], s["hl"][r.k + 1][:l_.stop - l_.start]),
+                          (self.tape_f[self._t(r)], s["tapes"][r.k])]
+            self._copy(pairs)
+            self.q_cur, self.q_nxt = self.q_nxt, self.q_cur
+            self.u_cur, self.u_nxt = self.u_nxt, self.u_cur
+            self.l_cur, self.l_nxt = self.l_nxt, self.l_cur
         if bw:
+            pairs = []
             for r in bw:
                 s = self.state[r.rid]
                 b_, l_, k = self._b(r), self._l(r), r.k
-                self.qp_b[b_].copy_(s["hq"][k])
-                self.up_b[b_].copy_(s["hu"][k])
-                self.un_b[b_].copy_(s["hu"][k + 1])
-                self.ln_b[l_].copy_(s["hl"][k + 1][:l_.stop - l_.start])
-                self.tape_b[self._t(r)].copy_(s["tapes"][k])
+                pairs += [(s["hq"][k], self.qp_b[b_]), (s["hu"][k], self.up_b[b_]), (s["hu"][k + 1], self.un_b[b_]),
+                          (s["hl"][k + 1][:l_.stop - l_.start], self.ln_b[l_]),
+                          (s["tapes"][k], self.tape_b[self._t(r)]), (s["gq"], self.gqn[b_]), (s["gu"], self.gun[b_])]
                 if self.nc_w:
-                    self.ctrl_b[self._c(r)].copy_(s["ctrl"][k])
-                self.gqn[b_].copy_(s["gq"])
-                self.gun[b_].copy_(s["gu"])
-            wl = torch.cat([self.state[r.rid]["wl"] for r in bw])
+                    pairs.append((s["ctrl"][k], self.ctrl_b[self._c(r)]))
+            self._copy(pairs)
+            wl = self._wlist(bw)
             _capi.check(self.L.ostrich_step_adjoint_list(
                 self.sim.ctx, wl.data_ptr(), wl.numel(), self.qp_b.data_ptr(), self.up_b.data_ptr(),
                 self.ctrl_b.data_ptr(), self.un_b.data_ptr(), self.ln_b.data_ptr(), self.tape_b.data_ptr(),
                 self.gqn.data_ptr(), self.gun.data_ptr(), self.gqp.data_ptr(), self.gup.data_ptr(),
                 self.gctrl.data_ptr(), -1, None, self.stream), "ostrich_step_adjoint_list")
+            pairs = []
             for r in bw:
                 s = self.state[r.rid]
                 b_ = self._b(r)
-                s["gq"].copy_(self.gqp[b_])
-                s["gu"].copy_(self.gup[b_])
-                if self.nc_w:
+                pairs += [(self.gqp[b_], s["gq"]), (self.gup[b_], s["gu"])]
+            self._copy(pairs)
+            if self.nc_w:
+                for r in bw:
+                    s = self.state[r.rid]
                     gc = self.gctrl[self._c(r)]
                     _capi.check(self.L.ostrich_knot_grad_accumulate(s["basis"].data_ptr(), gc.data_ptr(), r.k,
                                                                     self.K, gc.numel(), s["gk"].data_ptr(),
                                                                     self.stream), "ostrich_knot_grad_accumulate")
-        torch.cuda.synchronize(self.dev)
 
 
 def _knots_of(b, K):

@@ -28,6 +28,19 @@ class FakeBackend:
     def idle(self, seconds):
         self.vtime += max(seconds, 0.0)
 
+    # markers on the virtual clock (the device backend records events on its stream)
+    def mark(self):
+        return self.vtime
+
+    def wait(self, marker):
+        pass
+
+    def seconds_between(self, a, b):
+        return b - a
+
+    def to_host(self, x):
+        return x
+
     def admit(self, r):
         self.state[r.rid] = {"knots": np.full(r.n_worlds, 1.0), "x": np.zeros(r.n_worlds), "g": np.zeros(r.n_worlds)}
 

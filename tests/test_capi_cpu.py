@@ -88,3 +88,21 @@ def test_binding_checks_arguments_before_any_call():
         sim._lam(np.zeros(3))
     sim.NL = 0
     assert sim._lam(np.zeros(0)).shape == (1,)
+
+
+def test_segment_copy_rejects_bad_arguments_before_any_launch():
+    """ostrich_copy_segments validates the whole list on the host first: a
+    negative count, a missing list, a negative length or a NULL pointer with a
+    positive length fail with OSTRICH_E_ARG and launch nothing (so these run
+    without a GPU)."""
+    from paper_2609_08800_amd import _capi
+    lib = _capi.load()
+    assert lib.ostrich_copy_segments(None, -1, None) != 0
+    assert lib.ostrich_copy_segments(None, 2, None) != 0
+    segs = (_capi.OstrichCopySeg * 2)()
+    segs[0].src, segs[0].dst, segs[0].n = 8, 16, 0      # empty: allowed
+    segs[1].src, segs[1].dst, segs[1].n = None, 16, 5   # NULL source with a positive length
+    assert lib.ostrich_copy_segments(segs, 2, None) != 0
+    segs[1].src, segs[1].n = 8, -1
+    assert lib.ostrich_copy_segments(segs, 2, None) != 0
+    assert lib.ostrich_copy_segments(segs, 0, None) == 0  # nothing to do

@@ -179,3 +179,31 @@ def test_served_knots_match_oracle_alone_and_in_a_terrain_mix(torch):
     assert any(len(rids) >= 3 for _, _, _, rids in eng2.ticks), "requests never shared a launch"
     n_terrain = sum(check_served_against_oracle(q, q.batch, Pt, q.T, iters, lr) for q in reqs)
     print("worlds compared: plane %d, terrain %d" % (n_plane, n_terrain))
+
+
+def test_segment_copies_match_per_tensor_copies(torch):
+    """The serving loop's batched copies: 70 segments of mixed lengths (empty
+    ones among them, more than one launch's 32) land exactly where a copy per
+    segment puts them, and nothing else in the destination changes."""
+    from paper_2609_08800_amd import _capi
+    L = _capi.load()
+    rng = np.random.default_rng(0)
+    src = torch.as_tensor(rng.normal(size=200_000), device="cuda:0")
+    dst = torch.full((200_000,), -7.0, dtype=torch.float64, device="cuda:0")
+    ref = dst.clone()
+    lens = rng.integers(0, 3000, size=70)
+    lens[[3, 40]] = 0
+    segs = (_capi.OstrichCopySeg * len(lens))()
+    o_src, o_dst = 0, 0
+    for i, n in enumerate(lens):
+        n = int(n)
+        segs[i].src = src.data_ptr() + 8 * o_src
+        segs[i].dst = dst.data_ptr() + 8 * o_dst
+        segs[i].n = n
+        ref[o_dst:o_dst + n] = src[o_src:o_src + n]
+        o_src += n + 17
+        o_dst += n + 5
+    stream = torch.cuda.current_stream().cuda_stream
+    assert L.ostrich_copy_segments(segs, len(lens), stream) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(dst, ref)
