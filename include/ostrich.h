@@ -113,7 +113,8 @@ typedef struct {
   double delta0;       /* contact activation margin (m) */
   int32_t ls_max;      /* step-length halvings of the residual-decrease test */
   int32_t refine;      /* most Krylov operator applications of the adjoint (0: factor only) */
-  int32_t team;        /* threads per world (64, 128 or 256; 0 = 128) before autotuning */
+  int32_t team;        /* threads per world (64, 128 or 256) before autotuning; 0: 128, or 256 for a
+                          bucket whose on-chip workspace fits only one 128-thread workgroup per CU */
   int32_t schedule;    /* OSTRICH_SCHED_FIXED or OSTRICH_SCHED_BUCKETED */
   int32_t truncate;    /* 1: the adjoint treats the contact geometry as a constant of the step, so no
                           derivative with respect to q- passes through a contact row or its force

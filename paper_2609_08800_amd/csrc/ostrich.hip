@@ -292,10 +292,21 @@ __global__ void __launch_bounds__(1024) k_plan(ost::Batch B, const int32_t* worl
 // test; terrain slots counted active), capped at the world's contact cap:
 // out[i] for worlds[i].  One 64-thread workgroup per world.
 __global__ void __launch_bounds__(64) k_count_active(ost::Batch B, ost::Params P, const int32_t* worlds,
-                                                     const double* q_prev, const double* u_prev, int32_t* out) {
-  const ost::WorldRef R = ost::world_ref(B, worlds[blockIdx.x]);
-  int c = ost::count_active(B, P, R, q_prev, u_prev, threadIdx.x, 64);
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+                                                     const double* q_prev, const double* u_prev,
+                                                     const int32_t* hist, int32_t* out) {
+  const int w = worlds[blockIdx.x];
+  const ost::WorldRef R = ost::world_ref(B, w);
+  int nt = 0;
+  int c = ost::count_active(B, P, R, q_prev, u_prev, threadIdx.x, 64, &nt);
+  for (int off = 32; off > 0; off >>= 1) {
+    c += __shfl_xor(c, off, 64);
+    nt += __shfl_xor(nt, off, 64);
+  }
+  // terrain slots: their contacts are only known after the step's mesh search,
+  // so the world's contact count of its previous step stands in for them (at
+  // most one per terrain slot); a world that then has more than the first
+  // carve holds is deferred to the full carve by the step itself
+  if (nt > 0) c += hist ? (hist[2 * w] < nt ? hist[2 * w] : nt) : nt;
   if (threadIdx.x == 0) out[blockIdx.x] = c < R.cap ? c : R.cap;
 }
 
@@ -754,9 +765,20 @@ static int configure_bucket(ostrich_ctx* ctx, Bucket& bk, int team, int split, b
   return 0;
 }
 
-// Default launch choice: the requested team (or 128), on chip when it fits.
+// Default launch choice: the requested team, on chip when it fits.  Without a
+// request: 128 threads (two wavefronts), or 256 when a world's on-chip
+// workspace leaves room for only one workgroup per CU, so that the one
+// workgroup's wavefronts still cover the CU's four SIMDs (terrain robots with
+// cylinder wheels: 1.7 x the served world-steps of 128 threads, same bits).
 static int default_config(ostrich_ctx* ctx, Bucket& bk) {
   int team = ctx->team;
+  if (team == 0) {
+    team = 128;
+    const size_t l128 = ost::world_lds_bytes(bk.caps, 128, ost::SPLIT_LDS, true);
+    if (l128 <= ctx->lds_limit && 2 * l128 > ctx->lds_limit &&
+        ost::world_lds_bytes(bk.caps, 256, ost::SPLIT_LDS, true) <= ctx->lds_limit)
+      team = 256;
+  }
   if (ost::world_lds_bytes(bk.caps, team, ost::SPLIT_LDS, true) <= ctx->lds_limit)
     return configure_bucket(ctx, bk, team, ost::SPLIT_LDS);
   return configure_bucket(ctx, bk, team, ost::SPLIT_GLOBAL);
@@ -829,8 +851,8 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
                         b->obs_off, b->lam_off, b->contact_cap};
   for (const void* q : need)
     if (!is_ptr_ok(q)) return fail(OSTRICH_E_ARG, "null array in batch");
-  int team = p->team > 0 ? p->team : 128;
-  if (!team_ok(team)) return fail(OSTRICH_E_ARG, "team must be 64, 128 or 256");
+  int team = p->team > 0 ? p->team : 0;  // 0: chosen per bucket (default_config)
+  if (team != 0 && !team_ok(team)) return fail(OSTRICH_E_ARG, "team must be 64, 128 or 256");
   const int W = b->n_worlds;
   std::vector<int32_t> bo(W + 1), jo(W + 1), so(W + 1), co(W + 1), lo(W + 1), cap(W);
   HIP_OK(hipMemcpy(bo.data(), b->body_off, (W + 1) * 4, hipMemcpyDeviceToHost));
@@ -1079,7 +1101,8 @@ static void launch_forward_t(ostrich_ctx* ctx, const Bucket& bk, hipStream_t st,
   const bool tier = bk.tier && tier_ok;
   int32_t* nact_now = tier ? sc.plan + 2 + 2 * n : nullptr;  // the split by this step's contacts
   if (nact_now)
-    hipLaunchKernelGGL(k_count_active, dim3(n), dim3(64), 0, st, ctx->B, ctx->P, wl, q_prev, u_prev, nact_now);
+    hipLaunchKernelGGL(k_count_active, dim3(n), dim3(64), 0, st, ctx->B, ctx->P, wl, q_prev, u_prev,
+                       (const int32_t*)ctx->d_hist, nact_now);
   hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, ctx->B, wl, n,
                      (const int32_t*)ctx->d_hist, (const int32_t*)nact_now, (const double*)nullptr,
                      (const int64_t*)nullptr, tier ? bk.caps1.nc : 0, sc.plan);

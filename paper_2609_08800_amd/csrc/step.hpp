@@ -210,17 +210,19 @@ OST_HD bool approach_active(const Params& P, int kind, const double* sr, const F
 }
 
 // Active contacts of world R at q- by the refresh's test, for a launch plan:
-// slots s0, s0 + ds, ... of the world (a team's share), terrain slots counted
-// active (their search is left to the step).  Returns the share's count.
+// slots s0, s0 + ds, ... of the world (a team's share), terrain slots left
+// out (their mesh search is the step's) and counted in *n_terrain.  Returns
+// the share's count of the other slots.
 OST_HD int count_active(const Batch& B, const Params& P, const WorldRef& R, const double* q_prev,
-                        const double* u_prev, int s0, int ds) {
+                        const double* u_prev, int s0, int ds, int* n_terrain) {
   int n = 0;
+  *n_terrain = 0;
   for (int s = s0; s < R.ns; s += ds) {
     const int* si = B.slot_int + 4 * (R.s0 + s);
     const double* sr = B.slot_real + 9 * (R.s0 + s);
     const int kind = si[0], a = si[1], b = si[2];
     if (kind == 3) {
-      ++n;
+      ++*n_terrain;
       continue;
     }
     const double* qa = q_prev + 7 * (R.b0 + a);

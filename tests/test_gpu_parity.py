@@ -656,3 +656,36 @@ def test_krylov_newton_step_is_rejected(torch):
     b = scenes.robot_batch(2, seed=3)
     with pytest.raises(Exception, match="switched off"):
         sim_for(b, scenes.solver_params(linear_solver=1))
+
+
+def test_config1_four_corner_box_rollout_gradient(torch):
+    """The box workload as configured: boxes on their four bottom corners (the
+    normal split over the corners is not unique), T = 50 with checkpoints every
+    10 steps, the benchmark's solver settings (tol 1e-10, budget 16).  Loss and
+    the gradient with respect to the initial velocity and pose against the
+    oracle's rollout, on the worlds whose every step converged on both sides:
+    the states, hence the loss, are unique.  The gradients pass through the q-
+    cotangents, which see the multiplier split through d(J^T lambda)/dq- and
+    could depend on each side's root (R29); here they meet the ordinary
+    gradient bar (1.7e-7 and 5.9e-8 seen at most)."""
+    b = scenes.box_batch(16, seed=0)
+    P = scenes.solver_params()
+    T = 50
+    sim = sim_for(b, P)
+    r = sim.rollout(b.q0, b.u0, None, None, T, ckpt_every=10, loss_body=b.loss_body, target=b.target)
+    ref = oracle.rollout(b, P, b.q0, b.u0, None, T)
+    gst = r["status"].cpu().numpy()
+    ok = [w for w in range(b.n_worlds) if not (ref["status"][w] & 6) and not (gst[w] & 6)]
+    print("worlds converged at every step on both sides:", len(ok), "of", b.n_worlds, flush=True)
+    assert len(ok) >= b.n_worlds // 2, (ref["status"], gst)
+    # each step is solved to tol 1e-10 on both sides, so the two states part by about that much per
+    # step, which a 50-step sliding rollout can amplify: 2.1e-8 relative seen on one world
+    np.testing.assert_allclose(r["loss"].cpu().numpy()[ok], ref["loss"][ok], rtol=1e-6, atol=1e-12)
+    for key in ("g_u0", "g_q0"):
+        errs = []
+        for w in ok:
+            rows = world_rows(b.body_off, [w])
+            g, x = r[key].cpu().numpy()[rows], ref[key][rows]
+            errs.append(np.linalg.norm(g - x) / max(np.linalg.norm(x), 1e-300))
+        print(key, "relative error per world: max %.2e median %.2e" % (max(errs), float(np.median(errs))), flush=True)
+        assert max(errs) <= GRAD_TOL, (key, max(errs))
