@@ -133,9 +133,12 @@ typedef struct {
                           at most this many active contacts, so that more worlds share a CU, and
                           hands every world with more to a second, persistent launch with the full
                           carve.  The two launches run side by side: a planning pass counts each
-                          world's active contacts at q- (the adjoint reads them from the tape) and
-                          sends the worlds that exceed the first carve to the second launch from the
-                          start.  0: automatic, the largest count that raises the workgroups per CU
+                          world's active contacts at q- (the adjoint reads them from the tape;
+                          a terrain slot, whose mesh search is the step's, counts with the
+                          world's contacts of its previous step) and sends the worlds that exceed
+                          the first carve to the second launch from the start; a world the first
+                          launch still finds too large is taken by a last launch after both.
+                          0: automatic, the largest count that raises the workgroups per CU
                           (two wavefronts per SIMD), if any; -1: never; n > 0: n, if below the
                           bucket's contact cap.  ostrich_autotune also times the untiered launch */
   double delta_reg_adj; /* relative regularisation (> 0) of the factor written to the tape, the one the
