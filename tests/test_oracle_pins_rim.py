@@ -64,11 +64,16 @@ def _rim_points(x, quat, local, axis_b, r, n_pts=20000):
     return x[None, :] + pl @ R.T
 
 
-def _disc_world(q, mu=0.8, local=(0.0, 0.0, 0.0), kind=scenes.SLOT_PLANE, axis=(0.0, 1.0, 0.0), hm_index=-1):
-    """One free wheel body with a single rim-circle slot."""
+def _disc_world(q, mu=0.8, local=(0.0, 0.0, 0.0), kind=scenes.SLOT_PLANE, axis=(0.0, 1.0, 0.0), hm_index=-1,
+                obstacle=None):
+    """One free wheel body with a single rim-circle slot (against the plane, a
+    heightmap, or the given static box (centre, half extents))."""
     wd = scenes.World(contact_cap=4)
     b = wd.add_body(1.0, scenes.cylinder_inertia_y(1.0, R_WHEEL, 0.05), tuple(q))
-    wd.add_slot(kind, b, local=local, radius=R_WHEEL, mu=mu, axis=axis, feature=0 if kind == scenes.SLOT_HEIGHTMAP else -1)
+    if obstacle is not None:
+        wd.add_obstacle(*obstacle)
+    feature = 0 if kind in (scenes.SLOT_HEIGHTMAP, scenes.SLOT_BOX) else -1
+    wd.add_slot(kind, b, local=local, radius=R_WHEEL, mu=mu, axis=axis, feature=feature)
     wd.knots = np.zeros((0, scenes.ROBOT_KNOTS))
     wd.heightmap = hm_index
     return wd
@@ -102,6 +107,23 @@ def test_rim_gap_on_the_plane_is_the_lowest_rim_point(tilt):
         x, qq = _pose_after(q0, u, P["h"])
         pts = _rim_points(x, qq, (0, 0, 0), (0, 1, 0), R_WHEEL)
         assert abs(g - pts[:, 2].min()) < 1e-8, (tilt, u, g, pts[:, 2].min())
+
+
+def test_rim_gap_on_the_obstacle_top_face():
+    """A tilted rim circle over the static box's top face (its centre above the
+    face's interior): the gap equals the least height of the rim's points above
+    the face, at q- and at a rotated iterate."""
+    P = scenes.solver_params()
+    top = 0.15
+    box = ((0.0, 0.0, 0.5 * top), (0.6, 0.4, 0.5 * top))
+    tilt = 0.4
+    q0 = np.r_[[0.1, -0.05, top + R_WHEEL * math.cos(tilt) - 0.003], _quat_axis_angle((1, 0.3, 0), tilt)]
+    b = scenes.pack([_disc_world(q0, kind=scenes.SLOT_BOX, obstacle=box)])
+    for u in (np.zeros(6), np.array([0.2, -0.1, -0.03, 0.4, 3.0, -0.2])):
+        g, _ = _inspect_gap(b, P, u)
+        x, qq = _pose_after(q0, u, P["h"])
+        pts = _rim_points(x, qq, (0, 0, 0), (0, 1, 0), R_WHEEL)
+        assert abs(g - (pts[:, 2].min() - top)) < 1e-8
 
 
 def test_rim_facing_the_plane_touches_with_its_centre_height():

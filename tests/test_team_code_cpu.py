@@ -130,6 +130,19 @@ def _scene(name):
     if name == "robots":
         b = scenes.robot_batch(3, seed=3)
         return b, scenes.solver_params(k_max=64), _robots_ctrl(b)
+    if name == "cylinder_robots":
+        # rim circles on the plane and on the obstacle box's side face, there with the
+        # axis oblique to the normal (n . a = 0.26), so that every term of the rim's
+        # depth and lever is live.  Two rims per wheel on the ground plus the hinge make
+        # the constraint rows nearly dependent; the q- pull-back of the multipliers along
+        # that direction is fixed by delta_reg_adj alone, and two implementations agree
+        # there only to a spread that falls faster than 1/delta_reg_adj (world 0, second
+        # step: 3.9e-4, 3.0e-6, 1.6e-7 at 1e-8, 1e-7, 1e-6).  Both sides take 1e-6 here.
+        rng = np.random.default_rng(4)
+        b = scenes.pack([scenes.robot_world(rng, yaw=float(rng.uniform(-0.3, 0.3)),
+                                            obstacle_x=float(rng.uniform(0.3, 0.5)), wheels="cylinder")
+                         for _ in range(3)])
+        return b, scenes.solver_params(k_max=64, delta_reg_adj=1e-6), _robots_ctrl(b)
     if name == "tripods":
         rng = np.random.default_rng(3)
         b = scenes.pack([tripod_world(tuple(rng.uniform(-1, 1, 2)) + (0.0,), tuple(rng.normal(0, 0.5, 3)),
@@ -145,7 +158,7 @@ def _scene(name):
     return b, scenes.solver_params(k_max=64, gravity=(0, 0, 0)), lambda k: np.array([-0.3, 0.5])
 
 
-@pytest.mark.parametrize("name", ["robots", "tripods", "position_servos", "hinges", "terrain"])
+@pytest.mark.parametrize("name", ["robots", "tripods", "position_servos", "hinges", "terrain", "cylinder_robots"])
 def test_team_code_matches_oracle(lib, name):
     """Forward states, contact sets and status, and the adjoint with the parameter
     cotangents, teacher-forced from the oracle's states over three steps (terrain:
@@ -255,7 +268,7 @@ def test_fixed_point_refinement_would_miss_the_tripod_adjoint(lib):
     assert rel(T.adjoint(q, u, None, o, gqn, gun, refine=8)["gu"], R["gu"]) <= 1e-12
 
 
-@pytest.mark.parametrize("name", ["robots", "terrain"])
+@pytest.mark.parametrize("name", ["robots", "terrain", "cylinder_robots"])
 def test_workspace_garbage_does_not_change_results(lib, name):
     """The same bits whatever the workspace held before the step: zeros, all bits
     set, or 0x7f bytes (forward, tape and adjoint)."""
@@ -327,7 +340,7 @@ def fibers(tmp_path_factory):
     return L
 
 
-@pytest.mark.parametrize("name", ["robots", "tripods", "position_servos", "terrain"])
+@pytest.mark.parametrize("name", ["robots", "tripods", "position_servos", "terrain", "cylinder_robots"])
 def test_team_of_128_is_schedule_independent(lib, fibers, name):
     """A team of 128 threads (two wavefronts' worth), run as fibers in random orders
     between barriers: forward and adjoint give the same bits under three schedules,
