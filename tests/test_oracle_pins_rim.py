@@ -9,7 +9,10 @@ compared with a brute-force minimum over 20,000 points of the rim, at q- and
 after a rotation of the iterate; the contact point's slip velocity, from the
 friction rows, with the velocity of the brute-force lowest rim point; the
 gap's Jacobian with central differences of the gap; a flat heightmap with the
-plane; and an upright wheel at rest with the weight it carries.
+plane; an upright wheel at rest with the weight it carries; and the contact's
+activation at q- with the brute-force lowest rim point.  Five plausible
+mistakes in the oracle's rim code, each planted in a copy of it, fail one of
+these pins.
 """
 import math
 
@@ -246,3 +249,55 @@ def test_rim_circle_on_a_body_face_is_rejected():
     a = wd.add_body(1.0, (1, 1, 1), (0, 0, 1, 0, 0, 0, 1))
     with pytest.raises(ValueError):
         wd.add_slot(scenes.SLOT_BODYFACE, a, radius=0.1, b=0, face_h=0.1, axis=(0, 1, 0))
+
+
+@pytest.mark.parametrize("above,active", [(0.002, False), (-0.002, True)])
+def test_rim_activation_uses_the_lowest_rim_point(above, active):
+    """A contact is activated at q- when its gap (at rest) is within delta0: a
+    rim circle tilted by 1 rad whose lowest point (brute force) is 2 mm above
+    or below delta0 is inactive or active.  A sphere of the same radius would
+    reach 4.6 cm lower and be active in both cases."""
+    P = scenes.solver_params()
+    q = np.r_[[0.1, 0.2, 0.0], _quat_axis_angle((1, 0, 0), 1.0)]
+    low = _rim_points(np.zeros(3), q[3:], (0, 0, 0), (0, 1, 0), R_WHEEL)[:, 2].min()
+    q[2] = P["delta0"] + above - low
+    b = scenes.pack([_disc_world(q)])
+    res = oracle.inspect(b, P, 0, b.q0, b.u0, None)
+    assert (res["m"] == 3) == active, (above, res["m"])
+
+
+# Plausible mistakes in the oracle's rim-circle code, each planted in a copy of
+# the oracle, must fail at least one of the pins above.
+def _pins_on_the_plane():
+    for tilt in (0.3, 1.0):
+        test_rim_gap_on_the_plane_is_the_lowest_rim_point(tilt)
+
+
+def _pin_slip():
+    test_rim_gap_jacobian_and_slip_velocity()
+
+
+def _pin_activation():
+    test_rim_activation_uses_the_lowest_rim_point(0.002, False)
+
+
+RIM_PLANTS = [
+    ("depth_without_sqrt", "  S sn = sqrt(s2);\n", "  S sn = s2;\n", [_pins_on_the_plane]),
+    ("support_sign", "if (d) *d = (n - a * na) * (1.0 / sn);", "if (d) *d = (n + a * na) * (1.0 / sn);",
+     [_pin_slip]),
+    ("axis_not_rotated", "C.noff - rim_depth(C.n, qrot(qa, cst3<S>(C.ax.x, C.ax.y, C.ax.z)), C.r,",
+     "C.noff - rim_depth(C.n, cst3<S>(C.ax.x, C.ax.y, C.ax.z), C.r,", [_pins_on_the_plane]),
+    ("sphere_lever", "S(C.loc.z)}) - dsup * C.r;", "S(C.loc.z)}) - C.n * C.r;", [_pin_slip]),
+    ("activation_gap_offset", "gap = gap + S.r - rim_depth(", "gap = gap - rim_depth(", [_pin_activation]),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pins", RIM_PLANTS, ids=[p[0] for p in RIM_PLANTS])
+def test_planted_rim_mistake_fails_its_pin(tmp_path, name, old, new, pins):
+    from test_oracle_pins_geometry import planted
+    with planted(tmp_path, old, new):
+        for pin in pins:
+            with pytest.raises(AssertionError):
+                pin()
+    for pin in pins:  # and the unplanted oracle passes them again
+        pin()
