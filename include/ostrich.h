@@ -124,7 +124,7 @@ typedef struct {
                           OSTRICH_LIN_KRYLOV (1) the paper's iterative alternative, a
                           matrix-free Krylov solve (restarted GMRES, Jacobi preconditioner,
                           products with A from the row blocks), the matrix never formed.
-                          OSTRICH_LIN_KRYLOV is switched off in this build: context creation
+                          OSTRICH_LIN_KRYLOV is switched off in this version: context creation
                           returns OSTRICH_E_UNSUPPORTED for it */
   int32_t krylov_iters; /* products with A per Newton step at most (0: 16, as the paper's 16
                           inner iterations); the solve stops earlier at 1e-12 of |rhs| */

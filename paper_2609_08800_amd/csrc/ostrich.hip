@@ -937,7 +937,7 @@ extern "C" int ostrich_ctx_create(const ostrich_batch* b, const ostrich_params* 
   if (p->linear_solver != OSTRICH_LIN_LU && p->linear_solver != OSTRICH_LIN_KRYLOV)
     return fail(OSTRICH_E_ARG, "linear_solver must be OSTRICH_LIN_LU or OSTRICH_LIN_KRYLOV");
   if (p->linear_solver == OSTRICH_LIN_KRYLOV)  // switched off: its kernel faulted on the GPU, cause not found
-    return fail(OSTRICH_E_UNSUPPORTED, "the matrix-free Krylov Newton step is switched off in this build");
+    return fail(OSTRICH_E_UNSUPPORTED, "the matrix-free Krylov Newton step is switched off in this version of the library");
   if (p->krylov_iters < 0) return fail(OSTRICH_E_ARG, "krylov_iters must be >= 0");
   ctx->P.lin = p->linear_solver;
   ctx->P.lin_iters = p->krylov_iters > 0 ? p->krylov_iters : 16;
