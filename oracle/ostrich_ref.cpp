@@ -10,7 +10,15 @@
 //
 // The terrain narrow phase searches every feature of the mesh (brute force);
 // its pins are the flat heightmap, which must reproduce the plane z = h0, and
-// hand-placed points over single features.
+// hand-placed points over single features.  A cylindrical wheel touches with
+// the two circles of its rims (Sec. IV-D), each reaching r sqrt(1 - (n . a)^2)
+// below its centre along a contact normal n; its pins compare against a
+// brute-force minimum over the rim's points.
+//
+// Every part has a pin of its own, from closed forms, brute force, central
+// differences or the paper's worked example (tests/test_oracle_pins*.py), and
+// planted mistakes in compiled copies of this file fail those pins; no part is
+// left unpinned.
 #include "ostrich_ref.h"
 
 #include <algorithm>
