@@ -9,8 +9,11 @@ compared with a brute-force minimum over 20,000 points of the rim, at q- and
 after a rotation of the iterate; the contact point's slip velocity, from the
 friction rows, with the velocity of the brute-force lowest rim point; the
 gap's Jacobian with central differences of the gap; a flat heightmap with the
-plane; an upright wheel at rest with the weight it carries; and the contact's
-activation at q- with the brute-force lowest rim point.  Five plausible
+plane; an upright wheel at rest with the weight it carries; the contact's
+activation at q- with the brute-force lowest rim point; and the exact step
+adjoint, whose q- and u- cotangents pass through the rim's depth and lever,
+with central differences of the step on single rim contacts on the plane and
+on the obstacle box's side face.  Five plausible
 mistakes in the oracle's rim code, each planted in a copy of it, fail one of
 these pins.
 """
@@ -301,3 +304,64 @@ def test_planted_rim_mistake_fails_its_pin(tmp_path, name, old, new, pins):
                 pin()
     for pin in pins:  # and the unplanted oracle passes them again
         pin()
+
+
+def _step_adjoint_fd(b, P, q, u):
+    """The oracle's exact step adjoint of a random linear loss of (q+, u+) against central
+    differences of the converged step in every component of q- and u- (the active set
+    unchanged by each perturbation).  Returns the relative deviation."""
+    lam = np.zeros(b.n_lam)
+    ref = oracle.step_forward(b, P, q, u, lam, None)
+    assert ref["status"][0] & 1 and ref["n_act"][0] == 1, ref["status"]
+    rng = np.random.default_rng(0)
+    gq, gu = rng.normal(size=q.shape), rng.normal(size=u.shape)
+    aq, au, _ = oracle.step_adjoint(b, P, q, u, lam, None, ref["u"], ref["lam"], gq, gu, mode=0)
+
+    def loss(qq, uu):
+        o = oracle.step_forward(b, P, qq, uu, lam, None)
+        assert o["status"][0] & 1 and np.array_equal(o["act_slot"], ref["act_slot"])
+        return float(np.sum(gq * o["q"]) + np.sum(gu * o["u"]))
+
+    g = np.concatenate([aq.ravel(), au.ravel()])
+    fd = np.zeros_like(g)
+    for i in range(g.size):
+        x = (q if i < q.size else u).copy()
+        j = i if i < q.size else i - q.size
+        d = 1e-6 * max(1.0, abs(x.flat[j]))
+        xp, xm = x.copy(), x.copy()
+        xp.flat[j] += d
+        xm.flat[j] -= d
+        lp = loss(xp, u) if i < q.size else loss(q, xp)
+        lm = loss(xm, u) if i < q.size else loss(q, xm)
+        fd[i] = (lp - lm) / (2 * d)
+    return np.linalg.norm(fd - g) / np.linalg.norm(g)
+
+
+def test_rim_step_adjoint_on_the_plane_matches_central_differences():
+    """A rim circle tilted by 0.3 rad (n . a = sin 0.3, so the depth and the contact
+    point turn with the axle), 2 mm into the plane, sliding and spinning under gravity
+    (mu = 0.3, a sliding contact): the exact adjoint's q- and u- cotangents, which pass
+    through the rim's depth and lever at q- and at the iterate, against central
+    differences of the step."""
+    P = scenes.solver_params(k_max=200, tol=1e-14)
+    tilt = 0.3
+    q0 = np.r_[[0.0, 0.0, R_WHEEL * math.cos(tilt) - 0.002], _quat_axis_angle((1, 0, 0), tilt)]
+    b = scenes.pack([_disc_world(q0, mu=0.3)])
+    u0 = np.array([[0.8, 0.3, -0.05, 0.4, 3.0, -0.5]])
+    dev = _step_adjoint_fd(b, P, b.q0.copy(), u0)
+    assert dev <= 1e-5, dev
+
+
+def test_rim_step_adjoint_on_the_obstacle_side_face_matches_central_differences():
+    """A rim circle yawed by 0.26 rad pressed 2 mm into the static box's -x face in zero
+    gravity (n = -x, n . a = sin 0.26): the same check as on the plane, through the box
+    feature's frame."""
+    P = scenes.solver_params(k_max=200, tol=1e-14, gravity=(0.0, 0.0, 0.0))
+    box = ((1.0, 0.0, 0.075), (0.6, 0.4, 0.075))
+    yaw = 0.26
+    x_face = box[0][0] - box[1][0]
+    q0 = np.r_[[x_face - R_WHEEL * math.cos(yaw) + 0.002, 0.05, 0.075], _quat_axis_angle((0, 0, 1), yaw)]
+    b = scenes.pack([_disc_world(q0, mu=0.3, kind=scenes.SLOT_BOX, obstacle=box)])
+    u0 = np.array([[0.5, 0.2, 0.1, 0.3, 2.0, -0.4]])
+    dev = _step_adjoint_fd(b, P, b.q0.copy(), u0)
+    assert dev <= 1e-5, dev

@@ -415,3 +415,39 @@ def test_tiered_carve_gives_the_same_bits(lib, name, nc1):
     nacts = np.concatenate(nacts)
     assert np.any(nacts > nc1) and np.any(nacts <= nc1), nacts
     assert deferred == 2 * np.sum(nacts > nc1)  # forward and adjoint
+
+
+def test_team_code_rim_adjoint_on_determinate_contacts(lib):
+    """One rim circle with its axis oblique to the contact normal, sliding on the plane
+    (n . a = sin 0.3) and sticking on the obstacle box's side face (n . a = sin 0.26, zero
+    gravity): one determinate contact, so no null direction for the regularisation to fix.
+    The kernel's step, and its q-, u- and friction-coefficient cotangents, against the
+    oracle's to 1e-12 of max(|reference|, 1) (1.3e-15 relative seen; the oracle's adjoint
+    matches central differences of the step to 5e-8 on these scenes).  Sticking on the box
+    face, the friction coefficient's cotangent is zero up to rounding."""
+    import math
+    from test_oracle_pins_rim import R_WHEEL, _disc_world, _quat_axis_angle
+    box = ((1.0, 0.0, 0.075), (0.6, 0.4, 0.075))
+    cases = [
+        (np.r_[[0.0, 0.0, R_WHEEL * math.cos(0.3) - 0.002], _quat_axis_angle((1, 0, 0), 0.3)],
+         dict(), dict(), [0.8, 0.3, -0.05, 0.4, 3.0, -0.5]),
+        (np.r_[[0.4 - R_WHEEL * math.cos(0.26) + 0.002, 0.05, 0.075], _quat_axis_angle((0, 0, 1), 0.26)],
+         dict(kind=scenes.SLOT_BOX, obstacle=box), dict(gravity=(0.0, 0.0, 0.0)), [0.5, 0.2, 0.1, 0.3, 2.0, -0.4]),
+    ]
+    for q0, wkw, pkw, u0 in cases:
+        b = scenes.pack([_disc_world(q0, mu=0.3, **wkw)])
+        P = scenes.solver_params(k_max=200, tol=1e-14, **pkw)
+        T = Team(lib, b, P)
+        q, u, lam = b.q0.copy(), np.array([u0]), np.zeros(b.n_lam)
+        o = T.forward(q, u, lam, None)
+        r = oracle.step_forward(b, P, q, u, lam, None)
+        assert o["status"][0] & 1 and r["status"][0] & 1 and o["n_act"][0] == 1
+        assert np.array_equal(o["act_slot"], r["act_slot"])
+        assert np.max(np.abs(o["u"] - r["u"])) <= STATE_TOL
+        rng = np.random.default_rng(1)
+        gqn, gun = rng.normal(size=q.shape), rng.normal(size=u.shape)
+        g = T.adjoint(q, u, None, o, gqn, gun)
+        R = oracle.step_adjoint_params(b, P, q, u, None, o["u"], o["lam"], gqn, gun, mode=0)
+        for key in ("gq", "gu", "g_mu"):
+            d, ref = np.linalg.norm(g[key].ravel() - R[key].ravel()), np.linalg.norm(R[key].ravel())
+            assert d <= 1e-12 * max(ref, 1.0), (key, d, ref)
