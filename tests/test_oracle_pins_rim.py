@@ -12,8 +12,8 @@ gap's Jacobian with central differences of the gap; a flat heightmap with the
 plane; an upright wheel at rest with the weight it carries; the contact's
 activation at q- with the brute-force lowest rim point; and the exact step
 adjoint, whose q- and u- cotangents pass through the rim's depth and lever,
-with central differences of the step on single rim contacts on the plane and
-on the obstacle box's side face.  Five plausible
+with central differences of the step on single rim contacts on the plane, on
+the obstacle box's side face and over its top edge.  Five plausible
 mistakes in the oracle's rim code, each planted in a copy of it, fail one of
 these pins.
 """
@@ -363,5 +363,29 @@ def test_rim_step_adjoint_on_the_obstacle_side_face_matches_central_differences(
     q0 = np.r_[[x_face - R_WHEEL * math.cos(yaw) + 0.002, 0.05, 0.075], _quat_axis_angle((0, 0, 1), yaw)]
     b = scenes.pack([_disc_world(q0, mu=0.3, kind=scenes.SLOT_BOX, obstacle=box)])
     u0 = np.array([[0.5, 0.2, 0.1, 0.3, 2.0, -0.4]])
+    dev = _step_adjoint_fd(b, P, b.q0.copy(), u0)
+    assert dev <= 1e-5, dev
+
+
+def _rim_over_box_edge():
+    """A rim circle (axis yawed by 0.26 rad) over the static box's -x top edge, its centre
+    in the edge's region, 2 mm into the edge along n = (-1, 0, 1)/sqrt 2, the normal from
+    the edge to the centre (it turns with the centre)."""
+    box = ((1.0, 0.0, 0.075), (0.6, 0.4, 0.075))
+    yaw = 0.26
+    n = np.array([-1.0, 0.0, 1.0]) / math.sqrt(2.0)
+    a = np.array([-math.sin(yaw), math.cos(yaw), 0.0])
+    depth = R_WHEEL * math.sqrt(1.0 - float(n @ a) ** 2)
+    c = np.array([0.4, 0.05, 0.15]) + n * (depth - 0.002)
+    q0 = np.r_[c, _quat_axis_angle((0, 0, 1), yaw)]
+    return scenes.pack([_disc_world(q0, mu=0.3, kind=scenes.SLOT_BOX, obstacle=box)])
+
+
+def test_rim_step_adjoint_over_the_obstacle_edge_matches_central_differences():
+    """The rim circle over the box's edge, sliding along it under gravity: the normal, the
+    depth and the lever all depend on q-; the exact adjoint against central differences."""
+    P = scenes.solver_params(k_max=200, tol=1e-14)
+    b = _rim_over_box_edge()
+    u0 = np.array([[0.3, 0.6, -0.1, 0.2, 2.0, -0.3]])
     dev = _step_adjoint_fd(b, P, b.q0.copy(), u0)
     assert dev <= 1e-5, dev
