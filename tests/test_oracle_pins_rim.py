@@ -13,7 +13,8 @@ plane; an upright wheel at rest with the weight it carries; the contact's
 activation at q- with the brute-force lowest rim point; and the exact step
 adjoint, whose q- and u- cotangents pass through the rim's depth and lever,
 with central differences of the step on single rim contacts on the plane, on
-the obstacle box's side face and over its top edge.  Five plausible
+the obstacle box's side face and over its top edge, and on a mesh edge and a
+mesh vertex.  Five plausible
 mistakes in the oracle's rim code, each planted in a copy of it, fail one of
 these pins.
 """
@@ -387,5 +388,38 @@ def test_rim_step_adjoint_over_the_obstacle_edge_matches_central_differences():
     P = scenes.solver_params(k_max=200, tol=1e-14)
     b = _rim_over_box_edge()
     u0 = np.array([[0.3, 0.6, -0.1, 0.2, 2.0, -0.3]])
+    dev = _step_adjoint_fd(b, P, b.q0.copy(), u0)
+    assert dev <= 1e-5, dev
+
+
+def _rim_on_mesh_feature(kind):
+    """A single rim circle (a wheel tipped by 0.4 rad about (1, 0.3, 0)) 2 mm into a convex
+    mesh feature along a normal n from the feature to the centre: the edge of the ridge
+    z = -|x| (n tipped 0.15 rad towards +x), or the vertex of the peak z = -(|x| + |y|)."""
+    n_grid, sp = 9, 0.1
+    xs = (np.arange(n_grid) - 4) * sp
+    if kind == "ridge":
+        heights = -np.abs(xs)[:, None] * np.ones(n_grid)[None, :]
+        foot = np.array([0.0, 0.013, 0.0])
+        n = np.array([math.sin(0.15), 0.0, math.cos(0.15)])
+    else:
+        heights = -(np.abs(xs)[:, None] + np.abs(xs)[None, :])
+        foot = np.zeros(3)
+        n = np.array([0.05, -0.04, 1.0]) / np.linalg.norm([0.05, -0.04, 1.0])
+    hm = scenes.Heightmap(n=n_grid, spacing=sp, origin=(xs[0], xs[0]), heights=heights)
+    quat = _quat_axis_angle((1, 0.3, 0), 0.4)
+    a = _rot(quat) @ np.array([0.0, 1.0, 0.0])
+    depth = R_WHEEL * math.sqrt(1.0 - float(n @ a) ** 2)
+    q0 = np.r_[foot + n * (depth - 0.002), quat]
+    return scenes.pack([_disc_world(q0, mu=0.3, kind=scenes.SLOT_HEIGHTMAP, hm_index=0)], [hm])
+
+
+@pytest.mark.parametrize("kind", ["ridge", "peak"])
+def test_rim_step_adjoint_on_mesh_edge_and_vertex_matches_central_differences(kind):
+    """Rim circles on a mesh edge and a mesh vertex, whose normals turn with the wheel's
+    centre: the exact adjoint against central differences of the step."""
+    P = scenes.solver_params(k_max=200, tol=1e-14)
+    b = _rim_on_mesh_feature(kind)
+    u0 = np.array([[0.2, 0.4, -0.1, 0.3, 2.5, -0.2]])
     dev = _step_adjoint_fd(b, P, b.q0.copy(), u0)
     assert dev <= 1e-5, dev

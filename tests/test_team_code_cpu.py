@@ -420,14 +420,16 @@ def test_tiered_carve_gives_the_same_bits(lib, name, nc1):
 def test_team_code_rim_adjoint_on_determinate_contacts(lib):
     """One rim circle with its axis oblique to the contact normal, sliding on the plane
     (n . a = sin 0.3), sticking on the obstacle box's side face (n . a = sin 0.26, zero
-    gravity) and sliding over the box's top edge (the normal turning with the centre): one
-    determinate contact, so no null direction for the regularisation to fix.
+    gravity), and sliding over the box's top edge, a mesh ridge's edge and a mesh peak's
+    vertex (normals that turn with the centre): one determinate contact, so no null
+    direction for the regularisation to fix.
     The kernel's step, and its q-, u- and friction-coefficient cotangents, against the
-    oracle's to 1e-12 of max(|reference|, 1) (1.3e-15 relative seen; the oracle's adjoint
+    oracle's to 1e-12 of max(|reference|, 1) (2.1e-15 relative seen; the oracle's adjoint
     matches central differences of the step to 5e-8 on these scenes).  Sticking on the box
     face, the friction coefficient's cotangent is zero up to rounding."""
     import math
-    from test_oracle_pins_rim import R_WHEEL, _disc_world, _quat_axis_angle, _rim_over_box_edge
+    from test_oracle_pins_rim import (R_WHEEL, _disc_world, _quat_axis_angle, _rim_on_mesh_feature,
+                                      _rim_over_box_edge)
     box = ((1.0, 0.0, 0.075), (0.6, 0.4, 0.075))
     cases = [
         (np.r_[[0.0, 0.0, R_WHEEL * math.cos(0.3) - 0.002], _quat_axis_angle((1, 0, 0), 0.3)],
@@ -435,10 +437,11 @@ def test_team_code_rim_adjoint_on_determinate_contacts(lib):
         (np.r_[[0.4 - R_WHEEL * math.cos(0.26) + 0.002, 0.05, 0.075], _quat_axis_angle((0, 0, 1), 0.26)],
          dict(kind=scenes.SLOT_BOX, obstacle=box), dict(gravity=(0.0, 0.0, 0.0)), [0.5, 0.2, 0.1, 0.3, 2.0, -0.4]),
     ]
-    edge = _rim_over_box_edge()  # over the box's top edge: the normal turns with the centre
-    cases.append((edge.q0[0], None, dict(), [0.3, 0.6, -0.1, 0.2, 2.0, -0.3]))
+    # over the box's top edge, and on a mesh ridge and a mesh peak: normals that turn with the centre
+    cases += [(_rim_over_box_edge(), None, dict(), [0.3, 0.6, -0.1, 0.2, 2.0, -0.3])]
+    cases += [(_rim_on_mesh_feature(k), None, dict(), [0.2, 0.4, -0.1, 0.3, 2.5, -0.2]) for k in ("ridge", "peak")]
     for q0, wkw, pkw, u0 in cases:
-        b = edge if wkw is None else scenes.pack([_disc_world(q0, mu=0.3, **wkw)])
+        b = q0 if wkw is None else scenes.pack([_disc_world(q0, mu=0.3, **wkw)])
         P = scenes.solver_params(k_max=200, tol=1e-14, **pkw)
         T = Team(lib, b, P)
         q, u, lam = b.q0.copy(), np.array([u0]), np.zeros(b.n_lam)
