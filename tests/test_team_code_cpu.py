@@ -212,15 +212,17 @@ def _root_residual(b, P, w, q, u, c, o):
     return float(np.linalg.norm(r["F"]))
 
 
-def test_team_code_on_cylinder_wheel_terrain(lib):
-    """Cylinder wheels (two rim circles each, Sec. IV-D) on terrain: contact sets
-    bit for bit; where both sides converge to the same state, that state to
-    STATE_TOL and every gradient block as in the test above; on a landing step
-    whose residual has several roots, or where only one side converges within
-    its budget, the team code's converged state is a root of the oracle's
-    residual (within ten times the tolerance)."""
+@pytest.mark.parametrize("truncate", [1, 0])
+def test_team_code_on_cylinder_wheel_terrain(lib, truncate):
+    """Cylinder wheels (two rim circles each, Sec. IV-D) on terrain, with the truncated
+    and with the complete q- pull-back (the latter through the mesh features' normals,
+    the rims' depths and levers at q-): contact sets bit for bit; where both sides
+    converge to the same state, that state to STATE_TOL and every gradient block as in
+    the test above; on a landing step whose residual has several roots, or where only one
+    side converges within its budget, the team code's converged state is a root of the
+    oracle's residual (within ten times the tolerance)."""
     b = scenes.terrain_batch(3, seed=5, n_maps=2)
-    P = scenes.solver_params(k_max=200, truncate=1)
+    P = scenes.solver_params(k_max=200, truncate=truncate)
     ctrl_at = _robots_ctrl(b)
     T = Team(lib, b, P)
     q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
