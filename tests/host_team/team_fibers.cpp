@@ -1,29 +1,47 @@
 // Host build of the library's per-world team procedures with a team of 128
 // threads run as fibers: between two barriers the threads run one after
 // another in a random order, so a missing barrier shows up as results that
-// depend on the schedule.  Test infrastructure, for CPU tests only.
+// depend on the schedule.  Each release also checks what the GPU needs and the
+// fibers alone would not enforce: a wavefront barrier or cross-lane exchange
+// involves the first wavefront only, an exchange (bcast, wmax) has all of its
+// lanes present at the same event, a team reduction (sum64, imax) every thread
+// of the team, and the threads released from one workgroup barrier have passed
+// the same number of barriers (no barrier under a branch that depends on the
+// thread).  Violations are counted, not fatal.  Test infrastructure, for CPU
+// tests only.
 #include <ucontext.h>
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <functional>
 #include <random>
+#include <string>
 #include <vector>
 #include "newton.hpp"
 #include "ostrich.h"
 using namespace ost;
+
+// fiber states
+enum { RUN = 0, AT_SYNC = 1, DONE = 2, AT_WSYNC = 3, AT_XLANE = 4, AT_REDUCE = 5 };
 
 struct Sched {
   int n;
   std::vector<ucontext_t> ctx;
   ucontext_t main;
   std::vector<std::vector<char>> stacks;
-  std::vector<int> state;  // 0 runnable, 1 at barrier, 2 done, 3 at wavefront barrier
+  std::vector<int> state;
+  std::vector<long> nbar, nwbar;  // workgroup-level and wavefront-level events passed
   std::vector<double> rv;
   std::vector<int> ri;
   std::mt19937 rng;
   std::function<void(int)> body;
   long phases = 0;
+  long violations = 0;
+  std::string first;
+  void violate(const std::string& what) {
+    if (violations++ == 0) first = what;
+  }
 };
 static Sched* gS = nullptr;
 
@@ -34,33 +52,34 @@ struct FiberTeam {
   int r;
   int rank() const { return r; }
   int size() const { return S->n; }
-  void sync() const {
-    S->state[r] = 1;
+  void wait(int st) const {
+    S->state[r] = st;
+    if (st == AT_SYNC || st == AT_REDUCE) ++S->nbar[r];
+    else ++S->nwbar[r];
     swapcontext(&S->ctx[r], &S->main);
   }
+  void sync() const { wait(AT_SYNC); }
   int wsize() const { return 64; }
-  void wsync() const {
-    S->state[r] = 3;
-    swapcontext(&S->ctx[r], &S->main);
-  }
+  void wsync() const { wait(AT_WSYNC); }
   double bcast(double v, int src) const {
+    if (src < 0 || src >= 64 || src >= S->n) S->violate("bcast from lane " + std::to_string(src));
     S->rv[r] = v;
-    wsync();
-    double o = S->rv[src];
-    wsync();
+    wait(AT_XLANE);
+    double o = S->rv[src < 0 ? 0 : (src >= S->n ? S->n - 1 : src)];
+    wait(AT_XLANE);
     return o;
   }
   double wmax(double v) const {
     S->rv[r] = v;
-    wsync();
+    wait(AT_XLANE);
     double m = S->rv[0];
     for (int i = 1; i < 64 && i < S->n; ++i) m = std::max(m, S->rv[i]);
-    wsync();
+    wait(AT_XLANE);
     return m;
   }
   double sum64(double v, double*) const {
     S->rv[r] = r < 64 ? v : 0.0;
-    sync();
+    wait(AT_REDUCE);
     double a[64];
     for (int l = 0; l < 64; ++l) a[l] = l < S->n ? S->rv[l] : 0.0;
     for (int off = 32; off > 0; off >>= 1) {
@@ -69,18 +88,50 @@ struct FiberTeam {
       std::memcpy(a, b, sizeof(a));
     }
     double res = a[0];
-    sync();
+    wait(AT_REDUCE);
     return res;
   }
   int imax(int v, double*) const {
     S->ri[r] = v;
-    sync();
+    wait(AT_REDUCE);
     int m = S->ri[0];
     for (int i = 1; i < S->n; ++i) m = std::max(m, S->ri[i]);
-    sync();
+    wait(AT_REDUCE);
     return m;
   }
 };
+
+// Checks one release point: `lanes` are the fibers released together (all at
+// one kind of barrier), the others keep waiting.
+static void check_release(Sched& S, bool wave_level, int kind) {
+  const int n = S.n, w0 = std::min(64, n);
+  if (wave_level) {
+    long c = -1;
+    for (int r = 0; r < n; ++r) {
+      const int st = S.state[r];
+      if (st != AT_WSYNC && st != AT_XLANE) continue;
+      if (r >= 64) S.violate("wavefront barrier reached by thread " + std::to_string(r) + " outside the first wavefront");
+      if (st != kind) S.violate("plain wavefront barrier and cross-lane exchange at one release");
+      if (c < 0) c = S.nwbar[r];
+      else if (S.nwbar[r] != c) S.violate("first-wavefront lanes at different wavefront events");
+    }
+    if (kind == AT_XLANE)
+      for (int r = 0; r < w0; ++r)
+        if (S.state[r] != AT_XLANE) S.violate("cross-lane exchange without lane " + std::to_string(r));
+    return;
+  }
+  long c = -1;
+  for (int r = 0; r < n; ++r) {
+    const int st = S.state[r];
+    if (st == DONE) {
+      if (kind == AT_REDUCE) S.violate("team reduction after thread " + std::to_string(r) + " finished");
+      continue;
+    }
+    if (st != kind) S.violate("workgroup barrier and team reduction at one release");
+    if (c < 0) c = S.nbar[r];
+    else if (S.nbar[r] != c) S.violate("threads released from different workgroup barriers");
+  }
+}
 
 static void tramp(int r) {
   gS->body(r);
@@ -93,7 +144,9 @@ static void run_team(Sched& S) {
   const int n = S.n;
   S.ctx.assign(n, ucontext_t{});
   S.stacks.assign(n, std::vector<char>(1 << 19));
-  S.state.assign(n, 0);
+  S.state.assign(n, RUN);
+  S.nbar.assign(n, 0);
+  S.nwbar.assign(n, 0);
   for (int r = 0; r < n; ++r) {
     getcontext(&S.ctx[r]);
     S.ctx[r].uc_stack.ss_sp = S.stacks[r].data();
@@ -103,23 +156,33 @@ static void run_team(Sched& S) {
   }
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
-  // all threads start runnable
+  // all threads start runnable; each phase runs every runnable thread until it
+  // waits or finishes, then releases one barrier: a wavefront-level one if any
+  // lane waits at one (the other threads keep waiting), else the workgroup's
   while (true) {
     std::shuffle(order.begin(), order.end(), S.rng);
     for (int r : order) {
-      if (S.state[r] != 0) continue;
+      if (S.state[r] != RUN) continue;
       swapcontext(&S.main, &S.ctx[r]);
     }
     ++S.phases;
-    bool wave = false, alive = false;
+    int wave_kind = 0, group_kind = 0;
+    bool alive = false;
     for (int r = 0; r < n; ++r) {
-      wave |= S.state[r] == 3;
-      alive |= S.state[r] != 2;
+      const int st = S.state[r];
+      if (st == AT_WSYNC || st == AT_XLANE) wave_kind = wave_kind ? wave_kind : st;
+      if (st == AT_SYNC || st == AT_REDUCE) group_kind = group_kind ? group_kind : st;
+      alive |= st != DONE;
     }
     if (!alive) break;
-    for (int r = 0; r < n; ++r) {
-      if (wave && S.state[r] == 3) S.state[r] = 0;
-      if (!wave && S.state[r] == 1) S.state[r] = 0;
+    if (wave_kind) {
+      check_release(S, true, wave_kind);
+      for (int r = 0; r < n; ++r)
+        if (S.state[r] == AT_WSYNC || S.state[r] == AT_XLANE) S.state[r] = RUN;
+    } else {
+      check_release(S, false, group_kind);
+      for (int r = 0; r < n; ++r)
+        if (S.state[r] == AT_SYNC || S.state[r] == AT_REDUCE) S.state[r] = RUN;
     }
   }
 }
@@ -131,6 +194,12 @@ struct FibCtx {
   int team;
   std::vector<char> ws;
   std::vector<int64_t> toff;
+  long violations = 0;
+  std::string first;
+  void take(const Sched& S) {
+    if (S.violations && !violations) first = S.first;
+    violations += S.violations;
+  }
 };
 
 extern "C" void* tf_create(const ostrich_batch* b, const ostrich_params* p, const int* caps6, const int64_t* toff,
@@ -183,6 +252,7 @@ extern "C" void tf_forward(void* h, unsigned seed, const double* q, const double
                       c->toff.data(), Mr);
     };
     run_team(S);
+    c->take(S);
   }
 }
 
@@ -205,5 +275,41 @@ extern "C" void tf_adjoint(void* h, unsigned seed, const double* q, const double
                     Mr);
     };
     run_team(S);
+    c->take(S);
   }
+}
+
+// Violations of the GPU's synchronisation rules seen so far (see the top of
+// this file); the first one's description goes to buf.
+extern "C" long tf_violations(void* h, char* buf, int len) {
+  FibCtx* c = (FibCtx*)h;
+  if (buf && len > 0) std::snprintf(buf, (size_t)len, "%s", c->first.c_str());
+  return c->violations;
+}
+
+// The checks above against small team procedures, one correct and three with a
+// planted mistake each: 0, correct (first-wavefront exchange beside a waiting
+// second wavefront, a barrier, a team reduction); 1, a barrier that only thread
+// 0 reaches; 2, an exchange that only lanes 0-9 enter; 3, a team reduction after
+// the second wavefront has finished.  Returns the violations counted.
+extern "C" long tf_selftest(int kind, int team) {
+  Sched S;
+  S.n = team;
+  S.rv.assign(team, 0.0);
+  S.ri.assign(team, 0);
+  S.rng.seed(11u + (unsigned)kind);
+  S.body = [&](int r) {
+    FiberTeam t{&S, r};
+    if (kind == 1 && r == 0) t.sync();
+    if (kind == 2) {
+      if (r < 10) (void)t.bcast(1.0, 3);
+    } else if (r < 64) {
+      (void)t.bcast((double)r, 3);
+    }
+    t.sync();
+    if (kind == 3 && r >= 64) return;
+    (void)t.sum64(1.0, nullptr);
+  };
+  run_team(S);
+  return S.violations;
 }

@@ -339,7 +339,16 @@ def fibers(tmp_path_factory):
     L.tf_destroy.argtypes = [ctypes.c_void_p]
     L.tf_forward.argtypes = [ctypes.c_void_p, ctypes.c_uint] + [ctypes.c_void_p] * 13
     L.tf_adjoint.argtypes = [ctypes.c_void_p, ctypes.c_uint] + [ctypes.c_void_p] * 11 + [ctypes.c_int]
+    L.tf_violations.restype = ctypes.c_long
+    L.tf_violations.argtypes = [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int]
+    L.tf_selftest.restype = ctypes.c_long
+    L.tf_selftest.argtypes = [ctypes.c_int, ctypes.c_int]
     return L
+
+
+def _violations(fibers, h):
+    buf = ctypes.create_string_buffer(256)
+    return fibers.tf_violations(h, buf, 256), buf.value.decode()
 
 
 @pytest.mark.parametrize("name", ["robots", "tripods", "position_servos", "terrain", "cylinder_robots"])
@@ -377,8 +386,61 @@ def test_team_of_128_is_schedule_independent(lib, fibers, name):
         assert np.max(np.abs(outs[0][1] - r["u"]) / np.maximum(1.0, np.abs(r["u"]))) <= STATE_TOL
         rq, ru, rc = oracle.step_adjoint(b, P, q, u, lam, c, outs[0][1], outs[0][2], gqn, gun, mode=0)
         assert rel(outs[0][5], rq) <= GRAD_TOL and rel(outs[0][6], ru) <= GRAD_TOL
+        assert _violations(fibers, h) == (0, "")
     finally:
         fibers.tf_destroy(h)
+
+
+def test_fiber_checks_catch_planted_synchronisation_mistakes(fibers):
+    """The fiber schedule's checks of the GPU's synchronisation rules pass a correct
+    team procedure and catch a barrier that one thread alone reaches, a cross-lane
+    exchange entered by part of the wavefront, and a team reduction after a wavefront
+    has finished."""
+    for team in (64, 128):
+        assert fibers.tf_selftest(0, team) == 0
+        assert fibers.tf_selftest(1, team) > 0
+        assert fibers.tf_selftest(2, team) > 0
+    assert fibers.tf_selftest(3, 128) > 0
+
+
+@pytest.mark.parametrize("name,lin", [(n, 0) for n in ("robots", "tripods", "terrain", "cylinder_robots")] +
+                         [(n, 1) for n in ("robots", "tripods", "cylinder_robots")])
+def test_team_procedures_keep_the_gpu_synchronisation_rules(lib, fibers, name, lin):
+    """Forward and adjoint of two steps, with the LU (lin 0) and the matrix-free
+    Krylov Newton step (lin 1), as fiber teams of 64 and 256 threads: every
+    wavefront barrier and cross-lane exchange involves the whole first wavefront and
+    nothing else, every team reduction the whole team, and the threads released from
+    a workgroup barrier have all passed the same barriers."""
+    b, P, ctrl_at = _scene(name)
+    if lin:
+        P = dict(P, linear_solver=1, krylov_iters=16)
+    T = Team(lib, b, P)
+    W = b.n_worlds
+    for team in (64, 256):
+        h = fibers.tf_create(ctypes.byref(T.cb), ctypes.byref(T.cp), T.caps.ctypes.data, T.toff.ctypes.data, team)
+        try:
+            q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+            rng = np.random.default_rng(2)
+            for k in range(2):
+                c = ctrl_at(k)
+                cv = np.ascontiguousarray(c if c is not None else np.zeros(max(b.n_ctrl, 1)), dtype=np.float64)
+                o = dict(q=np.zeros_like(q), u=np.zeros_like(u), lam=np.zeros_like(lam),
+                         act=np.full(max(b.n_slots, 1), -1, np.int32), n_act=np.zeros(W, np.int32),
+                         st=np.zeros(W, np.int32), it=np.zeros(W, np.int32), rn=np.zeros(W),
+                         tape=np.zeros(int(T.toff[-1])))
+                fibers.tf_forward(h, k + 1, q.ctypes.data, u.ctypes.data, lam.ctypes.data, cv.ctypes.data,
+                                  *[o[x].ctypes.data for x in ("q", "u", "lam", "act", "n_act", "st", "it", "rn",
+                                                               "tape")])
+                gqn, gun = rng.normal(size=q.shape), rng.normal(size=u.shape)
+                gq, gu, gc = np.zeros_like(q), np.zeros_like(u), np.zeros(max(b.n_ctrl, 1))
+                fibers.tf_adjoint(h, k + 1, q.ctypes.data, u.ctypes.data, cv.ctypes.data, o["u"].ctypes.data,
+                                  o["lam"].ctypes.data, o["tape"].ctypes.data, gqn.ctypes.data, gun.ctypes.data,
+                                  gq.ctypes.data, gu.ctypes.data, gc.ctypes.data, 8)
+                assert np.all(np.isfinite(o["u"])) or np.any(o["st"] & 4), (name, lin, team, k)
+                q, u, lam = o["q"], o["u"], o["lam"]
+            assert _violations(fibers, h) == (0, ""), (name, lin, team)
+        finally:
+            fibers.tf_destroy(h)
 
 
 @pytest.mark.parametrize("name,nc1", [("mixed", 5), ("terrain", 8)])
