@@ -37,6 +37,7 @@ struct HostCtx {
   Caps caps1;
   std::vector<char> ws1;
   int deferred = 0;
+  std::vector<int32_t> adj;  // per world: the adjoint's status bits of the last th_adjoint
 };
 
 extern "C" void* th_create(const ostrich_batch* b, const ostrich_params* p, const int* caps6, const int64_t* toff) {
@@ -113,17 +114,24 @@ extern "C" void th_adjoint(void* h, const double* q, const double* u, const doub
   HostCtx* c = (HostCtx*)h;
   SerialTeam t;
   WorldMem M = carve(c->ws.data(), c->caps, 1, SPLIT_LDS, nullptr, true);
+  c->adj.assign(c->B.n_worlds, 0);
   for (int w = 0; w < c->B.n_worlds; ++w) {
     refill(c);
     if (c->tier_nc > 0) {
       std::memset(c->ws1.data(), c->fill == 1 ? 0xFF : (c->fill == 2 ? 0x7F : 0), c->ws1.size());
       WorldMem M1 = carve(c->ws1.data(), c->caps1, 1, SPLIT_LDS, nullptr, true);
       if (adjoint_world(t, c->B, c->P, c->caps1, w, q, u, ctrl, un, ln, tape, c->toff.data(), gqn, gun, gq, gu, gc,
-                        refine, M1, gm, gmu, gkp))
+                        refine, M1, gm, gmu, gkp, c->adj.data()))
         continue;
       c->deferred++;
     }
     adjoint_world(t, c->B, c->P, c->caps, w, q, u, ctrl, un, ln, tape, c->toff.data(), gqn, gun, gq, gu, gc, refine, M,
-                  gm, gmu, gkp);
+                  gm, gmu, gkp, c->adj.data());
   }
+}
+
+// The adjoint's per-world status bits (OSTRICH_ST_ADJ_INEXACT) of the last th_adjoint.
+extern "C" void th_adj_status(void* h, int32_t* out) {
+  HostCtx* c = (HostCtx*)h;
+  for (size_t w = 0; w < c->adj.size(); ++w) out[w] = c->adj[w];
 }

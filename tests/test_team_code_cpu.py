@@ -44,6 +44,7 @@ def lib(tmp_path_factory):
     L.th_forward.argtypes = [ctypes.c_void_p] * 14
     L.th_adjoint.argtypes = [ctypes.c_void_p] * 15 + [ctypes.c_int]
     L.th_set_tier.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.th_adj_status.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     L.th_deferred.argtypes = [ctypes.c_void_p]
     L.th_deferred.restype = ctypes.c_int
     return L
@@ -521,3 +522,32 @@ def test_team_code_rim_adjoint_on_determinate_contacts(lib):
         for key in ("gq", "gu", "g_mu"):
             d, ref = np.linalg.norm(g[key].ravel() - R[key].ravel()), np.linalg.norm(R[key].ravel())
             assert d <= 1e-12 * max(ref, 1.0), (key, d, ref)
+
+
+def test_adjoint_krylov_converges_on_the_largest_stacks(lib):
+    """Stacks of 32 and 24 boxes (384 and 288 rows), teacher-forced from the oracle's
+    converged roots: the adjoint's Krylov solve of the exact system reaches its stop
+    within the default 8 operator applications at every step (no ST_ADJ_INEXACT), and
+    the velocity cotangents match the oracle's exact adjoint.  (At the benchmark's
+    budget of 16 Newton iterations these stacks end on best iterates that are not roots;
+    there the flag is raised, which is what it is for.)"""
+    from paper_2609_08800_amd import _capi as C
+    rng = np.random.default_rng(7)
+    b = scenes.pack([scenes.stack_world(rng, 32), scenes.stack_world(rng, 24)])
+    P = scenes.solver_params(k_max=200)
+    T = Team(lib, b, P)
+    q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    rs = np.random.default_rng(3)
+    for k in range(3):
+        o = T.forward(q, u, lam, None)
+        r = oracle.step_forward(b, P, q, u, lam, None)
+        gqn, gun = rs.normal(size=q.shape), rs.normal(size=u.shape)
+        g = T.adjoint(q, u, None, o, gqn, gun)
+        st = np.zeros(b.n_worlds, np.int32)
+        lib.th_adj_status(T.h, st.ctypes.data)
+        assert not np.any(st & C.ST_ADJ_INEXACT), (k, st)
+        R = oracle.step_adjoint_params(b, P, q, u, None, o["u"], o["lam"], gqn, gun, mode=0)
+        for w in range(b.n_worlds):
+            bs = slice(b.body_off[w], b.body_off[w + 1])
+            assert rel(g["gu"][bs].ravel(), R["gu"][bs].ravel()) <= GRAD_TOL, (k, w)
+        q, u, lam = r["q"], r["u"], r["lam"]
