@@ -551,3 +551,28 @@ def test_adjoint_krylov_converges_on_the_largest_stacks(lib):
             bs = slice(b.body_off[w], b.body_off[w + 1])
             assert rel(g["gu"][bs].ravel(), R["gu"][bs].ravel()) <= GRAD_TOL, (k, w)
         q, u, lam = r["q"], r["u"], r["lam"]
+
+
+def test_adjoint_inexact_flag_marks_a_krylov_solve_cut_short(lib):
+    """On the spinning, sliding tripods the exact system needs about four Krylov
+    applications: with one allowed the solve ends above its stop and ST_ADJ_INEXACT is
+    set for those worlds; with the default eight it is clear and the cotangents match
+    the oracle."""
+    from paper_2609_08800_amd import _capi as C
+    b, P, _ = _scene("tripods")
+    T = Team(lib, b, P)
+    q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    o = T.forward(q, u, lam, None)
+    rng = np.random.default_rng(4)
+    gqn, gun = rng.normal(size=q.shape), rng.normal(size=u.shape)
+    R = oracle.step_adjoint_params(b, P, q, u, None, o["u"], o["lam"], gqn, gun, mode=0)
+    flags = {}
+    for refine in (1, 8):
+        g = T.adjoint(q, u, None, o, gqn, gun, refine=refine)
+        st = np.zeros(b.n_worlds, np.int32)
+        lib.th_adj_status(T.h, st.ctypes.data)
+        flags[refine] = st & C.ST_ADJ_INEXACT
+        if refine == 8:
+            assert rel(g["gu"], R["gu"]) <= GRAD_TOL and rel(g["gq"], R["gq"]) <= GRAD_TOL
+    assert np.all(flags[1] != 0), flags
+    assert np.all(flags[8] == 0), flags
