@@ -150,7 +150,11 @@ typedef struct {
                           indeterminate (a robot on four wheels) the multiplier block has a null
                           direction that only this term fixes, and the cotangents of q- that see it
                           lose digits as 1 / delta_reg_adj.  1e-8 keeps both below the 1e-6
-                          gradient bar (bias about 4e-7, lost digits about 1e-7).
+                          gradient bar (bias about 4e-7, lost digits about 1e-7).  Cylindrical
+                          wheels standing with both rim circles on flat ground make the rows
+                          nearly dependent in the same way (two rims and the axle's hinge): there
+                          the q- cotangents of those wheels' positions along their axles agree
+                          between two implementations only to about 4e-4 at 1e-8 (1.6e-7 at 1e-6).
                           Raised tenfold while the factor's pivot test fails, the value used being
                           recorded in the tape */
 } ostrich_params;
