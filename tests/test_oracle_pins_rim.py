@@ -423,3 +423,19 @@ def test_rim_step_adjoint_on_mesh_edge_and_vertex_matches_central_differences(ki
     u0 = np.array([[0.2, 0.4, -0.1, 0.3, 2.5, -0.2]])
     dev = _step_adjoint_fd(b, P, b.q0.copy(), u0)
     assert dev <= 1e-5, dev
+
+
+def test_rim_parameter_cotangents_match_central_differences():
+    """Eq. (17) with a model parameter as xi through a rim contact: the mass and the
+    friction coefficient cotangents of a single rim circle sliding on the plane and
+    over the obstacle box's top edge, against central differences of the step."""
+    from test_oracle_pins import _param_fd
+    P = scenes.solver_params(k_max=200, tol=1e-14)
+    tilt = 0.3
+    q0 = np.r_[[0.0, 0.0, R_WHEEL * math.cos(tilt) - 0.002], _quat_axis_angle((1, 0, 0), tilt)]
+    plane = scenes.pack([_disc_world(q0, mu=0.3)])
+    plane.u0 = np.array([[0.8, 0.3, -0.05, 0.4, 3.0, -0.5]])
+    edge = _rim_over_box_edge()
+    edge.u0 = np.array([[0.3, 0.6, -0.1, 0.2, 2.0, -0.3]])
+    for b in (plane, edge):
+        assert _param_fd(b, P, None) == 2  # the mass and the slot's friction coefficient
