@@ -485,8 +485,9 @@ def test_tiered_carve_gives_the_same_bits(lib, name, nc1):
 def test_team_code_rim_adjoint_on_determinate_contacts(lib):
     """One rim circle with its axis oblique to the contact normal, sliding on the plane
     (n . a = sin 0.3), sticking on the obstacle box's side face (n . a = sin 0.26, zero
-    gravity), and sliding over the box's top edge, a mesh ridge's edge and a mesh peak's
-    vertex (normals that turn with the centre): one determinate contact, so no null
+    gravity), lying flat on the plane at rest and spinning (the degenerate circle whose
+    whole rim touches), and sliding over the box's top edge, a mesh ridge's edge and a mesh
+    peak's vertex (normals that turn with the centre): one determinate contact, so no null
     direction for the regularisation to fix.
     The kernel's step, and its q-, u- and friction-coefficient cotangents, against the
     oracle's to 1e-12 of max(|reference|, 1) (2.1e-15 relative seen; the oracle's adjoint
@@ -502,6 +503,10 @@ def test_team_code_rim_adjoint_on_determinate_contacts(lib):
         (np.r_[[0.4 - R_WHEEL * math.cos(0.26) + 0.002, 0.05, 0.075], _quat_axis_angle((0, 0, 1), 0.26)],
          dict(kind=scenes.SLOT_BOX, obstacle=box), dict(gravity=(0.0, 0.0, 0.0)), [0.5, 0.2, 0.1, 0.3, 2.0, -0.4]),
     ]
+    # lying flat on the plane (its axis along the normal: depth 0, the centre the contact point), at
+    # rest and spinning about the normal while it slides
+    flat = np.r_[[0.0, 0.0, -0.002], _quat_axis_angle((1, 0, 0), 0.5 * math.pi)]
+    cases += [(flat, dict(), dict(), [0.0] * 6), (flat, dict(), dict(), [0.3, 0.1, -0.02, 0.0, 0.0, 1.5])]
     # over the box's top edge, and on a mesh ridge and a mesh peak: normals that turn with the centre
     cases += [(_rim_over_box_edge(), None, dict(), [0.3, 0.6, -0.1, 0.2, 2.0, -0.3])]
     cases += [(_rim_on_mesh_feature(k), None, dict(), [0.2, 0.4, -0.1, 0.3, 2.5, -0.2]) for k in ("ridge", "peak")]
