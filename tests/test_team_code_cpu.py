@@ -25,16 +25,27 @@ STATE_TOL, GRAD_TOL = 1e-9, 1e-6
 
 
 @pytest.fixture(scope="module")
-def lib(tmp_path_factory):
+def host_builds(tmp_path_factory):
+    """Both host builds of the team code, compiled side by side: name -> library path."""
     hipcc = shutil.which("hipcc")
     if hipcc is None:
         pytest.skip("hipcc not available")
-    out = str(tmp_path_factory.mktemp("team") / "libteam_host.so")
-    subprocess.check_call([hipcc, "-O2", "-std=c++17", "-shared", "-fPIC",
-                           "-I", os.path.join(ROOT, "include"),
-                           "-I", os.path.join(ROOT, "paper_2609_08800_amd", "csrc"),
-                           os.path.join(ROOT, "tests", "host_team", "team_host.cpp"), "-o", out])
-    L = ctypes.CDLL(out)
+    d = tmp_path_factory.mktemp("team")
+    procs = {}
+    for name in ("team_host", "team_fibers"):
+        out = str(d / ("lib%s.so" % name))
+        procs[name] = (out, subprocess.Popen([hipcc, "-O2", "-std=c++17", "-shared", "-fPIC",
+                                              "-I", os.path.join(ROOT, "include"),
+                                              "-I", os.path.join(ROOT, "paper_2609_08800_amd", "csrc"),
+                                              os.path.join(ROOT, "tests", "host_team", name + ".cpp"), "-o", out]))
+    for name, (out, pr) in procs.items():
+        assert pr.wait() == 0, name
+    return {name: out for name, (out, _) in procs.items()}
+
+
+@pytest.fixture(scope="module")
+def lib(host_builds):
+    L = ctypes.CDLL(host_builds["team_host"])
     from paper_2609_08800_amd import _capi as C
     L.th_create.restype = ctypes.c_void_p
     L.th_create.argtypes = [ctypes.POINTER(C.OstrichBatch), ctypes.POINTER(C.OstrichParams), ctypes.c_void_p,
@@ -323,16 +334,8 @@ def test_krylov_newton_step_reaches_the_oracle_root(lib):
 
 
 @pytest.fixture(scope="module")
-def fibers(tmp_path_factory):
-    hipcc = shutil.which("hipcc")
-    if hipcc is None:
-        pytest.skip("hipcc not available")
-    out = str(tmp_path_factory.mktemp("fibers") / "libteam_fibers.so")
-    subprocess.check_call([hipcc, "-O2", "-std=c++17", "-shared", "-fPIC",
-                           "-I", os.path.join(ROOT, "include"),
-                           "-I", os.path.join(ROOT, "paper_2609_08800_amd", "csrc"),
-                           os.path.join(ROOT, "tests", "host_team", "team_fibers.cpp"), "-o", out])
-    L = ctypes.CDLL(out)
+def fibers(host_builds):
+    L = ctypes.CDLL(host_builds["team_fibers"])
     from paper_2609_08800_amd import _capi as C
     L.tf_create.restype = ctypes.c_void_p
     L.tf_create.argtypes = [ctypes.POINTER(C.OstrichBatch), ctypes.POINTER(C.OstrichParams), ctypes.c_void_p,
