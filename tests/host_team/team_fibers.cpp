@@ -196,6 +196,12 @@ struct FibCtx {
   std::vector<int64_t> toff;
   long violations = 0;
   std::string first;
+  // tiered carve (tier_nc > 0): each world first runs with a workspace for tier_nc
+  // active contacts and, if the team finds it too small, again with the full one
+  int tier_nc = 0;
+  Caps caps1;
+  std::vector<char> ws1;
+  int deferred = 0;
   void take(const Sched& S) {
     if (S.violations && !violations) first = S.first;
     violations += S.violations;
@@ -229,30 +235,61 @@ extern "C" void* tf_create(const ostrich_batch* b, const ostrich_params* p, cons
 }
 extern "C" void tf_destroy(void* h) { delete (FibCtx*)h; }
 
+// Runs one world's team procedure on a fresh schedule; returns whether it ran to
+// the end (a procedure returns false, before writing any output, when the world
+// does not fit the carve).  Every thread must return the same.
+template <class Body>
+static bool run_world(FibCtx* c, unsigned seed, int w, Body body) {
+  Sched S;
+  S.n = c->team;
+  S.rv.assign(c->team, 0.0);
+  S.ri.assign(c->team, 0);
+  S.rng.seed(seed * 7919 + w);
+  std::vector<int> ok(c->team, -1);
+  S.body = [&](int r) { ok[r] = body(FiberTeam{&S, r}) ? 1 : 0; };
+  run_team(S);
+  for (int r = 1; r < c->team; ++r)
+    if (ok[r] != ok[0]) S.violate("threads disagree whether the world fits the carve");
+  c->take(S);
+  return ok[0] == 1;
+}
+
+extern "C" void tf_set_tier(void* h, int nc) {
+  FibCtx* c = (FibCtx*)h;
+  c->tier_nc = nc;
+  c->caps1 = c->caps;
+  if (nc > 0) {
+    c->caps1.nc = nc;
+    const int mr = 5 * c->caps.nj + c->caps.nsv + 3 * nc;
+    c->caps1.mr = mr < c->caps.mr ? mr : c->caps.mr;
+    c->ws1.assign(world_lds_bytes(c->caps1, c->team, SPLIT_LDS, true) + 64, 0);
+  }
+  c->deferred = 0;
+}
+extern "C" int tf_deferred(void* h) { return ((FibCtx*)h)->deferred; }
+
 extern "C" void tf_forward(void* h, unsigned seed, const double* q, const double* u, const double* lam,
                            const double* ctrl, double* qn, double* un, double* ln, int* act, int* nact, int* st,
                            int* it, double* rn, double* tape) {
   FibCtx* c = (FibCtx*)h;
   for (int w = 0; w < c->B.n_worlds; ++w) {
-    Sched S;
-    S.n = c->team;
-    S.rv.assign(c->team, 0.0);
-    S.ri.assign(c->team, 0);
-    S.rng.seed(seed * 7919 + w);
-    std::memset(c->ws.data(), 0xFF, c->ws.size());
-    WorldMem M = carve(c->ws.data(), c->caps, c->team);
-    S.body = [&](int r) {
-      FiberTeam t{&S, r};
-      WorldMem Mr = M;
-      if (c->P.lin)
-        forward_world<FiberTeam, true>(t, c->B, c->P, c->caps, w, q, u, lam, ctrl, qn, un, ln, act, nact, st, it,
-                                       rn, tape, c->toff.data(), Mr);
-      else
-        forward_world(t, c->B, c->P, c->caps, w, q, u, lam, ctrl, qn, un, ln, act, nact, st, it, rn, tape,
-                      c->toff.data(), Mr);
+    auto fw = [&](std::vector<char>& ws, const Caps& caps) {
+      std::memset(ws.data(), 0xFF, ws.size());
+      WorldMem M = carve(ws.data(), caps, c->team);
+      return run_world(c, seed, w, [&](FiberTeam t) {
+        WorldMem Mr = M;
+        if (c->P.lin)
+          return forward_world<FiberTeam, true>(t, c->B, c->P, caps, w, q, u, lam, ctrl, qn, un, ln, act, nact, st,
+                                                it, rn, tape, c->toff.data(), Mr);
+        return forward_world(t, c->B, c->P, caps, w, q, u, lam, ctrl, qn, un, ln, act, nact, st, it, rn, tape,
+                             c->toff.data(), Mr);
+      });
     };
-    run_team(S);
-    c->take(S);
+    if (c->tier_nc > 0) {
+      if (fw(c->ws1, c->caps1)) continue;
+      c->deferred++;
+    }
+    fw(c->ws, c->caps);
   }
 }
 
@@ -261,21 +298,20 @@ extern "C" void tf_adjoint(void* h, unsigned seed, const double* q, const double
                            const double* gun, double* gq, double* gu, double* gc, int refine) {
   FibCtx* c = (FibCtx*)h;
   for (int w = 0; w < c->B.n_worlds; ++w) {
-    Sched S;
-    S.n = c->team;
-    S.rv.assign(c->team, 0.0);
-    S.ri.assign(c->team, 0);
-    S.rng.seed(seed * 7919 + w);
-    std::memset(c->ws.data(), 0xFF, c->ws.size());
-    WorldMem M = carve(c->ws.data(), c->caps, c->team, SPLIT_LDS, nullptr, true);
-    S.body = [&](int r) {
-      FiberTeam t{&S, r};
-      WorldMem Mr = M;
-      adjoint_world(t, c->B, c->P, c->caps, w, q, u, ctrl, un, ln, tape, c->toff.data(), gqn, gun, gq, gu, gc, refine,
-                    Mr);
+    auto bw = [&](std::vector<char>& ws, const Caps& caps) {
+      std::memset(ws.data(), 0xFF, ws.size());
+      WorldMem M = carve(ws.data(), caps, c->team, SPLIT_LDS, nullptr, true);
+      return run_world(c, seed, w, [&](FiberTeam t) {
+        WorldMem Mr = M;
+        return adjoint_world(t, c->B, c->P, caps, w, q, u, ctrl, un, ln, tape, c->toff.data(), gqn, gun, gq, gu, gc,
+                             refine, Mr);
+      });
     };
-    run_team(S);
-    c->take(S);
+    if (c->tier_nc > 0) {
+      if (bw(c->ws1, c->caps1)) continue;
+      c->deferred++;
+    }
+    bw(c->ws, c->caps);
   }
 }
 

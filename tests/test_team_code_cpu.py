@@ -347,6 +347,9 @@ def fibers(host_builds):
     L.tf_violations.argtypes = [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int]
     L.tf_selftest.restype = ctypes.c_long
     L.tf_selftest.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.tf_set_tier.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.tf_deferred.argtypes = [ctypes.c_void_p]
+    L.tf_deferred.restype = ctypes.c_int
     return L
 
 
@@ -584,3 +587,57 @@ def test_adjoint_inexact_flag_marks_a_krylov_solve_cut_short(lib):
             assert rel(g["gu"], R["gu"]) <= GRAD_TOL and rel(g["gq"], R["gq"]) <= GRAD_TOL
     assert np.all(flags[1] != 0), flags
     assert np.all(flags[8] == 0), flags
+
+
+@pytest.mark.parametrize("name,nc1", [("mixed", 5), ("terrain", 8)])
+def test_tiered_carve_as_a_fiber_team(lib, fibers, name, nc1):
+    """The tiered carve as 128-thread fiber teams over two steps: a world run first with
+    a workspace for nc1 contacts leaves, when it does not fit, with every thread agreeing
+    before any output is written, and runs again with the full workspace; forward, tape
+    and adjoint are the same bits as the untiered run, and the GPU's synchronisation
+    rules hold."""
+    if name == "mixed":
+        b = scenes.mixed_batch(3, 2, seed=4, max_boxes=3)
+        P = scenes.solver_params()
+    else:
+        b = scenes.terrain_batch(3, seed=5, n_maps=2)
+        P = scenes.solver_params(truncate=1)
+    ctrl_at = _robots_ctrl(b)
+    T = Team(lib, b, P)
+    W = b.n_worlds
+    h = fibers.tf_create(ctypes.byref(T.cb), ctypes.byref(T.cp), T.caps.ctypes.data, T.toff.ctypes.data, 128)
+    try:
+        q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+        rng = np.random.default_rng(3)
+        deferred, nacts = 0, []
+        for k in range(2):
+            c = ctrl_at(k)
+            cv = np.ascontiguousarray(c if c is not None else np.zeros(max(b.n_ctrl, 1)), dtype=np.float64)
+            gqn, gun = rng.normal(size=q.shape), rng.normal(size=u.shape)
+            runs = []
+            for tier in (0, nc1):
+                fibers.tf_set_tier(h, tier)
+                o = dict(q=np.zeros_like(q), u=np.zeros_like(u), lam=np.zeros_like(lam),
+                         act=np.full(max(b.n_slots, 1), -1, np.int32), n_act=np.zeros(W, np.int32),
+                         st=np.zeros(W, np.int32), it=np.zeros(W, np.int32), rn=np.zeros(W),
+                         tape=np.zeros(int(T.toff[-1])))
+                fibers.tf_forward(h, k + 1, q.ctypes.data, u.ctypes.data, lam.ctypes.data, cv.ctypes.data,
+                                  *[o[x].ctypes.data for x in ("q", "u", "lam", "act", "n_act", "st", "it", "rn",
+                                                               "tape")])
+                gq, gu, gc = np.zeros_like(q), np.zeros_like(u), np.zeros(max(b.n_ctrl, 1))
+                fibers.tf_adjoint(h, k + 1, q.ctypes.data, u.ctypes.data, cv.ctypes.data, o["u"].ctypes.data,
+                                  o["lam"].ctypes.data, o["tape"].ctypes.data, gqn.ctypes.data, gun.ctypes.data,
+                                  gq.ctypes.data, gu.ctypes.data, gc.ctypes.data, 8)
+                deferred += fibers.tf_deferred(h) if tier else 0
+                runs.append([o[x] for x in ("q", "u", "lam", "act", "n_act", "st", "it", "tape")] + [gq, gu, gc])
+            for x, y in zip(*runs):
+                assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), (name, k)
+            nacts.append(runs[0][4])
+            q, u, lam = runs[0][0], runs[0][1], runs[0][2]
+        nacts = np.concatenate(nacts)
+        assert np.any(nacts > nc1) and np.any(nacts <= nc1), nacts
+        assert deferred == 2 * np.sum(nacts > nc1)  # forward and adjoint
+        assert _violations(fibers, h) == (0, "")
+    finally:
+        fibers.tf_set_tier(h, 0)
+        fibers.tf_destroy(h)
