@@ -182,6 +182,12 @@ class ServingEngine:
                 r.iter_mark = self.be.mark()
                 active.append(r)
             if not active:
+                if pending and pending[0].arrival <= now:
+                    # nothing runs, so no slot, budget or heightmap will be freed: the head
+                    # request, which arrived and was not admitted, can never be
+                    r = pending[0]
+                    raise ValueError(f"request {r.rid} ({r.n_worlds} worlds) can never be admitted: the pool "
+                                     f"holds {self.be.capacity} worlds, or it needs a resource the backend lacks")
                 continue
             fw = [r for r in active if r.phase == 0]
             bw = [r for r in active if r.phase == 1]
@@ -214,6 +220,8 @@ class ServingEngine:
                             self.slots.release(r.slot0, r.n_worlds)
                             active.remove(r)
                             done.append(r)
+                            if not active:
+                                self.used = 0.0  # no rounding residue once nothing is held
                         else:
                             self.be.begin_iteration(r)
                             r.phase, r.k = 0, 0

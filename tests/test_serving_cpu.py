@@ -123,3 +123,15 @@ def test_lazy_request_worlds_are_built_once_and_only_when_read():
     built = lazy[1]._b
     _ = lazy[1].u0
     assert lazy[1]._b is built
+
+
+def test_request_larger_than_the_pool_is_rejected_not_waited_for():
+    """A request with more worlds than the pool holds can never be admitted: once
+    nothing runs (so nothing will free slots), the engine says so instead of spinning,
+    after serving what came before it."""
+    reqs = [Request(0, B(4), T=2, iters=1, arrival=0.0), Request(1, B(20), T=2, iters=1, arrival=0.0)]
+    be = FakeBackend(16, tick_seconds=0.01)
+    eng = ServingEngine(be, 1e12, clock=be.clock)
+    with pytest.raises(ValueError, match="can never be admitted"):
+        eng.run(reqs)
+    assert reqs[0].it == 1  # the admissible request ahead of it was served
