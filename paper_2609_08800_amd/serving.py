@@ -148,6 +148,10 @@ class ServingEngine:
         """Serve the requests (arrival times relative to now).  With a deadline
         (seconds), stop when it passes: requests still pending or active are
         reported as unfinished and their device memory is released."""
+        for r in requests:
+            if r.n_worlds < 1 or r.T < 1 or r.iters < 1:
+                raise ValueError(f"request {r.rid}: needs at least one world, one step and one iteration "
+                                 f"({r.n_worlds} worlds, T = {r.T}, {r.iters} iterations)")
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         active: List[Request] = []
         done: List[Request] = []

@@ -135,3 +135,14 @@ def test_request_larger_than_the_pool_is_rejected_not_waited_for():
     with pytest.raises(ValueError, match="can never be admitted"):
         eng.run(reqs)
     assert reqs[0].it == 1  # the admissible request ahead of it was served
+
+
+@pytest.mark.parametrize("n,T,iters", [(0, 3, 1), (2, 0, 1), (2, 3, 0)])
+def test_degenerate_requests_are_rejected(n, T, iters):
+    """A request without worlds, steps or iterations is an argument error, raised before
+    anything is admitted."""
+    be = FakeBackend(16, tick_seconds=0.01)
+    eng = ServingEngine(be, 1e12, clock=be.clock)
+    with pytest.raises(ValueError, match="at least one world"):
+        eng.run([Request(0, B(2), T=2, iters=1), Request(1, B(n), T=T, iters=iters)])
+    assert eng.ticks == [] and eng.used == 0.0
