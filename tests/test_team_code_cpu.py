@@ -1,13 +1,18 @@
 """The library's per-world team procedures (the code the GPU kernels run),
-compiled for the host with a team of one thread, against the oracle on the CPU.
+compiled for the host with a team of one thread, and with teams of 64 to 256
+threads run as fibers, against the oracle on the CPU.
 
 This checks the kernel's algorithm, not the GPU: every step of the fused
 forward, the Krylov adjoint solve and the parameter cotangents, on robots,
 spinning tripods (where the adjoint needs the exact geometric stiffness),
-position servos and the matrix-free Krylov Newton step (switched off on the
-GPU, exercised here).  A run with the workspace pre-filled with garbage must
-give the same bits as one with zeros: no entry is read before it is written.
-Bars as on the GPU: states 1e-9, gradients 1e-6.
+position servos, cylinder wheels (rim circles on the plane, the obstacle box
+and terrain), stacks of up to 32 boxes and the matrix-free Krylov Newton step
+(switched off on the GPU, exercised here).  A run with the workspace
+pre-filled with garbage must give the same bits as one with zeros: no entry is
+read before it is written.  The fiber teams give the same bits under any
+schedule and keep the GPU's synchronisation rules (checked at every barrier).
+Bars as on the GPU: states 1e-9, gradients 1e-6; 1e-12 on determinate single
+rim contacts.
 """
 import ctypes
 import os
