@@ -131,6 +131,10 @@ def step_forward(batch, params, q, u, lam, ctrl):
 
 
 def step_adjoint(batch, params, q, u, lam, ctrl, u_next, lam_next, gq_next, gu_next, mode=0):
+    """Cotangents of (q-, u-, controls) from those of (q+, u+) through one step (Sec. III-D).
+    mode 0: the exact implicit-function adjoint; 1: the paper's lagged Schur adjoint
+    (Eqs. (18)-(19)); 2: the adjoint solved with the forward's own Newton matrix (the
+    exact system without the geometric stiffness of J^T lambda)."""
     H = _Handle(batch, params)
     q, u, lam = _d(q), _d(u), _d(lam)
     ctrl = _d(ctrl if ctrl is not None else np.zeros(max(batch.n_ctrl, 1)))

@@ -1313,9 +1313,13 @@ void finalize_q(const double* qm, const double* u, int nb, double h, double* qn)
 //   H = [[M~ - h d(J^T lambda)/du, -h J^T], [G_u, G_lambda + h dreg_adj diag(Abar)]],
 // the multiplier block regularised by the adjoint's own delta_reg_adj (the
 // root does not depend on the regularisation of the Newton iterations, but
-// an adjoint solved with it would carry an O(delta_reg) bias).
+// an adjoint solved with it would carry an O(delta_reg) bias).  Without
+// `stiffness` the term - h d(J^T lambda)/du is left out: H is then the Newton
+// matrix the forward iteration factors (the generalized Jacobian of the rows,
+// the geometric stiffness of J^T lambda dropped), so an adjoint solved with it
+// is the paper's reuse of the forward's matrix (Sec. III-D) for this forward.
 void exact_jacobian(const StepCtx& X, const Eval<double>& E, const Schur& S, const double* u,
-                    const double* lam, std::vector<double>& H) {
+                    const double* lam, std::vector<double>& H, bool stiffness = true) {
   const Layout& L = X.L;
   const WorldD& W = X.W;
   const int nu = L.nu, m = L.m, n = nu + m;
@@ -1339,7 +1343,7 @@ void exact_jacobian(const StepCtx& X, const Eval<double>& E, const Schur& S, con
   Dd zero6[6], zero7[7];
   for (int t = 0; t < 6; ++t) zero6[t] = Dd(0.0);
   for (int t = 0; t < 7; ++t) zero7[t] = Dd(t == 6 ? 1.0 : 0.0);
-  for (int g = 0; g < m; g += group_size(L, g)) {
+  for (int g = 0; stiffness && g < m; g += group_size(L, g)) {
     int k = L.kind[g], a = L.ra[g], b = L.rb[g], ng = group_size(L, g);
     Contact<Dd> Cd{};
     if (k == R_NORMAL) Cd = lift_contact(X.C[L.idx[g]]);
@@ -1458,9 +1462,11 @@ void adjoint_world(StepCtx& X, const double* u_star, const double* lam_slots, co
     for (int i = 0; i < m; ++i) w[nu + i] = wl[i];
   } else {
     // Exact IFT, Eq. (16): H^T w = -[b; 0], H the full Jacobian of the scaled
-    // residual (its multiplier block regularised by delta_reg_adj).
+    // residual (its multiplier block regularised by delta_reg_adj); mode 2
+    // leaves out its geometric stiffness, solving with the forward's Newton
+    // matrix instead.
     std::vector<double> H;
-    exact_jacobian(X, E, S, u_star, lam.data(), H);
+    exact_jacobian(X, E, S, u_star, lam.data(), H, mode != 2);
     std::vector<double> Ht(n * n);
     for (int r = 0; r < n; ++r)
       for (int c = 0; c < n; ++c) Ht[r * n + c] = H[c * n + r];
@@ -1551,6 +1557,7 @@ extern "C" int ostrich_ref_step_adjoint(const ostrich_ref_batch* b, const ostric
                                         double* gu_prev, double* g_ctrl, int32_t mode) {
   (void)lam_prev;
   if (!b || !p || !q_prev || !u_prev || !u_next || !lam_next || !gq_next || !gu_next) return -1;
+  if (mode < 0 || mode > 2) return -1;
   Prm P = load_params(p);
   for (int w = 0; w < b->n_worlds; ++w) {
     StepCtx X;
@@ -1574,7 +1581,7 @@ extern "C" int ostrich_ref_step_adjoint_params(const ostrich_ref_batch* b, const
                                                double* g_ctrl, double* g_mass, double* g_mu, double* g_kp,
                                                int32_t mode) {
   if (!b || !p || !q_prev || !u_prev || !u_next || !lam_next || !gq_next || !gu_next || !gq_prev || !gu_prev ||
-      !g_mass || !g_mu || !g_kp)
+      !g_mass || !g_mu || !g_kp || mode < 0 || mode > 2)
     return -1;
   Prm P = load_params(p);
   for (int w = 0; w < b->n_worlds; ++w) {
@@ -1755,7 +1762,7 @@ extern "C" int ostrich_ref_rollout(const ostrich_ref_batch* b, const ostrich_ref
                                    const int32_t* loss_body, const double* target, double* loss, double* qT,
                                    double* uT, double* g_q0, double* g_u0, double* g_knots, int32_t mode,
                                    int32_t* status_or) {
-  if (!target) return -1;
+  if (!target || mode < 0 || mode > 2) return -1;
   return rollout_impl(b, p, q0, u0, knots, K, T, loss_body, target, nullptr, loss, qT, uT, g_q0, g_u0, g_knots, mode,
                       status_or);
 }
@@ -1765,7 +1772,8 @@ extern "C" int ostrich_ref_rollout_shaped(const ostrich_ref_batch* b, const ostr
                                           const int32_t* loss_body, const ostrich_ref_loss* spec, double* loss,
                                           double* qT, double* uT, double* g_q0, double* g_u0, double* g_knots,
                                           int32_t mode, int32_t* status_or) {
-  if (!spec || !spec->goal || ((spec->w_track != 0.0 || spec->w_yaw != 0.0) && !spec->ref)) return -1;
+  if (!spec || !spec->goal || ((spec->w_track != 0.0 || spec->w_yaw != 0.0) && !spec->ref) || mode < 0 || mode > 2)
+    return -1;
   return rollout_impl(b, p, q0, u0, knots, K, T, loss_body, nullptr, spec, loss, qT, uT, g_q0, g_u0, g_knots, mode,
                       status_or);
 }

@@ -78,7 +78,11 @@ int ostrich_ref_step_forward(const ostrich_ref_batch* b, const ostrich_ref_param
                              double* resnorm);
 
 /* mode 0: exact implicit-function-theorem adjoint; mode 1: the paper's lagged
- * Schur adjoint (Eqs. (18)-(19)) followed by the exact residual pull-back. */
+ * Schur adjoint (Eqs. (18)-(19)) followed by the exact residual pull-back;
+ * mode 2: the adjoint solved with the forward's own Newton matrix (the
+ * generalized Jacobian of the rows without the geometric stiffness of
+ * J^T lambda), the paper's reuse of the forward's matrix for this forward,
+ * followed by the same pull-back.  Other modes: -1. */
 int ostrich_ref_step_adjoint(const ostrich_ref_batch* b, const ostrich_ref_params* p,
                              const double* q_prev, const double* u_prev, const double* lam_prev,
                              const double* ctrl, const double* u_next, const double* lam_next,

@@ -923,3 +923,33 @@ def test_position_servo_gradients_match_finite_differences():
         fd[i] = (lp["loss"].sum() - lm["loss"].sum()) / (2 * d)
     g = base["g_knots"].reshape(-1)
     assert np.linalg.norm(fd - g) <= 1e-6 * np.linalg.norm(g), (fd, g)
+
+
+def test_adjoint_with_the_forward_newton_matrix():
+    """Mode 2 solves the adjoint with the forward's own Newton matrix: the exact system
+    without the geometric stiffness h d(J(u)^T lambda)/du.  Where J does not depend on
+    u (a sphere centred on its body: lever -r n, n fixed within the step) the two are
+    the same system and give the same bits; on a spinning, sliding tripod the stiffness
+    is there and the velocity cotangents differ (1.8e-3 here, tens of percent on the
+    faster tripods of the team-code tests), far beyond the rounding of two solves of
+    one system."""
+    w = scenes.World(contact_cap=4)
+    w.add_body(1.0, (0.004, 0.004, 0.004), (0.0, 0.0, 0.099, 0, 0, 0, 1), (0.8, 0.3, -0.1, 0.5, -0.4, 2.0))
+    w.add_slot(scenes.SLOT_PLANE, 0, radius=0.1, mu=0.3)
+    w.knots = np.zeros((0, scenes.ROBOT_KNOTS))
+    b = scenes.pack([w])
+    P = scenes.solver_params(k_max=64, tol=1e-13)
+    rng = np.random.default_rng(0)
+    for batch in (b, scenes.pack([tripod_world((0.9, 0.4, 0), (0.05, -0.05, 1.2), 0.2, (0.3, -0.2))])):
+        o = oracle.step_forward(batch, P, batch.q0, batch.u0, np.zeros(batch.n_lam), None)
+        assert o["status"][0] & 1 and o["n_act"][0] >= 1
+        gq, gu = rng.normal(size=batch.q0.shape), rng.normal(size=batch.u0.shape)
+        args = (batch, P, batch.q0, batch.u0, np.zeros(batch.n_lam), None, o["u"], o["lam"], gq, gu)
+        exact, fwd = oracle.step_adjoint(*args, mode=0), oracle.step_adjoint(*args, mode=2)
+        dev = np.linalg.norm(fwd[1] - exact[1]) / np.linalg.norm(exact[1])
+        if batch is b:
+            assert np.array_equal(fwd[0], exact[0]) and np.array_equal(fwd[1], exact[1])
+        else:
+            assert dev > 1e-4, dev
+    with pytest.raises(RuntimeError):
+        oracle.step_adjoint(*args, mode=3)

@@ -646,3 +646,38 @@ def test_tiered_carve_as_a_fiber_team(lib, fibers, name, nc1):
     finally:
         fibers.tf_set_tier(h, 0)
         fibers.tf_destroy(h)
+
+
+@pytest.mark.parametrize("name", ["tripods", "robots", "terrain", "cylinder_robots"])
+def test_factor_only_adjoint_matches_the_oracle_with_the_forward_matrix(lib, name):
+    """refine = 0, the adjoint solved with the stored factor alone (the paper's reuse of
+    the forward's matrix, Sec. III-D), against the oracle's mode 2, the same system
+    solved densely: every cotangent block per world as in the exact-adjoint test.  On
+    the tripods this system is tens of percent from the exact one, so the comparison
+    tells the two apart."""
+    b, P, ctrl_at = _scene(name)
+    T = Team(lib, b, P)
+    q, u, lam = b.q0.copy(), b.u0.copy(), np.zeros(b.n_lam)
+    rng = np.random.default_rng(5)
+    checked = 0
+    for k in range(2):
+        c = ctrl_at(k)
+        o = T.forward(q, u, lam, c)
+        r = oracle.step_forward(b, P, q, u, lam, c)
+        gqn, gun = rng.normal(size=q.shape), rng.normal(size=u.shape)
+        g = T.adjoint(q, u, c, o, gqn, gun, refine=0)
+        R = oracle.step_adjoint_params(b, P, q, u, c, o["u"], o["lam"], gqn, gun, mode=2)
+        for w in range(b.n_worlds):
+            if not (o["status"][w] & 1):
+                continue
+            checked += 1
+            bs, js = slice(b.body_off[w], b.body_off[w + 1]), slice(b.joint_off[w], b.joint_off[w + 1])
+            ss, cs = slice(b.slot_off[w], b.slot_off[w + 1]), slice(b.ctrl_off[w], b.ctrl_off[w + 1])
+            blocks = (("gq", bs), ("gu", bs), ("g_mass", bs), ("g_kp", js), ("g_mu", ss), ("gc", cs))
+            whole = np.linalg.norm(np.concatenate([R[key][sl].ravel() for key, sl in blocks]))
+            for key, sl in blocks:
+                got, ref = g[key][sl].ravel(), R[key][sl].ravel()
+                bar = GRAD_TOL * max(np.linalg.norm(ref), 1e-6 * whole, 1e-12)
+                assert np.linalg.norm(got - ref) <= bar, (k, w, key)
+        q, u, lam = r["q"], r["u"], r["lam"]
+    assert checked >= b.n_worlds
