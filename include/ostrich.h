@@ -112,7 +112,10 @@ typedef struct {
   double delta_reg;    /* relative Schur diagonal regularisation of the Newton iterations (> 0) */
   double delta0;       /* contact activation margin (m) */
   int32_t ls_max;      /* step-length halvings of the residual-decrease test */
-  int32_t refine;      /* most Krylov operator applications of the adjoint (0: factor only) */
+  int32_t refine;      /* most Krylov operator applications of the adjoint; 0: the stored factor alone, i.e.
+                          the system with the forward's Newton matrix (without the geometric stiffness of
+                          J^T lambda), the paper's reuse of the forward's factor (Sec. III-D); > 0: towards
+                          the exact implicit-function system (OSTRICH_ST_ADJ_INEXACT if not reached) */
   int32_t team;        /* threads per world (64, 128 or 256) before autotuning; 0: 128, or 256 for a
                           bucket whose on-chip workspace fits only one 128-thread workgroup per CU */
   int32_t schedule;    /* OSTRICH_SCHED_FIXED or OSTRICH_SCHED_BUCKETED */
