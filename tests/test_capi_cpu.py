@@ -106,3 +106,36 @@ def test_segment_copy_rejects_bad_arguments_before_any_launch():
     segs[1].src, segs[1].n = 8, -1
     assert lib.ostrich_copy_segments(segs, 2, None) != 0
     assert lib.ostrich_copy_segments(segs, 0, None) == 0  # nothing to do
+
+
+def test_product_does_not_use_the_oracle():
+    """The oracle is test infrastructure: no module of the package imports or names it,
+    no library source includes it, and the built library neither depends on the oracle's
+    shared object nor references any of its symbols."""
+    import ast
+    import shutil
+    import subprocess
+    pkg = os.path.join(ROOT, "paper_2609_08800_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            path = os.path.join(dirpath, f)
+            if f.endswith(".py"):
+                src = open(path).read()
+                for node in ast.walk(ast.parse(src)):
+                    if isinstance(node, ast.Import):
+                        assert not any(a.name.split(".")[0] == "oracle" for a in node.names), path
+                    if isinstance(node, ast.ImportFrom):
+                        assert (node.module or "").split(".")[0] != "oracle", path
+                assert "ostrich_ref" not in src, path
+            elif f.endswith((".hip", ".hpp", ".h", ".cpp")):
+                assert "ostrich_ref" not in open(path).read() and "oracle/" not in open(path).read(), path
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        assert "ostrich_ref" not in open(os.path.join(ROOT, "include", f)).read(), f
+    from paper_2609_08800_amd import _capi
+    so, readelf = _capi.SO_PATH, shutil.which("readelf")
+    if not os.path.exists(so) or readelf is None:
+        pytest.skip("library not built or readelf missing")
+    dyn = subprocess.run([readelf, "-dW", so], capture_output=True, text=True, check=True).stdout
+    assert "ostrich_ref" not in dyn
+    syms = subprocess.run([readelf, "--dyn-syms", "-W", so], capture_output=True, text=True, check=True).stdout
+    assert "ostrich_ref" not in syms
