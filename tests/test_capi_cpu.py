@@ -139,3 +139,20 @@ def test_product_does_not_use_the_oracle():
     assert "ostrich_ref" not in dyn
     syms = subprocess.run([readelf, "--dyn-syms", "-W", so], capture_output=True, text=True, check=True).stdout
     assert "ostrich_ref" not in syms
+
+
+def test_oracle_shares_no_code_with_the_library():
+    """The oracle includes only its own header and the C++ standard library, and imports
+    neither the package nor anything of the library's."""
+    import ast
+    odir = os.path.join(ROOT, "oracle")
+    for f in ("ostrich_ref.cpp", "ostrich_ref.h"):
+        for inc in re.findall(r'#include\s*[<"]([^>"]+)[>"]', open(os.path.join(odir, f)).read()):
+            assert inc == "ostrich_ref.h" or "/" not in inc and not inc.endswith((".hpp", ".hip")) and \
+                not inc.startswith(("ostrich.", "hip")), (f, inc)
+    tree = ast.parse(open(os.path.join(odir, "__init__.py")).read())
+    for node in ast.walk(tree):
+        mods = [a.name for a in node.names] if isinstance(node, ast.Import) else (
+            [node.module or ""] if isinstance(node, ast.ImportFrom) else [])
+        for m in mods:
+            assert m.split(".")[0] not in ("paper_2609_08800_amd", "torch"), m
