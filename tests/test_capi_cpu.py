@@ -156,3 +156,21 @@ def test_oracle_shares_no_code_with_the_library():
             [node.module or ""] if isinstance(node, ast.ImportFrom) else [])
         for m in mods:
             assert m.split(".")[0] not in ("paper_2609_08800_amd", "torch"), m
+
+
+def test_missing_library_and_missing_gpu_fail_loudly(monkeypatch, tmp_path):
+    """No fallback: loading an unbuilt library raises, and so does a simulator without a
+    ROCm GPU (on a machine that has one, only the first half applies)."""
+    from paper_2609_08800_amd import OstrichError, _capi
+    monkeypatch.setattr(_capi, "_lib", None)
+    monkeypatch.setattr(_capi, "SO_PATH", str(tmp_path / "missing" / "libostrich.so"))
+    with pytest.raises(OstrichError, match="not built"):
+        _capi.load()
+    monkeypatch.undo()
+    import torch
+    if torch.cuda.is_available():
+        return
+    import scenes
+    from paper_2609_08800_amd import Simulator
+    with pytest.raises(OstrichError, match="no CPU fallback"):
+        Simulator(scenes.robot_batch(1, seed=0), scenes.solver_params(), device="cuda:0")
