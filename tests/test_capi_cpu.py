@@ -174,3 +174,17 @@ def test_missing_library_and_missing_gpu_fail_loudly(monkeypatch, tmp_path):
     from paper_2609_08800_amd import Simulator
     with pytest.raises(OstrichError, match="no CPU fallback"):
         Simulator(scenes.robot_batch(1, seed=0), scenes.solver_params(), device="cuda:0")
+
+
+def test_no_committed_code_reads_the_reference_or_working_files():
+    """Sources, tests, the benchmark and the build entry read nothing from the paper's
+    folder and nothing from the untracked working folder."""
+    banned = ("/root/" + "reference", "_wo" + "rk/")
+    skip = {".git", "_work", "gpurun_out", "__pycache__", "_build"}
+    for dirpath, dirs, files in os.walk(ROOT):
+        dirs[:] = [d for d in dirs if d not in skip]
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp", ".sh", ".toml", ".cfg", ".txt")):
+                text = open(os.path.join(dirpath, f), errors="replace").read()
+                for b in banned:
+                    assert b not in text, (os.path.join(dirpath, f), b)
